@@ -1,0 +1,257 @@
+"""Checks that pin the CPU oracle to facts outside itself.
+
+Each check raises AssertionError on failure.  They are run against the real
+oracle (test_oracle_pins.py) and against deliberately broken copies of it
+(test_oracle_mutants.py), to show that a plausible mistake anywhere in the
+oracle -- a dropped term, a wrong sign or index, a swapped operand -- fails at
+least one of them.
+
+Sources of truth used here, none of them the oracle's own code:
+* rocRAND's Philox4x32-10 run on the host (an independent implementation),
+* exact rational arithmetic for the uniform construction and the box mapping,
+* 40-digit mpmath evaluation of each integrand at a point,
+* math.fsum brute force of the sums on tiny sample counts,
+* closed-form box integrals (tests/closed_forms.py): the estimate must sit
+  within a few standard errors of the exact value, the standard errors must
+  match the exact ones, and batches of z-scores must look standard normal,
+* textbook special cases (constant integrands, linearity in the amplitudes).
+"""
+
+from __future__ import annotations
+
+import math
+from fractions import Fraction
+
+import mpmath
+import numpy as np
+
+from paper_2104_10073_amd import workloads as W
+
+from closed_forms import exact_integral, exact_se, point_value
+
+EPS = 2.0 ** -52
+
+
+def exact_uniform(r: int) -> Fraction:
+    return Fraction(2 * (r & 0x7FFFFF) + 1, 1 << 24)
+
+
+def exact_point(t, i, words) -> list[float]:
+    """Sample coordinates from raw words: x_j = round(lo_j + (hi_j - lo_j) * u_j)."""
+    d = int(t["dim"][i])
+    xs = []
+    for j in range(d):
+        lo, hi = float(t["lo"][i, j]), float(t["hi"][i, j])
+        w = hi - lo
+        xs.append(float(Fraction(lo) + Fraction(w) * exact_uniform(words[j])))
+    return xs
+
+
+def small_mixed(n=40, dims=(1, 4), n_samples=20_000, gen_seed=31, base=0):
+    return W.mixed_batch(n, dim_range=dims, log10_samples=(4.0, 4.0001), gen_seed=gen_seed,
+                         base=base, sample_scale=n_samples / 10_000)
+
+
+# ---------------------------------------------------------------------------
+
+def check_philox_blocks(orc, rocrand_ref, n=24):
+    rng = np.random.Generator(np.random.PCG64(5))
+    cases = [(0, 0, 0, 0, 0, 0)]
+    for _ in range(n):
+        c = [int(v) for v in rng.integers(0, 2**32, 4)]
+        c[1] &= 0x0FFFFFFF
+        k = [int(v) for v in rng.integers(0, 2**32, 2)]
+        cases.append(tuple(c + k))
+    ref = rocrand_ref(["b " + " ".join(str(v) for v in cs) for cs in cases])
+    for cs, r in zip(cases, ref):
+        assert orc.philox(cs[:4], cs[4:]) == r, ("philox block", cs)
+
+
+def check_stream_layout(orc, rocrand_ref):
+    lines, expect = [], []
+    for seed in (3, W.stream_seed(9, 2)):
+        for dim in (1, 3, 5, 12):
+            for i0 in (0, 3, 12345):
+                lines.append(f"w {seed} {i0 * dim} {4 * dim}")
+                expect.append([orc.word(seed, dim, i, j) for i in range(i0, i0 + 4) for j in range(dim)])
+    for ln, r, e in zip(lines, rocrand_ref(lines), expect):
+        assert r == e, ("stream layout", ln)
+
+
+def check_uniform(orc):
+    rng = np.random.Generator(np.random.PCG64(6))
+    rs = [0, 1, 0x7FFFFF, 0x800000, 0xFFFFFFFF, 0x3F800000] + [int(v) for v in rng.integers(0, 2**32, 500)]
+    for r in rs:
+        u = orc.uniform(r)
+        assert 0.0 < u < 1.0, ("uniform range", r)
+        assert Fraction(u) == exact_uniform(r), ("uniform value", r)
+
+
+def check_sample_points(orc, rocrand_ref):
+    t = small_mixed(12, dims=(1, 12), gen_seed=41)
+    for i in range(len(t)):
+        d = int(t["dim"][i])
+        seed = int(t["seed"][i])
+        lines = [f"w {seed} {s * d} {d}" for s in (0, 1, 2, 1001)]
+        for s, words in zip((0, 1, 2, 1001), rocrand_ref(lines)):
+            want = exact_point(t, i, words)
+            got = orc.sample_point(t, i, s)
+            assert list(got) == want, ("sample point", i, s)
+
+
+def check_point_values(orc, n_points=25):
+    rng = np.random.Generator(np.random.PCG64(7))
+    t = small_mixed(24, dims=(1, 7), gen_seed=43)
+    for i in range(len(t)):
+        d = int(t["dim"][i])
+        fam = int(t["family"][i])
+        lo, hi = t["lo"][i, :d], t["hi"][i, :d]
+        for _ in range(n_points):
+            x = rng.uniform(lo, hi)
+            got = orc.evaluate(t, i, x)
+            ex = point_value(t, i, x)
+            p = t["params"][i]
+            if fam == W.HARMONIC:
+                scale = (abs(p[0]) + abs(p[1])) * (1.0 + float(np.sum(np.abs(p[W.V0:W.V0 + d] * x))))
+                tol = 8 * EPS * scale
+            elif fam == W.ABS_LINEAR:
+                scale = abs(p[0]) * (abs(p[1]) + float(np.sum(np.abs(p[W.V0:W.V0 + d] * x))))
+                tol = 8 * EPS * scale
+            elif fam == W.GAUSSIAN:
+                q = float(np.sum((x - p[W.V0:W.V0 + d]) ** 2)) / (2 * p[1] ** 2)
+                tol = EPS * (8 + 4 * q) * abs(float(ex)) + 1e-300
+            else:
+                tol = 64 * EPS * float(np.prod(1 + np.abs(p[W.V0:W.V0 + d] * x ** p[W.W0:W.W0 + d])))
+            assert abs(got - float(ex)) <= tol, ("point value", i, fam, got, float(ex))
+
+
+def check_brute_force_sums(orc, rocrand_ref):
+    """S1, S2 over N <= 16 samples equal fsum of exactly-evaluated f at exactly-mapped points."""
+    t = small_mixed(16, dims=(1, 6), gen_seed=47)
+    for i in range(len(t)):
+        d = int(t["dim"][i])
+        seed = int(t["seed"][i])
+        n = 1 + (i % 16)
+        words = rocrand_ref([f"w {seed} 0 {n * d}"])[0]
+        fs = []
+        for s in range(n):
+            x = exact_point(t, i, words[s * d:(s + 1) * d])
+            fs.append(point_value(t, i, x))
+        s1_ref = math.fsum(float(v) for v in fs)
+        s2_ref = math.fsum(float(v * v) for v in fs)
+        sabs = math.fsum(abs(float(v)) for v in fs)
+        s1, s2, sa = orc.partial_sums(t, i, 0, n)
+        # each f carries a few ulp of evaluation error (harmonic phases up to ~200 rad)
+        tol1 = 1e-13 * (sabs + 1.0)
+        assert abs(s1 - s1_ref) <= tol1, ("S1 brute force", i, s1, s1_ref)
+        assert abs(s2 - s2_ref) <= 1e-13 * (s2_ref + 1.0), ("S2 brute force", i, s2, s2_ref)
+        assert abs(sa - sabs) <= tol1, ("sum|f| brute force", i)
+        if n >= 2:
+            # finalize: textbook unbiased variance of the same f values
+            mean, se = orc.finalize(orc.volume(t, i), n, s1, s2)
+            fl = [float(v) for v in fs]
+            mu = math.fsum(fl) / n
+            var = math.fsum((v - mu) ** 2 for v in fl) / (n - 1)
+            V = float(np.prod(t["hi"][i, :d] - t["lo"][i, :d]))
+            assert abs(mean - V * mu) <= 1e-12 * V * (sabs / n + 1e-300), ("finalize mean", i)
+            se_ref = V * math.sqrt(var / n)
+            assert abs(se - se_ref) <= 1e-6 * se_ref + 1e-12 * V * math.sqrt(s2_ref / n) / n, ("finalize se", i)
+
+
+def check_finalize_textbook(orc):
+    """f = 1, 2, 3, 4 on a box of volume 2: mean 5, sample variance 5/3."""
+    mean, se = orc.finalize(2.0, 4, 10.0, 30.0)
+    assert mean == 5.0
+    assert abs(se - 2.0 * math.sqrt((5.0 / 3.0) / 4.0)) <= 1e-15
+
+
+def _z_scores(orc, t):
+    res, _ = orc.integrate(t, threads=8)
+    z = []
+    for i in range(len(t)):
+        ex = exact_integral(t, i)
+        se_ex = exact_se(t, i)
+        assert res["status"][i] == 0
+        if se_ex == 0.0:
+            assert res["mean"][i] == ex or abs(res["mean"][i] - ex) <= 1e-12 * abs(ex)
+            continue
+        z.append((res["mean"][i] - ex) / se_ex)
+        # the oracle's own SE estimates the exact one (relative error ~ 1/sqrt(N) times kurtosis)
+        assert abs(res["stderr"][i] / se_ex - 1.0) < 0.15, ("stderr vs exact", i, res["stderr"][i], se_ex)
+    return np.array(z)
+
+
+def check_closed_forms_4sigma(orc):
+    """Every estimate within 4 sigma of its exact integral on tiny inputs (d <= 4, N = 2e4)."""
+    t = small_mixed(40, dims=(1, 4), n_samples=20_000, gen_seed=53)
+    z = _z_scores(orc, t)
+    assert np.all(np.abs(z) < 4.0), ("4 sigma", np.max(np.abs(z)))
+
+
+def check_z_batch(orc, n_funcs=100):
+    """Batch z-scores look standard normal: Eq. (1) series and a mixed batch."""
+    for t in (W.eq1_series(n_samples=10_000, n_funcs=n_funcs),
+              small_mixed(n_funcs, dims=(1, 5), n_samples=10_000, gen_seed=59)):
+        z = _z_scores(orc, t)
+        m = len(z)
+        assert abs(z.mean()) < 4.0 / math.sqrt(m), ("z mean", z.mean())
+        assert abs((z * z).mean() - 1.0) < 4.0 * math.sqrt(2.0 / m), ("z^2 mean", (z * z).mean())
+
+
+def check_special_cases(orc):
+    # k = 0: f is the constant a; every sum is exact
+    t = W.empty(3)
+    W.set_harmonic(t, 0, 3, 1.5, -0.25, [0.0, 0.0, 0.0], [0, -1, 2], [1, 0.5, 2.25])
+    W.set_poly(t, 1, 5, [0.0] * 5, [1, 2, 3, 4, 2], [-1] * 5, [0.5] * 5)
+    W.set_abs_linear(t, 2, 2, -2.0, 10.0, [1.0, -1.0], [0, 0], [1, 1])  # L > 0 everywhere: f = -2 L
+    t["n_samples"][:] = 1000
+    t["seed"][:] = [1, 2, 3]
+    res, _ = orc.integrate(t, threads=1)
+    V0 = 1.0 * 1.5 * 0.25
+    assert res["sum_f"][0] == 1000 * 1.5 and res["stderr"][0] == 0.0
+    assert res["mean"][0] == V0 * 1.5
+    assert res["mean"][1] == 1.5 ** 5 and res["stderr"][1] == 0.0
+    # abs-linear with L > 0: the estimate is the sample mean of -2 (10 + x1 - x2)
+    s1 = 0.0
+    pts = [orc.sample_point(t, 2, s) for s in range(1000)]
+    s1 = math.fsum(-2.0 * (10.0 + x[0] - x[1]) for x in pts)
+    assert abs(res["sum_f"][2] - s1) <= 1e-12 * abs(s1)
+    # linearity in (a, b) on the same samples
+    base = W.harmonic_batch(4, n_samples=5000, gen_seed=61)
+    ta, tb = base.copy(), base.copy()
+    ta["params"][:, 1] = 0.0
+    ta["params"][:, 0] = 1.0
+    tb["params"][:, 0] = 0.0
+    tb["params"][:, 1] = 1.0
+    r, _ = orc.integrate(base, 1)
+    ra, _ = orc.integrate(ta, 1)
+    rb, _ = orc.integrate(tb, 1)
+    a, b = base["params"][:, 0], base["params"][:, 1]
+    lin = a * ra["sum_f"] + b * rb["sum_f"]
+    assert np.all(np.abs(r["sum_f"] - lin) <= 1e-12 * r["sum_abs"]), "linearity in (a, b)"
+
+
+def check_eq2_worked_values(orc):
+    """Eq. (2) on unit boxes: int |x1+x2| = 1 and int |x1+x2-x3| = 7/12; estimates within 4 sigma."""
+    t = W.eq2_series(n_samples=40_000)
+    assert abs(exact_integral(t, 0) - 1.0) < 1e-15
+    assert abs(exact_integral(t, 60) - 7.0 / 12.0) < 1e-15
+    sub = np.ascontiguousarray(t[[0, 10, 48, 49, 60, 99]])
+    res, _ = orc.integrate(sub, 2)
+    for i in range(len(sub)):
+        ex = exact_integral(sub, i)
+        assert abs(res["mean"][i] - ex) < 4 * exact_se(sub, i), ("Eq. 2", i)
+
+
+ALL_CHECKS = [
+    ("philox_blocks", lambda o, r: check_philox_blocks(o, r)),
+    ("stream_layout", lambda o, r: check_stream_layout(o, r)),
+    ("uniform", lambda o, r: check_uniform(o)),
+    ("sample_points", lambda o, r: check_sample_points(o, r)),
+    ("point_values", lambda o, r: check_point_values(o, n_points=6)),
+    ("brute_force", lambda o, r: check_brute_force_sums(o, r)),
+    ("finalize", lambda o, r: check_finalize_textbook(o)),
+    ("special_cases", lambda o, r: check_special_cases(o)),
+    ("closed_forms", lambda o, r: check_closed_forms_4sigma(o)),
+    ("eq2", lambda o, r: check_eq2_worked_values(o)),
+]
