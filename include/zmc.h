@@ -1,0 +1,195 @@
+/*
+ * zmc.h -- C ABI of the MI355X (gfx950) multi-function direct Monte Carlo library.
+ *
+ * The operation (paper: "Multi-function Integrations" and "Solution method"):
+ * many integrands, each with its own form, dimension (1..12) and box domain
+ * (Eq. (1): a cos(k.x) + b sin(k.x); Eq. (2): |x1+x2|, |x1+x2-x3|; plus
+ * Gaussian and product-polynomial forms), are each integrated by direct Monte
+ * Carlo: N uniform samples x_i in the box give
+ *
+ *     F_hat = V * (1/N) * sum f(x_i),   V = prod_j (hi_j - lo_j),
+ *     SE    = V * sqrt(s^2 / N),        s^2 = (sum f^2 - (sum f)^2 / N) / (N - 1),
+ *
+ * a value with an error bar for every integral (Fig. 1 caption).  Samples are
+ * counter-based: coordinate j of sample i of a function with seed s is the
+ * 32-bit word g = i*d + j of the Philox4x32-10 stream with key (s mod 2^32,
+ * s >> 32) and counter (g/4 mod 2^32, g/4 >> 32, 0, 0); the word r becomes
+ * u = (2*(r mod 2^23) + 1) * 2^-24 and x_j = lo_j + (hi_j - lo_j) * u.  A
+ * function's result therefore depends only on its own description, never on
+ * the rest of the batch, the launch shape or the tuning.
+ *
+ * Conventions for every entry point:
+ *   - Return an mc_status; nothing throws across the boundary.  On failure
+ *     mc_last_error(ctx) holds a message (thread-local when ctx is NULL).
+ *   - Host arrays (mc_function[], mc_result[]) are caller-owned; the library
+ *     copies what it needs before returning.
+ *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
+ *     null stream).  Work is enqueued asynchronously on that stream.
+ *   - A context is externally synchronized: one thread at a time.
+ */
+#ifndef ZMC_H
+#define ZMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define MC_MAX_DIM 12
+#define MC_N_PARAMS 32
+
+typedef enum {
+    MC_OK = 0,
+    MC_NOT_READY = 1,              /* results not finished yet (non-blocking query) */
+    MC_ERR_INVALID_ARG = -1,       /* NULL pointer, n_samples < 2, bad config field */
+    MC_ERR_UNSUPPORTED_FAMILY = -2,
+    MC_ERR_BAD_DIM = -3,           /* dim outside 1..12 */
+    MC_ERR_BAD_BOUNDS = -4,        /* lo/hi not finite or lo >= hi */
+    MC_ERR_BAD_PARAMS = -5,        /* non-finite parameter, sigma <= 0, bad degree */
+    MC_ERR_OUT_OF_MEMORY = -6,     /* device or pinned allocation failed */
+    MC_ERR_ADMISSION = -7,         /* request can never fit the context's capacity */
+    MC_ERR_HIP = -8,               /* a HIP runtime call failed (message has the HIP string) */
+    MC_ERR_NO_DEVICE = -9,         /* no usable gfx950 device, or device call on a validate-only context */
+    MC_ERR_ABORTED = -10,          /* work stopped by mc_abort before it finished */
+    MC_ERR_UNKNOWN_REQUEST = -11   /* request id never issued or results already taken */
+} mc_status;
+
+typedef enum {
+    MC_FAMILY_HARMONIC = 0,      /* f = a cos(k.x) + b sin(k.x)         params: a, b, k[0..d)     (Eq. 1) */
+    MC_FAMILY_ABS_LINEAR = 1,    /* f = a |c0 + c.x|                    params: a, c0, c[0..d)    (Eq. 2) */
+    MC_FAMILY_GAUSSIAN = 2,      /* f = A exp(-|x - mu|^2 / (2 s^2))    params: A, s, mu[0..d)          */
+    MC_FAMILY_POLY_PRODUCT = 3   /* f = prod_j (1 + p_j x_j^{n_j})      params: -, -, p[0..d), n[0..d)  */
+} mc_family;
+
+/* Parameter layout inside mc_function.params: params[0], params[1] are the two
+ * scalars; params[2 + j] is the first per-dimension vector (k, c, mu or p) and
+ * params[14 + j] the second (POLY_PRODUCT degrees n_j, integers 0..8 stored as
+ * doubles).  Unused entries are ignored but must be finite. */
+#define MC_PARAM_V0 2
+#define MC_PARAM_W0 14
+
+typedef enum {
+    MC_PREC_FP32_EVAL = 0,   /* FP32 sample mapping and evaluation, per-lane compensated FP32 sums,
+                                FP64 cross-lane reduction, variance and finalize */
+    MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
+} mc_precision;
+
+/* One integrand (472 bytes, no padding). */
+typedef struct mc_function {
+    uint32_t family;             /* mc_family */
+    uint32_t dim;                /* 1..MC_MAX_DIM */
+    uint64_t n_samples;          /* N >= 2, at most 2^40 */
+    uint64_t seed;               /* Philox key = (seed mod 2^32, seed >> 32) */
+    double lo[MC_MAX_DIM];       /* box, entries >= dim ignored */
+    double hi[MC_MAX_DIM];
+    double params[MC_N_PARAMS];
+} mc_function;
+
+/* One result (48 bytes). */
+typedef struct mc_result {
+    double mean;                 /* F_hat */
+    double std_error;            /* SE */
+    double sum_f;                /* S1 = sum f(x_i) */
+    double sum_f2;               /* S2 = sum f(x_i)^2 */
+    uint64_t n;                  /* N */
+    int32_t status;              /* MC_OK or MC_ERR_ABORTED */
+    uint32_t precision;          /* mc_precision the function ran in */
+} mc_result;
+
+/* Context flags. */
+#define MC_VALIDATE_ONLY 0x1u    /* host-only context: mc_submit validates and packs, no device is touched */
+#define MC_NO_GRAPH 0x2u         /* launch kernels directly instead of replaying captured HIP graphs */
+
+typedef struct mc_config {
+    int32_t device;              /* HIP device ordinal */
+    uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH */
+    uint32_t max_functions;      /* device function slots (0: 1 << 16) */
+    uint32_t max_tiles_per_run;  /* tiles one mc_run may launch; the rest waits for the next run (0: no cap) */
+    uint64_t max_partials;       /* device tile-partial slots, 16 bytes each (0: 1 << 22) */
+    uint64_t mem_budget_bytes;   /* upper bound on device memory the context holds (0: no bound) */
+    void* workspace;             /* optional caller-owned device memory for every device buffer */
+    uint64_t workspace_bytes;    /* its size; see mc_workspace_size */
+    uint32_t blocks_per_cu;      /* persistent-kernel workgroups per CU (0: tuned/default) */
+    uint32_t reserved;
+} mc_config;
+
+typedef struct mc_ctx mc_ctx;
+
+/* Fill *cfg with defaults (device 0, everything else 0). */
+mc_status mc_config_init(mc_config* cfg);
+
+/* Device bytes a context created from *cfg needs (so a caller can pass its own workspace). */
+mc_status mc_workspace_size(const mc_config* cfg, uint64_t* bytes);
+
+/* Create a context on cfg->device.  Allocates the function table, tile-partial
+ * arena, staging buffers and (unless MC_NO_GRAPH) captures the launch graphs.
+ * With MC_VALIDATE_ONLY nothing touches a device. */
+mc_status mc_create(const mc_config* cfg, mc_ctx** out);
+
+/* Wait for the context's outstanding work and free everything it owns. */
+mc_status mc_destroy(mc_ctx* ctx);
+
+/* Validate and queue n functions as one request evaluated in `precision`.
+ * The whole request is rejected on the first invalid function (its index is in
+ * mc_last_error); nothing partial is queued.  Requests are admitted to the device
+ * in submission order as function slots and partial memory free up; a request
+ * that could never fit returns MC_ERR_ADMISSION.  *out_request_id identifies it. */
+mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision,
+                    uint64_t* out_request_id);
+
+/* Admit what fits, then enqueue one launch of the batched path on `stream`:
+ * a persistent kernel over the admitted (function, sample-segment) tiles and a
+ * finalize kernel for every function whose last tile is in this launch, plus
+ * the copy of those results to host memory.  Returns without waiting.  Launches
+ * nothing (and returns MC_OK) when no admitted work is pending. */
+mc_status mc_run(mc_ctx* ctx, void* stream);
+
+/* Number of requests submitted but not yet complete, and tiles still waiting for a launch. */
+mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
+
+/* Copy the n results of a request into out (n must equal the request size).
+ * blocking = 0: MC_NOT_READY if the request is not finished (runs are still
+ * needed, or launched work has not completed).  blocking != 0: calls mc_run on
+ * the null stream as needed and waits.  Results can be taken once; the
+ * request's device resources are released when it completes. */
+mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking);
+
+/* Ask running persistent kernels to stop fetching tiles; unfinished functions
+ * complete with status MC_ERR_ABORTED.  Clears itself once all queued work drained. */
+mc_status mc_abort(mc_ctx* ctx);
+
+/* The plain baseline path: for each function one kernel launch with a grid
+ * sized to its N (one thread per 4 samples) and a second launch that reduces
+ * the block partials, FP64 evaluation, no batching and no graph.  Synchronous:
+ * returns when out[0..n) holds the results. */
+mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out,
+                                  void* stream);
+
+/* Tuning of the batched path: workgroups per CU for the persistent kernel and,
+ * per (precision, family, dim), log2 of the segments each wave takes per tile.
+ * Results never depend on these (the reduction tree is fixed per function). */
+mc_status mc_get_tuning(mc_ctx* ctx, uint32_t* blocks_per_cu, uint8_t* seg_log2 /* [2][4][12] */);
+mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_log2 /* [2][4][12] or NULL */);
+
+/* Time candidate tunings on synthetic functions of every (family, dim) in
+ * `precision` and keep the fastest.  Blocks until done; uses `stream`. */
+mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
+
+/* Kernel timing of the most recent completed mc_run (persistent kernel and
+ * finalize, in milliseconds, from HIP events on the launch stream). */
+mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms);
+
+/* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */
+const char* mc_last_error(mc_ctx* ctx);
+
+/* Library constants: samples per segment (the unit each wave reduces), wave size. */
+uint32_t mc_segment_samples(void);
+const char* mc_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ZMC_H */

@@ -1,0 +1,15 @@
+"""Multi-function direct Monte Carlo integration on MI355X (gfx950).
+
+The method (ZMCintegral multi-function integrations): many integrands that
+differ in form, dimension and box domain, each integrated by direct Monte
+Carlo, each result a value with a standard error.  The work runs in the HIP
+library ``libzmc.so`` (C ABI in ``include/zmc.h``); this package is its
+binding plus the seeded workload generator.
+"""
+
+from . import workloads
+from ._native import (MC_NO_GRAPH, MC_VALIDATE_ONLY, PREC_FP32, PREC_FP64, RESULT_DTYPE, Context, McError,
+                      load, segment_samples, version)
+
+__all__ = ["workloads", "Context", "McError", "PREC_FP32", "PREC_FP64", "RESULT_DTYPE", "MC_NO_GRAPH",
+           "MC_VALIDATE_ONLY", "load", "segment_samples", "version"]

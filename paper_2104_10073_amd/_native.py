@@ -1,0 +1,259 @@
+"""ctypes binding of libzmc.so (the C ABI declared in include/zmc.h).
+
+Argument marshalling only: every step of the integration runs in the library's
+HIP kernels.  There is no fallback: if the library is missing this module
+raises, it never computes anything itself.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+from .workloads import FUNC_DTYPE
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libzmc.so")
+
+MC_OK = 0
+MC_NOT_READY = 1
+STATUS_NAMES = {
+    0: "MC_OK", 1: "MC_NOT_READY", -1: "MC_ERR_INVALID_ARG", -2: "MC_ERR_UNSUPPORTED_FAMILY",
+    -3: "MC_ERR_BAD_DIM", -4: "MC_ERR_BAD_BOUNDS", -5: "MC_ERR_BAD_PARAMS", -6: "MC_ERR_OUT_OF_MEMORY",
+    -7: "MC_ERR_ADMISSION", -8: "MC_ERR_HIP", -9: "MC_ERR_NO_DEVICE", -10: "MC_ERR_ABORTED",
+    -11: "MC_ERR_UNKNOWN_REQUEST",
+}
+
+PREC_FP32 = 0
+PREC_FP64 = 1
+
+MC_VALIDATE_ONLY = 0x1
+MC_NO_GRAPH = 0x2
+
+RESULT_DTYPE = np.dtype([
+    ("mean", "<f8"), ("std_error", "<f8"), ("sum_f", "<f8"), ("sum_f2", "<f8"),
+    ("n", "<u8"), ("status", "<i4"), ("precision", "<u4"),
+])
+assert RESULT_DTYPE.itemsize == 48
+
+# Every symbol include/zmc.h declares.
+EXPORTS = [
+    "mc_config_init", "mc_workspace_size", "mc_create", "mc_destroy", "mc_submit", "mc_run",
+    "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
+    "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_last_error", "mc_segment_samples",
+    "mc_version",
+]
+
+
+class McConfig(ctypes.Structure):
+    _fields_ = [
+        ("device", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("max_functions", ctypes.c_uint32),
+        ("max_tiles_per_run", ctypes.c_uint32),
+        ("max_partials", ctypes.c_uint64),
+        ("mem_budget_bytes", ctypes.c_uint64),
+        ("workspace", ctypes.c_void_p),
+        ("workspace_bytes", ctypes.c_uint64),
+        ("blocks_per_cu", ctypes.c_uint32),
+        ("reserved", ctypes.c_uint32),
+    ]
+
+
+class McError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH):
+    """Load libzmc.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(
+            f"{path} is missing: build the HIP library first "
+            "(python -c 'import __graft_entry__ as g; g.build()' or python paper_2104_10073_amd/build.py)")
+    L = ctypes.CDLL(path)
+    vp, u64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)
+    L.mc_config_init.argtypes = [ctypes.POINTER(McConfig)]
+    L.mc_workspace_size.argtypes = [ctypes.POINTER(McConfig), u64p]
+    L.mc_create.argtypes = [ctypes.POINTER(McConfig), ctypes.POINTER(vp)]
+    L.mc_destroy.argtypes = [vp]
+    L.mc_submit.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, u64p]
+    L.mc_run.argtypes = [vp, vp]
+    L.mc_pending.argtypes = [vp, u64p, u64p]
+    L.mc_results.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.c_int]
+    L.mc_abort.argtypes = [vp]
+    L.mc_integrate_plain_fp64.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
+    L.mc_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
+    L.mc_set_tuning.argtypes = [vp, ctypes.c_uint32, vp]
+    L.mc_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_double]
+    L.mc_last_run_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.mc_last_error.argtypes = [vp]
+    L.mc_last_error.restype = ctypes.c_char_p
+    L.mc_segment_samples.restype = ctypes.c_uint32
+    L.mc_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if fn.restype is ctypes.c_int:  # default restype: mc_status
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def _stream_handle(stream) -> int | None:
+    """A hipStream_t as an integer: None (null stream), an int, or a torch.cuda.Stream."""
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    handle = getattr(stream, "cuda_stream", None)
+    if handle is None:
+        raise TypeError(f"cannot use {stream!r} as a HIP stream")
+    return int(handle)
+
+
+def as_table(fns) -> np.ndarray:
+    t = np.ascontiguousarray(fns)
+    if t.dtype != FUNC_DTYPE:
+        raise TypeError(f"function table must have dtype workloads.FUNC_DTYPE, got {t.dtype}")
+    return t
+
+
+class Context:
+    """One mc_ctx.  Device memory comes from the library or, with
+    ``workspace='torch'``, from a torch tensor the context keeps alive."""
+
+    def __init__(self, device: int = 0, flags: int = 0, max_functions: int = 0, max_tiles_per_run: int = 0,
+                 max_partials: int = 0, mem_budget_bytes: int = 0, workspace=None, blocks_per_cu: int = 0):
+        self.L = load()
+        cfg = McConfig()
+        self.L.mc_config_init(ctypes.byref(cfg))
+        cfg.device = device
+        cfg.flags = flags
+        cfg.max_functions = max_functions
+        cfg.max_tiles_per_run = max_tiles_per_run
+        cfg.max_partials = max_partials
+        cfg.mem_budget_bytes = mem_budget_bytes
+        cfg.blocks_per_cu = blocks_per_cu
+        self._workspace = None
+        if workspace is not None:
+            need = ctypes.c_uint64()
+            self._check(self.L.mc_workspace_size(ctypes.byref(cfg), ctypes.byref(need)), None)
+            if isinstance(workspace, str) and workspace == "torch":
+                import torch
+                workspace = torch.empty(int(need.value) + 256, dtype=torch.uint8, device=f"cuda:{device}")
+            ptr = int(workspace.data_ptr())
+            pad = (-ptr) % 256
+            cfg.workspace = ptr + pad
+            cfg.workspace_bytes = int(workspace.numel() * workspace.element_size()) - pad
+            self._workspace = workspace
+        h = ctypes.c_void_p()
+        self._check(self.L.mc_create(ctypes.byref(cfg), ctypes.byref(h)), None)
+        self.h = h
+        self.config = cfg
+
+    def _check(self, st: int, h) -> int:
+        if st < 0:
+            msg = self.L.mc_last_error(h)
+            raise McError(st, msg.decode() if msg else "")
+        return st
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.L.mc_destroy(self.h)
+            self.h = None
+        self._workspace = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- batched path
+    def submit(self, fns, precision: int = PREC_FP32) -> int:
+        t = as_table(fns)
+        rid = ctypes.c_uint64()
+        self._check(self.L.mc_submit(self.h, t.ctypes.data, len(t), precision, ctypes.byref(rid)), self.h)
+        return int(rid.value)
+
+    def run(self, stream=None):
+        self._check(self.L.mc_run(self.h, _stream_handle(stream)), self.h)
+
+    def pending(self):
+        r, t = ctypes.c_uint64(), ctypes.c_uint64()
+        self._check(self.L.mc_pending(self.h, ctypes.byref(r), ctypes.byref(t)), self.h)
+        return int(r.value), int(t.value)
+
+    def results(self, request_id: int, n: int, blocking: bool = True, allow_aborted: bool = False):
+        out = np.zeros(n, dtype=RESULT_DTYPE)
+        st = self.L.mc_results(self.h, request_id, out.ctypes.data, n, 1 if blocking else 0)
+        if st == MC_NOT_READY:
+            return None
+        if st == -10 and allow_aborted:
+            return out
+        self._check(st, self.h)
+        return out
+
+    def integrate(self, fns, precision: int = PREC_FP32, stream=None):
+        t = as_table(fns)
+        rid = self.submit(t, precision)
+        self.run(stream)
+        return self.results(rid, len(t), blocking=True)
+
+    def abort(self):
+        self._check(self.L.mc_abort(self.h), self.h)
+
+    # -- plain baseline
+    def plain_fp64(self, fns, stream=None):
+        t = as_table(fns)
+        out = np.zeros(len(t), dtype=RESULT_DTYPE)
+        self._check(self.L.mc_integrate_plain_fp64(self.h, t.ctypes.data, len(t), out.ctypes.data,
+                                                   _stream_handle(stream)), self.h)
+        return out
+
+    # -- tuning
+    def get_tuning(self):
+        b = ctypes.c_uint32()
+        seg = np.zeros((2, 4, 12), dtype=np.uint8)
+        self._check(self.L.mc_get_tuning(self.h, ctypes.byref(b), seg.ctypes.data), self.h)
+        return int(b.value), seg
+
+    def set_tuning(self, blocks_per_cu: int = 0, seg_log2=None):
+        ptr = None
+        if seg_log2 is not None:
+            seg = np.ascontiguousarray(seg_log2, dtype=np.uint8).reshape(2, 4, 12)
+            ptr = seg.ctypes.data
+        self._check(self.L.mc_set_tuning(self.h, blocks_per_cu, ptr), self.h)
+
+    def autotune(self, precision: int = PREC_FP32, stream=None, budget_seconds: float = 10.0):
+        self._check(self.L.mc_autotune(self.h, precision, _stream_handle(stream), budget_seconds), self.h)
+
+    def last_run_timing(self):
+        a, b = ctypes.c_double(), ctypes.c_double()
+        st = self.L.mc_last_run_timing(self.h, ctypes.byref(a), ctypes.byref(b))
+        if st != MC_OK:
+            return None
+        return a.value, b.value
+
+
+def segment_samples() -> int:
+    return int(load().mc_segment_samples())
+
+
+def version() -> str:
+    return load().mc_version().decode()

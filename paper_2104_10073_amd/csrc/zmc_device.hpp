@@ -1,0 +1,112 @@
+// zmc_device.hpp -- device-resident layouts shared by the host runtime and the gfx950 kernels.
+//
+// Work decomposition.  A function's samples are grouped in quads (4 consecutive
+// samples, which draw exactly `dim` consecutive Philox blocks) and quads in
+// segments of kSegQuads = 64 lanes x kQuadsPerLane quads.  Lane l of the wave
+// that owns segment s evaluates quads s*kSegQuads + k*64 + l for k = 0..15 and
+// keeps compensated sums; the 64 lane sums are combined by a fixed xor butterfly
+// in FP64.  Segment sums are combined by a fixed pairwise tree over the segment
+// index (zero-padded to a power of two).  A tile is an aligned power-of-two run
+// of segments handed to one workgroup; its sum is a subtree of that same tree,
+// so a function's result is bitwise independent of the tile size, the grid
+// shape, the batch it runs in and the order tiles are fetched.
+#pragma once
+
+#include <stdint.h>
+
+namespace zmc {
+
+constexpr int kMaxDim = 12;
+constexpr int kWave = 64;
+constexpr int kQuadsPerLane = 16;
+constexpr int kSegQuads = kWave * kQuadsPerLane;      // 1024 quads
+constexpr int kSegSamples = 4 * kSegQuads;            // 4096 samples
+constexpr int kBlockWaves = 4;                        // waves per workgroup
+constexpr int kBlockThreads = kWave * kBlockWaves;    // 256
+constexpr int kMaxSegLog2 = 6;                        // at most 64 segments per wave per tile
+constexpr int kNumFamilies = 4;
+
+enum Family : uint32_t { HARMONIC = 0, ABS_LINEAR = 1, GAUSSIAN = 2, POLY_PRODUCT = 3 };
+
+// One function as the kernels read it (built on the host from mc_function).
+// Everything a tile needs sits in one 64-byte-aligned record so a wave loads it
+// with a handful of scalar loads.
+struct alignas(64) DevFn {
+    uint32_t family;
+    uint32_t dim;
+    uint32_t key0, key1;          // Philox key
+    uint64_t n_samples;
+    uint64_t n_quads;             // ceil(n_samples / 4)
+    uint32_t n_segments;          // ceil(n_quads / kSegQuads)
+    uint32_t precision;           // 0 = FP32 evaluation, 1 = FP64
+    double volume;                // prod_j (hi_j - lo_j)
+    double scale1, scale2;        // S1 = scale1 * sum g, S2 = scale2 * sum g^2 (FP32 path)
+
+    // FP64 path: the definition, in its own operation order.
+    double lo[kMaxDim];
+    double w[kMaxDim];            // hi - lo
+    double v[kMaxDim];            // k / c / mu / p
+    double s0, s1, h;             // (a, b) / (a, c0) / (A, sigma, 0.5/sigma^2)
+    int32_t deg[kMaxDim];         // POLY_PRODUCT exponents
+
+    // FP32 path: coefficients of each family in the variable t_j = 1 + m_j 2^-23,
+    // the float whose mantissa is the low 23 bits of the Philox word, so that
+    // u_j = t_j - (1 - 2^-24) exactly.
+    float fc[kMaxDim];            // HARMONIC kappa_j (revolutions per unit t); ABS gamma_j;
+                                  // GAUSSIAN sqrt(h') w_j; POLY w_j
+    float fo[kMaxDim];            // GAUSSIAN centre m_j in t-space; POLY lo_j
+    float fp[kMaxDim];            // POLY p_j
+    float f0, f0lo;               // HARMONIC phase offset (revolutions); ABS offset as hi + lo
+    uint32_t kfam;                // kernel variant: the family, or 4 for a product polynomial of degree > 4
+    uint32_t pad_;
+};
+
+// A tile: segments [seg0, seg0 + 4 << seg_log2) of function fn (clipped to the
+// function's segment count), partial written to partials[out].
+struct Tile {
+    uint32_t fn;
+    uint32_t seg0;
+    uint32_t seg_log2;            // log2 of segments per wave
+    uint32_t out;
+};
+
+// Finalize record: function fn's tile partials are partials[part0 .. part0 + n_tiles).
+struct Fin {
+    uint32_t fn;
+    uint32_t part0;
+    uint32_t n_tiles;
+    uint32_t res;                 // index into the launch's result array
+};
+
+struct Partial {
+    double s1, s2;
+};
+
+// Result record, identical in layout to mc_result.
+struct DevResult {
+    double mean, std_error, sum_f, sum_f2;
+    uint64_t n;
+    int32_t status;
+    uint32_t precision;
+};
+
+// Everything one launch reads; lives in device memory at a fixed address per
+// launch slot so a captured graph can be replayed with new contents.  FP32 and
+// FP64 tiles go to two kernels (each with its own register budget); both
+// write into the same partial arena, then one finalize kernel runs.
+struct alignas(64) LaunchDesc {
+    const DevFn* fns;
+    const Tile* tiles32;
+    const Tile* tiles64;
+    Partial* partials;
+    const Fin* fins;
+    DevResult* results;
+    uint32_t* counters;                    // [0]: next FP32 tile, [1]: next FP64 tile, [2]: abort seen
+    const volatile uint32_t* abort_flag;   // host-mapped word; nonzero asks the kernels to stop
+    uint32_t n_tiles32;
+    uint32_t n_tiles64;
+    uint32_t n_fins;
+    uint32_t pad_;
+};
+
+}  // namespace zmc

@@ -1,0 +1,1184 @@
+// zmc_host.hip -- host runtime of the C ABI in include/zmc.h.
+//
+// Responsibilities: validate and pack function tables (FP64 coefficients in the
+// reference operation order, FP32 local-coordinate coefficients derived in FP64
+// and rounded once), admit requests into device function slots and a tile-
+// partial arena as space frees up, cut functions into tiles, order tiles by
+// cost, and enqueue launches (persistent FP32 kernel, persistent FP64 kernel,
+// finalize, result copy) on the caller's stream from a small ring of launch
+// slots, each with a captured HIP graph.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <string>
+#include <unordered_map>
+#include <vector>
+
+#include "../../include/zmc.h"
+#include "zmc_device.hpp"
+
+namespace zmc {
+const void* plain_kernel_ptr(uint32_t family, uint32_t dim);
+const void* batched_kernel_ptr(bool fp64);
+const void* finalize_kernel_ptr();
+const void* plain_reduce_kernel_ptr();
+}  // namespace zmc
+
+using namespace zmc;
+
+static_assert(sizeof(mc_function) == 472, "mc_function layout");
+static_assert(sizeof(mc_result) == 48, "mc_result layout");
+static_assert(sizeof(mc_config) == 56, "mc_config layout");
+static_assert(sizeof(DevResult) == sizeof(mc_result), "result layout");
+static_assert(sizeof(Tile) == 16 && sizeof(Fin) == 16 && sizeof(Partial) == 16, "record layout");
+
+namespace {
+
+thread_local std::string g_thread_error;
+
+constexpr int kLaunchSlots = 3;
+constexpr uint64_t kMaxSamples = 1ull << 40;
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+// ---------------------------------------------------------------- small helpers
+
+struct HipError {
+    hipError_t e;
+    const char* what;
+};
+
+#define HIP_TRY(expr)                                   \
+    do {                                                \
+        hipError_t e_ = (expr);                         \
+        if (e_ != hipSuccess) throw HipError{e_, #expr}; \
+    } while (0)
+
+// First-fit range allocator over [0, capacity) with coalescing free list.
+class RangeAlloc {
+public:
+    void reset(uint64_t cap)
+    {
+        cap_ = cap;
+        free_.clear();
+        if (cap > 0) free_[0] = cap;
+        used_ = 0;
+    }
+    bool alloc(uint64_t n, uint64_t* off)
+    {
+        if (n == 0) {
+            *off = 0;
+            return true;
+        }
+        for (auto it = free_.begin(); it != free_.end(); ++it) {
+            if (it->second >= n) {
+                *off = it->first;
+                const uint64_t rest = it->second - n, start = it->first + n;
+                free_.erase(it);
+                if (rest > 0) free_[start] = rest;
+                used_ += n;
+                return true;
+            }
+        }
+        return false;
+    }
+    void release(uint64_t off, uint64_t n)
+    {
+        if (n == 0) return;
+        used_ -= n;
+        auto it = free_.emplace(off, n).first;
+        auto nx = std::next(it);
+        if (nx != free_.end() && it->first + it->second == nx->first) {
+            it->second += nx->second;
+            free_.erase(nx);
+        }
+        if (it != free_.begin()) {
+            auto pv = std::prev(it);
+            if (pv->first + pv->second == it->first) {
+                pv->second += it->second;
+                free_.erase(it);
+            }
+        }
+    }
+    uint64_t capacity() const { return cap_; }
+    uint64_t used() const { return used_; }
+
+private:
+    uint64_t cap_ = 0, used_ = 0;
+    std::map<uint64_t, uint64_t> free_;
+};
+
+// ---------------------------------------------------------------- validation
+
+mc_status validate_one(const mc_function& f, std::string* why)
+{
+    char buf[160];
+    if (f.family > MC_FAMILY_POLY_PRODUCT) {
+        snprintf(buf, sizeof buf, "unsupported family %u", f.family);
+        *why = buf;
+        return MC_ERR_UNSUPPORTED_FAMILY;
+    }
+    if (f.dim < 1 || f.dim > MC_MAX_DIM) {
+        snprintf(buf, sizeof buf, "dim %u outside 1..%d", f.dim, MC_MAX_DIM);
+        *why = buf;
+        return MC_ERR_BAD_DIM;
+    }
+    if (f.n_samples < 2 || f.n_samples > kMaxSamples) {
+        snprintf(buf, sizeof buf, "n_samples %llu outside 2..2^40", (unsigned long long)f.n_samples);
+        *why = buf;
+        return MC_ERR_INVALID_ARG;
+    }
+    for (uint32_t j = 0; j < f.dim; ++j) {
+        if (!std::isfinite(f.lo[j]) || !std::isfinite(f.hi[j]) || !(f.lo[j] < f.hi[j]) ||
+            !std::isfinite(f.hi[j] - f.lo[j])) {
+            snprintf(buf, sizeof buf, "bounds of coordinate %u are not finite with lo < hi", j);
+            *why = buf;
+            return MC_ERR_BAD_BOUNDS;
+        }
+    }
+    for (int j = 0; j < MC_N_PARAMS; ++j) {
+        if (!std::isfinite(f.params[j])) {
+            snprintf(buf, sizeof buf, "params[%d] is not finite", j);
+            *why = buf;
+            return MC_ERR_BAD_PARAMS;
+        }
+    }
+    if (f.family == MC_FAMILY_GAUSSIAN && !(f.params[1] > 0.0)) {
+        *why = "gaussian sigma must be > 0";
+        return MC_ERR_BAD_PARAMS;
+    }
+    if (f.family == MC_FAMILY_POLY_PRODUCT) {
+        for (uint32_t j = 0; j < f.dim; ++j) {
+            const double d = f.params[MC_PARAM_W0 + j];
+            if (!(d >= 0.0 && d <= 8.0 && d == std::floor(d))) {
+                snprintf(buf, sizeof buf, "polynomial degree of coordinate %u must be an integer in 0..8", j);
+                *why = buf;
+                return MC_ERR_BAD_PARAMS;
+            }
+        }
+    }
+    return MC_OK;
+}
+
+// ---------------------------------------------------------------- packing
+
+float frac_to_float(long double x)
+{
+    long double r = x - std::floor(x);
+    float f = (float)r;
+    if (f >= 1.0f) f = 0.0f;
+    return f;
+}
+
+void pack_function(const mc_function& f, int precision, DevFn* d)
+{
+    std::memset(d, 0, sizeof(DevFn));
+    const uint32_t D = f.dim;
+    d->family = f.family;
+    d->kfam = f.family;
+    d->dim = D;
+    d->key0 = (uint32_t)(f.seed & 0xFFFFFFFFull);
+    d->key1 = (uint32_t)(f.seed >> 32);
+    d->n_samples = f.n_samples;
+    d->n_quads = (f.n_samples + 3) / 4;
+    d->n_segments = (uint32_t)((d->n_quads + kSegQuads - 1) / kSegQuads);
+    d->precision = (uint32_t)precision;
+    double vol = 1.0;
+    for (uint32_t j = 0; j < D; ++j) {
+        d->lo[j] = f.lo[j];
+        d->w[j] = f.hi[j] - f.lo[j];
+        d->v[j] = f.params[MC_PARAM_V0 + j];
+        vol *= d->w[j];
+    }
+    d->volume = vol;
+    d->s0 = f.params[0];
+    d->s1 = f.params[1];
+    if (f.family == MC_FAMILY_GAUSSIAN) d->h = 0.5 / (f.params[1] * f.params[1]);
+    if (f.family == MC_FAMILY_POLY_PRODUCT)
+        for (uint32_t j = 0; j < D; ++j) d->deg[j] = (int32_t)f.params[MC_PARAM_W0 + j];
+    d->scale1 = 1.0;
+    d->scale2 = 1.0;
+    if (precision == MC_PREC_FP64) return;
+
+    // FP32 evaluation: coefficients in t_j = u_j + C, C = 1 - 2^-24.
+    const long double C = 1.0L - std::ldexp(1.0L, -24);
+    switch (f.family) {
+    case MC_FAMILY_HARMONIC: {
+        const double a = f.params[0], b = f.params[1];
+        const double R = std::hypot(a, b);
+        const long double phi = (R > 0.0) ? (long double)std::atan2(b, a) : 0.0L;
+        long double off = -phi / (long double)kTwoPi;
+        for (uint32_t j = 0; j < D; ++j) {
+            const long double k = f.params[MC_PARAM_V0 + j];
+            const long double kappa = k * (long double)d->w[j] / (long double)kTwoPi;
+            d->fc[j] = (float)kappa;
+            off += k * (long double)f.lo[j] / (long double)kTwoPi - C * (long double)d->fc[j];
+        }
+        d->f0 = frac_to_float(off);
+        d->scale1 = R;
+        d->scale2 = R * R;
+        break;
+    }
+    case MC_FAMILY_ABS_LINEAR: {
+        long double off = f.params[1];
+        for (uint32_t j = 0; j < D; ++j) {
+            const long double c = f.params[MC_PARAM_V0 + j];
+            d->fc[j] = (float)(c * (long double)d->w[j]);
+            off += c * (long double)f.lo[j] - C * (long double)d->fc[j];
+        }
+        d->f0 = (float)off;
+        d->f0lo = (float)(off - (long double)d->f0);
+        d->scale1 = f.params[0];
+        d->scale2 = f.params[0] * f.params[0];
+        break;
+    }
+    case MC_FAMILY_GAUSSIAN: {
+        const long double sigma = f.params[1];
+        const long double hh = 1.4426950408889634073599246810019L / (2.0L * sigma * sigma);  // log2(e) / (2 s^2)
+        const long double sq = std::sqrt(hh);
+        for (uint32_t j = 0; j < D; ++j) {
+            d->fc[j] = (float)((long double)d->w[j] * sq);
+            d->fo[j] = (float)(C + ((long double)f.params[MC_PARAM_V0 + j] - (long double)f.lo[j]) /
+                                       (long double)d->w[j]);
+        }
+        d->scale1 = f.params[0];
+        d->scale2 = f.params[0] * f.params[0];
+        break;
+    }
+    default: {  // POLY_PRODUCT
+        int maxdeg = 0;
+        for (uint32_t j = 0; j < D; ++j) {
+            d->fc[j] = (float)d->w[j];
+            d->fo[j] = (float)f.lo[j];
+            d->fp[j] = (float)f.params[MC_PARAM_V0 + j];
+            maxdeg = std::max(maxdeg, (int)d->deg[j]);
+        }
+        if (maxdeg > 4) d->kfam = 4;
+        break;
+    }
+    }
+}
+
+// Relative VALU cost of one sample (full-rate issue slots), used to order tiles.
+double sample_cost(uint32_t family, uint32_t dim, int precision)
+{
+    const double philox = 15.0 * dim;
+    double fam;
+    switch (family) {
+    case MC_FAMILY_HARMONIC: fam = dim + 6.0; break;
+    case MC_FAMILY_ABS_LINEAR: fam = dim + 2.0; break;
+    case MC_FAMILY_GAUSSIAN: fam = 3.0 * dim + 5.0; break;
+    default: fam = 8.0 * dim; break;
+    }
+    double c = philox + dim + fam + 4.0;
+    if (precision == MC_PREC_FP64) c *= 3.0;
+    return c;
+}
+
+// ---------------------------------------------------------------- context state
+
+struct Request;
+
+struct FnState {
+    uint32_t slot;        // device function slot
+    uint32_t seg_log2;
+    uint32_t n_tiles;
+    uint32_t next_tile;   // next tile to put into a launch
+    uint64_t part0;       // first partial slot
+    double tile_cost;
+};
+
+struct Request {
+    uint64_t id;
+    int32_t precision;
+    std::vector<mc_function> fns;     // caller's table (copied at submit)
+    DevFn* packed = nullptr;          // packed table (pinned host memory on a device context)
+    bool packed_pinned = false;
+    std::vector<FnState> st;
+    std::vector<mc_result> results;
+    std::vector<uint32_t> order;      // functions by descending per-tile cost
+    uint32_t order_pos = 0;           // next function in `order` with tiles left
+    uint64_t part_base = 0, part_count = 0;
+    uint32_t slot_base = 0;
+    bool admitted = false;
+    uint32_t fns_done = 0;
+    uint64_t tiles_total = 0, tiles_launched = 0;
+    bool aborted = false;
+};
+
+struct FinRef {
+    Request* req;
+    uint32_t index;
+};
+
+struct LaunchSlot {
+    // device
+    LaunchDesc* d_desc = nullptr;   // followed by 4 counters (uint32) in the same allocation
+    Tile* d_tiles32 = nullptr;
+    Tile* d_tiles64 = nullptr;
+    Fin* d_fins = nullptr;
+    DevResult* d_results = nullptr;
+    // pinned host
+    uint8_t* h_desc = nullptr;      // LaunchDesc + counters
+    Tile* h_tiles32 = nullptr;
+    Tile* h_tiles64 = nullptr;
+    Fin* h_fins = nullptr;
+    DevResult* h_results = nullptr;
+    hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
+    hipGraphExec_t graph = nullptr;
+    bool in_flight = false;
+    uint64_t seq = 0;
+    uint32_t n_tiles32 = 0, n_tiles64 = 0, n_fins = 0;
+    std::vector<FinRef> fin_refs;
+    std::vector<Request*> touched;  // requests with tiles in this launch
+};
+
+constexpr size_t kDescBytes = 256;  // LaunchDesc (64-aligned, < 128 bytes) + counters
+
+}  // namespace
+
+struct mc_ctx {
+    mc_config cfg{};
+    bool validate_only = false;
+    bool use_graph = true;
+    int device = 0;
+    int num_cus = 0;
+    std::string err;
+
+    // capacities
+    uint32_t max_functions = 0;
+    uint64_t max_partials = 0;
+    uint32_t tile_cap = 0;   // per launch per precision
+    uint32_t fin_cap = 0;
+
+    // device memory
+    bool owns_memory = true;
+    void* mem_base = nullptr;
+    uint64_t mem_bytes = 0;
+    DevFn* d_fns = nullptr;
+    Partial* d_partials = nullptr;
+    LaunchSlot slots[kLaunchSlots];
+    uint32_t* h_abort = nullptr;      // host-mapped
+    uint32_t* d_abort = nullptr;
+
+    RangeAlloc fn_alloc, part_alloc;
+
+    // tuning
+    uint32_t blocks_per_cu32 = 4, blocks_per_cu64 = 2;
+    uint8_t seg_log2[2][5][kMaxDim];
+
+    // requests
+    uint64_t next_id = 1;
+    std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
+    std::deque<Request*> pending;     // submitted, not admitted (FIFO)
+    std::deque<Request*> active;      // admitted with tiles not yet launched
+    uint64_t launch_seq = 0;
+    double last_main_ms = 0.0, last_fin_ms = 0.0;
+    bool have_timing = false;
+};
+
+namespace {
+
+mc_status fail(mc_ctx* ctx, mc_status st, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    if (ctx) ctx->err = buf;
+    g_thread_error = buf;
+    return st;
+}
+
+mc_status fail_hip(mc_ctx* ctx, const HipError& e)
+{
+    return fail(ctx, MC_ERR_HIP, "%s failed: %s", e.what, hipGetErrorString(e.e));
+}
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+struct Layout {
+    uint64_t fns, partials, slot_desc, slot_tiles, slot_fins, slot_results, total;
+};
+
+Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap)
+{
+    Layout L{};
+    uint64_t off = 0;
+    L.fns = off;
+    off = align_up(off + (uint64_t)max_functions * sizeof(DevFn), 256);
+    L.partials = off;
+    off = align_up(off + max_partials * sizeof(Partial), 256);
+    L.slot_desc = off;
+    off = align_up(off + kLaunchSlots * kDescBytes, 256);
+    L.slot_tiles = off;
+    off = align_up(off + (uint64_t)kLaunchSlots * 2 * tile_cap * sizeof(Tile), 256);
+    L.slot_fins = off;
+    off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(Fin), 256);
+    L.slot_results = off;
+    off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(DevResult), 256);
+    L.total = off;
+    return L;
+}
+
+void resolve_capacities(const mc_config& cfg, uint32_t* max_functions, uint64_t* max_partials, uint32_t* tile_cap,
+                        uint32_t* fin_cap)
+{
+    *max_functions = cfg.max_functions ? cfg.max_functions : (1u << 16);
+    *tile_cap = cfg.max_tiles_per_run ? cfg.max_tiles_per_run : (1u << 20);
+    *fin_cap = *max_functions;
+    if (cfg.max_partials) {
+        *max_partials = cfg.max_partials;
+    } else {
+        *max_partials = 1ull << 22;
+        if (cfg.mem_budget_bytes) {
+            Layout fixed = compute_layout(*max_functions, 0, *tile_cap, *fin_cap);
+            if (cfg.mem_budget_bytes > fixed.total + 4096)
+                *max_partials = std::min<uint64_t>(*max_partials, (cfg.mem_budget_bytes - fixed.total - 4096) / sizeof(Partial));
+            else
+                *max_partials = 1;
+        }
+    }
+}
+
+// Tiles of one function for a given seg_log2.
+uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
+{
+    const uint32_t per_tile = (uint32_t)kBlockWaves << seg_log2;
+    return (n_segments + per_tile - 1) / per_tile;
+}
+
+void free_packed(Request* r)
+{
+    if (!r->packed) return;
+    if (r->packed_pinned) (void)hipHostFree(r->packed);
+    else std::free(r->packed);
+    r->packed = nullptr;
+}
+
+void free_request_resources(mc_ctx* ctx, Request* r)
+{
+    free_packed(r);
+    if (!r->admitted) return;
+    ctx->fn_alloc.release(r->slot_base, r->fns.size());
+    ctx->part_alloc.release(r->part_base, r->part_count);
+    r->admitted = false;
+}
+
+// Collect finished launches: scatter their results into the requests.
+void reap(mc_ctx* ctx, bool wait_all)
+{
+    for (;;) {
+        LaunchSlot* oldest = nullptr;
+        for (auto& s : ctx->slots)
+            if (s.in_flight && (!oldest || s.seq < oldest->seq)) oldest = &s;
+        if (!oldest) return;
+        hipError_t q = wait_all ? hipEventSynchronize(oldest->ev_done) : hipEventQuery(oldest->ev_done);
+        if (q == hipErrorNotReady) return;
+        if (q != hipSuccess) throw HipError{q, "hipEventQuery(launch)"};
+        LaunchSlot& s = *oldest;
+        for (uint32_t i = 0; i < s.n_fins; ++i) {
+            const FinRef& fr = s.fin_refs[i];
+            mc_result& out = fr.req->results[fr.index];
+            std::memcpy(&out, &s.h_results[i], sizeof(mc_result));
+            if (out.status != MC_OK) fr.req->aborted = true;
+            fr.req->fns_done++;
+            if (fr.req->fns_done == fr.req->fns.size()) free_request_resources(ctx, fr.req);
+        }
+        {
+            float a = 0.f, b = 0.f;
+            if (hipEventElapsedTime(&a, s.ev_start, s.ev_main) == hipSuccess &&
+                hipEventElapsedTime(&b, s.ev_main, s.ev_end) == hipSuccess) {
+                ctx->last_main_ms = a;
+                ctx->last_fin_ms = b;
+                ctx->have_timing = true;
+            }
+        }
+        s.in_flight = false;
+        s.fin_refs.clear();
+        s.touched.clear();
+    }
+}
+
+// Move pending requests into device slots while they fit (FIFO).
+void admit(mc_ctx* ctx, hipStream_t stream)
+{
+    while (!ctx->pending.empty()) {
+        Request* r = ctx->pending.front();
+        const uint64_t nf = r->fns.size();
+        uint64_t parts = 0;
+        for (auto& s : r->st) parts += s.n_tiles;
+        uint64_t slot_off = 0, part_off = 0;
+        if (!ctx->fn_alloc.alloc(nf, &slot_off)) return;
+        if (!ctx->part_alloc.alloc(parts, &part_off)) {
+            ctx->fn_alloc.release(slot_off, nf);
+            return;
+        }
+        r->slot_base = (uint32_t)slot_off;
+        r->part_base = part_off;
+        r->part_count = parts;
+        uint64_t p = part_off;
+        for (uint32_t i = 0; i < nf; ++i) {
+            r->st[i].slot = (uint32_t)slot_off + i;
+            r->st[i].part0 = p;
+            p += r->st[i].n_tiles;
+        }
+        HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice, stream));
+        r->admitted = true;
+        ctx->pending.pop_front();
+        ctx->active.push_back(r);
+    }
+}
+
+void capture_graph(mc_ctx* ctx, LaunchSlot& s);
+
+void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream)
+{
+    LaunchDesc* dd = s.d_desc;
+    void* args[] = {&dd};
+    HIP_TRY(hipEventRecord(s.ev_start, stream));
+    HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32), dim3(kBlockThreads),
+                            args, 0, stream));
+    HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64), dim3(kBlockThreads),
+                            args, 0, stream));
+    HIP_TRY(hipEventRecord(s.ev_main, stream));
+    HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
+    HIP_TRY(hipEventRecord(s.ev_end, stream));
+}
+
+void capture_graph(mc_ctx* ctx, LaunchSlot& s)
+{
+    if (s.graph) {
+        (void)hipGraphExecDestroy(s.graph);
+        s.graph = nullptr;
+    }
+    hipStream_t cs;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipGraph_t g = nullptr;
+    try {
+        HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        enqueue_kernels(ctx, s, cs);
+        HIP_TRY(hipStreamEndCapture(cs, &g));
+        HIP_TRY(hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0));
+    } catch (...) {
+        if (g) (void)hipGraphDestroy(g);
+        (void)hipStreamDestroy(cs);
+        throw;
+    }
+    (void)hipGraphDestroy(g);
+    HIP_TRY(hipStreamDestroy(cs));
+}
+
+// Build and enqueue one launch.  Returns false if no admitted work was pending.
+bool launch(mc_ctx* ctx, hipStream_t stream)
+{
+    if (ctx->active.empty()) return false;
+    // a free slot (wait for the oldest launch if all are in flight)
+    LaunchSlot* slot = nullptr;
+    for (;;) {
+        for (auto& s : ctx->slots)
+            if (!s.in_flight) {
+                slot = &s;
+                break;
+            }
+        if (slot) break;
+        reap(ctx, true);
+    }
+    LaunchSlot& s = *slot;
+    s.n_tiles32 = s.n_tiles64 = s.n_fins = 0;
+    s.fin_refs.clear();
+    s.touched.clear();
+    // Take tiles request by request (admission order), within a request by
+    // descending per-tile cost; stop at the per-launch tile capacity.
+    while (!ctx->active.empty()) {
+        Request* r = ctx->active.front();
+        const bool f64 = r->precision == MC_PREC_FP64;
+        uint32_t& nt = f64 ? s.n_tiles64 : s.n_tiles32;
+        Tile* out = f64 ? s.h_tiles64 : s.h_tiles32;
+        bool full = false;
+        bool touched = false;
+        while (r->order_pos < r->order.size()) {
+            const uint32_t fi = r->order[r->order_pos];
+            FnState& fs = r->st[fi];
+            const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
+            while (fs.next_tile < fs.n_tiles && nt < ctx->tile_cap) {
+                Tile& t = out[nt++];
+                t.fn = fs.slot;
+                t.seg0 = fs.next_tile * per_tile;
+                t.seg_log2 = fs.seg_log2;
+                t.out = (uint32_t)(fs.part0 + fs.next_tile);
+                fs.next_tile++;
+                r->tiles_launched++;
+                touched = true;
+            }
+            if (fs.next_tile == fs.n_tiles) {
+                if (s.n_fins >= ctx->fin_cap) {
+                    full = true;
+                    break;
+                }
+                Fin& f = s.h_fins[s.n_fins];
+                f.fn = fs.slot;
+                f.part0 = (uint32_t)fs.part0;
+                f.n_tiles = fs.n_tiles;
+                f.res = s.n_fins;
+                s.fin_refs.push_back(FinRef{r, fi});
+                s.n_fins++;
+                r->order_pos++;
+            } else {
+                full = true;  // tile capacity reached
+                break;
+            }
+        }
+        if (touched) s.touched.push_back(r);
+        if (r->order_pos == r->order.size()) ctx->active.pop_front();
+        if (full) break;
+    }
+    if (s.n_tiles32 == 0 && s.n_tiles64 == 0 && s.n_fins == 0) return false;
+
+    // Launches may be enqueued on different streams; a function's tiles can span
+    // launches, so each launch waits for the previous one.
+    for (auto& o : ctx->slots)
+        if (&o != &s && o.in_flight && o.seq == ctx->launch_seq) HIP_TRY(hipStreamWaitEvent(stream, o.ev_done, 0));
+    LaunchDesc* hd = (LaunchDesc*)s.h_desc;
+    std::memset(s.h_desc, 0, kDescBytes);
+    hd->fns = ctx->d_fns;
+    hd->tiles32 = s.d_tiles32;
+    hd->tiles64 = s.d_tiles64;
+    hd->partials = ctx->d_partials;
+    hd->fins = s.d_fins;
+    hd->results = s.d_results;
+    hd->counters = (uint32_t*)((uint8_t*)s.d_desc + 128);
+    hd->abort_flag = ctx->d_abort;
+    hd->n_tiles32 = s.n_tiles32;
+    hd->n_tiles64 = s.n_tiles64;
+    hd->n_fins = s.n_fins;
+    // the previous use of this slot's staging has completed (slot not in flight)
+    HIP_TRY(hipMemcpyAsync(s.d_desc, s.h_desc, kDescBytes, hipMemcpyHostToDevice, stream));
+    if (s.n_tiles32)
+        HIP_TRY(hipMemcpyAsync(s.d_tiles32, s.h_tiles32, (size_t)s.n_tiles32 * sizeof(Tile), hipMemcpyHostToDevice, stream));
+    if (s.n_tiles64)
+        HIP_TRY(hipMemcpyAsync(s.d_tiles64, s.h_tiles64, (size_t)s.n_tiles64 * sizeof(Tile), hipMemcpyHostToDevice, stream));
+    if (s.n_fins) HIP_TRY(hipMemcpyAsync(s.d_fins, s.h_fins, (size_t)s.n_fins * sizeof(Fin), hipMemcpyHostToDevice, stream));
+    if (ctx->use_graph) {
+        if (!s.graph) capture_graph(ctx, s);
+        HIP_TRY(hipGraphLaunch(s.graph, stream));
+    } else {
+        enqueue_kernels(ctx, s, stream);
+    }
+    if (s.n_fins)
+        HIP_TRY(hipMemcpyAsync(s.h_results, s.d_results, (size_t)s.n_fins * sizeof(DevResult), hipMemcpyDeviceToHost,
+                               stream));
+    HIP_TRY(hipEventRecord(s.ev_done, stream));
+    s.in_flight = true;
+    s.seq = ++ctx->launch_seq;
+    return true;
+}
+
+void destroy_device(mc_ctx* ctx)
+{
+    for (auto& s : ctx->slots) {
+        if (s.graph) (void)hipGraphExecDestroy(s.graph);
+        for (hipEvent_t e : {s.ev_start, s.ev_main, s.ev_end, s.ev_done})
+            if (e) (void)hipEventDestroy(e);
+        for (void* p : {(void*)s.h_desc, (void*)s.h_tiles32, (void*)s.h_tiles64, (void*)s.h_fins, (void*)s.h_results})
+            if (p) (void)hipHostFree(p);
+        s = LaunchSlot{};
+    }
+    if (ctx->h_abort) (void)hipHostFree(ctx->h_abort);
+    if (ctx->owns_memory && ctx->mem_base) (void)hipFree(ctx->mem_base);
+    ctx->h_abort = nullptr;
+    ctx->mem_base = nullptr;
+}
+
+void default_tuning(mc_ctx* ctx)
+{
+    for (int p = 0; p < 2; ++p)
+        for (int f = 0; f < 5; ++f)
+            for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = 0;
+}
+
+}  // namespace
+
+// ====================================================================== C ABI
+
+extern "C" {
+
+mc_status mc_config_init(mc_config* cfg)
+{
+    if (!cfg) return fail(nullptr, MC_ERR_INVALID_ARG, "cfg is NULL");
+    std::memset(cfg, 0, sizeof(*cfg));
+    return MC_OK;
+}
+
+mc_status mc_workspace_size(const mc_config* cfg, uint64_t* bytes)
+{
+    if (!cfg || !bytes) return fail(nullptr, MC_ERR_INVALID_ARG, "NULL argument");
+    uint32_t mf, tc, fc;
+    uint64_t mp;
+    resolve_capacities(*cfg, &mf, &mp, &tc, &fc);
+    *bytes = compute_layout(mf, mp, tc, fc).total;
+    return MC_OK;
+}
+
+mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
+{
+    if (!out) return fail(nullptr, MC_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    mc_config cfg{};
+    if (cfg_in) cfg = *cfg_in;
+    std::unique_ptr<mc_ctx> ctx(new mc_ctx());
+    ctx->cfg = cfg;
+    ctx->validate_only = (cfg.flags & MC_VALIDATE_ONLY) != 0;
+    ctx->use_graph = (cfg.flags & MC_NO_GRAPH) == 0;
+    ctx->device = cfg.device;
+    default_tuning(ctx.get());
+    resolve_capacities(cfg, &ctx->max_functions, &ctx->max_partials, &ctx->tile_cap, &ctx->fin_cap);
+    ctx->fn_alloc.reset(ctx->max_functions);
+    ctx->part_alloc.reset(ctx->max_partials);
+    if (ctx->validate_only) {
+        *out = ctx.release();
+        return MC_OK;
+    }
+    try {
+        int ndev = 0;
+        if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= cfg.device || cfg.device < 0)
+            return fail(nullptr, MC_ERR_NO_DEVICE, "no HIP device %d (found %d)", cfg.device, ndev);
+        HIP_TRY(hipSetDevice(cfg.device));
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, cfg.device));
+        if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+            return fail(nullptr, MC_ERR_NO_DEVICE, "device %d is %s; this library is built for gfx950", cfg.device,
+                        prop.gcnArchName);
+        ctx->num_cus = prop.multiProcessorCount;
+        int occ32 = 0, occ64 = 0;
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, batched_kernel_ptr(false), kBlockThreads, 0));
+        HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64, batched_kernel_ptr(true), kBlockThreads, 0));
+        ctx->blocks_per_cu32 = cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ32);
+        ctx->blocks_per_cu64 = (uint32_t)std::max(1, occ64);
+
+        Layout L = compute_layout(ctx->max_functions, ctx->max_partials, ctx->tile_cap, ctx->fin_cap);
+        if (cfg.mem_budget_bytes && L.total > cfg.mem_budget_bytes)
+            return fail(nullptr, MC_ERR_OUT_OF_MEMORY, "context needs %llu device bytes, budget is %llu",
+                        (unsigned long long)L.total, (unsigned long long)cfg.mem_budget_bytes);
+        if (cfg.workspace) {
+            if (cfg.workspace_bytes < L.total)
+                return fail(nullptr, MC_ERR_INVALID_ARG, "workspace of %llu bytes is smaller than the %llu needed",
+                            (unsigned long long)cfg.workspace_bytes, (unsigned long long)L.total);
+            if (((uintptr_t)cfg.workspace & 255u) != 0)
+                return fail(nullptr, MC_ERR_INVALID_ARG, "workspace must be 256-byte aligned");
+            ctx->owns_memory = false;
+            ctx->mem_base = cfg.workspace;
+        } else {
+            if (hipMalloc(&ctx->mem_base, L.total) != hipSuccess)
+                return fail(nullptr, MC_ERR_OUT_OF_MEMORY, "hipMalloc of %llu bytes failed", (unsigned long long)L.total);
+        }
+        ctx->mem_bytes = L.total;
+        uint8_t* base = (uint8_t*)ctx->mem_base;
+        ctx->d_fns = (DevFn*)(base + L.fns);
+        ctx->d_partials = (Partial*)(base + L.partials);
+        for (int i = 0; i < kLaunchSlots; ++i) {
+            LaunchSlot& s = ctx->slots[i];
+            s.d_desc = (LaunchDesc*)(base + L.slot_desc + (uint64_t)i * kDescBytes);
+            s.d_tiles32 = (Tile*)(base + L.slot_tiles) + (uint64_t)i * 2 * ctx->tile_cap;
+            s.d_tiles64 = s.d_tiles32 + ctx->tile_cap;
+            s.d_fins = (Fin*)(base + L.slot_fins) + (uint64_t)i * ctx->fin_cap;
+            s.d_results = (DevResult*)(base + L.slot_results) + (uint64_t)i * ctx->fin_cap;
+            HIP_TRY(hipHostMalloc((void**)&s.h_desc, kDescBytes, hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void**)&s.h_tiles32, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void**)&s.h_tiles64, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void**)&s.h_fins, (size_t)ctx->fin_cap * sizeof(Fin), hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void**)&s.h_results, (size_t)ctx->fin_cap * sizeof(DevResult), hipHostMallocDefault));
+            HIP_TRY(hipEventCreate(&s.ev_start));
+            HIP_TRY(hipEventCreate(&s.ev_main));
+            HIP_TRY(hipEventCreate(&s.ev_end));
+            HIP_TRY(hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
+        }
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_abort, 64, hipHostMallocMapped | hipHostMallocCoherent));
+        *ctx->h_abort = 0u;
+        HIP_TRY(hipHostGetDevicePointer((void**)&ctx->d_abort, ctx->h_abort, 0));
+    } catch (const HipError& e) {
+        mc_status st = fail_hip(nullptr, e);
+        destroy_device(ctx.get());
+        return st;
+    }
+    *out = ctx.release();
+    return MC_OK;
+}
+
+mc_status mc_destroy(mc_ctx* ctx)
+{
+    if (!ctx) return MC_OK;
+    if (!ctx->validate_only) {
+        (void)hipSetDevice(ctx->device);
+        for (auto& s : ctx->slots)
+            if (s.in_flight) (void)hipEventSynchronize(s.ev_done);
+    }
+    for (auto& kv : ctx->requests) free_packed(kv.second.get());
+    if (!ctx->validate_only) destroy_device(ctx);
+    delete ctx;
+    return MC_OK;
+}
+
+mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision, uint64_t* out_request_id)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!fns || n == 0 || !out_request_id) return fail(ctx, MC_ERR_INVALID_ARG, "empty request or NULL argument");
+    if (precision != MC_PREC_FP32_EVAL && precision != MC_PREC_FP64)
+        return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
+    if (n > ctx->max_functions)
+        return fail(ctx, MC_ERR_ADMISSION, "request of %zu functions exceeds the %u function slots", n,
+                    ctx->max_functions);
+    std::unique_ptr<Request> r(new Request());
+    r->precision = precision;
+    r->fns.assign(fns, fns + n);
+    if (!ctx->validate_only && hipHostMalloc((void**)&r->packed, n * sizeof(DevFn), hipHostMallocDefault) == hipSuccess) {
+        r->packed_pinned = true;
+    } else {
+        r->packed = (DevFn*)std::malloc(n * sizeof(DevFn));
+        if (!r->packed) return fail(ctx, MC_ERR_OUT_OF_MEMORY, "host allocation for %zu functions failed", n);
+    }
+    struct PackedGuard {
+        Request* r;
+        bool armed = true;
+        ~PackedGuard() { if (armed) free_packed(r); }
+    } guard{r.get()};
+    r->st.resize(n);
+    r->results.assign(n, mc_result{});
+    uint64_t parts = 0;
+    for (size_t i = 0; i < n; ++i) {
+        std::string why;
+        mc_status st = validate_one(fns[i], &why);
+        if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
+        pack_function(fns[i], precision, &r->packed[i]);
+        FnState& fs = r->st[i];
+        const DevFn& d = r->packed[i];
+        uint32_t L = ctx->seg_log2[precision == MC_PREC_FP64 ? 1 : 0][d.kfam][d.dim - 1];
+        // no point in tiles larger than the function
+        while (L > 0 && ((uint32_t)kBlockWaves << (L - 1)) >= d.n_segments) --L;
+        fs.seg_log2 = L;
+        fs.n_tiles = tiles_for(d.n_segments, L);
+        fs.next_tile = 0;
+        fs.tile_cost = sample_cost(d.family, d.dim, precision) *
+                       (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
+        parts += fs.n_tiles;
+        r->tiles_total += fs.n_tiles;
+    }
+    if (parts > ctx->max_partials)
+        return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
+                    (unsigned long long)parts, (unsigned long long)ctx->max_partials);
+    r->order.resize(n);
+    for (size_t i = 0; i < n; ++i) r->order[i] = (uint32_t)i;
+    std::stable_sort(r->order.begin(), r->order.end(),
+                     [&](uint32_t a, uint32_t b) { return r->st[a].tile_cost > r->st[b].tile_cost; });
+    guard.armed = false;
+    r->id = ctx->next_id++;
+    *out_request_id = r->id;
+    Request* rp = r.get();
+    ctx->requests.emplace(rp->id, std::move(r));
+    if (!ctx->validate_only) ctx->pending.push_back(rp);
+    return MC_OK;
+}
+
+mc_status mc_run(mc_ctx* ctx, void* stream)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        reap(ctx, false);
+        admit(ctx, s);
+        if (ctx->active.empty() && !ctx->pending.empty()) {
+            // everything admitted has been launched; wait for a launch to free space
+            bool any = false;
+            for (auto& sl : ctx->slots) any = any || sl.in_flight;
+            if (any) {
+                reap(ctx, true);
+                admit(ctx, s);
+            }
+        }
+        launch(ctx, s);
+        if (ctx->h_abort && *ctx->h_abort) {
+            bool any = false;
+            for (auto& sl : ctx->slots) any = any || sl.in_flight;
+            if (!any && ctx->active.empty() && ctx->pending.empty()) *ctx->h_abort = 0u;
+        }
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    return MC_OK;
+}
+
+mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    uint64_t nr = 0, nt = 0;
+    for (auto& kv : ctx->requests) {
+        Request* r = kv.second.get();
+        if (r->fns_done < r->fns.size()) nr++;
+        nt += r->tiles_total - r->tiles_launched;
+    }
+    if (requests) *requests = nr;
+    if (tiles) *tiles = nt;
+    return MC_OK;
+}
+
+mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    auto it = ctx->requests.find(request_id);
+    if (it == ctx->requests.end())
+        return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
+    Request* r = it->second.get();
+    if (!out || n != r->fns.size())
+        return fail(ctx, MC_ERR_INVALID_ARG, "request %llu has %zu functions, got n=%zu", (unsigned long long)request_id,
+                    r->fns.size(), n);
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        reap(ctx, false);
+        while (r->fns_done < r->fns.size()) {
+            if (!blocking) return MC_NOT_READY;
+            if (r->tiles_launched < r->tiles_total || !r->admitted) {
+                mc_status st = mc_run(ctx, nullptr);
+                if (st != MC_OK) return st;
+            } else {
+                reap(ctx, true);
+            }
+        }
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    std::memcpy(out, r->results.data(), n * sizeof(mc_result));
+    const bool aborted = r->aborted;
+    ctx->requests.erase(it);
+    return aborted ? MC_ERR_ABORTED : MC_OK;
+}
+
+mc_status mc_abort(mc_ctx* ctx)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->h_abort) *ctx->h_abort = 1u;
+    return MC_OK;
+}
+
+mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out, void* stream)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!fns || !out || n == 0) return fail(ctx, MC_ERR_INVALID_ARG, "empty request or NULL argument");
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    std::vector<DevFn> packed(n);
+    uint64_t max_blocks = 1;
+    for (size_t i = 0; i < n; ++i) {
+        std::string why;
+        mc_status st = validate_one(fns[i], &why);
+        if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
+        pack_function(fns[i], MC_PREC_FP64, &packed[i]);
+        const uint64_t blocks = (packed[i].n_quads + 255) / 256;
+        if (blocks > 0x7FFFFFFFull) return fail(ctx, MC_ERR_INVALID_ARG, "function %zu: too many samples for one grid", i);
+        max_blocks = std::max(max_blocks, blocks);
+    }
+    DevFn* d_fns = nullptr;
+    Partial* d_parts = nullptr;
+    DevResult* d_res = nullptr;
+    mc_status status = MC_OK;
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(hipMalloc(&d_fns, n * sizeof(DevFn)));
+        HIP_TRY(hipMalloc(&d_parts, max_blocks * sizeof(Partial)));
+        HIP_TRY(hipMalloc(&d_res, n * sizeof(DevResult)));
+        HIP_TRY(hipMemcpyAsync(d_fns, packed.data(), n * sizeof(DevFn), hipMemcpyHostToDevice, s));
+        for (size_t i = 0; i < n; ++i) {
+            const DevFn* f = d_fns + i;
+            const uint32_t blocks = (uint32_t)((packed[i].n_quads + 255) / 256);
+            void* a1[] = {&f, &d_parts};
+            HIP_TRY(hipLaunchKernel(plain_kernel_ptr(packed[i].family, packed[i].dim), dim3(blocks), dim3(256), a1, 0, s));
+            DevResult* r = d_res + i;
+            void* a2[] = {&f, &d_parts, (void*)&blocks, &r};
+            HIP_TRY(hipLaunchKernel(plain_reduce_kernel_ptr(), dim3(1), dim3(256), a2, 0, s));
+        }
+        HIP_TRY(hipMemcpyAsync(out, d_res, n * sizeof(DevResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } catch (const HipError& e) {
+        status = fail_hip(ctx, e);
+    }
+    if (d_fns) (void)hipFree(d_fns);
+    if (d_parts) (void)hipFree(d_parts);
+    if (d_res) (void)hipFree(d_res);
+    return status;
+}
+
+mc_status mc_get_tuning(mc_ctx* ctx, uint32_t* blocks_per_cu, uint8_t* seg_log2)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (blocks_per_cu) *blocks_per_cu = ctx->blocks_per_cu32;
+    if (seg_log2)
+        for (int p = 0; p < 2; ++p)
+            for (int f = 0; f < 4; ++f)
+                for (int d = 0; d < kMaxDim; ++d) seg_log2[(p * 4 + f) * kMaxDim + d] = ctx->seg_log2[p][f][d];
+    return MC_OK;
+}
+
+mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_log2)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (blocks_per_cu > 32) return fail(ctx, MC_ERR_INVALID_ARG, "blocks_per_cu %u > 32", blocks_per_cu);
+    if (seg_log2) {
+        for (int i = 0; i < 2 * 4 * kMaxDim; ++i)
+            if (seg_log2[i] > kMaxSegLog2) return fail(ctx, MC_ERR_INVALID_ARG, "seg_log2 entry %d > %d", i, kMaxSegLog2);
+        for (int p = 0; p < 2; ++p)
+            for (int f = 0; f < 4; ++f)
+                for (int d = 0; d < kMaxDim; ++d) {
+                    ctx->seg_log2[p][f][d] = seg_log2[(p * 4 + f) * kMaxDim + d];
+                    if (f == 3) ctx->seg_log2[p][4][d] = ctx->seg_log2[p][3][d];
+                }
+    }
+    if (blocks_per_cu) {
+        ctx->blocks_per_cu32 = blocks_per_cu;
+        // graphs bake the grid size in: recapture lazily
+        for (auto& s : ctx->slots) {
+            if (s.in_flight) (void)hipEventSynchronize(s.ev_done);
+            if (s.graph) {
+                (void)hipGraphExecDestroy(s.graph);
+                s.graph = nullptr;
+            }
+        }
+        try {
+            reap(ctx, true);
+        } catch (const HipError& e) {
+            return fail_hip(ctx, e);
+        }
+    }
+    return MC_OK;
+}
+
+
+// Synthetic function of a given class for tuning trials (unit box, moderate parameters).
+static mc_function tune_function(uint32_t family, uint32_t dim, uint64_t n_samples, uint64_t seed, bool high_degree)
+{
+    mc_function f;
+    std::memset(&f, 0, sizeof f);
+    f.family = family;
+    f.dim = dim;
+    f.n_samples = n_samples;
+    f.seed = seed;
+    for (uint32_t j = 0; j < dim; ++j) {
+        f.lo[j] = 0.0;
+        f.hi[j] = 1.0;
+    }
+    f.params[0] = 1.0;
+    f.params[1] = family == MC_FAMILY_GAUSSIAN ? 0.5 : 0.5;
+    for (uint32_t j = 0; j < dim; ++j) {
+        f.params[MC_PARAM_V0 + j] = family == MC_FAMILY_POLY_PRODUCT ? 0.5 : 3.0;
+        f.params[MC_PARAM_W0 + j] = family == MC_FAMILY_POLY_PRODUCT ? (high_degree ? 6.0 : 3.0) : 0.0;
+    }
+    return f;
+}
+
+// Time one batch through the normal path; returns the persistent-kernel milliseconds.
+static double time_batch(mc_ctx* ctx, const std::vector<mc_function>& fns, int32_t precision, hipStream_t stream)
+{
+    uint64_t id = 0;
+    if (mc_submit(ctx, fns.data(), fns.size(), precision, &id) != MC_OK) return -1.0;
+    double total = 0.0;
+    auto it = ctx->requests.find(id);
+    Request* r = it->second.get();
+    for (int guard = 0; guard < 64 && r->fns_done < r->fns.size(); ++guard) {
+        if (mc_run(ctx, stream) != MC_OK) return -1.0;
+        reap(ctx, true);
+        total += ctx->last_main_ms;
+    }
+    std::vector<mc_result> out(fns.size());
+    if (mc_results(ctx, id, out.data(), out.size(), 1) != MC_OK) return -1.0;
+    return total;
+}
+
+extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    if (precision != MC_PREC_FP32_EVAL && precision != MC_PREC_FP64)
+        return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
+    const auto t0 = std::chrono::steady_clock::now();
+    auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
+    hipStream_t s = (hipStream_t)stream;
+    const int p = precision == MC_PREC_FP64 ? 1 : 0;
+    // Enough work to fill the chip several times over, small enough to time quickly.
+    const uint32_t n_fns = (uint32_t)std::max(64, ctx->num_cus);
+    // 1) workgroups per CU, on a 4-D harmonic batch
+    if (p == 0) {
+        int occ = 0;
+        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel_ptr(false), kBlockThreads, 0);
+        uint32_t best_b = ctx->blocks_per_cu32;
+        double best_t = 1e30;
+        std::vector<mc_function> fns;
+        for (uint32_t i = 0; i < n_fns; ++i) fns.push_back(tune_function(MC_FAMILY_HARMONIC, 4, 1u << 20, i, false));
+        for (int b = std::max(1, occ); b >= 1 && elapsed() < budget_seconds * 0.3; b = b > 2 ? b - 1 : b - 1) {
+            if (mc_set_tuning(ctx, (uint32_t)b, nullptr) != MC_OK) break;
+            time_batch(ctx, fns, precision, s);  // warm (graph capture)
+            const double t = time_batch(ctx, fns, precision, s);
+            if (t > 0 && t < best_t) {
+                best_t = t;
+                best_b = (uint32_t)b;
+            }
+        }
+        mc_set_tuning(ctx, best_b, nullptr);
+    }
+    // 2) segments per wave per tile, per (family, dim)
+    const uint32_t dims[] = {1, 2, 3, 4, 6, 8, 12};
+    const int nfam = p == 0 ? 5 : 4;
+    for (int fam = 0; fam < nfam && elapsed() < budget_seconds; ++fam) {
+        for (uint32_t di = 0; di < sizeof(dims) / sizeof(dims[0]) && elapsed() < budget_seconds; ++di) {
+            const uint32_t dim = dims[di];
+            std::vector<mc_function> fns;
+            const uint32_t family = fam == 4 ? (uint32_t)MC_FAMILY_POLY_PRODUCT : (uint32_t)fam;
+            const uint64_t n = (uint64_t)(4u << 20) / dim;
+            for (uint32_t i = 0; i < n_fns; ++i) fns.push_back(tune_function(family, dim, n, i, fam == 4));
+            int best_l = 0;
+            double best_t = 1e30;
+            for (int l = 0; l <= 3; ++l) {
+                ctx->seg_log2[p][fam][dim - 1] = (uint8_t)l;
+                const double t = time_batch(ctx, fns, precision, s);
+                if (t > 0 && t < best_t * 0.98) {
+                    best_t = t;
+                    best_l = l;
+                }
+            }
+            // apply to this dim and the untested dims up to the next tested one
+            const uint32_t next = di + 1 < sizeof(dims) / sizeof(dims[0]) ? dims[di + 1] : kMaxDim + 1;
+            for (uint32_t d = dim; d < next; ++d) ctx->seg_log2[p][fam][d - 1] = (uint8_t)best_l;
+        }
+    }
+    return MC_OK;
+}
+
+mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ctx->have_timing) return fail(ctx, MC_NOT_READY, "no completed run yet");
+    if (main_ms) *main_ms = ctx->last_main_ms;
+    if (finalize_ms) *finalize_ms = ctx->last_fin_ms;
+    return MC_OK;
+}
+
+const char* mc_last_error(mc_ctx* ctx)
+{
+    if (ctx) return ctx->err.c_str();
+    return g_thread_error.c_str();
+}
+
+uint32_t mc_segment_samples(void) { return (uint32_t)kSegSamples; }
+
+const char* mc_version(void) { return "zmc-gfx950 0.1"; }
+
+}  // extern "C"

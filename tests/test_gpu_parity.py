@@ -1,0 +1,70 @@
+"""HIP path against the CPU oracle on the same seeded inputs (run on an MI355X).
+
+FP64 paths (plain and batched) must match the oracle's compensated sums to
+1e-12 relative to sum|f| (S2: relative to itself); the FP32-evaluation batched
+path must put every estimate within 0.01 of the oracle's standard error of it.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_common as G
+from paper_2104_10073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import paper_2104_10073_amd as Z
+    c = Z.Context(device=0)
+    yield c
+    c.close()
+
+
+def test_eq1_plain_fp64(ctx):
+    t = W.eq1_series(n_samples=10_000)
+    orc = G.oracle_results(t)
+    G.check_fp64(ctx.plain_fp64(t), orc, "plain eq1")
+
+
+def test_eq1_batched_fp64_and_fp32(ctx):
+    import paper_2104_10073_amd as Z
+    t = W.eq1_series(n_samples=10_000)
+    orc = G.oracle_results(t)
+    G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "batched fp64 eq1")
+    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "batched fp32 eq1")
+
+
+def test_eq2_batched(ctx):
+    import paper_2104_10073_amd as Z
+    t = W.eq2_series(n_samples=20_000)
+    orc = G.oracle_results(t)
+    G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "eq2 fp64")
+    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "eq2 fp32")
+
+
+def test_edge_cases_all_paths(ctx):
+    import paper_2104_10073_amd as Z
+    t = G.edge_table()
+    orc = G.oracle_results(t)
+    G.check_fp64(ctx.plain_fp64(t), orc, "plain edges")
+    G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "batched fp64 edges")
+    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "batched fp32 edges")
+
+
+def test_mixed_small_batch(ctx):
+    """Mixed form and dimension 1..12 at oracle-sized N (several tiles and a ragged tail each)."""
+    import paper_2104_10073_amd as Z
+    t = W.mixed_batch(300, dim_range=(1, 12), log10_samples=(2.0, 5.3), gen_seed=101)
+    orc = G.oracle_results(t)
+    G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "mixed fp64")
+    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "mixed fp32")
+
+
+def test_plain_matches_batched_fp64(ctx):
+    import paper_2104_10073_amd as Z
+    t = W.mixed_batch(64, dim_range=(1, 12), log10_samples=(3.0, 5.0), gen_seed=103)
+    a = ctx.plain_fp64(t)
+    b = ctx.integrate(t, Z.PREC_FP64)
+    assert np.all(np.abs(a["sum_f"] - b["sum_f"]) <= 1e-12 * np.sqrt(b["n"] * b["sum_f2"]) + 1e-300)
