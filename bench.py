@@ -81,6 +81,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--autotune", type=float, default=0.0, help="seconds of autotuning before timing")
+    ap.add_argument("--no-graph", action="store_true", help="direct kernel launches instead of graph replays")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (tiles sharded across GPUs, one gather "
@@ -98,7 +99,15 @@ def main():
     batches = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=b) for b in range(K + Wm)]
     evals_per_step = W.total_evals(batches[0])
 
-    ctx = Z.Context(device=0, workspace="torch")
+    # One launch per step: FIFO scheduling with the per-launch tile cap set to one
+    # batch's tile count, so each mc_run takes exactly the next seed's batch.
+    probe = Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY)
+    probe.submit(batches[0], Z.PREC_FP32)
+    tiles_per_batch = probe.validate_tiles()
+    probe.close()
+    flags = Z.MC_NO_GRAPH if args.no_graph else 0
+    ctx = Z.Context(device=0, workspace="torch", flags=flags, policy=Z.MC_SCHED_FIFO,
+                    max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
     if args.autotune > 0:
         ctx.autotune(Z.PREC_FP32, stream=stream, budget_seconds=args.autotune)
     ids = [ctx.submit(b, Z.PREC_FP32) for b in batches]
@@ -108,20 +117,26 @@ def main():
         ctx.run(stream)
         ctx.results(ids[i], n)
     torch.cuda.synchronize()
-    main_ms = []
+    st0 = ctx.stats()
     t0 = time.perf_counter()
     results = []
+    # step i's launch is enqueued before step i-1's results are collected, so the
+    # host's work-list building overlaps the GPU
+    ctx.run(stream)
     for i in range(Wm, Wm + K):
-        ctx.run(stream)
+        if i + 1 < Wm + K:
+            ctx.run(stream)
         results.append(ctx.results(ids[i], n))
-        tm = ctx.last_run_timing()
-        main_ms.append(tm[0])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    st1 = ctx.stats()
     value = evals_per_step * K / dt
+    launches = st1["launches"] - st0["launches"]
+    assert launches == K and st1["samples"] - st0["samples"] == evals_per_step * K, (st0, st1)
+    assert st1["bad_records"] == 0
 
     # roofline of the persistent kernel from its HIP-event time
-    avg_main_s = float(np.mean(main_ms)) * 1e-3
+    avg_main_s = (st1["main_ms"] - st0["main_ms"]) / launches * 1e-3
     slots = algorithmic_slots_per_eval("harmonic", 4) * evals_per_step
     achieved = slots / avg_main_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,

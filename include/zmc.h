@@ -11,9 +11,10 @@
  *     SE    = V * sqrt(s^2 / N),        s^2 = (sum f^2 - (sum f)^2 / N) / (N - 1),
  *
  * a value with an error bar for every integral (Fig. 1 caption).  Samples are
- * counter-based: coordinate j of sample i of a function with seed s is the
- * 32-bit word g = i*d + j of the Philox4x32-10 stream with key (s mod 2^32,
- * s >> 32) and counter (g/4 mod 2^32, g/4 >> 32, 0, 0); the word r becomes
+ * counter-based and taken four at a time: coordinate j of sample i of a
+ * d-dimensional function with seed s is output word i mod 4 of the
+ * Philox4x32-10 block with key (s mod 2^32, s >> 32) and counter
+ * (b mod 2^32, b >> 32, 0, 0), b = (i / 4) * d + j; the word r becomes
  * u = (2*(r mod 2^23) + 1) * 2^-24 and x_j = lo_j + (hi_j - lo_j) * u.  A
  * function's result therefore depends only on its own description, never on
  * the rest of the batch, the launch shape or the tuning.
@@ -72,7 +73,9 @@ typedef enum {
 
 typedef enum {
     MC_PREC_FP32_EVAL = 0,   /* FP32 sample mapping and evaluation, per-lane compensated FP32 sums,
-                                FP64 cross-lane reduction, variance and finalize */
+                                FP64 cross-lane reduction, variance and finalize.  A function whose
+                                spread is too small for FP32 to resolve (sigma / rms below
+                                400 * 2^-24 * sqrt(N)) is re-run in FP64; its result says so. */
     MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
 } mc_precision;
 
@@ -95,12 +98,13 @@ typedef struct mc_result {
     double sum_f2;               /* S2 = sum f(x_i)^2 */
     uint64_t n;                  /* N */
     int32_t status;              /* MC_OK or MC_ERR_ABORTED */
-    uint32_t precision;          /* mc_precision the function ran in */
+    uint32_t precision;          /* mc_precision the result was computed in */
 } mc_result;
 
 /* Context flags. */
 #define MC_VALIDATE_ONLY 0x1u    /* host-only context: mc_submit validates and packs, no device is touched */
 #define MC_NO_GRAPH 0x2u         /* launch kernels directly instead of replaying captured HIP graphs */
+#define MC_NO_PROMOTE 0x4u       /* keep FP32 results of nearly constant integrands instead of re-running them in FP64 */
 
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */
@@ -112,8 +116,12 @@ typedef struct mc_config {
     void* workspace;             /* optional caller-owned device memory for every device buffer */
     uint64_t workspace_bytes;    /* its size; see mc_workspace_size */
     uint32_t blocks_per_cu;      /* persistent-kernel workgroups per CU (0: tuned/default) */
-    uint32_t reserved;
+    uint32_t policy;             /* MC_SCHED_FAIR (0) or MC_SCHED_FIFO: how mc_run shares a launch */
 } mc_config;
+
+/* Scheduling policies for the tiles of one launch (results never depend on them). */
+#define MC_SCHED_FAIR 0u  /* every active request gets an equal share of the launch (small requests finish fast) */
+#define MC_SCHED_FIFO 1u  /* fill the launch from the oldest request on */
 
 typedef struct mc_ctx mc_ctx;
 
@@ -134,8 +142,10 @@ mc_status mc_destroy(mc_ctx* ctx);
 /* Validate and queue n functions as one request evaluated in `precision`.
  * The whole request is rejected on the first invalid function (its index is in
  * mc_last_error); nothing partial is queued.  Requests are admitted to the device
- * in submission order as function slots and partial memory free up; a request
- * that could never fit returns MC_ERR_ADMISSION.  *out_request_id identifies it. */
+ * in submission order as function slots and partial memory free up (at submit
+ * if they fit, else in a later mc_run); admission uploads the packed table on
+ * the library's own upload stream.  A request that could never fit returns
+ * MC_ERR_ADMISSION.  *out_request_id identifies it. */
 mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision,
                     uint64_t* out_request_id);
 
@@ -143,8 +153,13 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
  * a persistent kernel over the admitted (function, sample-segment) tiles and a
  * finalize kernel for every function whose last tile is in this launch, plus
  * the copy of those results to host memory.  Returns without waiting.  Launches
- * nothing (and returns MC_OK) when no admitted work is pending. */
+ * nothing and returns MC_OK when no admitted work is pending, or MC_NOT_READY
+ * when all launch slots are still in flight (call again later). */
 mc_status mc_run(mc_ctx* ctx, void* stream);
+
+/* Ids of requests that completed since the previous call (their results can be
+ * taken without waiting): up to `cap` ids into completed[], the count in *n. */
+mc_status mc_poll(mc_ctx* ctx, uint64_t* completed, size_t cap, size_t* n);
 
 /* Number of requests submitted but not yet complete, and tiles still waiting for a launch. */
 mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
@@ -156,8 +171,10 @@ mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
  * request's device resources are released when it completes. */
 mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking);
 
-/* Ask running persistent kernels to stop fetching tiles; unfinished functions
- * complete with status MC_ERR_ABORTED.  Clears itself once all queued work drained. */
+/* Ask running persistent kernels to stop fetching tiles.  Every request submitted
+ * before the call completes with status MC_ERR_ABORTED on its unfinished functions
+ * (mc_results returns MC_ERR_ABORTED); the next mc_run waits for the launches in
+ * flight, then clears the request so later work runs normally. */
 mc_status mc_abort(mc_ctx* ctx);
 
 /* The plain baseline path: for each function one kernel launch with a grid
@@ -177,9 +194,23 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
  * `precision` and keep the fastest.  Blocks until done; uses `stream`. */
 mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
 
-/* Kernel timing of the most recent completed mc_run (persistent kernel and
+/* Kernel timing of the most recent completed mc_run (persistent kernels and
  * finalize, in milliseconds, from HIP events on the launch stream). */
 mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms);
+
+/* Cumulative counters of a context since it was created (completed launches only). */
+typedef struct mc_stats {
+    uint64_t launches;           /* completed launches */
+    uint64_t tiles32, tiles64;   /* tiles run by the FP32 and FP64 persistent kernels */
+    uint64_t functions;          /* function results produced (promoted ones count twice) */
+    uint64_t samples;            /* integrand evaluations in those tiles */
+    uint64_t promoted;           /* FP32 functions re-run in FP64 */
+    uint64_t bad_records;        /* records that failed the kernels' bounds checks (always 0 unless corrupt) */
+    double main_ms;              /* sum of persistent-kernel time (HIP events) */
+    double finalize_ms;          /* sum of finalize time */
+} mc_stats;
+
+mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out);
 
 /* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */
 const char* mc_last_error(mc_ctx* ctx);

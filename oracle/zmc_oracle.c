@@ -23,9 +23,12 @@
  *
  *   RNG      Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel random
  *            numbers: as easy as 1, 2, 3", SC'11).  Key = (seed mod 2^32,
- *            seed >> 32).  Coordinate j of sample i uses uniform index
- *            g = i*d + j: Philox block b = g / 4, output word g mod 4,
- *            counter = (b mod 2^32, b >> 32, 0, 0).
+ *            seed >> 32).  Samples are taken four at a time: sample i is
+ *            member s = i mod 4 of quad q = i / 4, and its coordinate j is
+ *            output word s of the Philox block with counter
+ *            (b mod 2^32, b >> 32, 0, 0), b = q*d + j.  A quad uses exactly
+ *            d blocks and no output word is wasted; equivalently coordinate j
+ *            of sample i is word g = 4*(q*d + j) + s of the function's stream.
  *   Uniform  u = (2*(r mod 2^23) + 1) * 2^-24 from a 32-bit word r: the
  *            midpoints of a 2^23 grid, strictly inside (0, 1), exact in FP32
  *            and FP64.
@@ -125,13 +128,14 @@ double orc_uniform(uint32_t r)
 /* The 32-bit word that coordinate j of sample i draws. */
 uint32_t orc_word(uint64_t seed, uint32_t dim, uint64_t i, uint32_t j)
 {
-    uint64_t g = i * (uint64_t)dim + (uint64_t)j;
-    uint64_t b = g >> 2;
+    uint64_t q = i / 4u;                       /* quad */
+    uint32_t s = (uint32_t)(i % 4u);           /* member of the quad */
+    uint64_t b = q * (uint64_t)dim + (uint64_t)j;
     uint32_t ctr[4] = {(uint32_t)b, (uint32_t)(b >> 32), 0u, 0u};
     uint32_t key[2] = {(uint32_t)seed, (uint32_t)(seed >> 32)};
     uint32_t out[4];
     orc_philox4x32_10(ctr, key, out);
-    return out[g & 3u];
+    return out[s];
 }
 
 void orc_sample_point(const orc_function* fn, uint64_t i, double* x)

@@ -31,6 +31,9 @@ PREC_FP64 = 1
 
 MC_VALIDATE_ONLY = 0x1
 MC_NO_GRAPH = 0x2
+MC_NO_PROMOTE = 0x4
+MC_SCHED_FAIR = 0
+MC_SCHED_FIFO = 1
 
 RESULT_DTYPE = np.dtype([
     ("mean", "<f8"), ("std_error", "<f8"), ("sum_f", "<f8"), ("sum_f2", "<f8"),
@@ -41,9 +44,9 @@ assert RESULT_DTYPE.itemsize == 48
 # Every symbol include/zmc.h declares.
 EXPORTS = [
     "mc_config_init", "mc_workspace_size", "mc_create", "mc_destroy", "mc_submit", "mc_run",
-    "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
-    "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_last_error", "mc_segment_samples",
-    "mc_version",
+    "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
+    "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
+    "mc_segment_samples", "mc_version",
 ]
 
 
@@ -58,8 +61,19 @@ class McConfig(ctypes.Structure):
         ("workspace", ctypes.c_void_p),
         ("workspace_bytes", ctypes.c_uint64),
         ("blocks_per_cu", ctypes.c_uint32),
-        ("reserved", ctypes.c_uint32),
+        ("policy", ctypes.c_uint32),
     ]
+
+
+class McStats(ctypes.Structure):
+    _fields_ = [
+        ("launches", ctypes.c_uint64), ("tiles32", ctypes.c_uint64), ("tiles64", ctypes.c_uint64),
+        ("functions", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
+        ("bad_records", ctypes.c_uint64), ("main_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+    ]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
 
 
 class McError(RuntimeError):
@@ -88,6 +102,7 @@ def load(path: str = LIB_PATH):
     L.mc_destroy.argtypes = [vp]
     L.mc_submit.argtypes = [vp, vp, ctypes.c_size_t, ctypes.c_int32, u64p]
     L.mc_run.argtypes = [vp, vp]
+    L.mc_poll.argtypes = [vp, u64p, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mc_pending.argtypes = [vp, u64p, u64p]
     L.mc_results.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.c_int]
     L.mc_abort.argtypes = [vp]
@@ -96,6 +111,7 @@ def load(path: str = LIB_PATH):
     L.mc_set_tuning.argtypes = [vp, ctypes.c_uint32, vp]
     L.mc_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_double]
     L.mc_last_run_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    L.mc_get_stats.argtypes = [vp, ctypes.POINTER(McStats)]
     L.mc_last_error.argtypes = [vp]
     L.mc_last_error.restype = ctypes.c_char_p
     L.mc_segment_samples.restype = ctypes.c_uint32
@@ -132,7 +148,8 @@ class Context:
     ``workspace='torch'``, from a torch tensor the context keeps alive."""
 
     def __init__(self, device: int = 0, flags: int = 0, max_functions: int = 0, max_tiles_per_run: int = 0,
-                 max_partials: int = 0, mem_budget_bytes: int = 0, workspace=None, blocks_per_cu: int = 0):
+                 max_partials: int = 0, mem_budget_bytes: int = 0, workspace=None, blocks_per_cu: int = 0,
+                 policy: int = MC_SCHED_FAIR):
         self.L = load()
         cfg = McConfig()
         self.L.mc_config_init(ctypes.byref(cfg))
@@ -143,6 +160,7 @@ class Context:
         cfg.max_partials = max_partials
         cfg.mem_budget_bytes = mem_budget_bytes
         cfg.blocks_per_cu = blocks_per_cu
+        cfg.policy = policy
         self._workspace = None
         if workspace is not None:
             need = ctypes.c_uint64()
@@ -191,8 +209,20 @@ class Context:
         self._check(self.L.mc_submit(self.h, t.ctypes.data, len(t), precision, ctypes.byref(rid)), self.h)
         return int(rid.value)
 
-    def run(self, stream=None):
-        self._check(self.L.mc_run(self.h, _stream_handle(stream)), self.h)
+    def run(self, stream=None) -> bool:
+        """Enqueue one launch; False when every launch slot is still busy (nothing launched)."""
+        return self._check(self.L.mc_run(self.h, _stream_handle(stream)), self.h) == MC_OK
+
+    def poll(self, cap: int = 4096):
+        """Ids of requests completed since the previous poll."""
+        ids = (ctypes.c_uint64 * cap)()
+        n = ctypes.c_size_t()
+        self._check(self.L.mc_poll(self.h, ids, cap, ctypes.byref(n)), self.h)
+        return [int(ids[i]) for i in range(n.value)]
+
+    def validate_tiles(self) -> int:
+        """Tiles that the submitted, not yet launched work would take (works on any context)."""
+        return self.pending()[1]
 
     def pending(self):
         r, t = ctypes.c_uint64(), ctypes.c_uint64()
@@ -242,6 +272,11 @@ class Context:
 
     def autotune(self, precision: int = PREC_FP32, stream=None, budget_seconds: float = 10.0):
         self._check(self.L.mc_autotune(self.h, precision, _stream_handle(stream), budget_seconds), self.h)
+
+    def stats(self) -> dict:
+        st = McStats()
+        self._check(self.L.mc_get_stats(self.h, ctypes.byref(st)), self.h)
+        return st.as_dict()
 
     def last_run_timing(self):
         a, b = ctypes.c_double(), ctypes.c_double()

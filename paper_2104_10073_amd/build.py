@@ -34,17 +34,28 @@ def _run(cmd):
     return proc
 
 
-def build(verbose: bool = False) -> str:
+def _newer(a: str, b: str) -> bool:
+    return os.path.exists(b) and os.path.getmtime(b) >= os.path.getmtime(a)
+
+
+def build(verbose: bool = False, incremental: bool = False) -> str:
+    """Compile both translation units (in parallel) and link libzmc.so.
+
+    incremental=True skips an object that is newer than its source and the
+    shared headers (for development; the default always recompiles)."""
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     procs = []
+    headers = [os.path.join(CSRC, "zmc_device.hpp"), os.path.join(INCLUDE, "zmc.h")]
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
+        objs.append(obj)
+        if incremental and all(_newer(x, obj) for x in [os.path.join(CSRC, src), *headers]):
+            continue
         cmd = [HIPCC, *COMMON, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append((cmd, subprocess.Popen(cmd, stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True)))
-        objs.append(obj)
     for cmd, p in procs:
         out, err = p.communicate()
         if p.returncode != 0:
@@ -57,4 +68,4 @@ def build(verbose: bool = False) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose=True))
+    print(build(verbose=True, incremental="--incremental" in sys.argv))

@@ -1,11 +1,12 @@
 // zmc_device.hpp -- device-resident layouts shared by the host runtime and the gfx950 kernels.
 //
 // Work decomposition.  A function's samples are grouped in quads (4 consecutive
-// samples, which draw exactly `dim` consecutive Philox blocks) and quads in
-// segments of kSegQuads = 64 lanes x kQuadsPerLane quads.  Lane l of the wave
-// that owns segment s evaluates quads s*kSegQuads + k*64 + l for k = 0..15 and
-// keeps compensated sums; the 64 lane sums are combined by a fixed xor butterfly
-// in FP64.  Segment sums are combined by a fixed pairwise tree over the segment
+// samples; quad q of a d-dimensional function draws Philox blocks q*d .. q*d+d-1,
+// block q*d + j holding coordinate j of the four samples) and quads in segments
+// of kSegQuads = 64 lanes x kQuadsPerLane quads.  Lane l of the wave that owns
+// segment s evaluates quads s*kSegQuads + k*64 + l for k = 0..15 and keeps
+// compensated sums; the 64 lane sums are combined by a fixed xor butterfly in
+// FP64.  Segment sums are combined by a fixed pairwise tree over the segment
 // index (zero-padded to a power of two).  A tile is an aligned power-of-two run
 // of segments handed to one workgroup; its sum is a subtree of that same tree,
 // so a function's result is bitwise independent of the tile size, the grid
@@ -53,11 +54,11 @@ struct alignas(64) DevFn {
     // the float whose mantissa is the low 23 bits of the Philox word, so that
     // u_j = t_j - (1 - 2^-24) exactly.
     float fc[kMaxDim];            // HARMONIC kappa_j (revolutions per unit t); ABS gamma_j;
-                                  // GAUSSIAN sqrt(h') w_j; POLY w_j
+                                  // GAUSSIAN sqrt(log2(e) / (2 sigma^2)) w_j; POLY w_j
     float fo[kMaxDim];            // GAUSSIAN centre m_j in t-space; POLY lo_j
     float fp[kMaxDim];            // POLY p_j
     float f0, f0lo;               // HARMONIC phase offset (revolutions); ABS offset as hi + lo
-    uint32_t kfam;                // kernel variant: the family, or 4 for a product polynomial of degree > 4
+    uint32_t kfam;                // family as the kernels dispatch on it
     uint32_t pad_;
 };
 
@@ -90,6 +91,13 @@ struct DevResult {
     uint32_t precision;
 };
 
+// Counters of one launch (zeroed by every descriptor upload).
+constexpr int kCounterTiles32 = 0;     // next FP32 tile to fetch
+constexpr int kCounterTiles64 = 1;     // next FP64 tile to fetch
+constexpr int kCounterAborted = 2;     // a workgroup stopped because the abort word was set
+constexpr int kCounterBadRecords = 3;  // tile or finalize records that failed their bounds checks
+constexpr int kNumCounters = 4;
+
 // Everything one launch reads; lives in device memory at a fixed address per
 // launch slot so a captured graph can be replayed with new contents.  FP32 and
 // FP64 tiles go to two kernels (each with its own register budget); both
@@ -101,12 +109,13 @@ struct alignas(64) LaunchDesc {
     Partial* partials;
     const Fin* fins;
     DevResult* results;
-    uint32_t* counters;                    // [0]: next FP32 tile, [1]: next FP64 tile, [2]: abort seen
-    const volatile uint32_t* abort_flag;   // host-mapped word; nonzero asks the kernels to stop
+    uint32_t* counters;                    // kNumCounters words, right after this descriptor
+    const uint32_t* abort_word;            // device word; nonzero asks the kernels to stop fetching tiles
+    uint64_t n_partials;                   // size of the partial arena (bounds checks)
+    uint32_t n_fns;                        // size of the function table (bounds checks)
     uint32_t n_tiles32;
     uint32_t n_tiles64;
     uint32_t n_fins;
-    uint32_t pad_;
 };
 
 }  // namespace zmc

@@ -27,7 +27,7 @@
 #include "zmc_device.hpp"
 
 namespace zmc {
-const void* plain_kernel_ptr(uint32_t family, uint32_t dim);
+const void* plain_kernel_ptr();
 const void* batched_kernel_ptr(bool fp64);
 const void* finalize_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
@@ -38,6 +38,7 @@ using namespace zmc;
 static_assert(sizeof(mc_function) == 472, "mc_function layout");
 static_assert(sizeof(mc_result) == 48, "mc_result layout");
 static_assert(sizeof(mc_config) == 56, "mc_config layout");
+static_assert(sizeof(mc_stats) == 72, "mc_stats layout");
 static_assert(sizeof(DevResult) == sizeof(mc_result), "result layout");
 static_assert(sizeof(Tile) == 16 && sizeof(Fin) == 16 && sizeof(Partial) == 16, "record layout");
 
@@ -254,14 +255,11 @@ void pack_function(const mc_function& f, int precision, DevFn* d)
         break;
     }
     default: {  // POLY_PRODUCT
-        int maxdeg = 0;
         for (uint32_t j = 0; j < D; ++j) {
             d->fc[j] = (float)d->w[j];
             d->fo[j] = (float)f.lo[j];
             d->fp[j] = (float)f.params[MC_PARAM_V0 + j];
-            maxdeg = std::max(maxdeg, (int)d->deg[j]);
         }
-        if (maxdeg > 4) d->kfam = 4;
         break;
     }
     }
@@ -294,6 +292,7 @@ struct FnState {
     uint32_t next_tile;   // next tile to put into a launch
     uint64_t part0;       // first partial slot
     double tile_cost;
+    bool f64;             // evaluated by the FP64 kernel (requested, or promoted from FP32)
 };
 
 struct Request {
@@ -306,12 +305,16 @@ struct Request {
     std::vector<mc_result> results;
     std::vector<uint32_t> order;      // functions by descending per-tile cost
     uint32_t order_pos = 0;           // next function in `order` with tiles left
+    std::vector<uint32_t> redo;       // functions promoted from FP32 to FP64, to run again
+    uint32_t redo_pos = 0;
     uint64_t part_base = 0, part_count = 0;
     uint32_t slot_base = 0;
     bool admitted = false;
+    hipEvent_t uploaded = nullptr;    // upload of the packed table (library upload stream)
     uint32_t fns_done = 0;
     uint64_t tiles_total = 0, tiles_launched = 0;
     bool aborted = false;
+    uint32_t n_promoted = 0;
 };
 
 struct FinRef {
@@ -337,11 +340,13 @@ struct LaunchSlot {
     bool in_flight = false;
     uint64_t seq = 0;
     uint32_t n_tiles32 = 0, n_tiles64 = 0, n_fins = 0;
+    uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
     std::vector<Request*> touched;  // requests with tiles in this launch
 };
 
-constexpr size_t kDescBytes = 256;  // LaunchDesc (64-aligned, < 128 bytes) + counters
+constexpr size_t kDescBytes = 256;  // LaunchDesc followed by its counters
+static_assert(sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t) <= kDescBytes, "launch descriptor size");
 
 }  // namespace
 
@@ -366,23 +371,29 @@ struct mc_ctx {
     DevFn* d_fns = nullptr;
     Partial* d_partials = nullptr;
     LaunchSlot slots[kLaunchSlots];
-    uint32_t* h_abort = nullptr;      // host-mapped
-    uint32_t* d_abort = nullptr;
+    uint32_t* d_abort_word = nullptr;  // device word the persistent kernels poll
+    uint32_t* h_words = nullptr;       // pinned {0, 1}: sources for setting / clearing it
+    bool abort_requested = false;
 
     RangeAlloc fn_alloc, part_alloc;
 
     // tuning
     uint32_t blocks_per_cu32 = 4, blocks_per_cu64 = 2;
-    uint8_t seg_log2[2][5][kMaxDim];
+    uint8_t seg_log2[2][kNumFamilies][kMaxDim];
 
     // requests
     uint64_t next_id = 1;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> requests;
     std::deque<Request*> pending;     // submitted, not admitted (FIFO)
     std::deque<Request*> active;      // admitted with tiles not yet launched
+    std::deque<uint64_t> completed;   // request ids finished since the last mc_poll
+    hipStream_t upload_stream = nullptr;
+    uint32_t policy = MC_SCHED_FAIR;
+    bool promote = true;
     uint64_t launch_seq = 0;
     double last_main_ms = 0.0, last_fin_ms = 0.0;
     bool have_timing = false;
+    mc_stats stats{};
 };
 
 namespace {
@@ -407,7 +418,7 @@ mc_status fail_hip(mc_ctx* ctx, const HipError& e)
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    uint64_t fns, partials, slot_desc, slot_tiles, slot_fins, slot_results, total;
+    uint64_t fns, partials, slot_desc, slot_tiles, slot_fins, slot_results, abort_word, total;
 };
 
 Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap)
@@ -426,6 +437,8 @@ Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t ti
     off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(Fin), 256);
     L.slot_results = off;
     off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(DevResult), 256);
+    L.abort_word = off;
+    off = align_up(off + sizeof(uint32_t), 256);
     L.total = off;
     return L;
 }
@@ -468,31 +481,94 @@ void free_packed(Request* r)
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
     free_packed(r);
+    if (r->uploaded) {
+        (void)hipEventDestroy(r->uploaded);
+        r->uploaded = nullptr;
+    }
     if (!r->admitted) return;
     ctx->fn_alloc.release(r->slot_base, r->fns.size());
     ctx->part_alloc.release(r->part_base, r->part_count);
     r->admitted = false;
 }
 
-// Collect finished launches: scatter their results into the requests.
-void reap(mc_ctx* ctx, bool wait_all)
+bool has_work(const Request* r)
 {
+    return r->order_pos < r->order.size() || r->redo_pos < r->redo.size();
+}
+
+// FP32 evaluation rounds each sample to about 2^-24 of its size; a bias of a
+// few such units of the RMS value must stay below 0.01 of the standard error,
+// i.e. sigma / rms must exceed 100 * 4 * 2^-24 * sqrt(N).  Below that (nearly
+// constant integrands) the FP32 result cannot be trusted to that accuracy.
+bool fp32_unresolved(const mc_result& r)
+{
+    const double n = (double)r.n;
+    if (!(n >= 2.0)) return false;
+    const double rms2 = r.sum_f2 / n;
+    if (!(rms2 > 0.0)) return false;                 // f == 0 everywhere: exact in FP32
+    const double var = (r.sum_f2 - r.sum_f * r.sum_f / n) / (n - 1.0);
+    const double ratio = var > 0.0 ? std::sqrt(var / rms2) : 0.0;
+    return ratio < 400.0 * std::ldexp(1.0, -24) * std::sqrt(n);
+}
+
+void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
+{
+    FnState& fs = r->st[fi];
+    fs.f64 = true;
+    fs.next_tile = 0;
+    r->tiles_total += fs.n_tiles;
+    pack_function(r->fns[fi], MC_PREC_FP64, &r->packed[fi]);
+    HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &r->packed[fi], sizeof(DevFn), hipMemcpyHostToDevice,
+                           ctx->upload_stream));
+    HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+    const bool was_active = has_work(r);
+    r->redo.push_back(fi);
+    r->n_promoted++;
+    ctx->stats.promoted++;
+    if (!was_active) ctx->active.push_back(r);
+}
+
+// Collect finished launches (oldest first): scatter their results into the
+// requests.  wait = 0: only what has completed; 1: wait for the oldest launch
+// in flight first; 2: wait for every launch in flight.
+void reap(mc_ctx* ctx, int wait)
+{
+    bool waited = false;
     for (;;) {
         LaunchSlot* oldest = nullptr;
         for (auto& s : ctx->slots)
             if (s.in_flight && (!oldest || s.seq < oldest->seq)) oldest = &s;
         if (!oldest) return;
-        hipError_t q = wait_all ? hipEventSynchronize(oldest->ev_done) : hipEventQuery(oldest->ev_done);
+        const bool block = wait == 2 || (wait == 1 && !waited);
+        waited = true;
+        hipError_t q = block ? hipEventSynchronize(oldest->ev_done) : hipEventQuery(oldest->ev_done);
         if (q == hipErrorNotReady) return;
         if (q != hipSuccess) throw HipError{q, "hipEventQuery(launch)"};
         LaunchSlot& s = *oldest;
+        const uint32_t* cnt = (const uint32_t*)(s.h_desc + sizeof(LaunchDesc));
+        const uint32_t bad = cnt[kCounterBadRecords];
+        if (bad != 0) {
+            char buf[160];
+            snprintf(buf, sizeof buf, "launch %llu: %u tile/finalize records failed the kernels' bounds checks",
+                     (unsigned long long)s.seq, bad);
+            ctx->err = buf;
+        }
         for (uint32_t i = 0; i < s.n_fins; ++i) {
             const FinRef& fr = s.fin_refs[i];
             mc_result& out = fr.req->results[fr.index];
             std::memcpy(&out, &s.h_results[i], sizeof(mc_result));
+            if (bad != 0) out.status = MC_ERR_HIP;
+            if (out.status == MC_OK && out.precision == MC_PREC_FP32_EVAL && ctx->promote &&
+                fp32_unresolved(out)) {
+                promote_to_fp64(ctx, fr.req, fr.index);
+                continue;
+            }
             if (out.status != MC_OK) fr.req->aborted = true;
             fr.req->fns_done++;
-            if (fr.req->fns_done == fr.req->fns.size()) free_request_resources(ctx, fr.req);
+            if (fr.req->fns_done == fr.req->fns.size()) {
+                free_request_resources(ctx, fr.req);
+                ctx->completed.push_back(fr.req->id);
+            }
         }
         {
             float a = 0.f, b = 0.f;
@@ -501,7 +577,15 @@ void reap(mc_ctx* ctx, bool wait_all)
                 ctx->last_main_ms = a;
                 ctx->last_fin_ms = b;
                 ctx->have_timing = true;
+                ctx->stats.main_ms += a;
+                ctx->stats.finalize_ms += b;
             }
+            ctx->stats.launches++;
+            ctx->stats.tiles32 += s.n_tiles32;
+            ctx->stats.tiles64 += s.n_tiles64;
+            ctx->stats.functions += s.n_fins;
+            ctx->stats.samples += s.n_samples;
+            ctx->stats.bad_records += bad;
         }
         s.in_flight = false;
         s.fin_refs.clear();
@@ -509,8 +593,10 @@ void reap(mc_ctx* ctx, bool wait_all)
     }
 }
 
-// Move pending requests into device slots while they fit (FIFO).
-void admit(mc_ctx* ctx, hipStream_t stream)
+// Move pending requests into device slots while they fit (FIFO).  The packed
+// table goes up on the library's upload stream; launches that use a request
+// wait for its upload event.
+void admit(mc_ctx* ctx)
 {
     while (!ctx->pending.empty()) {
         Request* r = ctx->pending.front();
@@ -532,8 +618,11 @@ void admit(mc_ctx* ctx, hipStream_t stream)
             r->st[i].part0 = p;
             p += r->st[i].n_tiles;
         }
-        HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice, stream));
-        r->admitted = true;
+        r->admitted = true;  // from here on the slots are released with the request
+        HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice,
+                               ctx->upload_stream));
+        HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
+        HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
         ctx->pending.pop_front();
         ctx->active.push_back(r);
     }
@@ -578,76 +667,99 @@ void capture_graph(mc_ctx* ctx, LaunchSlot& s)
     HIP_TRY(hipStreamDestroy(cs));
 }
 
-// Build and enqueue one launch.  Returns false if no admitted work was pending.
-bool launch(mc_ctx* ctx, hipStream_t stream)
+// Put up to `budget` tiles of request r into launch slot s (functions in
+// descending per-tile cost), with a finalize record for every function whose
+// last tile goes in.  Returns false when a capacity of the slot is exhausted.
+bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
 {
+    uint64_t taken = 0;
+    bool room = true;
+    while (has_work(r)) {
+        const bool in_order = r->order_pos < r->order.size();
+        const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
+        FnState& fs = r->st[fi];
+        uint32_t& nt = fs.f64 ? s.n_tiles64 : s.n_tiles32;
+        Tile* out = fs.f64 ? s.h_tiles64 : s.h_tiles32;
+        const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
+        const uint64_t tile_samples = (uint64_t)per_tile * kSegSamples;
+        const uint64_t fn_samples = r->fns[fi].n_samples;
+        while (fs.next_tile < fs.n_tiles && nt < ctx->tile_cap && taken < budget) {
+            const uint64_t first = (uint64_t)fs.next_tile * tile_samples;
+            s.n_samples += std::min<uint64_t>(tile_samples, fn_samples - first);
+            Tile& t = out[nt++];
+            t.fn = fs.slot;
+            t.seg0 = fs.next_tile * per_tile;
+            t.seg_log2 = fs.seg_log2;
+            t.out = (uint32_t)(fs.part0 + fs.next_tile);
+            fs.next_tile++;
+            r->tiles_launched++;
+            taken++;
+        }
+        if (taken > 0 && (s.touched.empty() || s.touched.back() != r)) s.touched.push_back(r);
+        if (fs.next_tile < fs.n_tiles) {
+            room = nt < ctx->tile_cap;
+            break;
+        }
+        if (s.n_fins >= ctx->fin_cap) {
+            room = false;
+            break;
+        }
+        Fin& f = s.h_fins[s.n_fins];
+        f.fn = fs.slot;
+        f.part0 = (uint32_t)fs.part0;
+        f.n_tiles = fs.n_tiles;
+        f.res = s.n_fins;
+        s.fin_refs.push_back(FinRef{r, fi});
+        s.n_fins++;
+        if (in_order) r->order_pos++;
+        else r->redo_pos++;
+        if (has_work(r) && taken >= budget) break;
+    }
+    return room;
+}
+
+// Build and enqueue one launch.  Returns false if nothing was launched (no
+// admitted work, or no free launch slot).
+bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
+{
+    *no_slot = false;
     if (ctx->active.empty()) return false;
-    // a free slot (wait for the oldest launch if all are in flight)
     LaunchSlot* slot = nullptr;
-    for (;;) {
-        for (auto& s : ctx->slots)
-            if (!s.in_flight) {
-                slot = &s;
-                break;
-            }
-        if (slot) break;
-        reap(ctx, true);
+    for (auto& s : ctx->slots)
+        if (!s.in_flight) {
+            slot = &s;
+            break;
+        }
+    if (!slot) {
+        *no_slot = true;
+        return false;
     }
     LaunchSlot& s = *slot;
     s.n_tiles32 = s.n_tiles64 = s.n_fins = 0;
+    s.n_samples = 0;
     s.fin_refs.clear();
     s.touched.clear();
-    // Take tiles request by request (admission order), within a request by
-    // descending per-tile cost; stop at the per-launch tile capacity.
-    while (!ctx->active.empty()) {
-        Request* r = ctx->active.front();
-        const bool f64 = r->precision == MC_PREC_FP64;
-        uint32_t& nt = f64 ? s.n_tiles64 : s.n_tiles32;
-        Tile* out = f64 ? s.h_tiles64 : s.h_tiles32;
-        bool full = false;
-        bool touched = false;
-        while (r->order_pos < r->order.size()) {
-            const uint32_t fi = r->order[r->order_pos];
-            FnState& fs = r->st[fi];
-            const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
-            while (fs.next_tile < fs.n_tiles && nt < ctx->tile_cap) {
-                Tile& t = out[nt++];
-                t.fn = fs.slot;
-                t.seg0 = fs.next_tile * per_tile;
-                t.seg_log2 = fs.seg_log2;
-                t.out = (uint32_t)(fs.part0 + fs.next_tile);
-                fs.next_tile++;
-                r->tiles_launched++;
-                touched = true;
-            }
-            if (fs.next_tile == fs.n_tiles) {
-                if (s.n_fins >= ctx->fin_cap) {
-                    full = true;
-                    break;
-                }
-                Fin& f = s.h_fins[s.n_fins];
-                f.fn = fs.slot;
-                f.part0 = (uint32_t)fs.part0;
-                f.n_tiles = fs.n_tiles;
-                f.res = s.n_fins;
-                s.fin_refs.push_back(FinRef{r, fi});
-                s.n_fins++;
-                r->order_pos++;
-            } else {
-                full = true;  // tile capacity reached
-                break;
-            }
-        }
-        if (touched) s.touched.push_back(r);
-        if (r->order_pos == r->order.size()) ctx->active.pop_front();
-        if (full) break;
+    // FIFO fills the launch from the oldest request; FAIR gives every active
+    // request an equal share first, so a small request never waits behind a
+    // large one for more than one launch.
+    const uint64_t n_active = ctx->active.size();
+    const uint64_t share = ctx->policy == MC_SCHED_FIFO ? UINT64_MAX
+                                                         : std::max<uint64_t>(ctx->tile_cap / n_active, 64);
+    std::deque<Request*> keep;
+    for (Request* r : ctx->active) {
+        if (has_work(r)) take_tiles(ctx, s, r, share);
+        if (has_work(r)) keep.push_back(r);
     }
+    ctx->active.swap(keep);
     if (s.n_tiles32 == 0 && s.n_tiles64 == 0 && s.n_fins == 0) return false;
 
     // Launches may be enqueued on different streams; a function's tiles can span
-    // launches, so each launch waits for the previous one.
+    // launches, so each launch waits for the previous one, and for the uploads
+    // of the function tables it reads.
     for (auto& o : ctx->slots)
         if (&o != &s && o.in_flight && o.seq == ctx->launch_seq) HIP_TRY(hipStreamWaitEvent(stream, o.ev_done, 0));
+    for (Request* r : s.touched)
+        if (r->uploaded) HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
     LaunchDesc* hd = (LaunchDesc*)s.h_desc;
     std::memset(s.h_desc, 0, kDescBytes);
     hd->fns = ctx->d_fns;
@@ -656,8 +768,10 @@ bool launch(mc_ctx* ctx, hipStream_t stream)
     hd->partials = ctx->d_partials;
     hd->fins = s.d_fins;
     hd->results = s.d_results;
-    hd->counters = (uint32_t*)((uint8_t*)s.d_desc + 128);
-    hd->abort_flag = ctx->d_abort;
+    hd->counters = (uint32_t*)((uint8_t*)s.d_desc + sizeof(LaunchDesc));
+    hd->abort_word = ctx->d_abort_word;
+    hd->n_partials = ctx->max_partials;
+    hd->n_fns = ctx->max_functions;
     hd->n_tiles32 = s.n_tiles32;
     hd->n_tiles64 = s.n_tiles64;
     hd->n_fins = s.n_fins;
@@ -677,10 +791,43 @@ bool launch(mc_ctx* ctx, hipStream_t stream)
     if (s.n_fins)
         HIP_TRY(hipMemcpyAsync(s.h_results, s.d_results, (size_t)s.n_fins * sizeof(DevResult), hipMemcpyDeviceToHost,
                                stream));
+    HIP_TRY(hipMemcpyAsync(s.h_desc + sizeof(LaunchDesc), (uint8_t*)s.d_desc + sizeof(LaunchDesc),
+                           kNumCounters * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipEventRecord(s.ev_done, stream));
     s.in_flight = true;
     s.seq = ++ctx->launch_seq;
     return true;
+}
+
+// After mc_abort: let the launches in flight drain (their kernels stop at the
+// next tile fetch), complete every request that was queued with status
+// MC_ERR_ABORTED, then clear the abort word so later work runs normally.
+void finish_abort(mc_ctx* ctx)
+{
+    reap(ctx, 2);
+    auto cancel = [&](Request* r) {
+        for (uint32_t i = 0; i < r->fns.size(); ++i) {
+            mc_result& out = r->results[i];
+            std::memset(&out, 0, sizeof out);
+            out.n = r->fns[i].n_samples;
+            out.status = MC_ERR_ABORTED;
+            out.precision = (uint32_t)r->precision;
+        }
+        r->aborted = true;
+        r->fns_done = (uint32_t)r->fns.size();
+        r->order_pos = (uint32_t)r->order.size();
+        r->redo_pos = (uint32_t)r->redo.size();
+        free_request_resources(ctx, r);
+        ctx->completed.push_back(r->id);
+    };
+    for (Request* r : ctx->active) cancel(r);
+    for (Request* r : ctx->pending) cancel(r);
+    ctx->active.clear();
+    ctx->pending.clear();
+    HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[0], sizeof(uint32_t), hipMemcpyHostToDevice,
+                           ctx->upload_stream));
+    HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
+    ctx->abort_requested = false;
 }
 
 void destroy_device(mc_ctx* ctx)
@@ -693,16 +840,18 @@ void destroy_device(mc_ctx* ctx)
             if (p) (void)hipHostFree(p);
         s = LaunchSlot{};
     }
-    if (ctx->h_abort) (void)hipHostFree(ctx->h_abort);
+    if (ctx->upload_stream) (void)hipStreamDestroy(ctx->upload_stream);
+    ctx->upload_stream = nullptr;
+    if (ctx->h_words) (void)hipHostFree(ctx->h_words);
     if (ctx->owns_memory && ctx->mem_base) (void)hipFree(ctx->mem_base);
-    ctx->h_abort = nullptr;
+    ctx->h_words = nullptr;
     ctx->mem_base = nullptr;
 }
 
 void default_tuning(mc_ctx* ctx)
 {
     for (int p = 0; p < 2; ++p)
-        for (int f = 0; f < 5; ++f)
+        for (int f = 0; f < kNumFamilies; ++f)
             for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = 0;
 }
 
@@ -739,7 +888,10 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
     ctx->cfg = cfg;
     ctx->validate_only = (cfg.flags & MC_VALIDATE_ONLY) != 0;
     ctx->use_graph = (cfg.flags & MC_NO_GRAPH) == 0;
+    ctx->promote = (cfg.flags & MC_NO_PROMOTE) == 0;
     ctx->device = cfg.device;
+    if (cfg.policy > MC_SCHED_FIFO) return fail(nullptr, MC_ERR_INVALID_ARG, "unknown policy %u", cfg.policy);
+    ctx->policy = cfg.policy;
     default_tuning(ctx.get());
     resolve_capacities(cfg, &ctx->max_functions, &ctx->max_partials, &ctx->tile_cap, &ctx->fin_cap);
     ctx->fn_alloc.reset(ctx->max_functions);
@@ -802,9 +954,14 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             HIP_TRY(hipEventCreate(&s.ev_end));
             HIP_TRY(hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
         }
-        HIP_TRY(hipHostMalloc((void**)&ctx->h_abort, 64, hipHostMallocMapped | hipHostMallocCoherent));
-        *ctx->h_abort = 0u;
-        HIP_TRY(hipHostGetDevicePointer((void**)&ctx->d_abort, ctx->h_abort, 0));
+        HIP_TRY(hipStreamCreateWithFlags(&ctx->upload_stream, hipStreamNonBlocking));
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault));
+        ctx->h_words[0] = 0u;
+        ctx->h_words[1] = 1u;
+        ctx->d_abort_word = (uint32_t*)(base + L.abort_word);
+        HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[0], sizeof(uint32_t), hipMemcpyHostToDevice,
+                               ctx->upload_stream));
+        HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
     } catch (const HipError& e) {
         mc_status st = fail_hip(nullptr, e);
         destroy_device(ctx.get());
@@ -867,6 +1024,7 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
         fs.seg_log2 = L;
         fs.n_tiles = tiles_for(d.n_segments, L);
         fs.next_tile = 0;
+        fs.f64 = precision == MC_PREC_FP64;
         fs.tile_cost = sample_cost(d.family, d.dim, precision) *
                        (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
         parts += fs.n_tiles;
@@ -884,7 +1042,15 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     *out_request_id = r->id;
     Request* rp = r.get();
     ctx->requests.emplace(rp->id, std::move(r));
-    if (!ctx->validate_only) ctx->pending.push_back(rp);
+    if (!ctx->validate_only) {
+        ctx->pending.push_back(rp);
+        try {
+            HIP_TRY(hipSetDevice(ctx->device));
+            admit(ctx);
+        } catch (const HipError& e) {
+            return fail_hip(ctx, e);
+        }
+    }
     return MC_OK;
 }
 
@@ -892,28 +1058,34 @@ mc_status mc_run(mc_ctx* ctx, void* stream)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    bool no_slot = false;
     try {
         HIP_TRY(hipSetDevice(ctx->device));
         hipStream_t s = (hipStream_t)stream;
-        reap(ctx, false);
-        admit(ctx, s);
-        if (ctx->active.empty() && !ctx->pending.empty()) {
-            // everything admitted has been launched; wait for a launch to free space
-            bool any = false;
-            for (auto& sl : ctx->slots) any = any || sl.in_flight;
-            if (any) {
-                reap(ctx, true);
-                admit(ctx, s);
-            }
-        }
-        launch(ctx, s);
-        if (ctx->h_abort && *ctx->h_abort) {
-            bool any = false;
-            for (auto& sl : ctx->slots) any = any || sl.in_flight;
-            if (!any && ctx->active.empty() && ctx->pending.empty()) *ctx->h_abort = 0u;
-        }
+        reap(ctx, 0);
+        if (ctx->abort_requested) finish_abort(ctx);
+        admit(ctx);
+        launch(ctx, s, &no_slot);
     } catch (const HipError& e) {
         return fail_hip(ctx, e);
+    }
+    return no_slot ? MC_NOT_READY : MC_OK;
+}
+
+mc_status mc_poll(mc_ctx* ctx, uint64_t* completed, size_t cap, size_t* n)
+{
+    if (!ctx || !n || (cap > 0 && !completed)) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    *n = 0;
+    if (ctx->validate_only) return MC_OK;
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        reap(ctx, 0);
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    while (*n < cap && !ctx->completed.empty()) {
+        completed[(*n)++] = ctx->completed.front();
+        ctx->completed.pop_front();
     }
     return MC_OK;
 }
@@ -945,14 +1117,15 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
     if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
     try {
         HIP_TRY(hipSetDevice(ctx->device));
-        reap(ctx, false);
+        reap(ctx, 0);
         while (r->fns_done < r->fns.size()) {
             if (!blocking) return MC_NOT_READY;
             if (r->tiles_launched < r->tiles_total || !r->admitted) {
                 mc_status st = mc_run(ctx, nullptr);
-                if (st != MC_OK) return st;
+                if (st == MC_NOT_READY) reap(ctx, 1);  // all slots busy: wait for the oldest launch
+                else if (st != MC_OK) return st;
             } else {
-                reap(ctx, true);
+                reap(ctx, 1);
             }
         }
     } catch (const HipError& e) {
@@ -967,7 +1140,17 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
 mc_status mc_abort(mc_ctx* ctx)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
-    if (ctx->h_abort) *ctx->h_abort = 1u;
+    if (ctx->validate_only) return MC_OK;
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        // The upload stream is non-blocking, so the word changes while kernels run.
+        HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[1], sizeof(uint32_t), hipMemcpyHostToDevice,
+                               ctx->upload_stream));
+        HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
+        ctx->abort_requested = true;
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
     return MC_OK;
 }
 
@@ -1002,7 +1185,7 @@ mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n,
             const DevFn* f = d_fns + i;
             const uint32_t blocks = (uint32_t)((packed[i].n_quads + 255) / 256);
             void* a1[] = {&f, &d_parts};
-            HIP_TRY(hipLaunchKernel(plain_kernel_ptr(packed[i].family, packed[i].dim), dim3(blocks), dim3(256), a1, 0, s));
+            HIP_TRY(hipLaunchKernel(plain_kernel_ptr(), dim3(blocks), dim3(256), a1, 0, s));
             DevResult* r = d_res + i;
             void* a2[] = {&f, &d_parts, (void*)&blocks, &r};
             HIP_TRY(hipLaunchKernel(plain_reduce_kernel_ptr(), dim3(1), dim3(256), a2, 0, s));
@@ -1038,10 +1221,7 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
             if (seg_log2[i] > kMaxSegLog2) return fail(ctx, MC_ERR_INVALID_ARG, "seg_log2 entry %d > %d", i, kMaxSegLog2);
         for (int p = 0; p < 2; ++p)
             for (int f = 0; f < 4; ++f)
-                for (int d = 0; d < kMaxDim; ++d) {
-                    ctx->seg_log2[p][f][d] = seg_log2[(p * 4 + f) * kMaxDim + d];
-                    if (f == 3) ctx->seg_log2[p][4][d] = ctx->seg_log2[p][3][d];
-                }
+                for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = seg_log2[(p * 4 + f) * kMaxDim + d];
     }
     if (blocks_per_cu) {
         ctx->blocks_per_cu32 = blocks_per_cu;
@@ -1054,7 +1234,7 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
             }
         }
         try {
-            reap(ctx, true);
+            reap(ctx, 2);
         } catch (const HipError& e) {
             return fail_hip(ctx, e);
         }
@@ -1095,7 +1275,7 @@ static double time_batch(mc_ctx* ctx, const std::vector<mc_function>& fns, int32
     Request* r = it->second.get();
     for (int guard = 0; guard < 64 && r->fns_done < r->fns.size(); ++guard) {
         if (mc_run(ctx, stream) != MC_OK) return -1.0;
-        reap(ctx, true);
+        reap(ctx, 2);
         total += ctx->last_main_ms;
     }
     std::vector<mc_result> out(fns.size());
@@ -1136,14 +1316,14 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
     }
     // 2) segments per wave per tile, per (family, dim)
     const uint32_t dims[] = {1, 2, 3, 4, 6, 8, 12};
-    const int nfam = p == 0 ? 5 : 4;
+    const int nfam = kNumFamilies;
     for (int fam = 0; fam < nfam && elapsed() < budget_seconds; ++fam) {
         for (uint32_t di = 0; di < sizeof(dims) / sizeof(dims[0]) && elapsed() < budget_seconds; ++di) {
             const uint32_t dim = dims[di];
             std::vector<mc_function> fns;
-            const uint32_t family = fam == 4 ? (uint32_t)MC_FAMILY_POLY_PRODUCT : (uint32_t)fam;
+            const uint32_t family = (uint32_t)fam;
             const uint64_t n = (uint64_t)(4u << 20) / dim;
-            for (uint32_t i = 0; i < n_fns; ++i) fns.push_back(tune_function(family, dim, n, i, fam == 4));
+            for (uint32_t i = 0; i < n_fns; ++i) fns.push_back(tune_function(family, dim, n, i, false));
             int best_l = 0;
             double best_t = 1e30;
             for (int l = 0; l <= 3; ++l) {
@@ -1168,6 +1348,13 @@ mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms)
     if (!ctx->have_timing) return fail(ctx, MC_NOT_READY, "no completed run yet");
     if (main_ms) *main_ms = ctx->last_main_ms;
     if (finalize_ms) *finalize_ms = ctx->last_fin_ms;
+    return MC_OK;
+}
+
+mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out)
+{
+    if (!ctx || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    *out = ctx->stats;
     return MC_OK;
 }
 

@@ -1,8 +1,7 @@
 // zmc_kernels.hip -- gfx950 kernels of the multi-function direct Monte Carlo path.
 //
 // Per sample (paper, "Solution method": direct Monte Carlo per integrand):
-//   1. counter-based uniforms: Philox4x32-10 (SC'11) in registers, coordinate j of
-//      sample i reads word g = i*d + j of the function's stream;
+//   1. counter-based uniforms: Philox4x32-10 (SC'11) in registers;
 //   2. mapping into the function's box;
 //   3. the integrand (Eq. (1) harmonic, Eq. (2) |linear|, Gaussian, product polynomial);
 //   4. compensated per-lane sums of f and f^2;
@@ -10,6 +9,13 @@
 // its segments, and per function an atomic-free FP64 finalize pass giving the
 // mean and standard error.  No MFMA: nothing here is a dense contraction; the
 // bound is VALU issue (integer multiplies of Philox, FP32 FMAs, transcendentals).
+//
+// Sample layout.  Samples are handled four at a time (a quad): quad q of a
+// d-dimensional function uses Philox blocks q*d .. q*d + d - 1, and block
+// q*d + j holds coordinate j of the quad's four samples, one per output word.
+// So one lane evaluates a quad with a loop over the coordinates that produces
+// one block and folds its four words into four sample states: the dimension is
+// a runtime loop bound and a single code path serves d = 1..12.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -34,7 +40,7 @@ __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 // third round on every round is two 32x32->64 products and two 3-input xors.
 // Round keys are wave-uniform and stay in scalar registers.
 __device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint32_t k0, uint32_t k1,
-                                             uint32_t* out)
+                                             uint32_t out[4])
 {
     uint32_t c0, c1, c2, c3;
     {   // round 1: c2 = c3 = 0
@@ -75,6 +81,18 @@ __device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint3
     out[3] = c3;
 }
 
+// ---------------------------------------------------------------- function records
+
+// Function records are read-only while kernels run.  Reading them through the
+// constant address space turns every wave-uniform field access into a scalar
+// load (scalar cache, scalar registers) instead of 64 identical vector loads.
+typedef const __attribute__((address_space(4))) DevFn CDevFn;
+
+__device__ __forceinline__ CDevFn* scalar_view(const DevFn* p)
+{
+    return (CDevFn*)(uintptr_t)p;
+}
+
 // ---------------------------------------------------------------- uniforms
 
 // t = 1 + m 2^-23 in [1, 2) from the low 23 bits m of a word: one VALU op.
@@ -94,29 +112,30 @@ __device__ __forceinline__ double word_to_u64(uint32_t r)
 
 // ---------------------------------------------------------------- FP32 integrands
 
-// Evaluators work incrementally so a quad's Philox words are consumed as soon
-// as their block is produced: init() gives the per-sample state, add(st, j, w)
-// folds coordinate j (from word w) into it, finish(st) returns g with
-// f = scale1 * g (scale1 and scale2 = scale1^2 are applied in FP64 at
-// finalize).  Constants are wave-uniform, loaded once per tile, and were
-// derived on the host in FP64 and rounded once.
+// An evaluator holds a function (wave-uniform pointer) and works on the four
+// samples of a quad: init() sets their states, add(st, j, w) folds coordinate j
+// from the block's four words, finish() returns g with f = scale1 * g (scale1
+// and scale2 = scale1^2 are applied in FP64 at finalize).  Coefficients were
+// derived on the host in FP64 and rounded once; they are read with scalar loads.
 
-template <int FAM, int D> struct Eval32;
+template <int FAM> struct Eval32;
 
 // Eq. (1): a cos(theta) + b sin(theta) = R cos(theta - phi).  The phase in
 // revolutions is f0 + sum_j kappa_j t_j; v_fract + v_cos_f32 (which computes
 // cos(2 pi x)) give the cosine: one transcendental per sample.
-template <int D> struct Eval32<HARMONIC, D> {
-    float c[D];
-    float f0;
-    __device__ __forceinline__ void load(const DevFn* fn)
+template <> struct Eval32<HARMONIC> {
+    CDevFn* fn;
+    __device__ __forceinline__ void init(float st[4]) const
     {
-#pragma unroll
-        for (int j = 0; j < D; ++j) c[j] = fn->fc[j];
-        f0 = fn->f0;
+        const float f0 = fn->f0;
+        for (int s = 0; s < 4; ++s) st[s] = f0;
     }
-    __device__ __forceinline__ float init() const { return f0; }
-    __device__ __forceinline__ void add(float& th, int j, uint32_t w) const { th = fmaf(c[j], word_to_t(w), th); }
+    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
+    {
+        const float c = fn->fc[j];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), st[s]);
+    }
     __device__ __forceinline__ float finish(float th) const
     {
         return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(th));
@@ -125,119 +144,106 @@ template <int D> struct Eval32<HARMONIC, D> {
 
 // Eq. (2): a |c0 + c.x|; the offset is carried as a two-float sum so the
 // hyperplane is placed to FP64 accuracy.
-template <int D> struct Eval32<ABS_LINEAR, D> {
-    float c[D];
-    float f0, f0lo;
-    __device__ __forceinline__ void load(const DevFn* fn)
+template <> struct Eval32<ABS_LINEAR> {
+    CDevFn* fn;
+    __device__ __forceinline__ void init(float st[4]) const
     {
-#pragma unroll
-        for (int j = 0; j < D; ++j) c[j] = fn->fc[j];
-        f0 = fn->f0;
-        f0lo = fn->f0lo;
+        const float f0 = fn->f0;
+        for (int s = 0; s < 4; ++s) st[s] = f0;
     }
-    __device__ __forceinline__ float init() const { return f0; }
-    __device__ __forceinline__ void add(float& s, int j, uint32_t w) const { s = fmaf(c[j], word_to_t(w), s); }
-    __device__ __forceinline__ float finish(float s) const { return fabsf(s + f0lo); }
+    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
+    {
+        const float c = fn->fc[j];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), st[s]);
+    }
+    __device__ __forceinline__ float finish(float st) const { return fabsf(st + fn->f0lo); }
 };
 
 // A exp(-|x - mu|^2 / (2 sigma^2)) = A 2^(-sum_j (c_j (t_j - m_j))^2); t - m is
 // exact (both in [1, 2] for a centre inside the box), v_exp_f32 computes 2^x.
-template <int D> struct Eval32<GAUSSIAN, D> {
-    float c[D], m[D];
-    __device__ __forceinline__ void load(const DevFn* fn)
+template <> struct Eval32<GAUSSIAN> {
+    CDevFn* fn;
+    __device__ __forceinline__ void init(float st[4]) const
     {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            c[j] = fn->fc[j];
-            m[j] = fn->fo[j];
-        }
+        for (int s = 0; s < 4; ++s) st[s] = 0.0f;
     }
-    __device__ __forceinline__ float init() const { return 0.0f; }
-    __device__ __forceinline__ void add(float& q, int j, uint32_t w) const
+    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
-        const float y = c[j] * (word_to_t(w) - m[j]);
-        q = fmaf(y, y, q);
+        const float c = fn->fc[j], m = fn->fo[j];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float y = c * (word_to_t(w[s]) - m);
+            st[s] = fmaf(y, y, st[s]);
+        }
     }
     __device__ __forceinline__ float finish(float q) const { return __builtin_amdgcn_exp2f(-q); }
 };
 
-// prod_j (1 + p_j x_j^{n_j}), x_j = lo_j + w_j u_j with u_j = t_j - (1 - 2^-24) exact.
-// Each factor is a degree-MAXDEG polynomial in x_j whose only non-zero
-// coefficients are the constant 1 and p_j at power n_j (the constant is 1 + p_j
-// when n_j = 0); Horner's rule evaluates it without branches.
-template <int D, int MAXDEG> struct Eval32Poly {
-    float c[D], o[D];
-    float h[D][MAXDEG];   // h[j][k]: coefficient of x^(k+1)
-    float h0[D];          // constant term
-    __device__ __forceinline__ void load(const DevFn* fn)
+// prod_j (1 + p_j x_j^{n_j}), x_j = lo_j + w_j u_j with u_j = t_j - (1 - 2^-24)
+// exact; the power is a wave-uniform loop shared by the quad's four samples.
+template <> struct Eval32<POLY_PRODUCT> {
+    CDevFn* fn;
+    __device__ __forceinline__ void init(float st[4]) const
     {
-#pragma unroll
-        for (int j = 0; j < D; ++j) {
-            c[j] = fn->fc[j];
-            o[j] = fn->fo[j];
-            const int n = fn->deg[j];
-            const float pj = fn->fp[j];
-#pragma unroll
-            for (int k = 0; k < MAXDEG; ++k) h[j][k] = (n == k + 1) ? pj : 0.0f;
-            h0[j] = (n == 0) ? 1.0f + pj : 1.0f;
-        }
+        for (int s = 0; s < 4; ++s) st[s] = 1.0f;
     }
-    __device__ __forceinline__ float init() const { return 1.0f; }
-    __device__ __forceinline__ void add(float& g, int j, uint32_t w) const
+    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
-        const float x = fmaf(c[j], word_to_t(w) - kTShift, o[j]);
-        float acc = h[j][MAXDEG - 1];
+        const float c = fn->fc[j], o = fn->fo[j], p = fn->fp[j];
+        const int e = fn->deg[j];
+        float x[4], xp[4];
 #pragma unroll
-        for (int k = MAXDEG - 2; k >= 0; --k) acc = fmaf(acc, x, h[j][k]);
-        g *= fmaf(acc, x, h0[j]);
+        for (int s = 0; s < 4; ++s) {
+            x[s] = fmaf(c, word_to_t(w[s]) - kTShift, o);
+            xp[s] = 1.0f;
+        }
+        for (int k = 0; k < e; ++k) {
+#pragma unroll
+            for (int s = 0; s < 4; ++s) xp[s] *= x[s];
+        }
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] *= fmaf(p, xp[s], 1.0f);
     }
     __device__ __forceinline__ float finish(float g) const { return g; }
 };
 
-template <int D> struct Eval32<POLY_PRODUCT, D> : Eval32Poly<D, 4> {};
-// Degrees 5..8 use the same evaluator with eight Horner steps (family id 4 inside the kernels).
-constexpr int kPolyHighFamily = 4;
-template <int D> struct Eval32<kPolyHighFamily, D> : Eval32Poly<D, 8> {};
-
 // ---------------------------------------------------------------- FP64 integrands
 
 // The definition in its reference operation order (explicit fma), FP64 libm.
-template <int FAM, int D> struct Eval64 {
-    double lo[D], w[D], v[D];
-    double s0, s1, h;
-    int n[D];
-    __device__ __forceinline__ void load(const DevFn* fn)
+template <int FAM> struct Eval64 {
+    CDevFn* fn;
+    __device__ __forceinline__ void init(double st[4]) const
     {
+        double v = 0.0;
+        if constexpr (FAM == ABS_LINEAR) v = fn->s1;
+        if constexpr (FAM == POLY_PRODUCT) v = 1.0;
+        for (int s = 0; s < 4; ++s) st[s] = v;
+    }
+    __device__ __forceinline__ void add(double st[4], uint32_t j, const uint32_t w[4]) const
+    {
+        const double lo = fn->lo[j], wd = fn->w[j], v = fn->v[j];
+        double x[4];
 #pragma unroll
-        for (int j = 0; j < D; ++j) {
-            lo[j] = fn->lo[j];
-            w[j] = fn->w[j];
-            v[j] = fn->v[j];
-            n[j] = fn->deg[j];
-        }
-        s0 = fn->s0;
-        s1 = fn->s1;
-        h = fn->h;
-    }
-    __device__ __forceinline__ double init() const
-    {
-        if constexpr (FAM == ABS_LINEAR) return s1;
-        else if constexpr (FAM == POLY_PRODUCT) return 1.0;
-        else return 0.0;
-    }
-    __device__ __forceinline__ void add(double& st, int j, uint32_t wd) const
-    {
-        const double x = fma(w[j], word_to_u64(wd), lo[j]);
+        for (int s = 0; s < 4; ++s) x[s] = fma(wd, word_to_u64(w[s]), lo);
         if constexpr (FAM == HARMONIC || FAM == ABS_LINEAR) {
-            st = fma(v[j], x, st);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) st[s] = fma(v, x[s], st[s]);
         } else if constexpr (FAM == GAUSSIAN) {
-            const double t = x - v[j];
-            st = fma(t, t, st);
+#pragma unroll
+            for (int s = 0; s < 4; ++s) {
+                const double t = x[s] - v;
+                st[s] = fma(t, t, st[s]);
+            }
         } else {
-            double xp = 1.0;
-            const int e = n[j];
-            for (int k = 0; k < e; ++k) xp *= x;
-            st *= fma(v[j], xp, 1.0);
+            const int e = fn->deg[j];
+            double xp[4] = {1.0, 1.0, 1.0, 1.0};
+            for (int k = 0; k < e; ++k) {
+#pragma unroll
+                for (int s = 0; s < 4; ++s) xp[s] *= x[s];
+            }
+#pragma unroll
+            for (int s = 0; s < 4; ++s) st[s] *= fma(v, xp[s], 1.0);
         }
     }
     __device__ __forceinline__ double finish(double st) const
@@ -245,42 +251,30 @@ template <int FAM, int D> struct Eval64 {
         if constexpr (FAM == HARMONIC) {
             double sn, cs;
             sincos(st, &sn, &cs);
-            return fma(s0, cs, s1 * sn);
+            return fma(fn->s0, cs, fn->s1 * sn);
         } else if constexpr (FAM == ABS_LINEAR) {
-            return s0 * fabs(st);
+            return fn->s0 * fabs(st);
         } else if constexpr (FAM == GAUSSIAN) {
-            return s0 * exp(-st * h);
+            return fn->s0 * exp(-st * fn->h);
         } else {
             return st;
         }
     }
 };
 
-// One quad (4 consecutive samples, quad index q): the d Philox blocks q*d .. q*d+d-1
-// hold the 4d words in sample-major order; each block's words are folded into
-// the states of the samples they belong to as soon as it is produced.
-constexpr int kIlpBlocks = 2;
-
-template <class Ev, int D, class T>
-__device__ __forceinline__ void eval_quad(const Ev& ev, uint32_t k0, uint32_t k1, uint64_t q, T g[4])
+// One quad q of samples: d Philox blocks q*d .. q*d + d - 1, block j giving
+// coordinate j of the four samples.
+template <class Ev, class T>
+__device__ __forceinline__ void eval_quad(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, T g[4])
 {
     T st[4];
-#pragma unroll
-    for (int s = 0; s < 4; ++s) st[s] = ev.init();
-    const uint64_t b0 = q * (uint64_t)D;
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-        const uint64_t b = b0 + (uint64_t)i;
+    ev.init(st);
+    const uint64_t b0 = q * (uint64_t)d;
+    for (uint32_t j = 0; j < d; ++j) {
+        const uint64_t b = b0 + j;
         uint32_t w[4];
         philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-            const int gi = 4 * i + e;   // word index inside the quad: sample gi / D, coordinate gi % D
-            ev.add(st[gi / D], gi % D, w[e]);
-        }
-        // Keep at most kIlpBlocks blocks in flight: enough independent work per wave
-        // to cover latencies, few enough registers for several waves per SIMD.
-        if ((i % kIlpBlocks) == kIlpBlocks - 1) __builtin_amdgcn_sched_barrier(0);
+        ev.add(st, j, w);
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s) g[s] = ev.finish(st[s]);
@@ -307,20 +301,21 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
 
 // ---------------------------------------------------------------- one segment
 
-// Lane sums over the lane's 16 quads of one segment.  TAIL marks the function's
-// last segment, the only one that can hold quads or samples past N.
-template <int FAM, int D, bool TAIL>
-__device__ __forceinline__ void segment_fp32(const Eval32<FAM, D>& ev, uint32_t k0, uint32_t k1, uint64_t quad0,
-                                             uint64_t n_quads, uint64_t n_samples, double& out1, double& out2)
+// Lane sums over the lane's 16 quads of one segment.  `tail` marks the
+// function's last segment, the only one that can hold quads or samples past N.
+template <int FAM>
+__device__ __forceinline__ void segment_fp32(const Eval32<FAM>& ev, uint32_t d, uint32_t k0, uint32_t k1,
+                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
+                                             double& out1, double& out2)
 {
     float s1 = 0.0f, c1 = 0.0f, s2 = 0.0f, c2 = 0.0f;
 #pragma unroll 1
     for (int k = 0; k < kQuadsPerLane; ++k) {
         const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (TAIL && q >= n_quads) break;
+        if (tail && q >= n_quads) break;
         float g[4];
-        eval_quad<Eval32<FAM, D>, D, float>(ev, k0, k1, q, g);
-        if (TAIL) {
+        eval_quad(ev, d, k0, k1, q, g);
+        if (tail) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 if (4 * q + (uint64_t)s >= n_samples) g[s] = 0.0f;
@@ -334,18 +329,19 @@ __device__ __forceinline__ void segment_fp32(const Eval32<FAM, D>& ev, uint32_t 
     out2 = (double)s2 - (double)c2;
 }
 
-template <int FAM, int D, bool TAIL>
-__device__ __forceinline__ void segment_fp64(const Eval64<FAM, D>& ev, uint32_t k0, uint32_t k1, uint64_t quad0,
-                                             uint64_t n_quads, uint64_t n_samples, double& out1, double& out2)
+template <int FAM>
+__device__ __forceinline__ void segment_fp64(const Eval64<FAM>& ev, uint32_t d, uint32_t k0, uint32_t k1,
+                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
+                                             double& out1, double& out2)
 {
     double s1 = 0.0, s2 = 0.0;
 #pragma unroll 1
     for (int k = 0; k < kQuadsPerLane; ++k) {
         const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (TAIL && q >= n_quads) break;
+        if (tail && q >= n_quads) break;
         double f[4];
-        eval_quad<Eval64<FAM, D>, D, double>(ev, k0, k1, q, f);
-        if (TAIL) {
+        eval_quad(ev, d, k0, k1, q, f);
+        if (tail) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 if (4 * q + (uint64_t)s >= n_samples) f[s] = 0.0;
@@ -361,78 +357,35 @@ __device__ __forceinline__ void segment_fp64(const Eval64<FAM, D>& ev, uint32_t 
 
 // Wave `wave` of the workgroup evaluates segments seg0 + wave*2^L + i, i < 2^L,
 // and leaves each segment's (S1, S2) in LDS slot wave*2^L + i (zero past the
-// function's last segment).
-template <bool F64, int FAM, int D>
-__device__ __forceinline__ void tile_segments(const DevFn* __restrict__ fn, uint32_t seg0, uint32_t seg_log2,
-                                           uint32_t wave, uint32_t lane, Partial* s_seg)
+// function's last segment).  All arguments are wave-uniform.
+template <bool F64, int FAM>
+__device__ __forceinline__ void tile_segments(CDevFn* fn, uint32_t seg0, uint32_t seg_log2, uint32_t wave,
+                                              uint32_t lane, Partial* s_seg)
 {
-    // Everything here is wave-uniform; say so, so the function's constants are
-    // fetched with scalar loads and stay in scalar registers.
-    fn = (const DevFn*)(((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(uintptr_t)fn)) |
-                        ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)((uintptr_t)fn >> 32)) << 32));
-    seg0 = __builtin_amdgcn_readfirstlane(seg0);
-    seg_log2 = __builtin_amdgcn_readfirstlane(seg_log2);
-    wave = __builtin_amdgcn_readfirstlane(wave);
     const uint32_t per_wave = 1u << seg_log2;
     const uint32_t n_seg = fn->n_segments;
     const uint64_t n_quads = fn->n_quads;
     const uint64_t n_samples = fn->n_samples;
+    const uint32_t d = fn->dim;
     const uint32_t k0 = fn->key0, k1 = fn->key1;
     const uint32_t first = seg0 + wave * per_wave;
-    if constexpr (F64) {
-        Eval64<FAM, D> ev;
-        ev.load(fn);
-        for (uint32_t i = 0; i < per_wave; ++i) {
-            const uint32_t seg = first + i;
-            double a = 0.0, b = 0.0;
-            if (seg < n_seg) {
-                const uint64_t quad0 = (uint64_t)seg * kSegQuads + lane;
-                if ((uint64_t)(seg + 1) * kSegSamples <= n_samples)
-                    segment_fp64<FAM, D, false>(ev, k0, k1, quad0, n_quads, n_samples, a, b);
-                else
-                    segment_fp64<FAM, D, true>(ev, k0, k1, quad0, n_quads, n_samples, a, b);
-                a = wave_sum(a);
-                b = wave_sum(b);
+    for (uint32_t i = 0; i < per_wave; ++i) {
+        const uint32_t seg = first + i;
+        double a = 0.0, b = 0.0;
+        if (seg < n_seg) {
+            const uint64_t quad0 = (uint64_t)seg * kSegQuads + lane;
+            const bool tail = (uint64_t)(seg + 1) * kSegSamples > n_samples;
+            if constexpr (F64) {
+                const Eval64<FAM> ev{fn};
+                segment_fp64<FAM>(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
+            } else {
+                const Eval32<FAM> ev{fn};
+                segment_fp32<FAM>(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
             }
-            if (lane == 0) s_seg[wave * per_wave + i] = Partial{a, b};
+            a = wave_sum(a);
+            b = wave_sum(b);
         }
-    } else {
-        Eval32<FAM, D> ev;
-        ev.load(fn);
-        for (uint32_t i = 0; i < per_wave; ++i) {
-            const uint32_t seg = first + i;
-            double a = 0.0, b = 0.0;
-            if (seg < n_seg) {
-                const uint64_t quad0 = (uint64_t)seg * kSegQuads + lane;
-                if ((uint64_t)(seg + 1) * kSegSamples <= n_samples)
-                    segment_fp32<FAM, D, false>(ev, k0, k1, quad0, n_quads, n_samples, a, b);
-                else
-                    segment_fp32<FAM, D, true>(ev, k0, k1, quad0, n_quads, n_samples, a, b);
-                a = wave_sum(a);
-                b = wave_sum(b);
-            }
-            if (lane == 0) s_seg[wave * per_wave + i] = Partial{a, b};
-        }
-    }
-}
-
-template <bool F64, int FAM>
-__device__ __forceinline__ void dispatch_dim(uint32_t dim, const DevFn* fn, uint32_t seg0, uint32_t seg_log2,
-                                             uint32_t wave, uint32_t lane, Partial* s_seg)
-{
-    switch (dim) {
-    case 1: tile_segments<F64, FAM, 1>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 2: tile_segments<F64, FAM, 2>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 3: tile_segments<F64, FAM, 3>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 4: tile_segments<F64, FAM, 4>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 5: tile_segments<F64, FAM, 5>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 6: tile_segments<F64, FAM, 6>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 7: tile_segments<F64, FAM, 7>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 8: tile_segments<F64, FAM, 8>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 9: tile_segments<F64, FAM, 9>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 10: tile_segments<F64, FAM, 10>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    case 11: tile_segments<F64, FAM, 11>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-    default: tile_segments<F64, FAM, 12>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        if (lane == 0) s_seg[wave * per_wave + i] = Partial{a, b};
     }
 }
 
@@ -463,26 +416,31 @@ __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, 
 // ---------------------------------------------------------------- kernels
 
 // Persistent batched kernel: every workgroup fetches tiles from the launch's
-// tile list through one counter until the list is exhausted (or the host-mapped
-// abort word is set), evaluates them, and writes one partial per tile.
+// tile list through one counter until the list is exhausted (or the abort word
+// in device memory is set), evaluates them, and writes one partial per tile.
+// Indices read from the lists are checked against the launch's bounds; a bad
+// record is skipped and counted instead of being dereferenced.
 template <bool F64>
 __device__ __forceinline__ void batched_body(const LaunchDesc* __restrict__ Ld)
 {
     __shared__ Partial s_seg[kBlockWaves << kMaxSegLog2];
     __shared__ uint32_t s_tile;
-    const DevFn* __restrict__ fns = Ld->fns;
-    const Tile* __restrict__ tiles = F64 ? Ld->tiles64 : Ld->tiles32;
+    const DevFn* fns = Ld->fns;
+    const Tile* tiles = F64 ? Ld->tiles64 : Ld->tiles32;
     const uint32_t n_tiles = F64 ? Ld->n_tiles64 : Ld->n_tiles32;
+    const uint32_t n_fns = Ld->n_fns;
+    const uint64_t n_partials = Ld->n_partials;
     uint32_t* counters = Ld->counters;
+    const uint32_t* abort_word = Ld->abort_word;
     Partial* partials = Ld->partials;
-    const volatile uint32_t* abort_flag = Ld->abort_flag;
     const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = threadIdx.x / kWave;
+    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     for (uint32_t iter = 0;; ++iter) {
         if (threadIdx.x == 0) {
-            uint32_t ti = atomicAdd(&counters[F64 ? 1 : 0], 1u);
-            if (abort_flag != nullptr && (iter & 7u) == 0u && *abort_flag != 0u) {
-                atomicOr(&counters[2], 1u);
+            uint32_t ti = atomicAdd(&counters[F64 ? kCounterTiles64 : kCounterTiles32], 1u);
+            if ((iter & 7u) == 0u &&
+                __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
+                atomicOr(&counters[kCounterAborted], 1u);
                 ti = n_tiles;
             }
             s_tile = ti;
@@ -494,30 +452,33 @@ __device__ __forceinline__ void batched_body(const LaunchDesc* __restrict__ Ld)
         const uint32_t fi = __builtin_amdgcn_readfirstlane(t.fn);
         const uint32_t seg0 = __builtin_amdgcn_readfirstlane(t.seg0);
         const uint32_t seg_log2 = __builtin_amdgcn_readfirstlane(t.seg_log2);
-        const DevFn* fn = fns + fi;
-        const uint32_t fam = __builtin_amdgcn_readfirstlane(fn->kfam);
-        const uint32_t dim = __builtin_amdgcn_readfirstlane(fn->dim);
-        switch (fam) {
-        case HARMONIC: dispatch_dim<F64, HARMONIC>(dim, fn, seg0, seg_log2, wave, lane, s_seg); break;
-        case ABS_LINEAR: dispatch_dim<F64, ABS_LINEAR>(dim, fn, seg0, seg_log2, wave, lane, s_seg); break;
-        case GAUSSIAN: dispatch_dim<F64, GAUSSIAN>(dim, fn, seg0, seg_log2, wave, lane, s_seg); break;
-        case POLY_PRODUCT: dispatch_dim<F64, POLY_PRODUCT>(dim, fn, seg0, seg_log2, wave, lane, s_seg); break;
-        default:
-            if constexpr (F64) dispatch_dim<F64, POLY_PRODUCT>(dim, fn, seg0, seg_log2, wave, lane, s_seg);
-            else dispatch_dim<F64, kPolyHighFamily>(dim, fn, seg0, seg_log2, wave, lane, s_seg);
-            break;
+        const uint32_t out = __builtin_amdgcn_readfirstlane(t.out);
+        bool ok = fi < n_fns && seg_log2 <= (uint32_t)kMaxSegLog2 && out < n_partials;
+        CDevFn* fn = scalar_view(fns + (ok ? fi : 0u));
+        const uint32_t fam = fn->kfam;
+        const uint32_t dim = fn->dim;
+        ok = ok && dim >= 1 && dim <= (uint32_t)kMaxDim && fam <= (uint32_t)POLY_PRODUCT;
+        if (ok) {
+            switch (fam) {
+            case HARMONIC: tile_segments<F64, HARMONIC>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+            case ABS_LINEAR: tile_segments<F64, ABS_LINEAR>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+            case GAUSSIAN: tile_segments<F64, GAUSSIAN>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+            default: tile_segments<F64, POLY_PRODUCT>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+            }
+        } else if (threadIdx.x == 0) {
+            atomicAdd(&counters[kCounterBadRecords], 1u);
         }
         __syncthreads();
-        if (wave == 0) tile_tree(s_seg, (uint32_t)kBlockWaves << seg_log2, lane, &partials[t.out]);
+        if (ok && wave == 0) tile_tree(s_seg, (uint32_t)kBlockWaves << seg_log2, lane, &partials[out]);
     }
 }
 
-extern "C" __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) void zmc_batched_fp32(const LaunchDesc* __restrict__ Ld)
+extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp32(const LaunchDesc* __restrict__ Ld)
 {
     batched_body<false>(Ld);
 }
 
-extern "C" __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_waves_per_eu(2, 8))) void zmc_batched_fp64(const LaunchDesc* __restrict__ Ld)
+extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(const LaunchDesc* __restrict__ Ld)
 {
     batched_body<true>(Ld);
 }
@@ -527,18 +488,27 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) __attribute__((amdgpu_wav
 // is the pairwise tree over tile index; then mean and standard error in FP64.
 extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const LaunchDesc* __restrict__ Ld)
 {
-    const DevFn* __restrict__ fns = Ld->fns;
-    const Fin* __restrict__ fins = Ld->fins;
+    const DevFn* fns = Ld->fns;
+    const Fin* fins = Ld->fins;
     Partial* partials = Ld->partials;
     DevResult* results = Ld->results;
     const uint32_t n_fins = Ld->n_fins;
-    const bool aborted = __builtin_amdgcn_readfirstlane(((volatile uint32_t*)Ld->counters)[2]) != 0u;
+    const uint32_t n_fns = Ld->n_fns;
+    const uint64_t n_partials = Ld->n_partials;
+    uint32_t* counters = Ld->counters;
+    const bool aborted =
+        __hip_atomic_load(&counters[kCounterAborted], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t gw = blockIdx.x * kBlockWaves + threadIdx.x / kWave;
     const uint32_t nw = gridDim.x * kBlockWaves;
     for (uint32_t f = gw; f < n_fins; f += nw) {
         const Fin fin = fins[f];
-        const DevFn* fn = fns + fin.fn;
+        if (!(fin.fn < n_fns && fin.n_tiles >= 1 && (uint64_t)fin.part0 + fin.n_tiles <= n_partials &&
+              fin.res < n_fins)) {
+            if (lane == 0) atomicAdd(&counters[kCounterBadRecords], 1u);
+            continue;
+        }
+        CDevFn* fn = scalar_view(fns + fin.fn);
         Partial* P = partials + fin.part0;
         uint32_t n = fin.n_tiles;
         while (n > 1) {
@@ -582,18 +552,29 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
 
 // One thread per quad over a grid sized to the function's N, block sums in LDS,
 // one partial per block; a second single-block kernel reduces the partials.
-template <int FAM, int D>
-__global__ __launch_bounds__(256) void plain_fp64_kernel(const DevFn* __restrict__ fn, Partial* __restrict__ out)
+template <int FAM>
+__device__ __forceinline__ void plain_quad(CDevFn* fn, uint64_t q, double f[4])
+{
+    const Eval64<FAM> ev{fn};
+    eval_quad(ev, fn->dim, fn->key0, fn->key1, q, f);
+}
+
+extern "C" __global__ __launch_bounds__(256) void zmc_plain_fp64(const DevFn* __restrict__ fn_in,
+                                                                 Partial* __restrict__ out)
 {
     __shared__ double s1[256], s2[256];
-    Eval64<FAM, D> ev;
-    ev.load(fn);
+    CDevFn* fn = scalar_view(fn_in);
     const uint64_t q = (uint64_t)blockIdx.x * 256u + threadIdx.x;
     const uint64_t n_samples = fn->n_samples;
     double a = 0.0, b = 0.0;
     if (q < fn->n_quads) {
         double f[4];
-        eval_quad<Eval64<FAM, D>, D, double>(ev, fn->key0, fn->key1, q, f);
+        switch (fn->family) {
+        case HARMONIC: plain_quad<HARMONIC>(fn, q, f); break;
+        case ABS_LINEAR: plain_quad<ABS_LINEAR>(fn, q, f); break;
+        case GAUSSIAN: plain_quad<GAUSSIAN>(fn, q, f); break;
+        default: plain_quad<POLY_PRODUCT>(fn, q, f); break;
+        }
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
             if (4 * q + (uint64_t)s < n_samples) {
@@ -615,10 +596,11 @@ __global__ __launch_bounds__(256) void plain_fp64_kernel(const DevFn* __restrict
     if (threadIdx.x == 0) out[blockIdx.x] = Partial{s1[0], s2[0]};
 }
 
-extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* __restrict__ fn,
+extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* __restrict__ fn_in,
                                                                    const Partial* __restrict__ parts,
                                                                    uint32_t n_parts, DevResult* __restrict__ res)
 {
+    CDevFn* fn = scalar_view(fn_in);
     __shared__ double s1[256], s2[256];
     double a = 0.0, b = 0.0;
     for (uint32_t i = threadIdx.x; i < n_parts; i += 256) {
@@ -653,27 +635,8 @@ extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* 
     }
 }
 
-// Host-side table of the plain kernels, indexed [family][dim - 1].
-typedef void (*PlainKernel)(const DevFn*, Partial*);
-
-#define ZMC_PLAIN_ROW(F)                                                                              \
-    {plain_fp64_kernel<F, 1>, plain_fp64_kernel<F, 2>, plain_fp64_kernel<F, 3>, plain_fp64_kernel<F, 4>, \
-     plain_fp64_kernel<F, 5>, plain_fp64_kernel<F, 6>, plain_fp64_kernel<F, 7>, plain_fp64_kernel<F, 8>, \
-     plain_fp64_kernel<F, 9>, plain_fp64_kernel<F, 10>, plain_fp64_kernel<F, 11>, plain_fp64_kernel<F, 12>}
-
-const PlainKernel kPlainKernels[kNumFamilies][kMaxDim] = {
-    ZMC_PLAIN_ROW(HARMONIC), ZMC_PLAIN_ROW(ABS_LINEAR), ZMC_PLAIN_ROW(GAUSSIAN), ZMC_PLAIN_ROW(POLY_PRODUCT)};
-
-const void* plain_kernel_ptr(uint32_t family, uint32_t dim)
-{
-    return (const void*)kPlainKernels[family][dim - 1];
-}
-
-const void* batched_kernel_ptr(bool fp64)
-{
-    return fp64 ? (const void*)zmc_batched_fp64 : (const void*)zmc_batched_fp32;
-}
-
+const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
+const void* batched_kernel_ptr(bool fp64) { return fp64 ? (const void*)zmc_batched_fp64 : (const void*)zmc_batched_fp32; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }
 

@@ -32,6 +32,26 @@ from closed_forms import exact_integral, exact_se, point_value
 EPS = 2.0 ** -52
 
 
+def word_index(dim: int, i: int, j: int) -> int:
+    """Stream position of coordinate j of sample i: word s = i mod 4 of block (i // 4) * dim + j."""
+    return 4 * ((i // 4) * dim + j) + (i % 4)
+
+
+def stream_words(rocrand_ref, seed: int, dim: int, samples) -> dict:
+    """rocRAND's words for the given samples (all coordinates), keyed by (i, j)."""
+    samples = list(samples)
+    quads = sorted({i // 4 for i in samples})
+    lines = [f"w {seed} {4 * q * dim} {4 * dim}" for q in quads]
+    got = rocrand_ref(lines)
+    out = {}
+    for q, words in zip(quads, got):
+        for i in samples:
+            if i // 4 == q:
+                for j in range(dim):
+                    out[(i, j)] = words[word_index(dim, i, j) - 4 * q * dim]
+    return out
+
+
 def exact_uniform(r: int) -> Fraction:
     return Fraction(2 * (r & 0x7FFFFF) + 1, 1 << 24)
 
@@ -68,14 +88,14 @@ def check_philox_blocks(orc, rocrand_ref, n=24):
 
 
 def check_stream_layout(orc, rocrand_ref):
-    lines, expect = [], []
     for seed in (3, W.stream_seed(9, 2)):
         for dim in (1, 3, 5, 12):
             for i0 in (0, 3, 12345):
-                lines.append(f"w {seed} {i0 * dim} {4 * dim}")
-                expect.append([orc.word(seed, dim, i, j) for i in range(i0, i0 + 4) for j in range(dim)])
-    for ln, r, e in zip(lines, rocrand_ref(lines), expect):
-        assert r == e, ("stream layout", ln)
+                samples = range(i0, i0 + 6)
+                ref = stream_words(rocrand_ref, seed, dim, samples)
+                for i in samples:
+                    for j in range(dim):
+                        assert orc.word(seed, dim, i, j) == ref[(i, j)], ("stream layout", seed, dim, i, j)
 
 
 def check_uniform(orc):
@@ -92,9 +112,10 @@ def check_sample_points(orc, rocrand_ref):
     for i in range(len(t)):
         d = int(t["dim"][i])
         seed = int(t["seed"][i])
-        lines = [f"w {seed} {s * d} {d}" for s in (0, 1, 2, 1001)]
-        for s, words in zip((0, 1, 2, 1001), rocrand_ref(lines)):
-            want = exact_point(t, i, words)
+        samples = (0, 1, 2, 5, 1001)
+        ref = stream_words(rocrand_ref, seed, d, samples)
+        for s in samples:
+            want = exact_point(t, i, [ref[(s, j)] for j in range(d)])
             got = orc.sample_point(t, i, s)
             assert list(got) == want, ("sample point", i, s)
 
@@ -132,10 +153,10 @@ def check_brute_force_sums(orc, rocrand_ref):
         d = int(t["dim"][i])
         seed = int(t["seed"][i])
         n = 1 + (i % 16)
-        words = rocrand_ref([f"w {seed} 0 {n * d}"])[0]
+        ref = stream_words(rocrand_ref, seed, d, range(n))
         fs = []
         for s in range(n):
-            x = exact_point(t, i, words[s * d:(s + 1) * d])
+            x = exact_point(t, i, [ref[(s, j)] for j in range(d)])
             fs.append(point_value(t, i, x))
         s1_ref = math.fsum(float(v) for v in fs)
         s2_ref = math.fsum(float(v * v) for v in fs)
@@ -168,6 +189,7 @@ def check_finalize_textbook(orc):
 def _z_scores(orc, t):
     res, _ = orc.integrate(t, threads=8)
     z = []
+    ratios = []
     for i in range(len(t)):
         ex = exact_integral(t, i)
         se_ex = exact_se(t, i)
@@ -176,8 +198,15 @@ def _z_scores(orc, t):
             assert res["mean"][i] == ex or abs(res["mean"][i] - ex) <= 1e-12 * abs(ex)
             continue
         z.append((res["mean"][i] - ex) / se_ex)
-        # the oracle's own SE estimates the exact one (relative error ~ 1/sqrt(N) times kurtosis)
-        assert abs(res["stderr"][i] / se_ex - 1.0) < 0.15, ("stderr vs exact", i, res["stderr"][i], se_ex)
+        # The oracle's own SE estimates the exact one; its relative spread is about
+        # sqrt((kurtosis - 1) / (4 N)), large for narrow Gaussians and high powers,
+        # so single functions get a loose bound and the batch a tight one.
+        r = res["stderr"][i] / se_ex
+        assert abs(r - 1.0) < 0.5, ("stderr vs exact", i, res["stderr"][i], se_ex)
+        ratios.append(r)
+    ratios = np.array(ratios)
+    assert abs(np.median(ratios) - 1.0) < 0.03, ("median SE ratio", np.median(ratios))
+    assert abs(np.mean(ratios ** 2) - 1.0) < 0.1, ("mean variance ratio", np.mean(ratios ** 2))
     return np.array(z)
 
 

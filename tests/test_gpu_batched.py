@@ -1,0 +1,130 @@
+"""Properties of the batched path on the GPU: results depend only on each function.
+
+The per-function reduction tree is fixed (lane butterfly, pairwise over
+segments and tiles), so tuning, launch shape, scheduling policy, launch
+splitting and the rest of the batch must leave every result bitwise equal.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_common as G
+from paper_2104_10073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _Z():
+    import paper_2104_10073_amd as Z
+    return Z
+
+
+def _batch():
+    return W.mixed_batch(120, dim_range=(1, 12), log10_samples=(3.0, 5.6), gen_seed=211)
+
+
+def _same(a, b, label):
+    for k in ("mean", "std_error", "sum_f", "sum_f2", "n", "status", "precision"):
+        assert np.array_equal(a[k], b[k]), f"{label}: field {k} differs"
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_tuning_and_launch_shape_invariance(prec):
+    Z = _Z()
+    t = _batch()
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c0:
+        ref = c0.integrate(t, prec)
+        b, seg = c0.get_tuning()
+    seg2 = np.full((2, 4, 12), 3, dtype=np.uint8)
+    with Z.Context(flags=Z.MC_NO_GRAPH, blocks_per_cu=1, max_tiles_per_run=37) as c1:
+        c1.set_tuning(1, seg2)
+        r1 = c1.integrate(t, prec)
+    _same(ref, r1, "seg_log2=3, 1 block/CU, 37 tiles per launch")
+    with Z.Context(flags=Z.MC_NO_GRAPH, policy=Z.MC_SCHED_FIFO) as c2:
+        c2.set_tuning(0, np.full((2, 4, 12), 1, dtype=np.uint8))
+        r2 = c2.integrate(t, prec)
+    _same(ref, r2, "FIFO, seg_log2=1")
+
+
+def test_alone_vs_mix():
+    """Each function's result alone equals its result inside a mixed batch, bitwise."""
+    Z = _Z()
+    t = _batch()
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        mix = c.integrate(t, Z.PREC_FP32)
+        for i in (0, 7, 33, 90, 119):
+            alone = c.integrate(np.ascontiguousarray(t[i:i + 1]), Z.PREC_FP32)
+            _same(alone, mix[i:i + 1], f"function {i}")
+
+
+def test_concurrent_requests_and_small_budget():
+    """Many requests in flight under a partial arena too small for all of them at once:
+    admission waits for space, every request completes, results equal the alone runs."""
+    Z = _Z()
+    reqs = W.serving_requests(12, max_funcs=40, log10_samples=(3.0, 5.0), gen_seed=17)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        alone = [c.integrate(r, Z.PREC_FP32) for r in reqs]
+    need = max(int(np.sum(np.ceil(np.ceil(np.ceil(r["n_samples"] / 4) / 1024) / 4))) for r in reqs)
+    with Z.Context(flags=Z.MC_NO_GRAPH, max_partials=need + 8, max_tiles_per_run=64) as c:
+        ids = [c.submit(r, Z.PREC_FP32) for r in reqs]
+        done = {}
+        for _ in range(10_000):
+            c.run()
+            for rid in c.poll():
+                done[rid] = True
+            if len(done) == len(ids):
+                break
+        outs = [c.results(rid, len(r)) for rid, r in zip(ids, reqs)]
+    for k, (a, b) in enumerate(zip(alone, outs)):
+        _same(a, b, f"request {k}")
+
+
+def test_abort_then_recover():
+    """Abort while the persistent kernels run (~0.1 s of work): they stop at their next
+    tile fetch, the request comes back aborted, and later work is unaffected."""
+    Z = _Z()
+    t = W.harmonic_batch(48, n_samples=1_000_000_000)
+    queued = W.eq1_series(n_samples=10_000, n_funcs=4)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        rid = c.submit(t, Z.PREC_FP32)
+        c.run()
+        rid2 = c.submit(queued, Z.PREC_FP32)   # queued before the abort: cancelled too
+        c.abort()
+        r = c.results(rid, len(t), allow_aborted=True)
+        assert np.all(r["status"] == -10)
+        r2 = c.results(rid2, len(queued), allow_aborted=True)
+        assert np.all(r2["status"] == -10)
+        # the abort word clears once the queue has drained; new work runs normally
+        small = W.eq1_series(n_samples=20_000, n_funcs=8)
+        got = c.integrate(small, Z.PREC_FP64)
+        G.check_fp64(got, G.oracle_results(small), "after abort")
+
+
+def test_torch_workspace_and_stream():
+    import torch
+    Z = _Z()
+    t = W.eq1_series(n_samples=30_000, n_funcs=20)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        ref = c.integrate(t, Z.PREC_FP32)
+    s = torch.cuda.Stream()
+    with Z.Context(flags=Z.MC_NO_GRAPH, workspace="torch") as c:
+        with torch.cuda.stream(s):
+            got = c.integrate(t, Z.PREC_FP32, stream=s)
+    _same(ref, got, "torch workspace + side stream")
+
+
+def test_promotion_of_nearly_constant_functions():
+    """A nearly constant integrand cannot be resolved in FP32; it comes back from FP64."""
+    Z = _Z()
+    t = W.empty(3)
+    W.set_gaussian(t, 0, 4, 2.0, 1e3, [0.5] * 4, [0] * 4, [1] * 4)
+    W.set_poly(t, 1, 3, [1e-9] * 3, [2, 2, 2], [0] * 3, [1] * 3)
+    W.set_harmonic(t, 2, 4, 1.0, 0.5, [20.0] * 4, [0] * 4, [1] * 4)
+    t["n_samples"][:] = 1_000_000
+    t["seed"][:] = [5, 6, 7]
+    orc = G.oracle_results(t)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        r = c.integrate(t, Z.PREC_FP32)
+    assert r["precision"].tolist() == [1, 1, 0]
+    G.check_fp64(r[:2], orc[:2], "promoted")
+    G.check_fp32(r[2:], orc[2:], "not promoted")

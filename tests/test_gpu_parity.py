@@ -17,7 +17,7 @@ pytestmark = pytest.mark.gpu
 @pytest.fixture(scope="module")
 def ctx():
     import paper_2104_10073_amd as Z
-    c = Z.Context(device=0)
+    c = Z.Context(device=0, flags=Z.MC_NO_GRAPH)
     yield c
     c.close()
 
@@ -60,6 +60,16 @@ def test_mixed_small_batch(ctx):
     orc = G.oracle_results(t)
     G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "mixed fp64")
     G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "mixed fp32")
+
+
+def test_eq1_full_fp32_matches_oracle_sampled(ctx):
+    """Eq. (1) series at the paper's 10^6 samples per n: every 10th function against the oracle."""
+    import paper_2104_10073_amd as Z
+    t = W.eq1_series(n_samples=1_000_000)
+    r = ctx.integrate(t, Z.PREC_FP32)
+    sub = np.arange(0, 100, 10)
+    orc = G.oracle_results(t[sub])
+    G.check_fp32(r[sub], orc, "eq1 1e6 fp32")
 
 
 def test_plain_matches_batched_fp64(ctx):

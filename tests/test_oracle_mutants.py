@@ -22,8 +22,11 @@ MUTANTS = [
     ("philox xor operand", "uint32_t n2 = hi0 ^ c[3] ^ k1;", "uint32_t n2 = hi0 ^ c[1] ^ k1;"),
     ("uniform high bits", "uint32_t m = r & 0x7FFFFFu;", "uint32_t m = r >> 9;"),
     ("uniform left endpoint", "(double)(2u * m + 1u)", "(double)(2u * m)"),
-    ("stream index stride", "uint64_t g = i * (uint64_t)dim + (uint64_t)j;",
-     "uint64_t g = i * (uint64_t)(dim + 1) + (uint64_t)j;"),
+    ("stream block stride", "uint64_t b = q * (uint64_t)dim + (uint64_t)j;",
+     "uint64_t b = q * (uint64_t)(dim + 1) + (uint64_t)j;"),
+    ("quad member ignored", "return out[s];", "return out[j & 3u];"),
+    ("quad index is the sample index", "uint64_t q = i / 4u;                       /* quad */",
+     "uint64_t q = i;"),
     ("counter words in 2-3", "{(uint32_t)b, (uint32_t)(b >> 32), 0u, 0u}", "{0u, 0u, (uint32_t)b, (uint32_t)(b >> 32)}"),
     ("key halves swapped", "{(uint32_t)seed, (uint32_t)(seed >> 32)}", "{(uint32_t)(seed >> 32), (uint32_t)seed}"),
     ("mapping drops lo", "x[j] = fma(w, u, fn->lo[j]);", "x[j] = w * u;"),

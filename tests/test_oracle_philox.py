@@ -27,23 +27,35 @@ def test_philox_blocks_match_rocrand(orc, rocrand_ref):
 
 
 def test_stream_layout_matches_rocrand(orc, rocrand_ref):
-    """Word g of function seed s is rocRAND's g-th output for seed s (subsequence 0)."""
-    lines, expect = [], []
+    """Coordinate j of sample i is word 4*((i//4)*d + j) + i%4 of rocRAND's stream for seed s."""
+    from oracle_pins import stream_words
     for seed in (0, 7, W.stream_seed(3, 17), W.stream_seed(0xFFFFFFFF, 0xFFFFFFFF), 2**63 + 5):
         for dim in (1, 3, 4, 7, 12):
             for i0 in (0, 1, 5, 1_000_003):
-                n = 6
-                lines.append(f"w {seed} {i0 * dim} {n * dim}")
-                expect.append([orc.word(seed, dim, i, j) for i in range(i0, i0 + n) for j in range(dim)])
-    ref = rocrand_ref(lines)
-    for ln, r, e in zip(lines, ref, expect):
-        assert r == e, ln
+                samples = range(i0, i0 + 9)
+                ref = stream_words(rocrand_ref, seed, dim, samples)
+                for i in samples:
+                    for j in range(dim):
+                        assert orc.word(seed, dim, i, j) == ref[(i, j)], (seed, dim, i, j)
+
+
+def test_quad_uses_consecutive_blocks(orc, rocrand_ref):
+    """A quad of samples consumes exactly d consecutive Philox blocks, nothing wasted."""
+    seed, dim = 99, 5
+    words = rocrand_ref([f"w {seed} 0 {4 * dim * 3}"])[0]
+    got = []
+    for q in range(3):
+        for j in range(dim):
+            got.extend(orc.word(seed, dim, 4 * q + s, j) for s in range(4))
+    assert got == words
 
 
 def test_high_counter_word(orc, rocrand_ref):
     """Block index past 2^32 carries into counter word 1."""
+    from oracle_pins import stream_words
     seed, dim = 12345, 12
-    i = (1 << 32) // 3 + 77  # g = i*12 > 2^34, block > 2^32
-    line = f"w {seed} {i * dim} {dim}"
-    ref = rocrand_ref([line])[0]
-    assert ref == [orc.word(seed, dim, i, j) for j in range(dim)]
+    i = 4 * ((1 << 32) // 12 + 77)  # first block of the quad > 2^32
+    ref = stream_words(rocrand_ref, seed, dim, range(i, i + 4))
+    for s in range(4):
+        for j in range(dim):
+            assert orc.word(seed, dim, i + s, j) == ref[(i + s, j)]
