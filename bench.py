@@ -71,6 +71,43 @@ def cpu_baseline(table, budget_s: float = 10.0):
                       f"({evals:.3g} evals, {dt:.1f} s wall, threads over functions)"}, orc, done
 
 
+def serving_leg(Z, W, stream, args):
+    """Continuous batching under open-loop Poisson arrivals at a fixed QPS.
+
+    Requests of floor(10^U(0,3)) functions (mixed forms, dims 1..12, 10^4..10^7
+    samples each).  The saturated rate is measured first with every request
+    arriving at t = 0; the offered QPS is `serve_load` times it.  Latency is
+    arrival to results-on-host; the first 10 % of requests are warm-up.
+    """
+    from paper_2104_10073_amd import serving
+
+    n = args.serve_requests
+    reqs = W.serving_requests(n, gen_seed=5)
+    flags = Z.MC_NO_GRAPH if args.no_graph else 0
+    with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 15,
+                   max_functions=1 << 17, max_partials=1 << 24) as ctx:
+        sat = serving.serve(ctx, reqs, np.zeros(n), stream)
+        sat_qps = n / sat["wall_s"]
+        qps = args.serve_load * sat_qps
+        arrivals = W.poisson_arrivals(n, qps, seed=5)
+        run = serving.serve(ctx, reqs, arrivals, stream, keep_results=True)
+        summ = serving.summarize(run, arrivals)
+        # each result alone equals its result inside the mix
+        rng = np.random.Generator(np.random.PCG64(23))
+        picks = rng.choice(n, size=min(20, n), replace=False)
+        same = True
+        for i in picks:
+            alone = ctx.integrate(reqs[i], Z.PREC_FP32, stream=stream)
+            mixed = run["results"][i]
+            same = same and all(np.array_equal(alone[k], mixed[k]) for k in ("mean", "std_error", "sum_f", "sum_f2"))
+    summ.update({"offered_qps": qps, "saturated_qps": sat_qps, "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
+                 "load_fraction": args.serve_load, "alone_equals_mix_bitwise": bool(same),
+                 "requests_checked_alone": int(len(picks)),
+                 "workload": "requests of floor(10^U(0,3)) functions, forms mixed, dims U{1..12}, "
+                             "10^U(4,7) samples each, Poisson arrivals"})
+    return summ
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -82,6 +119,10 @@ def main():
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--autotune", type=float, default=0.0, help="seconds of autotuning before timing")
     ap.add_argument("--no-graph", action="store_true", help="direct kernel launches instead of graph replays")
+    ap.add_argument("--serve-requests", type=int, default=1000,
+                    help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--serve-load", type=float, default=0.5,
+                    help="offered load as a fraction of the measured saturated request rate")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (tiles sharded across GPUs, one gather "
@@ -179,6 +220,9 @@ def main():
                                                               np.sqrt(r64["n"] * r64["sum_f2"]))),
         }
     ctx.close()
+
+    if args.serve_requests > 0:
+        out["serving"] = serving_leg(Z, W, stream, args)
 
     if not args.no_cpu_baseline:
         cb, orc, done = cpu_baseline(batches[Wm])

@@ -1,0 +1,84 @@
+"""Seeded workload generator and host-side planning (CPU only)."""
+
+import numpy as np
+import pytest
+
+from paper_2104_10073_amd import workloads as W
+
+
+def test_tables_are_deterministic_and_well_formed():
+    a = W.mixed_batch(300, dim_range=(1, 7), gen_seed=3)
+    b = W.mixed_batch(300, dim_range=(1, 7), gen_seed=3)
+    assert a.tobytes() == b.tobytes()
+    assert set(np.unique(a["family"])) == {0, 1, 2, 3}
+    assert a["dim"].min() >= 1 and a["dim"].max() <= 7
+    assert np.all(a["n_samples"] >= 10_000) and np.all(a["n_samples"] <= 10_000_000)
+    for i in range(len(a)):
+        d = int(a["dim"][i])
+        w = a["hi"][i, :d] - a["lo"][i, :d]
+        assert np.all(w >= 0.5) and np.all(w <= 2.0)
+        assert np.all(a["lo"][i, d:] == 0) and np.all(a["hi"][i, d:] == 0)
+    # distinct streams per function, base in the high word
+    assert len(set(a["seed"].tolist())) == len(a)
+    assert W.stream_seed(7, 3) == (7 << 32) | 3
+
+
+def test_harmonic_batch_bases_share_parameters():
+    a = W.harmonic_batch(50, base=0)
+    b = W.harmonic_batch(50, base=3)
+    assert np.array_equal(a["params"], b["params"])
+    assert not np.array_equal(a["seed"], b["seed"])
+    k = a["params"][:, W.V0:W.V0 + 4]
+    assert k.min() >= 5 and k.max() <= 30
+
+
+def test_eq1_series_matches_paper_definition():
+    t = W.eq1_series()
+    n = np.arange(1, 101)
+    assert np.allclose(t["params"][:, W.V0], (n + 50) / (2 * np.pi))
+    assert np.all(t["params"][:, 0] == 1) and np.all(t["params"][:, 1] == 1)
+    assert np.all(t["dim"] == 4)
+
+
+def test_high_dim_near_zero_selection_is_real():
+    """Every 10th function is near-zero by the tests' own exact closed forms."""
+    from closed_forms import exact_integral
+    t = W.high_dim_batch(40, n_samples=1000)
+    for i in range(9, 40, 10):
+        assert abs(exact_integral(t, i)) < 1e-4, i
+    assert t["dim"].min() >= 8 and t["dim"].max() <= 12
+
+
+def test_serving_requests_shapes():
+    reqs = W.serving_requests(50, gen_seed=5)
+    sizes = [len(r) for r in reqs]
+    assert min(sizes) >= 1 and max(sizes) <= 1000
+    for r_i, r in enumerate(reqs):
+        assert np.all(r["seed"] >> 32 == r_i)
+        assert r["dim"].min() >= 1 and r["dim"].max() <= 12
+    arr = W.poisson_arrivals(1000, 200.0)
+    assert np.all(np.diff(arr) > 0)
+    assert abs(1000 / arr[-1] - 200.0) < 30.0
+
+
+def test_tile_planning_counts():
+    """Tiles per function = ceil(segments / 4) with segments of 4096 samples (default tuning)."""
+    import paper_2104_10073_amd as Z
+    c = Z.Context(flags=Z.MC_VALIDATE_ONLY)
+    t = W.eq1_series(n_funcs=6)
+    t["n_samples"][:] = [2, 4096, 4097, 16384, 16385, 10_000_000]
+    c.submit(t)
+    segs = np.ceil(np.ceil(t["n_samples"] / 4) / 1024)
+    assert c.pending()[1] == int(np.sum(np.ceil(segs / 4)))
+    assert Z.segment_samples() == 4096
+    c.close()
+
+
+def test_serving_summary_math():
+    from paper_2104_10073_amd.serving import summarize
+    lat = np.linspace(0.001, 0.1, 100)
+    out = {"latency_s": lat, "done_s": np.arange(100) * 0.01 + lat, "wall_s": 1.0, "evals": 10**9}
+    s = summarize(out, np.arange(100) * 0.01, warmup_frac=0.1)
+    assert s["measured"] == 90
+    assert abs(s["p50_ms"] - np.percentile(lat[10:], 50) * 1e3) < 1e-9
+    assert s["sustained_evals_per_s"] == 1e9
