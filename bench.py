@@ -177,7 +177,7 @@ def main():
     assert st1["bad_records"] == 0
 
     # roofline of the persistent kernel from its HIP-event time
-    avg_main_s = (st1["main_ms"] - st0["main_ms"]) / launches * 1e-3
+    avg_main_s = (st1["fp32_ms"] - st0["fp32_ms"]) / launches * 1e-3
     slots = algorithmic_slots_per_eval("harmonic", 4) * evals_per_step
     achieved = slots / avg_main_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,

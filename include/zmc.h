@@ -206,7 +206,8 @@ typedef struct mc_stats {
     uint64_t samples;            /* integrand evaluations in those tiles */
     uint64_t promoted;           /* FP32 functions re-run in FP64 */
     uint64_t bad_records;        /* records that failed the kernels' bounds checks (always 0 unless corrupt) */
-    double main_ms;              /* sum of persistent-kernel time (HIP events) */
+    double fp32_ms;              /* sum of FP32 persistent-kernel time (HIP events on the launch stream) */
+    double fp64_ms;              /* sum of FP64 persistent-kernel time */
     double finalize_ms;          /* sum of finalize time */
 } mc_stats;
 

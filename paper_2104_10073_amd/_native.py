@@ -69,7 +69,8 @@ class McStats(ctypes.Structure):
     _fields_ = [
         ("launches", ctypes.c_uint64), ("tiles32", ctypes.c_uint64), ("tiles64", ctypes.c_uint64),
         ("functions", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
-        ("bad_records", ctypes.c_uint64), ("main_ms", ctypes.c_double), ("finalize_ms", ctypes.c_double),
+        ("bad_records", ctypes.c_uint64), ("fp32_ms", ctypes.c_double), ("fp64_ms", ctypes.c_double),
+        ("finalize_ms", ctypes.c_double),
     ]
 
     def as_dict(self):
@@ -94,6 +95,13 @@ def load(path: str = LIB_PATH):
         raise ImportError(
             f"{path} is missing: build the HIP library first "
             "(python -c 'import __graft_entry__ as g; g.build()' or python paper_2104_10073_amd/build.py)")
+    # One HIP runtime per process: PyTorch ships its own libamdhip64 (same soname),
+    # and its streams and memory are only valid in that runtime.  Loading torch
+    # first makes libzmc.so bind to it instead of starting a second runtime.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     L = ctypes.CDLL(path)
     vp, u64p = ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64)
     L.mc_config_init.argtypes = [ctypes.POINTER(McConfig)]

@@ -38,7 +38,7 @@ using namespace zmc;
 static_assert(sizeof(mc_function) == 472, "mc_function layout");
 static_assert(sizeof(mc_result) == 48, "mc_result layout");
 static_assert(sizeof(mc_config) == 56, "mc_config layout");
-static_assert(sizeof(mc_stats) == 72, "mc_stats layout");
+static_assert(sizeof(mc_stats) == 80, "mc_stats layout");
 static_assert(sizeof(DevResult) == sizeof(mc_result), "result layout");
 static_assert(sizeof(Tile) == 16 && sizeof(Fin) == 16 && sizeof(Partial) == 16, "record layout");
 
@@ -335,7 +335,7 @@ struct LaunchSlot {
     Tile* h_tiles64 = nullptr;
     Fin* h_fins = nullptr;
     DevResult* h_results = nullptr;
-    hipEvent_t ev_start = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
+    hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
     bool in_flight = false;
     uint64_t seq = 0;
@@ -571,13 +571,15 @@ void reap(mc_ctx* ctx, int wait)
             }
         }
         {
-            float a = 0.f, b = 0.f;
+            float a = 0.f, a32 = 0.f, b = 0.f;
             if (hipEventElapsedTime(&a, s.ev_start, s.ev_main) == hipSuccess &&
+                hipEventElapsedTime(&a32, s.ev_start, s.ev_mid) == hipSuccess &&
                 hipEventElapsedTime(&b, s.ev_main, s.ev_end) == hipSuccess) {
                 ctx->last_main_ms = a;
                 ctx->last_fin_ms = b;
                 ctx->have_timing = true;
-                ctx->stats.main_ms += a;
+                ctx->stats.fp32_ms += a32;
+                ctx->stats.fp64_ms += a - a32;
                 ctx->stats.finalize_ms += b;
             }
             ctx->stats.launches++;
@@ -637,6 +639,7 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream)
     HIP_TRY(hipEventRecord(s.ev_start, stream));
     HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32), dim3(kBlockThreads),
                             args, 0, stream));
+    HIP_TRY(hipEventRecord(s.ev_mid, stream));
     HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64), dim3(kBlockThreads),
                             args, 0, stream));
     HIP_TRY(hipEventRecord(s.ev_main, stream));
@@ -834,7 +837,7 @@ void destroy_device(mc_ctx* ctx)
 {
     for (auto& s : ctx->slots) {
         if (s.graph) (void)hipGraphExecDestroy(s.graph);
-        for (hipEvent_t e : {s.ev_start, s.ev_main, s.ev_end, s.ev_done})
+        for (hipEvent_t e : {s.ev_start, s.ev_mid, s.ev_main, s.ev_end, s.ev_done})
             if (e) (void)hipEventDestroy(e);
         for (void* p : {(void*)s.h_desc, (void*)s.h_tiles32, (void*)s.h_tiles64, (void*)s.h_fins, (void*)s.h_results})
             if (p) (void)hipHostFree(p);
@@ -950,6 +953,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             HIP_TRY(hipHostMalloc((void**)&s.h_fins, (size_t)ctx->fin_cap * sizeof(Fin), hipHostMallocDefault));
             HIP_TRY(hipHostMalloc((void**)&s.h_results, (size_t)ctx->fin_cap * sizeof(DevResult), hipHostMallocDefault));
             HIP_TRY(hipEventCreate(&s.ev_start));
+            HIP_TRY(hipEventCreate(&s.ev_mid));
             HIP_TRY(hipEventCreate(&s.ev_main));
             HIP_TRY(hipEventCreate(&s.ev_end));
             HIP_TRY(hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
