@@ -83,7 +83,7 @@ def serving_leg(Z, W, stream, args):
 
     n = args.serve_requests
     reqs = W.serving_requests(n, gen_seed=5)
-    flags = Z.MC_NO_GRAPH if args.no_graph else 0
+    flags = 0 if args.graph else Z.MC_NO_GRAPH
     with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 15,
                    max_functions=1 << 17, max_partials=1 << 24) as ctx:
         sat = serving.serve(ctx, reqs, np.zeros(n), stream)
@@ -118,11 +118,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
     ap.add_argument("--autotune", type=float, default=0.0, help="seconds of autotuning before timing")
-    ap.add_argument("--no-graph", action="store_true", help="direct kernel launches instead of graph replays")
+    ap.add_argument("--graph", action="store_true",
+                    help="replay captured HIP graphs (then only whole-launch times are measured)")
     ap.add_argument("--serve-requests", type=int, default=1000,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturated request rate")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only copy a device buffer of this many MiB 5 times (scale for HBM counters) and exit")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (tiles sharded across GPUs, one gather "
@@ -135,6 +138,17 @@ def main():
     from paper_2104_10073_amd import workloads as W
 
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        # A plain device-to-device copy of known size: FETCH_SIZE / WRITE_SIZE of its
+        # dispatches calibrate the counters read on the integration kernels.
+        nbytes = args.copy_calibration << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_calibration_bytes": nbytes, "copies": 5}))
+        return
     stream = torch.cuda.current_stream()
     K, Wm = args.steps, args.warmup
     batches = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=b) for b in range(K + Wm)]
@@ -146,7 +160,7 @@ def main():
     probe.submit(batches[0], Z.PREC_FP32)
     tiles_per_batch = probe.validate_tiles()
     probe.close()
-    flags = Z.MC_NO_GRAPH if args.no_graph else 0
+    flags = 0 if args.graph else Z.MC_NO_GRAPH
     ctx = Z.Context(device=0, workspace="torch", flags=flags, policy=Z.MC_SCHED_FIFO,
                     max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
     if args.autotune > 0:
@@ -176,8 +190,10 @@ def main():
     assert launches == K and st1["samples"] - st0["samples"] == evals_per_step * K, (st0, st1)
     assert st1["bad_records"] == 0
 
-    # roofline of the persistent kernel from its HIP-event time
-    avg_main_s = (st1["fp32_ms"] - st0["fp32_ms"]) / launches * 1e-3
+    # roofline of the persistent kernel from its HIP-event time (graph launches are
+    # timed as a whole: FP32 kernel + empty FP64 kernel + finalize)
+    key = "graph_ms" if args.graph else "fp32_ms"
+    avg_main_s = (st1[key] - st0[key]) / launches * 1e-3
     slots = algorithmic_slots_per_eval("harmonic", 4) * evals_per_step
     achieved = slots / avg_main_s
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,

@@ -194,8 +194,8 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
  * `precision` and keep the fastest.  Blocks until done; uses `stream`. */
 mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
 
-/* Kernel timing of the most recent completed mc_run (persistent kernels and
- * finalize, in milliseconds, from HIP events on the launch stream). */
+/* Kernel timing of the most recent completed direct-launch mc_run (persistent
+ * kernels and finalize, in milliseconds, from HIP events on the launch stream). */
 mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms);
 
 /* Cumulative counters of a context since it was created (completed launches only). */
@@ -206,9 +206,10 @@ typedef struct mc_stats {
     uint64_t samples;            /* integrand evaluations in those tiles */
     uint64_t promoted;           /* FP32 functions re-run in FP64 */
     uint64_t bad_records;        /* records that failed the kernels' bounds checks (always 0 unless corrupt) */
-    double fp32_ms;              /* sum of FP32 persistent-kernel time (HIP events on the launch stream) */
-    double fp64_ms;              /* sum of FP64 persistent-kernel time */
-    double finalize_ms;          /* sum of finalize time */
+    double fp32_ms;              /* direct launches: sum of FP32 persistent-kernel time (HIP events on the launch stream) */
+    double fp64_ms;              /* direct launches: sum of FP64 persistent-kernel time */
+    double finalize_ms;          /* direct launches: sum of finalize time */
+    double graph_ms;             /* graph launches: sum of whole-graph time (all three kernels) */
 } mc_stats;
 
 mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out);

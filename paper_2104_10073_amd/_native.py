@@ -70,7 +70,7 @@ class McStats(ctypes.Structure):
         ("launches", ctypes.c_uint64), ("tiles32", ctypes.c_uint64), ("tiles64", ctypes.c_uint64),
         ("functions", ctypes.c_uint64), ("samples", ctypes.c_uint64), ("promoted", ctypes.c_uint64),
         ("bad_records", ctypes.c_uint64), ("fp32_ms", ctypes.c_double), ("fp64_ms", ctypes.c_double),
-        ("finalize_ms", ctypes.c_double),
+        ("finalize_ms", ctypes.c_double), ("graph_ms", ctypes.c_double),
     ]
 
     def as_dict(self):

@@ -38,7 +38,7 @@ using namespace zmc;
 static_assert(sizeof(mc_function) == 472, "mc_function layout");
 static_assert(sizeof(mc_result) == 48, "mc_result layout");
 static_assert(sizeof(mc_config) == 56, "mc_config layout");
-static_assert(sizeof(mc_stats) == 80, "mc_stats layout");
+static_assert(sizeof(mc_stats) == 88, "mc_stats layout");
 static_assert(sizeof(DevResult) == sizeof(mc_result), "result layout");
 static_assert(sizeof(Tile) == 16 && sizeof(Fin) == 16 && sizeof(Partial) == 16, "record layout");
 
@@ -56,6 +56,15 @@ struct HipError {
     hipError_t e;
     const char* what;
 };
+
+// Calls whose failure is not an error of the operation (cleanup, optional
+// timing) go through quiet(): HIP keeps the last error of a thread until
+// someone reads it, and a stale one would surface in the caller's next HIP call
+// (PyTorch checks it after every launch).
+inline void quiet(hipError_t e)
+{
+    if (e != hipSuccess) (void)hipGetLastError();
+}
 
 #define HIP_TRY(expr)                                   \
     do {                                                \
@@ -338,6 +347,7 @@ struct LaunchSlot {
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
     bool in_flight = false;
+    bool graphed = false;             // this launch replayed the slot's graph
     uint64_t seq = 0;
     uint32_t n_tiles32 = 0, n_tiles64 = 0, n_fins = 0;
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
@@ -473,7 +483,7 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
 void free_packed(Request* r)
 {
     if (!r->packed) return;
-    if (r->packed_pinned) (void)hipHostFree(r->packed);
+    if (r->packed_pinned) quiet(hipHostFree(r->packed));
     else std::free(r->packed);
     r->packed = nullptr;
 }
@@ -482,7 +492,7 @@ void free_request_resources(mc_ctx* ctx, Request* r)
 {
     free_packed(r);
     if (r->uploaded) {
-        (void)hipEventDestroy(r->uploaded);
+        quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
     }
     if (!r->admitted) return;
@@ -571,16 +581,26 @@ void reap(mc_ctx* ctx, int wait)
             }
         }
         {
-            float a = 0.f, a32 = 0.f, b = 0.f;
-            if (hipEventElapsedTime(&a, s.ev_start, s.ev_main) == hipSuccess &&
-                hipEventElapsedTime(&a32, s.ev_start, s.ev_mid) == hipSuccess &&
-                hipEventElapsedTime(&b, s.ev_main, s.ev_end) == hipSuccess) {
-                ctx->last_main_ms = a;
-                ctx->last_fin_ms = b;
-                ctx->have_timing = true;
-                ctx->stats.fp32_ms += a32;
-                ctx->stats.fp64_ms += a - a32;
-                ctx->stats.finalize_ms += b;
+            float a = 0.f, a32 = 0.f, b = 0.f, g = 0.f;
+            if (s.graphed) {
+                const hipError_t e = hipEventElapsedTime(&g, s.ev_start, s.ev_end);
+                quiet(e);
+                if (e == hipSuccess) ctx->stats.graph_ms += g;
+            } else {
+                const hipError_t e1 = hipEventElapsedTime(&a, s.ev_start, s.ev_main);
+                const hipError_t e2 = hipEventElapsedTime(&a32, s.ev_start, s.ev_mid);
+                const hipError_t e3 = hipEventElapsedTime(&b, s.ev_main, s.ev_end);
+                quiet(e1);
+                quiet(e2);
+                quiet(e3);
+                if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess) {
+                    ctx->last_main_ms = a;
+                    ctx->last_fin_ms = b;
+                    ctx->have_timing = true;
+                    ctx->stats.fp32_ms += a32;
+                    ctx->stats.fp64_ms += a - a32;
+                    ctx->stats.finalize_ms += b;
+                }
             }
             ctx->stats.launches++;
             ctx->stats.tiles32 += s.n_tiles32;
@@ -632,25 +652,29 @@ void admit(mc_ctx* ctx)
 
 void capture_graph(mc_ctx* ctx, LaunchSlot& s);
 
-void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream)
+// The three kernels of a launch.  Direct launches bracket each kernel with
+// timing events; a captured graph holds the kernels only and is timed as a
+// whole from outside (events recorded inside captured graphs are not
+// reliable timing sources).
+void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events)
 {
     LaunchDesc* dd = s.d_desc;
     void* args[] = {&dd};
-    HIP_TRY(hipEventRecord(s.ev_start, stream));
+    if (events) HIP_TRY(hipEventRecord(s.ev_start, stream));
     HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32), dim3(kBlockThreads),
                             args, 0, stream));
-    HIP_TRY(hipEventRecord(s.ev_mid, stream));
+    if (events) HIP_TRY(hipEventRecord(s.ev_mid, stream));
     HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64), dim3(kBlockThreads),
                             args, 0, stream));
-    HIP_TRY(hipEventRecord(s.ev_main, stream));
+    if (events) HIP_TRY(hipEventRecord(s.ev_main, stream));
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
-    HIP_TRY(hipEventRecord(s.ev_end, stream));
+    if (events) HIP_TRY(hipEventRecord(s.ev_end, stream));
 }
 
 void capture_graph(mc_ctx* ctx, LaunchSlot& s)
 {
     if (s.graph) {
-        (void)hipGraphExecDestroy(s.graph);
+        quiet(hipGraphExecDestroy(s.graph));
         s.graph = nullptr;
     }
     hipStream_t cs;
@@ -658,15 +682,15 @@ void capture_graph(mc_ctx* ctx, LaunchSlot& s)
     hipGraph_t g = nullptr;
     try {
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        enqueue_kernels(ctx, s, cs);
+        enqueue_kernels(ctx, s, cs, false);
         HIP_TRY(hipStreamEndCapture(cs, &g));
         HIP_TRY(hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0));
     } catch (...) {
-        if (g) (void)hipGraphDestroy(g);
-        (void)hipStreamDestroy(cs);
+        if (g) quiet(hipGraphDestroy(g));
+        quiet(hipStreamDestroy(cs));
         throw;
     }
-    (void)hipGraphDestroy(g);
+    quiet(hipGraphDestroy(g));
     HIP_TRY(hipStreamDestroy(cs));
 }
 
@@ -785,11 +809,14 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     if (s.n_tiles64)
         HIP_TRY(hipMemcpyAsync(s.d_tiles64, s.h_tiles64, (size_t)s.n_tiles64 * sizeof(Tile), hipMemcpyHostToDevice, stream));
     if (s.n_fins) HIP_TRY(hipMemcpyAsync(s.d_fins, s.h_fins, (size_t)s.n_fins * sizeof(Fin), hipMemcpyHostToDevice, stream));
+    s.graphed = ctx->use_graph;
     if (ctx->use_graph) {
         if (!s.graph) capture_graph(ctx, s);
+        HIP_TRY(hipEventRecord(s.ev_start, stream));
         HIP_TRY(hipGraphLaunch(s.graph, stream));
+        HIP_TRY(hipEventRecord(s.ev_end, stream));
     } else {
-        enqueue_kernels(ctx, s, stream);
+        enqueue_kernels(ctx, s, stream, true);
     }
     if (s.n_fins)
         HIP_TRY(hipMemcpyAsync(s.h_results, s.d_results, (size_t)s.n_fins * sizeof(DevResult), hipMemcpyDeviceToHost,
@@ -836,17 +863,17 @@ void finish_abort(mc_ctx* ctx)
 void destroy_device(mc_ctx* ctx)
 {
     for (auto& s : ctx->slots) {
-        if (s.graph) (void)hipGraphExecDestroy(s.graph);
+        if (s.graph) quiet(hipGraphExecDestroy(s.graph));
         for (hipEvent_t e : {s.ev_start, s.ev_mid, s.ev_main, s.ev_end, s.ev_done})
-            if (e) (void)hipEventDestroy(e);
+            if (e) quiet(hipEventDestroy(e));
         for (void* p : {(void*)s.h_desc, (void*)s.h_tiles32, (void*)s.h_tiles64, (void*)s.h_fins, (void*)s.h_results})
-            if (p) (void)hipHostFree(p);
+            if (p) quiet(hipHostFree(p));
         s = LaunchSlot{};
     }
-    if (ctx->upload_stream) (void)hipStreamDestroy(ctx->upload_stream);
+    if (ctx->upload_stream) quiet(hipStreamDestroy(ctx->upload_stream));
     ctx->upload_stream = nullptr;
-    if (ctx->h_words) (void)hipHostFree(ctx->h_words);
-    if (ctx->owns_memory && ctx->mem_base) (void)hipFree(ctx->mem_base);
+    if (ctx->h_words) quiet(hipHostFree(ctx->h_words));
+    if (ctx->owns_memory && ctx->mem_base) quiet(hipFree(ctx->mem_base));
     ctx->h_words = nullptr;
     ctx->mem_base = nullptr;
 }
@@ -979,9 +1006,9 @@ mc_status mc_destroy(mc_ctx* ctx)
 {
     if (!ctx) return MC_OK;
     if (!ctx->validate_only) {
-        (void)hipSetDevice(ctx->device);
+        quiet(hipSetDevice(ctx->device));
         for (auto& s : ctx->slots)
-            if (s.in_flight) (void)hipEventSynchronize(s.ev_done);
+            if (s.in_flight) quiet(hipEventSynchronize(s.ev_done));
     }
     for (auto& kv : ctx->requests) free_packed(kv.second.get());
     if (!ctx->validate_only) destroy_device(ctx);
@@ -1199,9 +1226,9 @@ mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n,
     } catch (const HipError& e) {
         status = fail_hip(ctx, e);
     }
-    if (d_fns) (void)hipFree(d_fns);
-    if (d_parts) (void)hipFree(d_parts);
-    if (d_res) (void)hipFree(d_res);
+    if (d_fns) quiet(hipFree(d_fns));
+    if (d_parts) quiet(hipFree(d_parts));
+    if (d_res) quiet(hipFree(d_res));
     return status;
 }
 
@@ -1231,9 +1258,9 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
         ctx->blocks_per_cu32 = blocks_per_cu;
         // graphs bake the grid size in: recapture lazily
         for (auto& s : ctx->slots) {
-            if (s.in_flight) (void)hipEventSynchronize(s.ev_done);
+            if (s.in_flight) quiet(hipEventSynchronize(s.ev_done));
             if (s.graph) {
-                (void)hipGraphExecDestroy(s.graph);
+                quiet(hipGraphExecDestroy(s.graph));
                 s.graph = nullptr;
             }
         }

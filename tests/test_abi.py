@@ -44,7 +44,7 @@ def test_struct_sizes(Z):
     assert W.FUNC_DTYPE.itemsize == 472
     assert _native.RESULT_DTYPE.itemsize == 48
     assert ctypes.sizeof(_native.McConfig) == 56
-    assert ctypes.sizeof(_native.McStats) == 80
+    assert ctypes.sizeof(_native.McStats) == 88
 
 
 def test_validate_only_accepts_workloads(Z):
