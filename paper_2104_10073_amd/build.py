@@ -46,7 +46,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     os.makedirs(BUILD, exist_ok=True)
     objs = []
     procs = []
-    headers = [os.path.join(CSRC, "zmc_device.hpp"), os.path.join(INCLUDE, "zmc.h")]
+    headers = [os.path.join(CSRC, "zmc_device.hpp"), os.path.join(CSRC, "zmc_device_code.hpp"),
+               os.path.join(INCLUDE, "zmc.h")]
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))
         objs.append(obj)

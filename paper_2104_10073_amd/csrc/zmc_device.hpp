@@ -25,7 +25,13 @@ constexpr int kSegSamples = 4 * kSegQuads;            // 4096 samples
 constexpr int kBlockWaves = 4;                        // waves per workgroup
 constexpr int kBlockThreads = kWave * kBlockWaves;    // 256
 constexpr int kMaxSegLog2 = 6;                        // at most 64 segments per wave per tile
-constexpr int kNumFamilies = 4;
+constexpr int kNumFamilies = 4;                       // built-in families
+constexpr int kMaxUserFamilies = 8;                   // run-time compiled families
+constexpr uint32_t kUserFamily0 = 16;                 // family id of the first run-time family
+constexpr int kKernelBuiltin32 = 0;                   // kernel indices: built-in FP32, built-in FP64,
+constexpr int kKernelBuiltin64 = 1;                   //   then FP32 / FP64 of each run-time family
+constexpr int kMaxKernels = 2 + 2 * kMaxUserFamilies;
+constexpr int kUserParams = 32;
 
 enum Family : uint32_t { HARMONIC = 0, ABS_LINEAR = 1, GAUSSIAN = 2, POLY_PRODUCT = 3 };
 
@@ -60,6 +66,10 @@ struct alignas(64) DevFn {
     float f0, f0lo;               // HARMONIC phase offset (revolutions); ABS offset as hi + lo
     uint32_t kfam;                // family as the kernels dispatch on it
     uint32_t pad_;
+
+    // Run-time compiled families: the caller's parameters as given and rounded to FP32.
+    double up[kUserParams];
+    float up32[kUserParams];
 };
 
 // A tile: segments [seg0, seg0 + 4 << seg_log2) of function fn (clipped to the
@@ -92,20 +102,19 @@ struct DevResult {
 };
 
 // Counters of one launch (zeroed by every descriptor upload).
-constexpr int kCounterTiles32 = 0;     // next FP32 tile to fetch
-constexpr int kCounterTiles64 = 1;     // next FP64 tile to fetch
-constexpr int kCounterAborted = 2;     // a workgroup stopped because the abort word was set
-constexpr int kCounterBadRecords = 3;  // tile or finalize records that failed their bounds checks
-constexpr int kNumCounters = 4;
+constexpr int kCounterAborted = 0;     // a workgroup stopped because the abort word was set
+constexpr int kCounterBadRecords = 1;  // tile or finalize records that failed their bounds checks
+constexpr int kCounterTiles = 2;       // kMaxKernels words: next tile of each kernel
+constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 
 // Everything one launch reads; lives in device memory at a fixed address per
-// launch slot so a captured graph can be replayed with new contents.  FP32 and
-// FP64 tiles go to two kernels (each with its own register budget); both
-// write into the same partial arena, then one finalize kernel runs.
+// launch slot so a captured graph can be replayed with new contents.  The tile
+// list is cut into one contiguous part per kernel (built-in FP32, built-in
+// FP64, each run-time family in FP32 and FP64); every kernel walks its part and
+// writes into the same partial arena, then one finalize kernel runs.
 struct alignas(64) LaunchDesc {
     const DevFn* fns;
-    const Tile* tiles32;
-    const Tile* tiles64;
+    const Tile* tiles;
     Partial* partials;
     const Fin* fins;
     DevResult* results;
@@ -113,9 +122,9 @@ struct alignas(64) LaunchDesc {
     const uint32_t* abort_word;            // device word; nonzero asks the kernels to stop fetching tiles
     uint64_t n_partials;                   // size of the partial arena (bounds checks)
     uint32_t n_fns;                        // size of the function table (bounds checks)
-    uint32_t n_tiles32;
-    uint32_t n_tiles64;
     uint32_t n_fins;
+    uint32_t tile_begin[kMaxKernels];
+    uint32_t tile_count[kMaxKernels];
 };
 
 }  // namespace zmc

@@ -8,6 +8,7 @@
 // finalize, result copy) on the caller's stream from a small ring of launch
 // slots, each with a captured HIP graph.
 #include <hip/hip_runtime.h>
+#include <hip/hiprtc.h>
 
 #include <algorithm>
 #include <chrono>
@@ -31,6 +32,10 @@ const void* plain_kernel_ptr();
 const void* batched_kernel_ptr(bool fp64);
 const void* finalize_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
+// Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
+// compiling caller-supplied families at run time.
+extern const char* const kRtcHeaderDevice;
+extern const char* const kRtcHeaderCode;
 }  // namespace zmc
 
 using namespace zmc;
@@ -125,6 +130,14 @@ private:
     uint64_t cap_ = 0, used_ = 0;
     std::map<uint64_t, uint64_t> free_;
 };
+
+// Index of the kernel that evaluates a family at a precision: the two built-in
+// kernels, then one FP32/FP64 pair per run-time family.
+int kernel_index(uint32_t family, bool f64)
+{
+    if (family < (uint32_t)kNumFamilies) return f64 ? kKernelBuiltin64 : kKernelBuiltin32;
+    return 2 + 2 * (int)(family - kUserFamily0) + (f64 ? 1 : 0);
+}
 
 // ---------------------------------------------------------------- validation
 
@@ -334,14 +347,12 @@ struct FinRef {
 struct LaunchSlot {
     // device
     LaunchDesc* d_desc = nullptr;   // followed by 4 counters (uint32) in the same allocation
-    Tile* d_tiles32 = nullptr;
-    Tile* d_tiles64 = nullptr;
+    Tile* d_tiles = nullptr;          // tile list, one contiguous part per kernel
     Fin* d_fins = nullptr;
     DevResult* d_results = nullptr;
     // pinned host
     uint8_t* h_desc = nullptr;      // LaunchDesc + counters
-    Tile* h_tiles32 = nullptr;
-    Tile* h_tiles64 = nullptr;
+    Tile* h_tiles = nullptr;
     Fin* h_fins = nullptr;
     DevResult* h_results = nullptr;
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
@@ -349,13 +360,15 @@ struct LaunchSlot {
     bool in_flight = false;
     bool graphed = false;             // this launch replayed the slot's graph
     uint64_t seq = 0;
-    uint32_t n_tiles32 = 0, n_tiles64 = 0, n_fins = 0;
+    uint32_t n_tiles = 0, n_fins = 0;
+    std::vector<Tile> kt[kMaxKernels];  // tiles of each kernel while the launch is built
+    uint32_t tile_begin[kMaxKernels] = {}, tile_count[kMaxKernels] = {};
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
     std::vector<Request*> touched;  // requests with tiles in this launch
 };
 
-constexpr size_t kDescBytes = 256;  // LaunchDesc followed by its counters
+constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters
 static_assert(sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t) <= kDescBytes, "launch descriptor size");
 
 }  // namespace
@@ -442,7 +455,7 @@ Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t ti
     L.slot_desc = off;
     off = align_up(off + kLaunchSlots * kDescBytes, 256);
     L.slot_tiles = off;
-    off = align_up(off + (uint64_t)kLaunchSlots * 2 * tile_cap * sizeof(Tile), 256);
+    off = align_up(off + (uint64_t)kLaunchSlots * tile_cap * sizeof(Tile), 256);
     L.slot_fins = off;
     off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(Fin), 256);
     L.slot_results = off;
@@ -603,8 +616,10 @@ void reap(mc_ctx* ctx, int wait)
                 }
             }
             ctx->stats.launches++;
-            ctx->stats.tiles32 += s.n_tiles32;
-            ctx->stats.tiles64 += s.n_tiles64;
+            for (int k = 0; k < kMaxKernels; ++k) {
+                if (k % 2 == 0) ctx->stats.tiles32 += s.tile_count[k];
+                else ctx->stats.tiles64 += s.tile_count[k];
+            }
             ctx->stats.functions += s.n_fins;
             ctx->stats.samples += s.n_samples;
             ctx->stats.bad_records += bad;
@@ -705,15 +720,16 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         const bool in_order = r->order_pos < r->order.size();
         const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
         FnState& fs = r->st[fi];
-        uint32_t& nt = fs.f64 ? s.n_tiles64 : s.n_tiles32;
-        Tile* out = fs.f64 ? s.h_tiles64 : s.h_tiles32;
+        std::vector<Tile>& out = s.kt[kernel_index(r->fns[fi].family, fs.f64)];
         const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
         const uint64_t tile_samples = (uint64_t)per_tile * kSegSamples;
         const uint64_t fn_samples = r->fns[fi].n_samples;
-        while (fs.next_tile < fs.n_tiles && nt < ctx->tile_cap && taken < budget) {
+        while (fs.next_tile < fs.n_tiles && s.n_tiles < ctx->tile_cap && taken < budget) {
             const uint64_t first = (uint64_t)fs.next_tile * tile_samples;
             s.n_samples += std::min<uint64_t>(tile_samples, fn_samples - first);
-            Tile& t = out[nt++];
+            out.emplace_back();
+            s.n_tiles++;
+            Tile& t = out.back();
             t.fn = fs.slot;
             t.seg0 = fs.next_tile * per_tile;
             t.seg_log2 = fs.seg_log2;
@@ -724,7 +740,7 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         }
         if (taken > 0 && (s.touched.empty() || s.touched.back() != r)) s.touched.push_back(r);
         if (fs.next_tile < fs.n_tiles) {
-            room = nt < ctx->tile_cap;
+            room = s.n_tiles < ctx->tile_cap;
             break;
         }
         if (s.n_fins >= ctx->fin_cap) {
@@ -762,7 +778,8 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         return false;
     }
     LaunchSlot& s = *slot;
-    s.n_tiles32 = s.n_tiles64 = s.n_fins = 0;
+    s.n_tiles = s.n_fins = 0;
+    for (auto& v : s.kt) v.clear();
     s.n_samples = 0;
     s.fin_refs.clear();
     s.touched.clear();
@@ -778,7 +795,17 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         if (has_work(r)) keep.push_back(r);
     }
     ctx->active.swap(keep);
-    if (s.n_tiles32 == 0 && s.n_tiles64 == 0 && s.n_fins == 0) return false;
+    if (s.n_tiles == 0 && s.n_fins == 0) return false;
+    // concatenate the kernels' tiles into the staging list
+    {
+        uint32_t off = 0;
+        for (int k = 0; k < kMaxKernels; ++k) {
+            s.tile_begin[k] = off;
+            s.tile_count[k] = (uint32_t)s.kt[k].size();
+            if (!s.kt[k].empty()) std::memcpy(s.h_tiles + off, s.kt[k].data(), s.kt[k].size() * sizeof(Tile));
+            off += s.tile_count[k];
+        }
+    }
 
     // Launches may be enqueued on different streams; a function's tiles can span
     // launches, so each launch waits for the previous one, and for the uploads
@@ -790,8 +817,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     LaunchDesc* hd = (LaunchDesc*)s.h_desc;
     std::memset(s.h_desc, 0, kDescBytes);
     hd->fns = ctx->d_fns;
-    hd->tiles32 = s.d_tiles32;
-    hd->tiles64 = s.d_tiles64;
+    hd->tiles = s.d_tiles;
     hd->partials = ctx->d_partials;
     hd->fins = s.d_fins;
     hd->results = s.d_results;
@@ -799,15 +825,15 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     hd->abort_word = ctx->d_abort_word;
     hd->n_partials = ctx->max_partials;
     hd->n_fns = ctx->max_functions;
-    hd->n_tiles32 = s.n_tiles32;
-    hd->n_tiles64 = s.n_tiles64;
+    for (int k = 0; k < kMaxKernels; ++k) {
+        hd->tile_begin[k] = s.tile_begin[k];
+        hd->tile_count[k] = s.tile_count[k];
+    }
     hd->n_fins = s.n_fins;
     // the previous use of this slot's staging has completed (slot not in flight)
     HIP_TRY(hipMemcpyAsync(s.d_desc, s.h_desc, kDescBytes, hipMemcpyHostToDevice, stream));
-    if (s.n_tiles32)
-        HIP_TRY(hipMemcpyAsync(s.d_tiles32, s.h_tiles32, (size_t)s.n_tiles32 * sizeof(Tile), hipMemcpyHostToDevice, stream));
-    if (s.n_tiles64)
-        HIP_TRY(hipMemcpyAsync(s.d_tiles64, s.h_tiles64, (size_t)s.n_tiles64 * sizeof(Tile), hipMemcpyHostToDevice, stream));
+    if (s.n_tiles)
+        HIP_TRY(hipMemcpyAsync(s.d_tiles, s.h_tiles, (size_t)s.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, stream));
     if (s.n_fins) HIP_TRY(hipMemcpyAsync(s.d_fins, s.h_fins, (size_t)s.n_fins * sizeof(Fin), hipMemcpyHostToDevice, stream));
     s.graphed = ctx->use_graph;
     if (ctx->use_graph) {
@@ -866,7 +892,7 @@ void destroy_device(mc_ctx* ctx)
         if (s.graph) quiet(hipGraphExecDestroy(s.graph));
         for (hipEvent_t e : {s.ev_start, s.ev_mid, s.ev_main, s.ev_end, s.ev_done})
             if (e) quiet(hipEventDestroy(e));
-        for (void* p : {(void*)s.h_desc, (void*)s.h_tiles32, (void*)s.h_tiles64, (void*)s.h_fins, (void*)s.h_results})
+        for (void* p : {(void*)s.h_desc, (void*)s.h_tiles, (void*)s.h_fins, (void*)s.h_results})
             if (p) quiet(hipHostFree(p));
         s = LaunchSlot{};
     }
@@ -970,13 +996,11 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         for (int i = 0; i < kLaunchSlots; ++i) {
             LaunchSlot& s = ctx->slots[i];
             s.d_desc = (LaunchDesc*)(base + L.slot_desc + (uint64_t)i * kDescBytes);
-            s.d_tiles32 = (Tile*)(base + L.slot_tiles) + (uint64_t)i * 2 * ctx->tile_cap;
-            s.d_tiles64 = s.d_tiles32 + ctx->tile_cap;
+            s.d_tiles = (Tile*)(base + L.slot_tiles) + (uint64_t)i * ctx->tile_cap;
             s.d_fins = (Fin*)(base + L.slot_fins) + (uint64_t)i * ctx->fin_cap;
             s.d_results = (DevResult*)(base + L.slot_results) + (uint64_t)i * ctx->fin_cap;
             HIP_TRY(hipHostMalloc((void**)&s.h_desc, kDescBytes, hipHostMallocDefault));
-            HIP_TRY(hipHostMalloc((void**)&s.h_tiles32, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
-            HIP_TRY(hipHostMalloc((void**)&s.h_tiles64, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
+            HIP_TRY(hipHostMalloc((void**)&s.h_tiles, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
             HIP_TRY(hipHostMalloc((void**)&s.h_fins, (size_t)ctx->fin_cap * sizeof(Fin), hipHostMallocDefault));
             HIP_TRY(hipHostMalloc((void**)&s.h_results, (size_t)ctx->fin_cap * sizeof(DevResult), hipHostMallocDefault));
             HIP_TRY(hipEventCreate(&s.ev_start));

@@ -1,486 +1,42 @@
-// zmc_kernels.hip -- gfx950 kernels of the multi-function direct Monte Carlo path.
-//
-// Per sample (paper, "Solution method": direct Monte Carlo per integrand):
-//   1. counter-based uniforms: Philox4x32-10 (SC'11) in registers;
-//   2. mapping into the function's box;
-//   3. the integrand (Eq. (1) harmonic, Eq. (2) |linear|, Gaussian, product polynomial);
-//   4. compensated per-lane sums of f and f^2;
-// then per segment a fixed 64-lane butterfly in FP64, per tile an LDS tree over
-// its segments, and per function an atomic-free FP64 finalize pass giving the
-// mean and standard error.  No MFMA: nothing here is a dense contraction; the
-// bound is VALU issue (integer multiplies of Philox, FP32 FMAs, transcendentals).
-//
-// Sample layout.  Samples are handled four at a time (a quad): quad q of a
-// d-dimensional function uses Philox blocks q*d .. q*d + d - 1, and block
-// q*d + j holds coordinate j of the quad's four samples, one per output word.
-// So one lane evaluates a quad with a loop over the coordinates that produces
-// one block and folds its four words into four sample states: the dimension is
-// a runtime loop bound and a single code path serves d = 1..12.
+// zmc_kernels.hip -- the built-in gfx950 kernels: the persistent batched kernels
+// for the four built-in families (FP32 and FP64 evaluation), the finalize pass,
+// and the plain one-launch-per-function FP64 path.  The device code itself is in
+// zmc_device_code.hpp.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "zmc_device.hpp"
+#include <type_traits>
+
+#include "zmc_device_code.hpp"
 
 namespace zmc {
 
-// ---------------------------------------------------------------- Philox4x32-10
-
-constexpr uint32_t kPhiloxM0 = 0xD2511F53u;
-constexpr uint32_t kPhiloxM1 = 0xCD9E8D57u;
-constexpr uint32_t kPhiloxW0 = 0x9E3779B9u;
-constexpr uint32_t kPhiloxW1 = 0xBB67AE85u;
-
-__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
-{
-    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);  // a ^ b ^ c in one VALU op
-}
-
-// Block at counter (b_lo, b_hi, 0, 0).  The two zero counter words make the first
-// round a single product and the second round's first xor two-input; from the
-// third round on every round is two 32x32->64 products and two 3-input xors.
-// Round keys are wave-uniform and stay in scalar registers.
-__device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint32_t k0, uint32_t k1,
-                                             uint32_t out[4])
-{
-    uint32_t c0, c1, c2, c3;
-    {   // round 1: c2 = c3 = 0
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * b_lo;
-        c0 = b_hi ^ k0;
-        c1 = 0u;
-        c2 = (uint32_t)(p0 >> 32) ^ k1;
-        c3 = (uint32_t)p0;
-    }
-    k0 += kPhiloxW0;
-    k1 += kPhiloxW1;
-    {   // round 2: c1 = 0
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = (uint32_t)(p1 >> 32) ^ k0;
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-    }
-#pragma unroll
-    for (int r = 2; r < 10; ++r) {
-        k0 += kPhiloxW0;
-        k1 += kPhiloxW1;
-        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
-        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
-        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
-        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
-        c1 = (uint32_t)p1;
-        c3 = (uint32_t)p0;
-        c0 = n0;
-        c2 = n2;
-    }
-    out[0] = c0;
-    out[1] = c1;
-    out[2] = c2;
-    out[3] = c3;
-}
-
-// ---------------------------------------------------------------- function records
-
-// Function records are read-only while kernels run.  Reading them through the
-// constant address space turns every wave-uniform field access into a scalar
-// load (scalar cache, scalar registers) instead of 64 identical vector loads.
-typedef const __attribute__((address_space(4))) DevFn CDevFn;
-
-__device__ __forceinline__ CDevFn* scalar_view(const DevFn* p)
-{
-    return (CDevFn*)(uintptr_t)p;
-}
-
-// ---------------------------------------------------------------- uniforms
-
-// t = 1 + m 2^-23 in [1, 2) from the low 23 bits m of a word: one VALU op.
-// The uniform of the definition is u = t - (1 - 2^-24) exactly.
-__device__ __forceinline__ float word_to_t(uint32_t r)
-{
-    return __uint_as_float((r & 0x007FFFFFu) | 0x3F800000u);
-}
-
-constexpr float kTShift = 0x1.fffffep-1f;  // 1 - 2^-24
-
-// u = (2 m + 1) 2^-24 in FP64, exact.
-__device__ __forceinline__ double word_to_u64(uint32_t r)
-{
-    return (double)(((r & 0x007FFFFFu) << 1) | 1u) * 0x1p-24;
-}
-
-// ---------------------------------------------------------------- FP32 integrands
-
-// An evaluator holds a function (wave-uniform pointer) and works on the four
-// samples of a quad: init() sets their states, add(st, j, w) folds coordinate j
-// from the block's four words, finish() returns g with f = scale1 * g (scale1
-// and scale2 = scale1^2 are applied in FP64 at finalize).  Coefficients were
-// derived on the host in FP64 and rounded once; they are read with scalar loads.
-
-template <int FAM> struct Eval32;
-
-// Eq. (1): a cos(theta) + b sin(theta) = R cos(theta - phi).  The phase in
-// revolutions is f0 + sum_j kappa_j t_j; v_fract + v_cos_f32 (which computes
-// cos(2 pi x)) give the cosine: one transcendental per sample.
-template <> struct Eval32<HARMONIC> {
-    CDevFn* fn;
-    __device__ __forceinline__ void init(float st[4]) const
-    {
-        const float f0 = fn->f0;
-        for (int s = 0; s < 4; ++s) st[s] = f0;
-    }
-    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
-    {
-        const float c = fn->fc[j];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), st[s]);
-    }
-    __device__ __forceinline__ float finish(float th) const
-    {
-        return __builtin_amdgcn_cosf(__builtin_amdgcn_fractf(th));
-    }
-};
-
-// Eq. (2): a |c0 + c.x|; the offset is carried as a two-float sum so the
-// hyperplane is placed to FP64 accuracy.
-template <> struct Eval32<ABS_LINEAR> {
-    CDevFn* fn;
-    __device__ __forceinline__ void init(float st[4]) const
-    {
-        const float f0 = fn->f0;
-        for (int s = 0; s < 4; ++s) st[s] = f0;
-    }
-    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
-    {
-        const float c = fn->fc[j];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), st[s]);
-    }
-    __device__ __forceinline__ float finish(float st) const { return fabsf(st + fn->f0lo); }
-};
-
-// A exp(-|x - mu|^2 / (2 sigma^2)) = A 2^(-sum_j (c_j (t_j - m_j))^2); t - m is
-// exact (both in [1, 2] for a centre inside the box), v_exp_f32 computes 2^x.
-template <> struct Eval32<GAUSSIAN> {
-    CDevFn* fn;
-    __device__ __forceinline__ void init(float st[4]) const
-    {
-        for (int s = 0; s < 4; ++s) st[s] = 0.0f;
-    }
-    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
-    {
-        const float c = fn->fc[j], m = fn->fo[j];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            const float y = c * (word_to_t(w[s]) - m);
-            st[s] = fmaf(y, y, st[s]);
-        }
-    }
-    __device__ __forceinline__ float finish(float q) const { return __builtin_amdgcn_exp2f(-q); }
-};
-
-// prod_j (1 + p_j x_j^{n_j}), x_j = lo_j + w_j u_j with u_j = t_j - (1 - 2^-24)
-// exact; the power is a wave-uniform loop shared by the quad's four samples.
-template <> struct Eval32<POLY_PRODUCT> {
-    CDevFn* fn;
-    __device__ __forceinline__ void init(float st[4]) const
-    {
-        for (int s = 0; s < 4; ++s) st[s] = 1.0f;
-    }
-    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
-    {
-        const float c = fn->fc[j], o = fn->fo[j], p = fn->fp[j];
-        const int e = fn->deg[j];
-        float x[4], xp[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) {
-            x[s] = fmaf(c, word_to_t(w[s]) - kTShift, o);
-            xp[s] = 1.0f;
-        }
-        for (int k = 0; k < e; ++k) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) xp[s] *= x[s];
-        }
-#pragma unroll
-        for (int s = 0; s < 4; ++s) st[s] *= fmaf(p, xp[s], 1.0f);
-    }
-    __device__ __forceinline__ float finish(float g) const { return g; }
-};
-
-// ---------------------------------------------------------------- FP64 integrands
-
-// The definition in its reference operation order (explicit fma), FP64 libm.
-template <int FAM> struct Eval64 {
-    CDevFn* fn;
-    __device__ __forceinline__ void init(double st[4]) const
-    {
-        double v = 0.0;
-        if constexpr (FAM == ABS_LINEAR) v = fn->s1;
-        if constexpr (FAM == POLY_PRODUCT) v = 1.0;
-        for (int s = 0; s < 4; ++s) st[s] = v;
-    }
-    __device__ __forceinline__ void add(double st[4], uint32_t j, const uint32_t w[4]) const
-    {
-        const double lo = fn->lo[j], wd = fn->w[j], v = fn->v[j];
-        double x[4];
-#pragma unroll
-        for (int s = 0; s < 4; ++s) x[s] = fma(wd, word_to_u64(w[s]), lo);
-        if constexpr (FAM == HARMONIC || FAM == ABS_LINEAR) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) st[s] = fma(v, x[s], st[s]);
-        } else if constexpr (FAM == GAUSSIAN) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s) {
-                const double t = x[s] - v;
-                st[s] = fma(t, t, st[s]);
-            }
-        } else {
-            const int e = fn->deg[j];
-            double xp[4] = {1.0, 1.0, 1.0, 1.0};
-            for (int k = 0; k < e; ++k) {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) xp[s] *= x[s];
-            }
-#pragma unroll
-            for (int s = 0; s < 4; ++s) st[s] *= fma(v, xp[s], 1.0);
-        }
-    }
-    __device__ __forceinline__ double finish(double st) const
-    {
-        if constexpr (FAM == HARMONIC) {
-            double sn, cs;
-            sincos(st, &sn, &cs);
-            return fma(fn->s0, cs, fn->s1 * sn);
-        } else if constexpr (FAM == ABS_LINEAR) {
-            return fn->s0 * fabs(st);
-        } else if constexpr (FAM == GAUSSIAN) {
-            return fn->s0 * exp(-st * fn->h);
-        } else {
-            return st;
-        }
-    }
-};
-
-// One quad q of samples: d Philox blocks q*d .. q*d + d - 1, block j giving
-// coordinate j of the four samples.
-template <class Ev, class T>
-__device__ __forceinline__ void eval_quad(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, T g[4])
-{
-    T st[4];
-    ev.init(st);
-    const uint64_t b0 = q * (uint64_t)d;
-    for (uint32_t j = 0; j < d; ++j) {
-        const uint64_t b = b0 + j;
-        uint32_t w[4];
-        philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
-        ev.add(st, j, w);
-    }
-#pragma unroll
-    for (int s = 0; s < 4; ++s) g[s] = ev.finish(st[s]);
-}
-
-// ---------------------------------------------------------------- reductions
-
-// Fixed xor butterfly: level m pairs lanes l and l^m, so the result is the
-// pairwise tree over lane order and every lane holds the same bits.
-__device__ __forceinline__ double wave_sum(double v)
-{
-#pragma unroll
-    for (int m = 1; m < kWave; m <<= 1) v += __shfl_xor(v, m, kWave);
-    return v;
-}
-
-__device__ __forceinline__ void kahan_add(float& s, float& c, float x)
-{
-    const float y = x - c;
-    const float t = s + y;
-    c = (t - s) - y;
-    s = t;
-}
-
-// ---------------------------------------------------------------- one segment
-
-// Lane sums over the lane's 16 quads of one segment.  `tail` marks the
-// function's last segment, the only one that can hold quads or samples past N.
-template <int FAM>
-__device__ __forceinline__ void segment_fp32(const Eval32<FAM>& ev, uint32_t d, uint32_t k0, uint32_t k1,
-                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
-                                             double& out1, double& out2)
-{
-    float s1 = 0.0f, c1 = 0.0f, s2 = 0.0f, c2 = 0.0f;
-#pragma unroll 1
-    for (int k = 0; k < kQuadsPerLane; ++k) {
-        const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (tail && q >= n_quads) break;
-        float g[4];
-        eval_quad(ev, d, k0, k1, q, g);
-        if (tail) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                if (4 * q + (uint64_t)s >= n_samples) g[s] = 0.0f;
-        }
-        const float a1 = (g[0] + g[1]) + (g[2] + g[3]);
-        const float a2 = fmaf(g[1], g[1], g[0] * g[0]) + fmaf(g[3], g[3], g[2] * g[2]);
-        kahan_add(s1, c1, a1);
-        kahan_add(s2, c2, a2);
-    }
-    out1 = (double)s1 - (double)c1;
-    out2 = (double)s2 - (double)c2;
-}
-
-template <int FAM>
-__device__ __forceinline__ void segment_fp64(const Eval64<FAM>& ev, uint32_t d, uint32_t k0, uint32_t k1,
-                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
-                                             double& out1, double& out2)
-{
-    double s1 = 0.0, s2 = 0.0;
-#pragma unroll 1
-    for (int k = 0; k < kQuadsPerLane; ++k) {
-        const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (tail && q >= n_quads) break;
-        double f[4];
-        eval_quad(ev, d, k0, k1, q, f);
-        if (tail) {
-#pragma unroll
-            for (int s = 0; s < 4; ++s)
-                if (4 * q + (uint64_t)s >= n_samples) f[s] = 0.0;
-        }
-        s1 += (f[0] + f[1]) + (f[2] + f[3]);
-        s2 += (f[0] * f[0] + f[1] * f[1]) + (f[2] * f[2] + f[3] * f[3]);
-    }
-    out1 = s1;
-    out2 = s2;
-}
-
-// ---------------------------------------------------------------- one tile
-
-// Wave `wave` of the workgroup evaluates segments seg0 + wave*2^L + i, i < 2^L,
-// and leaves each segment's (S1, S2) in LDS slot wave*2^L + i (zero past the
-// function's last segment).  All arguments are wave-uniform.
-template <bool F64, int FAM>
-__device__ __forceinline__ void tile_segments(CDevFn* fn, uint32_t seg0, uint32_t seg_log2, uint32_t wave,
-                                              uint32_t lane, Partial* s_seg)
-{
-    const uint32_t per_wave = 1u << seg_log2;
-    const uint32_t n_seg = fn->n_segments;
-    const uint64_t n_quads = fn->n_quads;
-    const uint64_t n_samples = fn->n_samples;
-    const uint32_t d = fn->dim;
-    const uint32_t k0 = fn->key0, k1 = fn->key1;
-    const uint32_t first = seg0 + wave * per_wave;
-    for (uint32_t i = 0; i < per_wave; ++i) {
-        const uint32_t seg = first + i;
-        double a = 0.0, b = 0.0;
-        if (seg < n_seg) {
-            const uint64_t quad0 = (uint64_t)seg * kSegQuads + lane;
-            const bool tail = (uint64_t)(seg + 1) * kSegSamples > n_samples;
-            if constexpr (F64) {
-                const Eval64<FAM> ev{fn};
-                segment_fp64<FAM>(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
-            } else {
-                const Eval32<FAM> ev{fn};
-                segment_fp32<FAM>(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
-            }
-            a = wave_sum(a);
-            b = wave_sum(b);
-        }
-        if (lane == 0) s_seg[wave * per_wave + i] = Partial{a, b};
-    }
-}
-
-// Pairwise tree over the tile's 4 * 2^L segment sums (L <= 6, so at most 4 per lane),
-// then the lane butterfly: the same tree as over the whole function.
-__device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, uint32_t lane, Partial* out)
-{
-    const uint32_t per = count > kWave ? count / kWave : 1u;
-    double a = 0.0, b = 0.0;
-    if (lane * per < count) {
-        const Partial* p = s_seg + lane * per;
-        if (per == 1) {
-            a = p[0].s1;
-            b = p[0].s2;
-        } else if (per == 2) {
-            a = p[0].s1 + p[1].s1;
-            b = p[0].s2 + p[1].s2;
-        } else {
-            a = (p[0].s1 + p[1].s1) + (p[2].s1 + p[3].s1);
-            b = (p[0].s2 + p[1].s2) + (p[2].s2 + p[3].s2);
-        }
-    }
-    a = wave_sum(a);
-    b = wave_sum(b);
-    if (lane == 0) *out = Partial{a, b};
-}
-
-// ---------------------------------------------------------------- kernels
-
-// Persistent batched kernel: every workgroup fetches tiles from the launch's
-// tile list through one counter until the list is exhausted (or the abort word
-// in device memory is set), evaluates them, and writes one partial per tile.
-// Indices read from the lists are checked against the launch's bounds; a bad
-// record is skipped and counted instead of being dereferenced.
+// Family dispatch of the built-in kernels (a wave-uniform branch per tile).
 template <bool F64>
-__device__ __forceinline__ void batched_body(const LaunchDesc* __restrict__ Ld)
-{
-    __shared__ Partial s_seg[kBlockWaves << kMaxSegLog2];
-    __shared__ uint32_t s_tile;
-    const DevFn* fns = Ld->fns;
-    const Tile* tiles = F64 ? Ld->tiles64 : Ld->tiles32;
-    const uint32_t n_tiles = F64 ? Ld->n_tiles64 : Ld->n_tiles32;
-    const uint32_t n_fns = Ld->n_fns;
-    const uint64_t n_partials = Ld->n_partials;
-    uint32_t* counters = Ld->counters;
-    const uint32_t* abort_word = Ld->abort_word;
-    Partial* partials = Ld->partials;
-    const uint32_t lane = threadIdx.x & (kWave - 1);
-    const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    for (uint32_t iter = 0;; ++iter) {
-        if (threadIdx.x == 0) {
-            uint32_t ti = atomicAdd(&counters[F64 ? kCounterTiles64 : kCounterTiles32], 1u);
-            if ((iter & 7u) == 0u &&
-                __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
-                atomicOr(&counters[kCounterAborted], 1u);
-                ti = n_tiles;
-            }
-            s_tile = ti;
+struct BuiltinDispatch {
+    template <int FAM>
+    using Ev = typename std::conditional<F64, Eval64<FAM>, Eval32<FAM>>::type;
+    __device__ static __forceinline__ bool run(CDevFn* fn, uint32_t fam, uint32_t seg0, uint32_t seg_log2,
+                                               uint32_t wave, uint32_t lane, Partial* s_seg)
+    {
+        switch (fam) {
+        case HARMONIC: tile_segments<Ev<HARMONIC>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
+        case ABS_LINEAR: tile_segments<Ev<ABS_LINEAR>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
+        case GAUSSIAN: tile_segments<Ev<GAUSSIAN>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
+        case POLY_PRODUCT: tile_segments<Ev<POLY_PRODUCT>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
+        default: return false;
         }
-        __syncthreads();
-        const uint32_t ti = __builtin_amdgcn_readfirstlane(s_tile);
-        if (ti >= n_tiles) break;
-        const Tile t = tiles[ti];
-        const uint32_t fi = __builtin_amdgcn_readfirstlane(t.fn);
-        const uint32_t seg0 = __builtin_amdgcn_readfirstlane(t.seg0);
-        const uint32_t seg_log2 = __builtin_amdgcn_readfirstlane(t.seg_log2);
-        const uint32_t out = __builtin_amdgcn_readfirstlane(t.out);
-        bool ok = fi < n_fns && seg_log2 <= (uint32_t)kMaxSegLog2 && out < n_partials;
-        CDevFn* fn = scalar_view(fns + (ok ? fi : 0u));
-        const uint32_t fam = fn->kfam;
-        const uint32_t dim = fn->dim;
-        ok = ok && dim >= 1 && dim <= (uint32_t)kMaxDim && fam <= (uint32_t)POLY_PRODUCT;
-        if (ok) {
-            switch (fam) {
-            case HARMONIC: tile_segments<F64, HARMONIC>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-            case ABS_LINEAR: tile_segments<F64, ABS_LINEAR>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-            case GAUSSIAN: tile_segments<F64, GAUSSIAN>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-            default: tile_segments<F64, POLY_PRODUCT>(fn, seg0, seg_log2, wave, lane, s_seg); break;
-            }
-        } else if (threadIdx.x == 0) {
-            atomicAdd(&counters[kCounterBadRecords], 1u);
-        }
-        __syncthreads();
-        if (ok && wave == 0) tile_tree(s_seg, (uint32_t)kBlockWaves << seg_log2, lane, &partials[out]);
     }
-}
+};
 
 extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp32(const LaunchDesc* __restrict__ Ld)
 {
-    batched_body<false>(Ld);
+    batched_body<BuiltinDispatch<false>>(Ld, kKernelBuiltin32);
 }
 
 extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(const LaunchDesc* __restrict__ Ld)
 {
-    batched_body<true>(Ld);
+    batched_body<BuiltinDispatch<true>>(Ld, kKernelBuiltin64);
 }
 
 // Per-function second pass, one wave per function: the tile partials are summed
@@ -556,7 +112,7 @@ template <int FAM>
 __device__ __forceinline__ void plain_quad(CDevFn* fn, uint64_t q, double f[4])
 {
     const Eval64<FAM> ev{fn};
-    eval_quad(ev, fn->dim, fn->key0, fn->key1, q, f);
+    ev.quad(fn->dim, fn->key0, fn->key1, q, f);
 }
 
 extern "C" __global__ __launch_bounds__(256) void zmc_plain_fp64(const DevFn* __restrict__ fn_in,
