@@ -34,6 +34,11 @@ sys.path.insert(0, ROOT)
 VALU_SLOT_PEAK = 256 * 128 * 2.4e9   # lane-slots per second
 
 
+def log(msg: str) -> None:
+    """Progress line on stderr (stdout carries only the JSON result)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def algorithmic_slots_per_eval(family: str, d: int) -> float:
     """Full-rate VALU lane-slots one sample needs (the method's own work, no overheads).
 
@@ -151,6 +156,7 @@ def main():
         return
     stream = torch.cuda.current_stream()
     K, Wm = args.steps, args.warmup
+    log(f"building {K + Wm} batches of {args.n_funcs} functions")
     batches = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=b) for b in range(K + Wm)]
     evals_per_step = W.total_evals(batches[0])
 
@@ -172,6 +178,7 @@ def main():
         ctx.run(stream)
         ctx.results(ids[i], n)
     torch.cuda.synchronize()
+    log(f"warmup done; timing {K} steps")
     st0 = ctx.stats()
     t0 = time.perf_counter()
     results = []
@@ -213,6 +220,7 @@ def main():
         "roofline": roof,
     }
 
+    log(f"timed: {value:.4g} evals/s, fp32 kernel {avg_main_s * 1e3:.3f} ms/launch")
     if not args.no_comparators:
         # batched FP64 and the plain one-launch-per-function FP64 path on the seed-0 batch
         b0 = batches[Wm]
@@ -238,9 +246,11 @@ def main():
     ctx.close()
 
     if args.serve_requests > 0:
+        log("serving leg")
         out["serving"] = serving_leg(Z, W, stream, args)
 
     if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
         cb, orc, done = cpu_baseline(batches[Wm])
         out["cpu_baseline"] = cb
         # parity of the timed FP32 results against the oracle on the functions it computed

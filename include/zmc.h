@@ -54,15 +54,19 @@ typedef enum {
     MC_ERR_HIP = -8,               /* a HIP runtime call failed (message has the HIP string) */
     MC_ERR_NO_DEVICE = -9,         /* no usable gfx950 device, or device call on a validate-only context */
     MC_ERR_ABORTED = -10,          /* work stopped by mc_abort before it finished */
-    MC_ERR_UNKNOWN_REQUEST = -11   /* request id never issued or results already taken */
+    MC_ERR_UNKNOWN_REQUEST = -11,  /* request id never issued or results already taken */
+    MC_ERR_COMPILE = -12           /* a run-time family did not compile (log in mc_last_error) */
 } mc_status;
 
 typedef enum {
     MC_FAMILY_HARMONIC = 0,      /* f = a cos(k.x) + b sin(k.x)         params: a, b, k[0..d)     (Eq. 1) */
     MC_FAMILY_ABS_LINEAR = 1,    /* f = a |c0 + c.x|                    params: a, c0, c[0..d)    (Eq. 2) */
     MC_FAMILY_GAUSSIAN = 2,      /* f = A exp(-|x - mu|^2 / (2 s^2))    params: A, s, mu[0..d)          */
-    MC_FAMILY_POLY_PRODUCT = 3   /* f = prod_j (1 + p_j x_j^{n_j})      params: -, -, p[0..d), n[0..d)  */
+    MC_FAMILY_POLY_PRODUCT = 3,  /* f = prod_j (1 + p_j x_j^{n_j})      params: -, -, p[0..d), n[0..d)  */
+    MC_FAMILY_USER0 = 16         /* first id handed out by mc_register_family (16 .. 16 + 7)           */
 } mc_family;
+
+#define MC_MAX_USER_FAMILIES 8
 
 /* Parameter layout inside mc_function.params: params[0], params[1] are the two
  * scalars; params[2 + j] is the first per-dimension vector (k, c, mu or p) and
@@ -213,6 +217,31 @@ typedef struct mc_stats {
 } mc_stats;
 
 mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out);
+
+/* Register an integrand family given as source text, compiled at run time for
+ * gfx950 (hipRTC).  The paper's program integrates functions of arbitrary form
+ * written by the user (program summary, "Nature of problem"; the multi-function
+ * class of "Solution method"); this is that capability for the batched kernels.
+ *
+ * `source` must define, at namespace scope,
+ *     template <class T>
+ *     __device__ T mc_user_integrand(const T* x, const T* p, uint32_t dim);
+ * x[0..dim) is the sample point inside the function's box, p[0..32) its
+ * mc_function.params, T = float for MC_PREC_FP32_EVAL and double for MC_PREC_FP64
+ * (FP32 evaluation sees x and p rounded to float; sums and the finalize stay as
+ * for the built-in families, including FP32 -> FP64 promotion).  HIP device math
+ * (sinf, exp, ...) is available.  The source is copied; the id written to
+ * *family_out (MC_FAMILY_USER0 + k, k < MC_MAX_USER_FAMILIES, in registration
+ * order) goes into mc_function.family for mc_submit on this context only.
+ * mc_integrate_plain_fp64 accepts built-in families only.
+ *
+ * Errors: MC_ERR_INVALID_ARG (NULL argument, or all 8 ids used), MC_ERR_COMPILE
+ * (the compiler log is in mc_last_error), MC_ERR_HIP (module load).  On a
+ * validate-only context the source is compiled but not loaded.  The caller's
+ * code runs unchecked inside the library's kernels: an out-of-bounds access in
+ * it faults like any kernel.  Launches on a context with registered families
+ * are enqueued directly, not as captured graphs. */
+mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_out);
 
 /* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */
 const char* mc_last_error(mc_ctx* ctx);

@@ -54,6 +54,8 @@ class Oracle:
         L.orc_word.restype = ctypes.c_uint32
         L.orc_sample_point.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_void_p]
         L.orc_sample_point.restype = None
+        L.orc_sample_points.argtypes = [ctypes.c_void_p, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_void_p]
+        L.orc_sample_points.restype = None
         L.orc_eval.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
         L.orc_eval.restype = ctypes.c_double
         L.orc_validate.argtypes = [ctypes.c_void_p]
@@ -97,6 +99,36 @@ class Oracle:
         x = np.zeros(12, dtype=np.float64)
         self.L.orc_sample_point(self._row(table, idx), i, x.ctypes.data)
         return x[: int(table["dim"][idx])]
+
+    def sample_points(self, table: np.ndarray, idx: int, i0: int, count: int) -> np.ndarray:
+        """Points of samples [i0, i0 + count) of function idx, shape (count, dim)."""
+        d = int(table["dim"][idx])
+        x = np.zeros((count, d), dtype=np.float64)
+        self.L.orc_sample_points(self._row(table, idx), i0, count, x.ctypes.data)
+        return x
+
+    def integrate_user(self, table: np.ndarray, f, chunk: int = 1 << 16):
+        """Direct MC of caller-defined integrands on the oracle's own samples.
+
+        ``f(x, p)`` evaluates the integrand in float64 on points x (n, d) with the
+        function's params p (32,); each function's sums are exact-rounded
+        (math.fsum over all its samples) and finalized like the built-in
+        families (paper, "Solution method": direct Monte Carlo per integrand)."""
+        import math
+        table = np.ascontiguousarray(table)
+        out = np.zeros(len(table), dtype=RESULT_DTYPE)
+        for i in range(len(table)):
+            n = int(table["n_samples"][i])
+            vals = []
+            for i0 in range(0, n, chunk):
+                x = self.sample_points(table, i, i0, min(chunk, n - i0))
+                vals.append(np.asarray(f(x, np.array(table["params"][i], dtype=np.float64)), dtype=np.float64))
+            v = np.concatenate(vals)
+            s1, s2, sa = math.fsum(v), math.fsum(v * v), math.fsum(np.abs(v))
+            vol = self.volume(table, i)
+            m, se = self.finalize(vol, n, s1, s2)
+            out[i] = (m, se, s1, s2, sa, vol, n, 0, 0)
+        return out
 
     def evaluate(self, table: np.ndarray, idx: int, x) -> float:
         xx = np.zeros(12, dtype=np.float64)

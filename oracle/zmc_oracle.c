@@ -147,6 +147,14 @@ void orc_sample_point(const orc_function* fn, uint64_t i, double* x)
     }
 }
 
+/* Points of samples [i0, i0 + count) of one function, row-major (count x dim):
+ * the same samples as above, for integrands evaluated outside this file (the
+ * run-time compiled families, whose formula the caller supplies). */
+void orc_sample_points(const orc_function* fn, uint64_t i0, uint64_t count, double* out)
+{
+    for (uint64_t k = 0; k < count; ++k) orc_sample_point(fn, i0 + k, out + k * fn->dim);
+}
+
 /* ---------------- integrands ---------------- */
 
 double orc_eval(const orc_function* fn, const double* x)

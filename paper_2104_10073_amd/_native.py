@@ -23,7 +23,7 @@ STATUS_NAMES = {
     0: "MC_OK", 1: "MC_NOT_READY", -1: "MC_ERR_INVALID_ARG", -2: "MC_ERR_UNSUPPORTED_FAMILY",
     -3: "MC_ERR_BAD_DIM", -4: "MC_ERR_BAD_BOUNDS", -5: "MC_ERR_BAD_PARAMS", -6: "MC_ERR_OUT_OF_MEMORY",
     -7: "MC_ERR_ADMISSION", -8: "MC_ERR_HIP", -9: "MC_ERR_NO_DEVICE", -10: "MC_ERR_ABORTED",
-    -11: "MC_ERR_UNKNOWN_REQUEST",
+    -11: "MC_ERR_UNKNOWN_REQUEST", -12: "MC_ERR_COMPILE",
 }
 
 PREC_FP32 = 0
@@ -34,6 +34,8 @@ MC_NO_GRAPH = 0x2
 MC_NO_PROMOTE = 0x4
 MC_SCHED_FAIR = 0
 MC_SCHED_FIFO = 1
+MC_FAMILY_USER0 = 16        # first run-time family id (mc_register_family)
+MC_MAX_USER_FAMILIES = 8
 
 RESULT_DTYPE = np.dtype([
     ("mean", "<f8"), ("std_error", "<f8"), ("sum_f", "<f8"), ("sum_f2", "<f8"),
@@ -46,7 +48,7 @@ EXPORTS = [
     "mc_config_init", "mc_workspace_size", "mc_create", "mc_destroy", "mc_submit", "mc_run",
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
-    "mc_segment_samples", "mc_version",
+    "mc_segment_samples", "mc_version", "mc_register_family",
 ]
 
 
@@ -121,6 +123,7 @@ def load(path: str = LIB_PATH):
     L.mc_last_run_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.mc_get_stats.argtypes = [vp, ctypes.POINTER(McStats)]
     L.mc_last_error.argtypes = [vp]
+    L.mc_register_family.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]
     L.mc_last_error.restype = ctypes.c_char_p
     L.mc_segment_samples.restype = ctypes.c_uint32
     L.mc_version.restype = ctypes.c_char_p
@@ -255,6 +258,12 @@ class Context:
 
     def abort(self):
         self._check(self.L.mc_abort(self.h), self.h)
+
+    def register_family(self, source: str) -> int:
+        """Compile an integrand family from source (see mc_register_family); returns its family id."""
+        fam = ctypes.c_uint32()
+        self._check(self.L.mc_register_family(self.h, source.encode(), ctypes.byref(fam)), self.h)
+        return int(fam.value)
 
     # -- plain baseline
     def plain_fp64(self, fns, stream=None):

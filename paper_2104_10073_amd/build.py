@@ -38,6 +38,22 @@ def _newer(a: str, b: str) -> bool:
     return os.path.exists(b) and os.path.getmtime(b) >= os.path.getmtime(a)
 
 
+def _rtc_headers_object() -> str:
+    """Object holding the device headers as strings, for run-time compiled families."""
+    parts = ["namespace zmc {"]
+    for var, name in (("kRtcHeaderDevice", "zmc_device.hpp"), ("kRtcHeaderCode", "zmc_device_code.hpp")):
+        text = open(os.path.join(CSRC, name)).read()
+        assert ")zmcrtc\"" not in text
+        parts.append(f'extern const char* const {var};\nconst char* const {var} = R"zmcrtc({text})zmcrtc";')
+    parts.append("}  // namespace zmc\n")
+    src = os.path.join(BUILD, "zmc_rtc_headers.cpp")
+    with open(src, "w") as f:
+        f.write("\n".join(parts))
+    obj = os.path.join(BUILD, "zmc_rtc_headers.o")
+    _run(["g++", "-O1", "-fPIC", "-c", src, "-o", obj])
+    return obj
+
+
 def build(verbose: bool = False, incremental: bool = False) -> str:
     """Compile both translation units (in parallel) and link libzmc.so.
 
@@ -62,8 +78,10 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
         if p.returncode != 0:
             sys.stderr.write(out + err)
             raise RuntimeError("build step failed: " + " ".join(cmd))
+    objs.append(_rtc_headers_object())
     tmp = LIB + ".tmp"
-    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs])
+    _run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs,
+          "-L/opt/rocm/lib", "-lhiprtc", "-Wl,-rpath,/opt/rocm/lib"])
     os.replace(tmp, LIB)
     return LIB
 

@@ -141,10 +141,13 @@ int kernel_index(uint32_t family, bool f64)
 
 // ---------------------------------------------------------------- validation
 
-mc_status validate_one(const mc_function& f, std::string* why)
+// n_user: run-time families registered on the context (ids kUserFamily0 ..
+// kUserFamily0 + n_user - 1); 0 where only the built-in families are accepted.
+mc_status validate_one(const mc_function& f, uint32_t n_user, std::string* why)
 {
     char buf[160];
-    if (f.family > MC_FAMILY_POLY_PRODUCT) {
+    const bool user = f.family >= kUserFamily0 && f.family < kUserFamily0 + n_user;
+    if (f.family > MC_FAMILY_POLY_PRODUCT && !user) {
         snprintf(buf, sizeof buf, "unsupported family %u", f.family);
         *why = buf;
         return MC_ERR_UNSUPPORTED_FAMILY;
@@ -229,6 +232,18 @@ void pack_function(const mc_function& f, int precision, DevFn* d)
         for (uint32_t j = 0; j < D; ++j) d->deg[j] = (int32_t)f.params[MC_PARAM_W0 + j];
     d->scale1 = 1.0;
     d->scale2 = 1.0;
+    if (f.family >= kUserFamily0) {
+        // run-time family: the point in the box and the raw parameters (both precisions)
+        for (int k = 0; k < kUserParams; ++k) {
+            d->up[k] = f.params[k];
+            d->up32[k] = (float)f.params[k];
+        }
+        for (uint32_t j = 0; j < D; ++j) {
+            d->fc[j] = (float)d->w[j];
+            d->fo[j] = (float)f.lo[j];
+        }
+        return;
+    }
     if (precision == MC_PREC_FP64) return;
 
     // FP32 evaluation: coefficients in t_j = u_j + C, C = 1 - 2^-24.
@@ -296,7 +311,8 @@ double sample_cost(uint32_t family, uint32_t dim, int precision)
     case MC_FAMILY_HARMONIC: fam = dim + 6.0; break;
     case MC_FAMILY_ABS_LINEAR: fam = dim + 2.0; break;
     case MC_FAMILY_GAUSSIAN: fam = 3.0 * dim + 5.0; break;
-    default: fam = 8.0 * dim; break;
+    case MC_FAMILY_POLY_PRODUCT: fam = 8.0 * dim; break;
+    default: fam = 40.0; break;  // run-time family: unknown, priced as a few transcendentals
     }
     double c = philox + dim + fam + 4.0;
     if (precision == MC_PREC_FP64) c *= 3.0;
@@ -369,6 +385,8 @@ struct LaunchSlot {
 };
 
 constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters
+static_assert(kUserFamily0 == (uint32_t)MC_FAMILY_USER0 && kMaxUserFamilies == MC_MAX_USER_FAMILIES,
+              "run-time family ids");
 static_assert(sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t) <= kDescBytes, "launch descriptor size");
 
 }  // namespace
@@ -417,6 +435,15 @@ struct mc_ctx {
     double last_main_ms = 0.0, last_fin_ms = 0.0;
     bool have_timing = false;
     mc_stats stats{};
+
+    // run-time compiled families (hipRTC): module and FP32/FP64 kernels of each
+    struct UserFamily {
+        hipModule_t module = nullptr;
+        hipFunction_t kernel[2] = {nullptr, nullptr};
+        uint32_t blocks_per_cu[2] = {1, 1};
+    };
+    UserFamily user[kMaxUserFamilies];
+    uint32_t n_user = 0;
 };
 
 namespace {
@@ -681,6 +708,14 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
     if (events) HIP_TRY(hipEventRecord(s.ev_mid, stream));
     HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64), dim3(kBlockThreads),
                             args, 0, stream));
+    // run-time families: kernels with no tiles in this launch are skipped
+    for (uint32_t u = 0; u < ctx->n_user; ++u)
+        for (int p = 0; p < 2; ++p) {
+            if (s.tile_count[2 + 2 * u + p] == 0) continue;
+            const mc_ctx::UserFamily& uf = ctx->user[u];
+            HIP_TRY(hipModuleLaunchKernel(uf.kernel[p], ctx->num_cus * uf.blocks_per_cu[p], 1, 1, kBlockThreads, 1, 1,
+                                          0, stream, args, nullptr));
+        }
     if (events) HIP_TRY(hipEventRecord(s.ev_main, stream));
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
     if (events) HIP_TRY(hipEventRecord(s.ev_end, stream));
@@ -835,8 +870,10 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     if (s.n_tiles)
         HIP_TRY(hipMemcpyAsync(s.d_tiles, s.h_tiles, (size_t)s.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, stream));
     if (s.n_fins) HIP_TRY(hipMemcpyAsync(s.d_fins, s.h_fins, (size_t)s.n_fins * sizeof(Fin), hipMemcpyHostToDevice, stream));
-    s.graphed = ctx->use_graph;
-    if (ctx->use_graph) {
+    // a launch graph holds the built-in kernels only: with run-time families
+    // registered, launches are enqueued directly
+    s.graphed = ctx->use_graph && ctx->n_user == 0;
+    if (s.graphed) {
         if (!s.graph) capture_graph(ctx, s);
         HIP_TRY(hipEventRecord(s.ev_start, stream));
         HIP_TRY(hipGraphLaunch(s.graph, stream));
@@ -898,6 +935,9 @@ void destroy_device(mc_ctx* ctx)
     }
     if (ctx->upload_stream) quiet(hipStreamDestroy(ctx->upload_stream));
     ctx->upload_stream = nullptr;
+    for (uint32_t u = 0; u < ctx->n_user; ++u)
+        if (ctx->user[u].module) quiet(hipModuleUnload(ctx->user[u].module));
+    ctx->n_user = 0;
     if (ctx->h_words) quiet(hipHostFree(ctx->h_words));
     if (ctx->owns_memory && ctx->mem_base) quiet(hipFree(ctx->mem_base));
     ctx->h_words = nullptr;
@@ -1068,12 +1108,14 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     uint64_t parts = 0;
     for (size_t i = 0; i < n; ++i) {
         std::string why;
-        mc_status st = validate_one(fns[i], &why);
+        mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
         pack_function(fns[i], precision, &r->packed[i]);
         FnState& fs = r->st[i];
         const DevFn& d = r->packed[i];
-        uint32_t L = ctx->seg_log2[precision == MC_PREC_FP64 ? 1 : 0][d.kfam][d.dim - 1];
+        // run-time families take the harmonic family's tile size
+        const uint32_t tf = d.kfam < (uint32_t)kNumFamilies ? d.kfam : (uint32_t)MC_FAMILY_HARMONIC;
+        uint32_t L = ctx->seg_log2[precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
         // no point in tiles larger than the function
         while (L > 0 && ((uint32_t)kBlockWaves << (L - 1)) >= d.n_segments) --L;
         fs.seg_log2 = L;
@@ -1218,7 +1260,7 @@ mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n,
     uint64_t max_blocks = 1;
     for (size_t i = 0; i < n; ++i) {
         std::string why;
-        mc_status st = validate_one(fns[i], &why);
+        mc_status st = validate_one(fns[i], 0, &why);  // built-in families only
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
         pack_function(fns[i], MC_PREC_FP64, &packed[i]);
         const uint64_t blocks = (packed[i].n_quads + 255) / 256;
@@ -1410,6 +1452,112 @@ mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out)
 {
     if (!ctx || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
     *out = ctx->stats;
+    return MC_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+// Source of the run-time kernels of one family: the caller's integrand wrapped
+// in the evaluator interface, and the FP32 and FP64 persistent kernels that
+// fetch only this family's part of a launch's tile list.
+std::string user_family_source(const char* user_source, uint32_t family, uint32_t kidx32)
+{
+    std::string src;
+    src += "#include \"zmc_device_code.hpp\"\n";
+    src += "namespace zmc_user {\n#line 1 \"integrand\"\n";
+    src += user_source;
+    src += "\n}  // namespace zmc_user\n";
+    src += "struct ZmcUserFn {\n"
+           "    template <class T>\n"
+           "    static __device__ __forceinline__ T f(const T* x, const T* p, uint32_t d)\n"
+           "    { return zmc_user::mc_user_integrand<T>(x, p, d); }\n"
+           "};\n";
+    char buf[512];
+    snprintf(buf, sizeof buf,
+             "extern \"C\" __global__ __launch_bounds__(%d) void zmc_user_fp32(const zmc::LaunchDesc* __restrict__ Ld)\n"
+             "{ zmc::batched_body<zmc::UserDispatch<ZmcUserFn, %uu, false>>(Ld, %uu); }\n"
+             "extern \"C\" __global__ __launch_bounds__(%d) void zmc_user_fp64(const zmc::LaunchDesc* __restrict__ Ld)\n"
+             "{ zmc::batched_body<zmc::UserDispatch<ZmcUserFn, %uu, true>>(Ld, %uu); }\n",
+             kBlockThreads, family, kidx32, kBlockThreads, family, kidx32 + 1);
+    src += buf;
+    return src;
+}
+
+// Compile with hipRTC for gfx950; returns the code object or sets *log.
+bool compile_user_family(const std::string& src, std::vector<char>* code, std::string* log)
+{
+    hiprtcProgram prog = nullptr;
+    const char* hdr_src[] = {kRtcHeaderDevice, kRtcHeaderCode};
+    const char* hdr_name[] = {"zmc_device.hpp", "zmc_device_code.hpp"};
+    if (hiprtcCreateProgram(&prog, src.c_str(), "zmc_user_family.hip", 2, hdr_src, hdr_name) != HIPRTC_SUCCESS) {
+        *log = "hiprtcCreateProgram failed";
+        return false;
+    }
+    // the same code generation as the built-in kernels
+    const char* opts[] = {"--offload-arch=gfx950", "-O3", "-std=c++17", "-ffp-contract=off", "-Xclang",
+                          "-target-feature", "-Xclang", "-packed-fp32-ops"};
+    const hiprtcResult rc = hiprtcCompileProgram(prog, (int)(sizeof opts / sizeof opts[0]), opts);
+    size_t log_size = 0;
+    hiprtcGetProgramLogSize(prog, &log_size);
+    std::string text(log_size, '\0');
+    if (log_size) hiprtcGetProgramLog(prog, &text[0]);
+    while (!text.empty() && text.back() == '\0') text.pop_back();
+    bool ok = rc == HIPRTC_SUCCESS;
+    if (ok) {
+        size_t n = 0;
+        ok = hiprtcGetCodeSize(prog, &n) == HIPRTC_SUCCESS && n > 0;
+        if (ok) {
+            code->resize(n);
+            ok = hiprtcGetCode(prog, code->data()) == HIPRTC_SUCCESS;
+        }
+    }
+    if (!ok) *log = std::string(hiprtcGetErrorString(rc)) + (text.empty() ? "" : ":\n" + text);
+    hiprtcDestroyProgram(&prog);
+    return ok;
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_out)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!source || !family_out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->n_user >= (uint32_t)kMaxUserFamilies)
+        return fail(ctx, MC_ERR_INVALID_ARG, "at most %d run-time families per context", kMaxUserFamilies);
+    const uint32_t u = ctx->n_user;
+    const uint32_t family = kUserFamily0 + u;
+    const std::string src = user_family_source(source, family, 2 + 2 * u);
+    std::vector<char> code;
+    std::string log;
+    if (!compile_user_family(src, &code, &log)) {
+        ctx->err = "run-time family did not compile: " + log;
+        g_thread_error = ctx->err;
+        return MC_ERR_COMPILE;
+    }
+    if (!ctx->validate_only) {
+        mc_ctx::UserFamily uf;
+        try {
+            HIP_TRY(hipSetDevice(ctx->device));
+            HIP_TRY(hipModuleLoadData(&uf.module, code.data()));
+            HIP_TRY(hipModuleGetFunction(&uf.kernel[0], uf.module, "zmc_user_fp32"));
+            HIP_TRY(hipModuleGetFunction(&uf.kernel[1], uf.module, "zmc_user_fp64"));
+            for (int p = 0; p < 2; ++p) {
+                int occ = 0;
+                HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, uf.kernel[p], kBlockThreads, 0));
+                uf.blocks_per_cu[p] = (uint32_t)std::max(1, occ);
+            }
+        } catch (const HipError& e) {
+            if (uf.module) quiet(hipModuleUnload(uf.module));
+            return fail_hip(ctx, e);
+        }
+        ctx->user[u] = uf;
+    }
+    ctx->n_user = u + 1;
+    *family_out = family;
     return MC_OK;
 }
 

@@ -1,0 +1,97 @@
+"""Run-time compiled integrand families (hipRTC) against the oracle, on an MI355X.
+
+A request mixes built-in families with two caller-defined ones, so one launch
+runs the built-in kernels and both families' kernels over their own parts of
+the tile list.  Built-in rows are checked against the oracle's formulas, the
+caller's rows against the oracle's samples evaluated by the numpy form of the
+same integrand; the bars are those of the built-in families.
+"""
+
+import numpy as np
+import pytest
+
+import gpu_common as G
+import user_families as U
+from oracle import oracle as O
+from paper_2104_10073_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _table(fam_a, fam_b):
+    builtin = W.mixed_batch(30, dim_range=(1, 12), log10_samples=(2.0, 5.0), gen_seed=901)
+    ua = U.user_table(20, fam_a, gen_seed=902, base=1)
+    ub = U.user_table(20, fam_b, gen_seed=903, base=2)
+    # edge sizes and dims on the caller's family: partial quads, a single segment, dim 12
+    ue = U.user_table(6, fam_a, gen_seed=904, base=3, dim_range=(12, 12))
+    ue["n_samples"] = [2, 3, 5, 4095, 4097, 70_001]
+    t = np.concatenate([builtin, ua, ub, ue])
+    return t, slice(0, 30), [(slice(30, 50), U.quad_sine_np), (slice(50, 70), U.rational_np),
+                             (slice(70, 76), U.quad_sine_np)]
+
+
+def _oracle(t, parts):
+    orc = np.zeros(len(t), dtype=O.RESULT_DTYPE)
+    b, users = parts
+    orc[b] = G.oracle_results(t[b])
+    for sl, f in users:
+        orc[sl] = O.default().integrate_user(t[sl], f)
+    return orc
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2104_10073_amd as Z
+    c = Z.Context(device=0, flags=Z.MC_NO_GRAPH)
+    fa = c.register_family(U.QUAD_SINE_SRC)
+    fb = c.register_family(U.RATIONAL_SRC)
+    t, b, users = _table(fa, fb)
+    orc = _oracle(t, (b, users))
+    yield c, t, orc, (fa, fb)
+    c.close()
+
+
+def test_user_families_fp64(setup):
+    import paper_2104_10073_amd as Z
+    c, t, orc, _ = setup
+    print("user families fp64: functions", len(t), flush=True)
+    G.check_fp64(c.integrate(t, Z.PREC_FP64), orc, "user fp64")
+
+
+def test_user_families_fp32(setup):
+    import paper_2104_10073_amd as Z
+    c, t, orc, _ = setup
+    print("user families fp32: functions", len(t), flush=True)
+    G.check_fp32(c.integrate(t, Z.PREC_FP32), orc, "user fp32")
+
+
+def test_user_family_alone_equals_mixed(setup):
+    import paper_2104_10073_amd as Z
+    c, t, _, _ = setup
+    mixed = c.integrate(t, Z.PREC_FP32)
+    alone = c.integrate(t[30:50], Z.PREC_FP32)
+    for k in ("mean", "std_error", "sum_f", "sum_f2"):
+        assert np.array_equal(alone[k], mixed[k][30:50]), k
+
+
+def test_user_family_on_graph_context_matches(setup):
+    """A context that would replay graphs launches directly once families are
+    registered; results are the same bits."""
+    import paper_2104_10073_amd as Z
+    c, t, _, _ = setup
+    ref = c.integrate(t, Z.PREC_FP32)
+    with Z.Context(device=0) as g:
+        assert g.register_family(U.QUAD_SINE_SRC) == Z.MC_FAMILY_USER0
+        assert g.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0 + 1
+        for _ in range(2):
+            got = g.integrate(t, Z.PREC_FP32)
+            for k in ("mean", "std_error", "sum_f", "sum_f2"):
+                assert np.array_equal(got[k], ref[k]), k
+
+
+def test_plain_path_rejects_user_family(setup):
+    import paper_2104_10073_amd as Z
+    c, t, _, _ = setup
+    with pytest.raises(Z.McError) as e:
+        c.plain_fp64(t[30:32])
+    assert e.value.status == -2
