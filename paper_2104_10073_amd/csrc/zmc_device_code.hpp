@@ -453,77 +453,88 @@ __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, 
 
 // A run-time compiled family calls F::f(x, p, d) once per sample, with x the
 // sample's d coordinates in the box and p the function's 32 parameters.  The
-// coordinate loop is unrolled to the maximum dimension behind wave-uniform
-// guards so the coordinates stay in registers.
-template <class F>
+// dimension is a template constant (one instantiation per dimension), so the
+// caller's loops over coordinates unroll and the point stays in registers.
+template <class F, uint32_t D>
 struct EvalUser32 {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
+    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
     {
-        float x[4][kMaxDim];
-        const uint64_t b0 = q * (uint64_t)d;
+        float x[4][D];
+        const uint64_t b0 = q * (uint64_t)D;
 #pragma unroll
-        for (int j = 0; j < kMaxDim; ++j) {
-            if ((uint32_t)j < d) {
-                const uint64_t b = b0 + (uint64_t)j;
-                uint32_t w[4];
-                philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
-                const float c = fn->fc[j], o = fn->fo[j];
+        for (uint32_t j = 0; j < D; ++j) {
+            const uint64_t b = b0 + (uint64_t)j;
+            uint32_t w[4];
+            philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+            const float c = fn->fc[j], o = fn->fo[j];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) x[s][j] = fmaf(c, word_to_t(w[s]) - kTShift, o);
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) x[s][j] = 0.0f;
-            }
+            for (int s = 0; s < 4; ++s) x[s][j] = fmaf(c, word_to_t(w[s]) - kTShift, o);
         }
         float p[kUserParams];
 #pragma unroll
         for (int k = 0; k < kUserParams; ++k) p[k] = fn->up32[k];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) g[s] = F::template f<float>(x[s], p, d);
+        for (int s = 0; s < 4; ++s) g[s] = F::template f<float>(x[s], p, D);
     }
 };
 
-template <class F>
+template <class F, uint32_t D>
 struct EvalUser64 {
     CDevFn* fn;
     typedef double Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, double g[4]) const
+    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, uint64_t q, double g[4]) const
     {
-        double x[4][kMaxDim];
-        const uint64_t b0 = q * (uint64_t)d;
+        double x[4][D];
+        const uint64_t b0 = q * (uint64_t)D;
 #pragma unroll
-        for (int j = 0; j < kMaxDim; ++j) {
-            if ((uint32_t)j < d) {
-                const uint64_t b = b0 + (uint64_t)j;
-                uint32_t w[4];
-                philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
-                const double lo = fn->lo[j], wd = fn->w[j];
+        for (uint32_t j = 0; j < D; ++j) {
+            const uint64_t b = b0 + (uint64_t)j;
+            uint32_t w[4];
+            philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+            const double lo = fn->lo[j], wd = fn->w[j];
 #pragma unroll
-                for (int s = 0; s < 4; ++s) x[s][j] = fma(wd, word_to_u64(w[s]), lo);
-            } else {
-#pragma unroll
-                for (int s = 0; s < 4; ++s) x[s][j] = 0.0;
-            }
+            for (int s = 0; s < 4; ++s) x[s][j] = fma(wd, word_to_u64(w[s]), lo);
         }
         double p[kUserParams];
 #pragma unroll
         for (int k = 0; k < kUserParams; ++k) p[k] = fn->up[k];
 #pragma unroll
-        for (int s = 0; s < 4; ++s) g[s] = F::template f<double>(x[s], p, d);
+        for (int s = 0; s < 4; ++s) g[s] = F::template f<double>(x[s], p, D);
     }
 };
 
-// Dispatch of a run-time compiled kernel: only its own family.
+template <class F, bool F64, uint32_t D>
+__device__ __forceinline__ void user_tile(CDevFn* fn, uint32_t seg0, uint32_t seg_log2, uint32_t wave,
+                                          uint32_t lane, Partial* s_seg)
+{
+    if constexpr (F64) tile_segments<EvalUser64<F, D>>(fn, seg0, seg_log2, wave, lane, s_seg);
+    else tile_segments<EvalUser32<F, D>>(fn, seg0, seg_log2, wave, lane, s_seg);
+}
+
+// Dispatch of a run-time compiled kernel: only its own family, by dimension.
 template <class F, uint32_t FAMILY, bool F64>
 struct UserDispatch {
     __device__ static __forceinline__ bool run(CDevFn* fn, uint32_t fam, uint32_t seg0, uint32_t seg_log2,
                                                uint32_t wave, uint32_t lane, Partial* s_seg)
     {
         if (fam != FAMILY) return false;
-        if constexpr (F64) tile_segments<EvalUser64<F>>(fn, seg0, seg_log2, wave, lane, s_seg);
-        else tile_segments<EvalUser32<F>>(fn, seg0, seg_log2, wave, lane, s_seg);
+        switch (fn->dim) {
+        case 1: user_tile<F, F64, 1>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 2: user_tile<F, F64, 2>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 3: user_tile<F, F64, 3>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 4: user_tile<F, F64, 4>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 5: user_tile<F, F64, 5>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 6: user_tile<F, F64, 6>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 7: user_tile<F, F64, 7>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 8: user_tile<F, F64, 8>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 9: user_tile<F, F64, 9>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 10: user_tile<F, F64, 10>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 11: user_tile<F, F64, 11>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        case 12: user_tile<F, F64, 12>(fn, seg0, seg_log2, wave, lane, s_seg); break;
+        default: return false;
+        }
         return true;
     }
 };
