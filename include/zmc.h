@@ -153,6 +153,32 @@ mc_status mc_destroy(mc_ctx* ctx);
 mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision,
                     uint64_t* out_request_id);
 
+/* One axis of a parameter grid: point k (0 <= k < count) sets
+ * params[param] = start + (double)k * step (the product rounded, then the sum). */
+typedef struct mc_grid_axis {
+    uint32_t param;              /* index into mc_function.params, 0..31 */
+    uint32_t count;              /* points on this axis, >= 1 */
+    double start;
+    double step;
+} mc_grid_axis;
+
+#define MC_MAX_GRID_AXES 4
+
+/* Submit one integrand form over a Cartesian grid of parameter values, as one
+ * request (the paper's functional mode: a single integrand with a large
+ * parameter space, program summary, "Solution method" and "Additional
+ * comments").  Function i, 0 <= i < prod_a count_a, is `base` with each axis's
+ * parameter set to its point k_a, where (k_0, k_1, ...) are the mixed-radix
+ * digits of i with axis 0 varying fastest, and seed = base->seed + i (so with
+ * base seed (b << 32) function i draws the stream (b << 32) | i).  Every
+ * function is validated as in mc_submit (first failing index in mc_last_error);
+ * results come back in order i through mc_results.  Errors: as mc_submit, plus
+ * MC_ERR_INVALID_ARG for n_axes outside 1..MC_MAX_GRID_AXES, a param index
+ * above 31, two axes on one parameter, a zero count, or a seed range that would
+ * wrap 2^64. */
+mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
+                         int32_t precision, uint64_t* out_request_id);
+
 /* Admit what fits, then enqueue one launch of the batched path on `stream`:
  * a persistent kernel over the admitted (function, sample-segment) tiles and a
  * finalize kernel for every function whose last tile is in this launch, plus

@@ -34,6 +34,8 @@ MC_NO_GRAPH = 0x2
 MC_NO_PROMOTE = 0x4
 MC_SCHED_FAIR = 0
 MC_SCHED_FIFO = 1
+GRID_AXIS_DTYPE = np.dtype([("param", "<u4"), ("count", "<u4"), ("start", "<f8"), ("step", "<f8")])
+MC_MAX_GRID_AXES = 4
 MC_FAMILY_USER0 = 16        # first run-time family id (mc_register_family)
 MC_MAX_USER_FAMILIES = 8
 
@@ -48,7 +50,7 @@ EXPORTS = [
     "mc_config_init", "mc_workspace_size", "mc_create", "mc_destroy", "mc_submit", "mc_run",
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
-    "mc_segment_samples", "mc_version", "mc_register_family",
+    "mc_segment_samples", "mc_version", "mc_register_family", "mc_submit_grid",
 ]
 
 
@@ -123,6 +125,7 @@ def load(path: str = LIB_PATH):
     L.mc_last_run_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.mc_get_stats.argtypes = [vp, ctypes.POINTER(McStats)]
     L.mc_last_error.argtypes = [vp]
+    L.mc_submit_grid.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.c_int32, u64p]
     L.mc_register_family.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]
     L.mc_last_error.restype = ctypes.c_char_p
     L.mc_segment_samples.restype = ctypes.c_uint32
@@ -219,6 +222,26 @@ class Context:
         rid = ctypes.c_uint64()
         self._check(self.L.mc_submit(self.h, t.ctypes.data, len(t), precision, ctypes.byref(rid)), self.h)
         return int(rid.value)
+
+    def submit_grid(self, base, axes, precision: int = PREC_FP32) -> int:
+        """Submit `base` (one table row) over a parameter grid; axes = [(param, count, start, step), ...]
+        (axis 0 varies fastest).  The request holds prod(count) functions."""
+        b = as_table(np.atleast_1d(base))
+        if len(b) != 1:
+            raise ValueError("base must be a single function")
+        ax = np.zeros(len(axes), dtype=GRID_AXIS_DTYPE)
+        for i, (param, count, start, step) in enumerate(axes):
+            ax[i] = (param, count, start, step)
+        rid = ctypes.c_uint64()
+        self._check(self.L.mc_submit_grid(self.h, b.ctypes.data, ax.ctypes.data, len(ax), precision,
+                                          ctypes.byref(rid)), self.h)
+        return int(rid.value)
+
+    def integrate_grid(self, base, axes, precision: int = PREC_FP32, stream=None):
+        n = int(np.prod([a[1] for a in axes]))
+        rid = self.submit_grid(base, axes, precision)
+        self.run(stream)
+        return self.results(rid, n, blocking=True)
 
     def run(self, stream=None) -> bool:
         """Enqueue one launch; False when every launch slot is still busy (nothing launched)."""

@@ -1151,6 +1151,41 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     return MC_OK;
 }
 
+mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
+                         int32_t precision, uint64_t* out_request_id)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!base || !axes || !out_request_id) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (n_axes < 1 || n_axes > MC_MAX_GRID_AXES)
+        return fail(ctx, MC_ERR_INVALID_ARG, "n_axes %u outside 1..%d", n_axes, MC_MAX_GRID_AXES);
+    uint64_t n = 1;
+    for (uint32_t a = 0; a < n_axes; ++a) {
+        if (axes[a].param >= (uint32_t)MC_N_PARAMS)
+            return fail(ctx, MC_ERR_INVALID_ARG, "axis %u: param index %u above %d", a, axes[a].param, MC_N_PARAMS - 1);
+        if (axes[a].count == 0) return fail(ctx, MC_ERR_INVALID_ARG, "axis %u: zero points", a);
+        for (uint32_t b = 0; b < a; ++b)
+            if (axes[b].param == axes[a].param)
+                return fail(ctx, MC_ERR_INVALID_ARG, "axes %u and %u set the same parameter", b, a);
+        n *= axes[a].count;
+        if (n > ctx->max_functions)
+            return fail(ctx, MC_ERR_ADMISSION, "grid of more than %u functions exceeds the context's function slots",
+                        ctx->max_functions);
+    }
+    if (base->seed > UINT64_MAX - (n - 1))
+        return fail(ctx, MC_ERR_INVALID_ARG, "seed range of the grid wraps 2^64");
+    std::vector<mc_function> fns(n, *base);
+    for (uint64_t i = 0; i < n; ++i) {
+        uint64_t rest = i;
+        for (uint32_t a = 0; a < n_axes; ++a) {
+            const uint64_t k = rest % axes[a].count;
+            rest /= axes[a].count;
+            fns[i].params[axes[a].param] = axes[a].start + (double)k * axes[a].step;
+        }
+        fns[i].seed = base->seed + i;
+    }
+    return mc_submit(ctx, fns.data(), fns.size(), precision, out_request_id);
+}
+
 mc_status mc_run(mc_ctx* ctx, void* stream)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");

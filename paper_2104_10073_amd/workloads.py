@@ -295,6 +295,40 @@ def serving_requests(n_requests: int = 3000, gen_seed: int = 5, max_funcs: int =
     return reqs
 
 
+def expand_grid(base: np.ndarray, axes) -> np.ndarray:
+    """The table a parameter grid stands for: row i is ``base`` with each axis
+    (param, count, start, step) set to start + k*step at the mixed-radix digit k
+    of i (axis 0 fastest) and seed base.seed + i."""
+    b = np.atleast_1d(base)
+    n = int(np.prod([int(a[1]) for a in axes]))
+    t = np.repeat(b[:1], n)
+    for i in range(n):
+        rest = i
+        for param, count, start, step in axes:
+            k = rest % int(count)
+            rest //= int(count)
+            t["params"][i, int(param)] = float(start) + float(k) * float(step)
+        t["seed"][i] = int(b["seed"][0]) + i
+    return t
+
+
+def functional_grid(n_k: int = 64, n_ab: int = 16, n_samples: int = 100_000, dim: int = 4, base: int = 0):
+    """The functional-mode workload: one harmonic form a cos(k.x) + b sin(k.x) on
+    [0,1]^dim, k_0 swept over n_k points in [5, 30] and a over n_ab points in
+    [0.5, 2]; b = 1 and k_j = 10 for j > 0.  Returns (base row, axes)."""
+    t = empty(1)
+    t["family"][0] = HARMONIC
+    t["dim"][0] = dim
+    t["n_samples"][0] = n_samples
+    t["seed"][0] = stream_seed(base, 0)
+    t["hi"][0, :dim] = 1.0
+    t["params"][0, 0] = 1.0
+    t["params"][0, 1] = 1.0
+    t["params"][0, V0:V0 + dim] = 10.0
+    axes = [(V0, n_k, 5.0, 25.0 / max(1, n_k - 1)), (0, n_ab, 0.5, 1.5 / max(1, n_ab - 1))]
+    return t, axes
+
+
 def poisson_arrivals(n: int, qps: float, seed: int = 5) -> np.ndarray:
     """Open-loop Poisson arrival times (seconds from start) at rate ``qps``."""
     rng = np.random.Generator(np.random.PCG64(seed + 1000))
