@@ -557,6 +557,7 @@ __device__ __forceinline__ void batched_body(const LaunchDesc* __restrict__ Ld, 
     const bool kidx_ok = kidx < (uint32_t)kMaxKernels;
     const Tile* tiles = Ld->tiles + (kidx_ok ? Ld->tile_begin[kidx] : 0u);
     const uint32_t n_tiles = kidx_ok ? Ld->tile_count[kidx] : 0u;
+    if (n_tiles == 0) return;  // (uniform over the grid) no tiles for this kernel in this launch
     const uint32_t n_fns = Ld->n_fns;
     const uint64_t n_partials = Ld->n_partials;
     uint32_t* counters = Ld->counters;

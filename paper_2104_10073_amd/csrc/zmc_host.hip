@@ -360,17 +360,19 @@ struct FinRef {
     uint32_t index;
 };
 
+// Staging of one launch: a device block and a pinned host block with the same
+// layout, so a launch needs one copy each way:
+//   [results area | LaunchDesc + counters (kDescBytes) | tiles | finalize records]
+// The launch's n_fins results sit at the end of the results area, right
+// before the descriptor; the tiles (one contiguous part per kernel) and the
+// finalize records follow the descriptor, packed.  Host to device: descriptor
+// (counters zeroed) + tiles + records.  Device to host: results + descriptor
+// + counters.
 struct LaunchSlot {
-    // device
-    LaunchDesc* d_desc = nullptr;   // followed by 4 counters (uint32) in the same allocation
-    Tile* d_tiles = nullptr;          // tile list, one contiguous part per kernel
-    Fin* d_fins = nullptr;
-    DevResult* d_results = nullptr;
-    // pinned host
-    uint8_t* h_desc = nullptr;      // LaunchDesc + counters
-    Tile* h_tiles = nullptr;
-    Fin* h_fins = nullptr;
-    DevResult* h_results = nullptr;
+    uint8_t* d_block = nullptr;     // device
+    uint8_t* h_block = nullptr;     // pinned host
+    LaunchDesc* d_desc = nullptr;   // d_block + results area (fixed: captured graphs use it)
+    hipStream_t stream = nullptr;   // stream of the slot's last launch
     hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
     hipGraphExec_t graph = nullptr;
     bool in_flight = false;
@@ -378,13 +380,14 @@ struct LaunchSlot {
     uint64_t seq = 0;
     uint32_t n_tiles = 0, n_fins = 0;
     std::vector<Tile> kt[kMaxKernels];  // tiles of each kernel while the launch is built
+    std::vector<Fin> fv;                // finalize records while the launch is built
     uint32_t tile_begin[kMaxKernels] = {}, tile_count[kMaxKernels] = {};
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
     std::vector<Request*> touched;  // requests with tiles in this launch
 };
 
-constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters
+constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters (zero padded)
 static_assert(kUserFamily0 == (uint32_t)MC_FAMILY_USER0 && kMaxUserFamilies == MC_MAX_USER_FAMILIES,
               "run-time family ids");
 static_assert(sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t) <= kDescBytes, "launch descriptor size");
@@ -404,6 +407,8 @@ struct mc_ctx {
     uint64_t max_partials = 0;
     uint32_t tile_cap = 0;   // per launch per precision
     uint32_t fin_cap = 0;
+    uint64_t slot_res_bytes = 0;  // results area of a launch slot's block (fin_cap results, 256-aligned)
+    uint64_t slot_bytes = 0;      // whole block
 
     // device memory
     bool owns_memory = true;
@@ -468,7 +473,7 @@ mc_status fail_hip(mc_ctx* ctx, const HipError& e)
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
-    uint64_t fns, partials, slot_desc, slot_tiles, slot_fins, slot_results, abort_word, total;
+    uint64_t fns, partials, slots, slot_res_bytes, slot_bytes, abort_word, total;
 };
 
 Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap)
@@ -479,14 +484,10 @@ Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t ti
     off = align_up(off + (uint64_t)max_functions * sizeof(DevFn), 256);
     L.partials = off;
     off = align_up(off + max_partials * sizeof(Partial), 256);
-    L.slot_desc = off;
-    off = align_up(off + kLaunchSlots * kDescBytes, 256);
-    L.slot_tiles = off;
-    off = align_up(off + (uint64_t)kLaunchSlots * tile_cap * sizeof(Tile), 256);
-    L.slot_fins = off;
-    off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(Fin), 256);
-    L.slot_results = off;
-    off = align_up(off + (uint64_t)kLaunchSlots * fin_cap * sizeof(DevResult), 256);
+    L.slots = off;
+    L.slot_res_bytes = align_up((uint64_t)fin_cap * sizeof(DevResult), 256);
+    L.slot_bytes = align_up(L.slot_res_bytes + kDescBytes + ((uint64_t)tile_cap + fin_cap) * sizeof(Tile), 256);
+    off += kLaunchSlots * L.slot_bytes;
     L.abort_word = off;
     off = align_up(off + sizeof(uint32_t), 256);
     L.total = off;
@@ -570,6 +571,7 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     pack_function(r->fns[fi], MC_PREC_FP64, &r->packed[fi]);
     HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &r->packed[fi], sizeof(DevFn), hipMemcpyHostToDevice,
                            ctx->upload_stream));
+    if (!r->uploaded) HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
     const bool was_active = has_work(r);
     r->redo.push_back(fi);
@@ -595,7 +597,9 @@ void reap(mc_ctx* ctx, int wait)
         if (q == hipErrorNotReady) return;
         if (q != hipSuccess) throw HipError{q, "hipEventQuery(launch)"};
         LaunchSlot& s = *oldest;
-        const uint32_t* cnt = (const uint32_t*)(s.h_desc + sizeof(LaunchDesc));
+        const uint8_t* hdesc = s.h_block + ctx->slot_res_bytes;
+        const uint32_t* cnt = (const uint32_t*)(hdesc + sizeof(LaunchDesc));
+        const DevResult* hres = (const DevResult*)hdesc - s.n_fins;
         const uint32_t bad = cnt[kCounterBadRecords];
         if (bad != 0) {
             char buf[160];
@@ -606,7 +610,7 @@ void reap(mc_ctx* ctx, int wait)
         for (uint32_t i = 0; i < s.n_fins; ++i) {
             const FinRef& fr = s.fin_refs[i];
             mc_result& out = fr.req->results[fr.index];
-            std::memcpy(&out, &s.h_results[i], sizeof(mc_result));
+            std::memcpy(&out, &hres[i], sizeof(mc_result));
             if (bad != 0) out.status = MC_ERR_HIP;
             if (out.status == MC_OK && out.precision == MC_PREC_FP32_EVAL && ctx->promote &&
                 fp32_unresolved(out)) {
@@ -702,12 +706,16 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
 {
     LaunchDesc* dd = s.d_desc;
     void* args[] = {&dd};
+    // a graph holds every built-in kernel (an empty one exits at once);
+    // direct launches skip kernels without tiles
     if (events) HIP_TRY(hipEventRecord(s.ev_start, stream));
-    HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32), dim3(kBlockThreads),
-                            args, 0, stream));
+    if (!events || s.tile_count[kKernelBuiltin32] != 0)
+        HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32),
+                                dim3(kBlockThreads), args, 0, stream));
     if (events) HIP_TRY(hipEventRecord(s.ev_mid, stream));
-    HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64), dim3(kBlockThreads),
-                            args, 0, stream));
+    if (!events || s.tile_count[kKernelBuiltin64] != 0)
+        HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64),
+                                dim3(kBlockThreads), args, 0, stream));
     // run-time families: kernels with no tiles in this launch are skipped
     for (uint32_t u = 0; u < ctx->n_user; ++u)
         for (int p = 0; p < 2; ++p) {
@@ -782,7 +790,8 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
             room = false;
             break;
         }
-        Fin& f = s.h_fins[s.n_fins];
+        s.fv.emplace_back();
+        Fin& f = s.fv.back();
         f.fn = fs.slot;
         f.part0 = (uint32_t)fs.part0;
         f.n_tiles = fs.n_tiles;
@@ -815,6 +824,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     LaunchSlot& s = *slot;
     s.n_tiles = s.n_fins = 0;
     for (auto& v : s.kt) v.clear();
+    s.fv.clear();
     s.n_samples = 0;
     s.fin_refs.clear();
     s.touched.clear();
@@ -831,32 +841,50 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     }
     ctx->active.swap(keep);
     if (s.n_tiles == 0 && s.n_fins == 0) return false;
-    // concatenate the kernels' tiles into the staging list
+    // stage: the kernels' tiles one part after another, then the finalize records
+    uint8_t* const hdesc = s.h_block + ctx->slot_res_bytes;
+    uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
+    Tile* const htiles = (Tile*)(hdesc + kDescBytes);
     {
         uint32_t off = 0;
         for (int k = 0; k < kMaxKernels; ++k) {
             s.tile_begin[k] = off;
             s.tile_count[k] = (uint32_t)s.kt[k].size();
-            if (!s.kt[k].empty()) std::memcpy(s.h_tiles + off, s.kt[k].data(), s.kt[k].size() * sizeof(Tile));
+            if (!s.kt[k].empty()) std::memcpy(htiles + off, s.kt[k].data(), s.kt[k].size() * sizeof(Tile));
             off += s.tile_count[k];
         }
+        if (s.n_fins) std::memcpy(htiles + s.n_tiles, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
     }
+    static_assert(sizeof(Fin) == sizeof(Tile), "tiles and finalize records share the staging stride");
 
     // Launches may be enqueued on different streams; a function's tiles can span
     // launches, so each launch waits for the previous one, and for the uploads
     // of the function tables it reads.
+    // (A launch on the same stream is ordered already: a cross-stream wait on an
+    // event of the same stream only adds latency.)
     for (auto& o : ctx->slots)
-        if (&o != &s && o.in_flight && o.seq == ctx->launch_seq) HIP_TRY(hipStreamWaitEvent(stream, o.ev_done, 0));
-    for (Request* r : s.touched)
-        if (r->uploaded) HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
-    LaunchDesc* hd = (LaunchDesc*)s.h_desc;
-    std::memset(s.h_desc, 0, kDescBytes);
+        if (&o != &s && o.in_flight && o.seq == ctx->launch_seq && o.stream != stream)
+            HIP_TRY(hipStreamWaitEvent(stream, o.ev_done, 0));
+    for (Request* r : s.touched) {
+        if (!r->uploaded) continue;
+        const hipError_t q = hipEventQuery(r->uploaded);
+        if (q == hipSuccess) {  // upload finished: nothing to wait for from now on
+            quiet(hipEventDestroy(r->uploaded));
+            r->uploaded = nullptr;
+        } else {
+            quiet(q);
+            if (q != hipErrorNotReady) throw HipError{q, "hipEventQuery(upload)"};
+            HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
+        }
+    }
+    LaunchDesc* hd = (LaunchDesc*)hdesc;
+    std::memset(hdesc, 0, kDescBytes);
     hd->fns = ctx->d_fns;
-    hd->tiles = s.d_tiles;
+    hd->tiles = (const Tile*)(ddesc + kDescBytes);
     hd->partials = ctx->d_partials;
-    hd->fins = s.d_fins;
-    hd->results = s.d_results;
-    hd->counters = (uint32_t*)((uint8_t*)s.d_desc + sizeof(LaunchDesc));
+    hd->fins = (const Fin*)(ddesc + kDescBytes) + s.n_tiles;
+    hd->results = (DevResult*)ddesc - s.n_fins;
+    hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));
     hd->abort_word = ctx->d_abort_word;
     hd->n_partials = ctx->max_partials;
     hd->n_fns = ctx->max_functions;
@@ -866,10 +894,9 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     }
     hd->n_fins = s.n_fins;
     // the previous use of this slot's staging has completed (slot not in flight)
-    HIP_TRY(hipMemcpyAsync(s.d_desc, s.h_desc, kDescBytes, hipMemcpyHostToDevice, stream));
-    if (s.n_tiles)
-        HIP_TRY(hipMemcpyAsync(s.d_tiles, s.h_tiles, (size_t)s.n_tiles * sizeof(Tile), hipMemcpyHostToDevice, stream));
-    if (s.n_fins) HIP_TRY(hipMemcpyAsync(s.d_fins, s.h_fins, (size_t)s.n_fins * sizeof(Fin), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipMemcpyAsync(ddesc, hdesc, kDescBytes + ((size_t)s.n_tiles + s.n_fins) * sizeof(Tile),
+                           hipMemcpyHostToDevice, stream));
+    s.stream = stream;
     // a launch graph holds the built-in kernels only: with run-time families
     // registered, launches are enqueued directly
     s.graphed = ctx->use_graph && ctx->n_user == 0;
@@ -881,11 +908,12 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     } else {
         enqueue_kernels(ctx, s, stream, true);
     }
-    if (s.n_fins)
-        HIP_TRY(hipMemcpyAsync(s.h_results, s.d_results, (size_t)s.n_fins * sizeof(DevResult), hipMemcpyDeviceToHost,
+    {
+        const size_t res_bytes = (size_t)s.n_fins * sizeof(DevResult);
+        HIP_TRY(hipMemcpyAsync(hdesc - res_bytes, ddesc - res_bytes,
+                               res_bytes + sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                stream));
-    HIP_TRY(hipMemcpyAsync(s.h_desc + sizeof(LaunchDesc), (uint8_t*)s.d_desc + sizeof(LaunchDesc),
-                           kNumCounters * sizeof(uint32_t), hipMemcpyDeviceToHost, stream));
+    }
     HIP_TRY(hipEventRecord(s.ev_done, stream));
     s.in_flight = true;
     s.seq = ++ctx->launch_seq;
@@ -929,8 +957,7 @@ void destroy_device(mc_ctx* ctx)
         if (s.graph) quiet(hipGraphExecDestroy(s.graph));
         for (hipEvent_t e : {s.ev_start, s.ev_mid, s.ev_main, s.ev_end, s.ev_done})
             if (e) quiet(hipEventDestroy(e));
-        for (void* p : {(void*)s.h_desc, (void*)s.h_tiles, (void*)s.h_fins, (void*)s.h_results})
-            if (p) quiet(hipHostFree(p));
+        if (s.h_block) quiet(hipHostFree(s.h_block));
         s = LaunchSlot{};
     }
     if (ctx->upload_stream) quiet(hipStreamDestroy(ctx->upload_stream));
@@ -1014,6 +1041,8 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         ctx->blocks_per_cu64 = (uint32_t)std::max(1, occ64);
 
         Layout L = compute_layout(ctx->max_functions, ctx->max_partials, ctx->tile_cap, ctx->fin_cap);
+        ctx->slot_res_bytes = L.slot_res_bytes;
+        ctx->slot_bytes = L.slot_bytes;
         if (cfg.mem_budget_bytes && L.total > cfg.mem_budget_bytes)
             return fail(nullptr, MC_ERR_OUT_OF_MEMORY, "context needs %llu device bytes, budget is %llu",
                         (unsigned long long)L.total, (unsigned long long)cfg.mem_budget_bytes);
@@ -1035,14 +1064,9 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         ctx->d_partials = (Partial*)(base + L.partials);
         for (int i = 0; i < kLaunchSlots; ++i) {
             LaunchSlot& s = ctx->slots[i];
-            s.d_desc = (LaunchDesc*)(base + L.slot_desc + (uint64_t)i * kDescBytes);
-            s.d_tiles = (Tile*)(base + L.slot_tiles) + (uint64_t)i * ctx->tile_cap;
-            s.d_fins = (Fin*)(base + L.slot_fins) + (uint64_t)i * ctx->fin_cap;
-            s.d_results = (DevResult*)(base + L.slot_results) + (uint64_t)i * ctx->fin_cap;
-            HIP_TRY(hipHostMalloc((void**)&s.h_desc, kDescBytes, hipHostMallocDefault));
-            HIP_TRY(hipHostMalloc((void**)&s.h_tiles, (size_t)ctx->tile_cap * sizeof(Tile), hipHostMallocDefault));
-            HIP_TRY(hipHostMalloc((void**)&s.h_fins, (size_t)ctx->fin_cap * sizeof(Fin), hipHostMallocDefault));
-            HIP_TRY(hipHostMalloc((void**)&s.h_results, (size_t)ctx->fin_cap * sizeof(DevResult), hipHostMallocDefault));
+            s.d_block = base + L.slots + (uint64_t)i * L.slot_bytes;
+            s.d_desc = (LaunchDesc*)(s.d_block + L.slot_res_bytes);
+            HIP_TRY(hipHostMalloc((void**)&s.h_block, L.slot_bytes, hipHostMallocDefault));
             HIP_TRY(hipEventCreate(&s.ev_start));
             HIP_TRY(hipEventCreate(&s.ev_mid));
             HIP_TRY(hipEventCreate(&s.ev_main));
