@@ -355,6 +355,12 @@ struct Request {
     uint32_t n_promoted = 0;
 };
 
+// A function's consecutive tiles in one launch and the cost of one of them.
+struct TileRun {
+    double cost;
+    uint32_t begin, count;
+};
+
 struct FinRef {
     Request* req;
     uint32_t index;
@@ -381,6 +387,7 @@ struct LaunchSlot {
     uint32_t n_tiles = 0, n_fins = 0;
     std::vector<Tile> kt[kMaxKernels];  // tiles of each kernel while the launch is built
     std::vector<Fin> fv;                // finalize records while the launch is built
+    std::vector<TileRun> runs[kMaxKernels];  // each function's tiles in kt[], with their cost
     uint32_t tile_begin[kMaxKernels] = {}, tile_count[kMaxKernels] = {};
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
@@ -763,7 +770,9 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         const bool in_order = r->order_pos < r->order.size();
         const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
         FnState& fs = r->st[fi];
-        std::vector<Tile>& out = s.kt[kernel_index(r->fns[fi].family, fs.f64)];
+        const int kidx = kernel_index(r->fns[fi].family, fs.f64);
+        std::vector<Tile>& out = s.kt[kidx];
+        const size_t run_begin = out.size();
         const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
         const uint64_t tile_samples = (uint64_t)per_tile * kSegSamples;
         const uint64_t fn_samples = r->fns[fi].n_samples;
@@ -781,6 +790,8 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
             r->tiles_launched++;
             taken++;
         }
+        if (out.size() > run_begin)
+            s.runs[kidx].push_back(TileRun{fs.tile_cost, (uint32_t)run_begin, (uint32_t)(out.size() - run_begin)});
         if (taken > 0 && (s.touched.empty() || s.touched.back() != r)) s.touched.push_back(r);
         if (fs.next_tile < fs.n_tiles) {
             room = s.n_tiles < ctx->tile_cap;
@@ -824,6 +835,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     LaunchSlot& s = *slot;
     s.n_tiles = s.n_fins = 0;
     for (auto& v : s.kt) v.clear();
+    for (auto& v : s.runs) v.clear();
     s.fv.clear();
     s.n_samples = 0;
     s.fin_refs.clear();
@@ -846,11 +858,20 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
     Tile* const htiles = (Tile*)(hdesc + kDescBytes);
     {
+        // Within a kernel's part, functions' runs go in descending tile cost, so
+        // the last tiles each workgroup fetches are the cheapest (a short tail).
+        // Results do not depend on the order.
         uint32_t off = 0;
         for (int k = 0; k < kMaxKernels; ++k) {
             s.tile_begin[k] = off;
             s.tile_count[k] = (uint32_t)s.kt[k].size();
-            if (!s.kt[k].empty()) std::memcpy(htiles + off, s.kt[k].data(), s.kt[k].size() * sizeof(Tile));
+            std::vector<TileRun>& rr = s.runs[k];
+            std::stable_sort(rr.begin(), rr.end(), [](const TileRun& a, const TileRun& b) { return a.cost > b.cost; });
+            uint32_t o = off;
+            for (const TileRun& run : rr) {
+                std::memcpy(htiles + o, s.kt[k].data() + run.begin, (size_t)run.count * sizeof(Tile));
+                o += run.count;
+            }
             off += s.tile_count[k];
         }
         if (s.n_fins) std::memcpy(htiles + s.n_tiles, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
@@ -1454,7 +1475,7 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
     // 1) workgroups per CU, on a 4-D harmonic batch
     if (p == 0) {
         int occ = 0;
-        hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel_ptr(false), kBlockThreads, 0);
+        quiet(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, batched_kernel_ptr(false), kBlockThreads, 0));
         uint32_t best_b = ctx->blocks_per_cu32;
         double best_t = 1e30;
         std::vector<mc_function> fns;
