@@ -104,25 +104,35 @@ struct DevResult {
 // Counters of one launch (zeroed by every descriptor upload).
 constexpr int kCounterAborted = 0;     // a workgroup stopped because the abort word was set
 constexpr int kCounterBadRecords = 1;  // tile or finalize records that failed their bounds checks
-constexpr int kCounterTiles = 2;       // kMaxKernels words: next tile of each kernel
+constexpr int kCounterFinWaves = 2;    // finalize waves done (the last one publishes the launch)
+constexpr int kCounterTiles = 3;       // kMaxKernels words: next tile of each kernel
 constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 
 // Everything one launch reads; lives in device memory at a fixed address per
-// launch slot so a captured graph can be replayed with new contents.  The tile
-// list is cut into one contiguous part per kernel (built-in FP32, built-in
-// FP64, each run-time family in FP32 and FP64); every kernel walks its part and
-// writes into the same partial arena, then one finalize kernel runs.
+// launch slot so a captured graph can be replayed with new contents.  The host
+// writes it, with zeroed counters, the tile list and the finalize records, into
+// pinned host memory; the launch's first kernel copies those `stage_bytes` into
+// device memory.  The tile list is cut into one contiguous part per kernel
+// (built-in FP32, built-in FP64, each run-time family in FP32 and FP64); every
+// kernel walks its part and writes into the same partial arena, then one
+// finalize kernel writes the results and counters straight into pinned host
+// memory and, last, the launch's sequence number into `host_done`.
 struct alignas(64) LaunchDesc {
+    uint64_t stage_bytes;                  // bytes from this descriptor on that the stage kernel copies
     const DevFn* fns;
     const Tile* tiles;
     Partial* partials;
     const Fin* fins;
-    DevResult* results;
-    uint32_t* counters;                    // kNumCounters words, right after this descriptor
+    DevResult* host_results;               // host memory: n_fins results
+    uint32_t* counters;                    // device: kNumCounters words, right after this descriptor
+    uint32_t* host_counters;               // host memory: copy of the counters at the end of the launch
+    uint32_t* host_done;                   // host memory: receives `seq` once results and counters are out
     const uint32_t* abort_word;            // device word; nonzero asks the kernels to stop fetching tiles
     uint64_t n_partials;                   // size of the partial arena (bounds checks)
     uint32_t n_fns;                        // size of the function table (bounds checks)
     uint32_t n_fins;
+    uint32_t seq;
+    uint32_t pad_;
     uint32_t tile_begin[kMaxKernels];
     uint32_t tile_count[kMaxKernels];
 };

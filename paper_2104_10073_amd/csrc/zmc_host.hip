@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <sched.h>
+#include <time.h>
+
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -31,6 +34,7 @@ namespace zmc {
 const void* plain_kernel_ptr();
 const void* batched_kernel_ptr(bool fp64);
 const void* finalize_kernel_ptr();
+const void* stage_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
 // compiling caller-supplied families at run time.
@@ -366,20 +370,33 @@ struct FinRef {
     uint32_t index;
 };
 
-// Staging of one launch: a device block and a pinned host block with the same
-// layout, so a launch needs one copy each way:
+// Timing events of one launch.  They are read once the runtime reports them
+// complete, which can be well after the launch has published its results, so
+// they come from a pool of their own rather than from the launch slot.
+struct EvSet {
+    hipEvent_t start = nullptr, mid = nullptr, main = nullptr, end = nullptr, done = nullptr;
+    bool pending = false;   // recorded, not yet read into the statistics
+    bool graphed = false;
+    bool released = false;  // the launch that recorded it has been reaped
+};
+constexpr size_t kEvPoolMax = 256;
+
+// Staging of one launch: a device block and a pinned (fine-grained) host block
+// with the same layout:
 //   [results area | LaunchDesc + counters (kDescBytes) | tiles | finalize records]
-// The launch's n_fins results sit at the end of the results area, right
-// before the descriptor; the tiles (one contiguous part per kernel) and the
-// finalize records follow the descriptor, packed.  Host to device: descriptor
-// (counters zeroed) + tiles + records.  Device to host: results + descriptor
-// + counters.
+// The host writes the descriptor (counters zeroed), the tiles (one contiguous
+// part per kernel) and the finalize records after the results area; the stage
+// kernel copies them to the device block.  The finalize kernel writes the
+// launch's n_fins results into the end of the host block's results area (right
+// before the descriptor) and the counters after the host copy of the
+// descriptor, then the launch's sequence number into the slot's done word.
 struct LaunchSlot {
     uint8_t* d_block = nullptr;     // device
     uint8_t* h_block = nullptr;     // pinned host
+    uint8_t* h_block_dev = nullptr; // device address of h_block
     LaunchDesc* d_desc = nullptr;   // d_block + results area (fixed: captured graphs use it)
     hipStream_t stream = nullptr;   // stream of the slot's last launch
-    hipEvent_t ev_start = nullptr, ev_mid = nullptr, ev_main = nullptr, ev_end = nullptr, ev_done = nullptr;
+    EvSet* ev = nullptr;            // events of the slot's last launch
     hipGraphExec_t graph = nullptr;
     bool in_flight = false;
     bool graphed = false;             // this launch replayed the slot's graph
@@ -426,6 +443,11 @@ struct mc_ctx {
     LaunchSlot slots[kLaunchSlots];
     uint32_t* d_abort_word = nullptr;  // device word the persistent kernels poll
     uint32_t* h_words = nullptr;       // pinned {0, 1}: sources for setting / clearing it
+    uint32_t* h_done = nullptr;        // pinned fine-grained: one done word per launch slot (16 words apart)
+    uint32_t* h_done_dev = nullptr;    // its device address
+    std::vector<std::unique_ptr<EvSet>> ev_pool;
+    std::vector<EvSet*> ev_free;
+    std::deque<EvSet*> ev_pending;     // recorded sets, oldest first
     bool abort_requested = false;
 
     RangeAlloc fn_alloc, part_alloc;
@@ -587,6 +609,112 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     if (!was_active) ctx->active.push_back(r);
 }
 
+// Read a launch's timing events into the statistics.  block = false: only if
+// the runtime already reports them complete.
+void collect_timing(mc_ctx* ctx, EvSet& e, bool block)
+{
+    if (!e.pending) return;
+    const hipError_t q = block ? hipEventSynchronize(e.end) : hipEventQuery(e.end);
+    quiet(q);
+    if (q == hipErrorNotReady) return;
+    e.pending = false;
+    if (q != hipSuccess) return;  // timing lost; results are unaffected
+    float a = 0.f, a32 = 0.f, b = 0.f, g = 0.f;
+    if (e.graphed) {
+        const hipError_t e1 = hipEventElapsedTime(&g, e.start, e.end);
+        quiet(e1);
+        if (e1 == hipSuccess) ctx->stats.graph_ms += g;
+        return;
+    }
+    const hipError_t e1 = hipEventElapsedTime(&a, e.start, e.main);
+    const hipError_t e2 = hipEventElapsedTime(&a32, e.start, e.mid);
+    const hipError_t e3 = hipEventElapsedTime(&b, e.main, e.end);
+    quiet(e1);
+    quiet(e2);
+    quiet(e3);
+    if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess) {
+        ctx->last_main_ms = a;
+        ctx->last_fin_ms = b;
+        ctx->have_timing = true;
+        ctx->stats.fp32_ms += a32;
+        ctx->stats.fp64_ms += a - a32;
+        ctx->stats.finalize_ms += b;
+    }
+}
+
+// Read the pending sets of reaped launches, oldest first; block = false stops at
+// the first one the runtime has not released yet.  Read sets return to the pool.
+void collect_pending(mc_ctx* ctx, bool block)
+{
+    while (!ctx->ev_pending.empty()) {
+        EvSet* e = ctx->ev_pending.front();
+        if (!e->released) return;
+        collect_timing(ctx, *e, block);
+        if (e->pending) return;
+        ctx->ev_pending.pop_front();
+        ctx->ev_free.push_back(e);
+    }
+}
+
+// Every reaped launch's timing (waits for the events).
+void collect_all_timing(mc_ctx* ctx) { collect_pending(ctx, true); }
+
+// A free event set for a new launch: reuses read sets, creates new ones up to
+// kEvPoolMax, and only then waits for the oldest pending one.
+EvSet* acquire_evset(mc_ctx* ctx)
+{
+    collect_pending(ctx, false);
+    if (ctx->ev_free.empty() && ctx->ev_pool.size() >= kEvPoolMax) collect_pending(ctx, true);
+    if (ctx->ev_free.empty()) {
+        std::unique_ptr<EvSet> e(new EvSet());
+        HIP_TRY(hipEventCreate(&e->start));
+        HIP_TRY(hipEventCreate(&e->mid));
+        HIP_TRY(hipEventCreate(&e->main));
+        HIP_TRY(hipEventCreate(&e->end));
+        HIP_TRY(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+        ctx->ev_free.push_back(e.get());
+        ctx->ev_pool.push_back(std::move(e));
+    }
+    EvSet* e = ctx->ev_free.back();
+    ctx->ev_free.pop_back();
+    e->pending = false;
+    e->released = false;
+    return e;
+}
+
+uint32_t load_done(const mc_ctx* ctx, const LaunchSlot& s)
+{
+    const uint32_t* w = ctx->h_done + 16 * (&s - ctx->slots);
+    return __atomic_load_n(w, __ATOMIC_ACQUIRE);
+}
+
+// Wait until the launch in `s` has published its results.  Spins, then yields,
+// then sleeps in short steps; if the runtime reports the launch's last event
+// complete while the done word still lags, that is an error (not a hang).
+void wait_done(mc_ctx* ctx, LaunchSlot& s)
+{
+    const uint32_t want = (uint32_t)s.seq;
+    for (uint64_t i = 0;; ++i) {
+        if (load_done(ctx, s) == want) return;
+        if (i < 4096) continue;
+        if (i < 65536) {
+            sched_yield();
+            continue;
+        }
+        if ((i & 255) == 0) {
+            const hipError_t q = hipEventQuery(s.ev->done);
+            quiet(q);
+            if (q != hipErrorNotReady) {
+                if (load_done(ctx, s) == want) return;
+                if (q != hipSuccess) throw HipError{q, "hipEventQuery(launch)"};
+                throw HipError{hipErrorUnknown, "launch finished without publishing its results"};
+            }
+        }
+        struct timespec ts{0, 20000};
+        nanosleep(&ts, nullptr);
+    }
+}
+
 // Collect finished launches (oldest first): scatter their results into the
 // requests.  wait = 0: only what has completed; 1: wait for the oldest launch
 // in flight first; 2: wait for every launch in flight.
@@ -600,9 +728,10 @@ void reap(mc_ctx* ctx, int wait)
         if (!oldest) return;
         const bool block = wait == 2 || (wait == 1 && !waited);
         waited = true;
-        hipError_t q = block ? hipEventSynchronize(oldest->ev_done) : hipEventQuery(oldest->ev_done);
-        if (q == hipErrorNotReady) return;
-        if (q != hipSuccess) throw HipError{q, "hipEventQuery(launch)"};
+        if (load_done(ctx, *oldest) != (uint32_t)oldest->seq) {
+            if (!block) return;
+            wait_done(ctx, *oldest);
+        }
         LaunchSlot& s = *oldest;
         const uint8_t* hdesc = s.h_block + ctx->slot_res_bytes;
         const uint32_t* cnt = (const uint32_t*)(hdesc + sizeof(LaunchDesc));
@@ -632,27 +761,7 @@ void reap(mc_ctx* ctx, int wait)
             }
         }
         {
-            float a = 0.f, a32 = 0.f, b = 0.f, g = 0.f;
-            if (s.graphed) {
-                const hipError_t e = hipEventElapsedTime(&g, s.ev_start, s.ev_end);
-                quiet(e);
-                if (e == hipSuccess) ctx->stats.graph_ms += g;
-            } else {
-                const hipError_t e1 = hipEventElapsedTime(&a, s.ev_start, s.ev_main);
-                const hipError_t e2 = hipEventElapsedTime(&a32, s.ev_start, s.ev_mid);
-                const hipError_t e3 = hipEventElapsedTime(&b, s.ev_main, s.ev_end);
-                quiet(e1);
-                quiet(e2);
-                quiet(e3);
-                if (e1 == hipSuccess && e2 == hipSuccess && e3 == hipSuccess) {
-                    ctx->last_main_ms = a;
-                    ctx->last_fin_ms = b;
-                    ctx->have_timing = true;
-                    ctx->stats.fp32_ms += a32;
-                    ctx->stats.fp64_ms += a - a32;
-                    ctx->stats.finalize_ms += b;
-                }
-            }
+            s.ev->released = true;
             ctx->stats.launches++;
             for (int k = 0; k < kMaxKernels; ++k) {
                 if (k % 2 == 0) ctx->stats.tiles32 += s.tile_count[k];
@@ -713,13 +822,22 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
 {
     LaunchDesc* dd = s.d_desc;
     void* args[] = {&dd};
+    {
+        // staging: descriptor, counters, tiles and finalize records, host -> device
+        const uint8_t* src = s.h_block_dev + ctx->slot_res_bytes;
+        uint8_t* dst = s.d_block + ctx->slot_res_bytes;
+        uint64_t cap = ctx->slot_bytes - ctx->slot_res_bytes;
+        void* sargs[] = {&src, &dst, &cap};
+        HIP_TRY(hipLaunchKernel(stage_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(256), sargs, 0, stream));
+    }
+    EvSet* e = s.ev;
     // a graph holds every built-in kernel (an empty one exits at once);
     // direct launches skip kernels without tiles
-    if (events) HIP_TRY(hipEventRecord(s.ev_start, stream));
+    if (events) HIP_TRY(hipEventRecord(e->start, stream));
     if (!events || s.tile_count[kKernelBuiltin32] != 0)
         HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32),
                                 dim3(kBlockThreads), args, 0, stream));
-    if (events) HIP_TRY(hipEventRecord(s.ev_mid, stream));
+    if (events) HIP_TRY(hipEventRecord(e->mid, stream));
     if (!events || s.tile_count[kKernelBuiltin64] != 0)
         HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64),
                                 dim3(kBlockThreads), args, 0, stream));
@@ -731,9 +849,9 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
             HIP_TRY(hipModuleLaunchKernel(uf.kernel[p], ctx->num_cus * uf.blocks_per_cu[p], 1, 1, kBlockThreads, 1, 1,
                                           0, stream, args, nullptr));
         }
-    if (events) HIP_TRY(hipEventRecord(s.ev_main, stream));
+    if (events) HIP_TRY(hipEventRecord(e->main, stream));
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
-    if (events) HIP_TRY(hipEventRecord(s.ev_end, stream));
+    if (events) HIP_TRY(hipEventRecord(e->end, stream));
 }
 
 void capture_graph(mc_ctx* ctx, LaunchSlot& s)
@@ -885,7 +1003,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     // event of the same stream only adds latency.)
     for (auto& o : ctx->slots)
         if (&o != &s && o.in_flight && o.seq == ctx->launch_seq && o.stream != stream)
-            HIP_TRY(hipStreamWaitEvent(stream, o.ev_done, 0));
+            HIP_TRY(hipStreamWaitEvent(stream, o.ev->done, 0));
     for (Request* r : s.touched) {
         if (!r->uploaded) continue;
         const hipError_t q = hipEventQuery(r->uploaded);
@@ -898,14 +1016,22 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
             HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
         }
     }
+    EvSet& ev = *acquire_evset(ctx);
+    s.ev = &ev;
+    const uint64_t seq = ctx->launch_seq + 1;
+    uint8_t* const hdesc_dev = s.h_block_dev + ctx->slot_res_bytes;
     LaunchDesc* hd = (LaunchDesc*)hdesc;
     std::memset(hdesc, 0, kDescBytes);
+    hd->stage_bytes = kDescBytes + ((uint64_t)s.n_tiles + s.n_fins) * sizeof(Tile);
     hd->fns = ctx->d_fns;
     hd->tiles = (const Tile*)(ddesc + kDescBytes);
     hd->partials = ctx->d_partials;
     hd->fins = (const Fin*)(ddesc + kDescBytes) + s.n_tiles;
-    hd->results = (DevResult*)ddesc - s.n_fins;
+    hd->host_results = (DevResult*)hdesc_dev - s.n_fins;
     hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));
+    hd->host_counters = (uint32_t*)(hdesc_dev + sizeof(LaunchDesc));
+    hd->host_done = ctx->h_done_dev + 16 * (&s - ctx->slots);
+    hd->seq = (uint32_t)seq;
     hd->abort_word = ctx->d_abort_word;
     hd->n_partials = ctx->max_partials;
     hd->n_fns = ctx->max_functions;
@@ -914,28 +1040,24 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         hd->tile_count[k] = s.tile_count[k];
     }
     hd->n_fins = s.n_fins;
-    // the previous use of this slot's staging has completed (slot not in flight)
-    HIP_TRY(hipMemcpyAsync(ddesc, hdesc, kDescBytes + ((size_t)s.n_tiles + s.n_fins) * sizeof(Tile),
-                           hipMemcpyHostToDevice, stream));
     s.stream = stream;
     // a launch graph holds the built-in kernels only: with run-time families
     // registered, launches are enqueued directly
     s.graphed = ctx->use_graph && ctx->n_user == 0;
+    ev.graphed = s.graphed;
     if (s.graphed) {
         if (!s.graph) capture_graph(ctx, s);
-        HIP_TRY(hipEventRecord(s.ev_start, stream));
+        HIP_TRY(hipEventRecord(ev.start, stream));
         HIP_TRY(hipGraphLaunch(s.graph, stream));
-        HIP_TRY(hipEventRecord(s.ev_end, stream));
+        HIP_TRY(hipEventRecord(ev.end, stream));
     } else {
         enqueue_kernels(ctx, s, stream, true);
     }
-    {
-        const size_t res_bytes = (size_t)s.n_fins * sizeof(DevResult);
-        HIP_TRY(hipMemcpyAsync(hdesc - res_bytes, ddesc - res_bytes,
-                               res_bytes + sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                               stream));
-    }
-    HIP_TRY(hipEventRecord(s.ev_done, stream));
+    // (orders launches on other streams after this one; completion itself is
+    // read from the done word)
+    HIP_TRY(hipEventRecord(ev.done, stream));
+    ev.pending = true;
+    ctx->ev_pending.push_back(&ev);
     s.in_flight = true;
     s.seq = ++ctx->launch_seq;
     return true;
@@ -976,8 +1098,6 @@ void destroy_device(mc_ctx* ctx)
 {
     for (auto& s : ctx->slots) {
         if (s.graph) quiet(hipGraphExecDestroy(s.graph));
-        for (hipEvent_t e : {s.ev_start, s.ev_mid, s.ev_main, s.ev_end, s.ev_done})
-            if (e) quiet(hipEventDestroy(e));
         if (s.h_block) quiet(hipHostFree(s.h_block));
         s = LaunchSlot{};
     }
@@ -986,7 +1106,15 @@ void destroy_device(mc_ctx* ctx)
     for (uint32_t u = 0; u < ctx->n_user; ++u)
         if (ctx->user[u].module) quiet(hipModuleUnload(ctx->user[u].module));
     ctx->n_user = 0;
+    for (auto& e : ctx->ev_pool)
+        for (hipEvent_t x : {e->start, e->mid, e->main, e->end, e->done})
+            if (x) quiet(hipEventDestroy(x));
+    ctx->ev_pool.clear();
+    ctx->ev_free.clear();
+    ctx->ev_pending.clear();
     if (ctx->h_words) quiet(hipHostFree(ctx->h_words));
+    if (ctx->h_done) quiet(hipHostFree(ctx->h_done));
+    ctx->h_done = nullptr;
     if (ctx->owns_memory && ctx->mem_base) quiet(hipFree(ctx->mem_base));
     ctx->h_words = nullptr;
     ctx->mem_base = nullptr;
@@ -1087,13 +1215,14 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             LaunchSlot& s = ctx->slots[i];
             s.d_block = base + L.slots + (uint64_t)i * L.slot_bytes;
             s.d_desc = (LaunchDesc*)(s.d_block + L.slot_res_bytes);
-            HIP_TRY(hipHostMalloc((void**)&s.h_block, L.slot_bytes, hipHostMallocDefault));
-            HIP_TRY(hipEventCreate(&s.ev_start));
-            HIP_TRY(hipEventCreate(&s.ev_mid));
-            HIP_TRY(hipEventCreate(&s.ev_main));
-            HIP_TRY(hipEventCreate(&s.ev_end));
-            HIP_TRY(hipEventCreateWithFlags(&s.ev_done, hipEventDisableTiming));
+            // fine-grained: kernels read the staged launch and write results into it
+            HIP_TRY(hipHostMalloc((void**)&s.h_block, L.slot_bytes, hipHostMallocMapped | hipHostMallocCoherent));
+            HIP_TRY(hipHostGetDevicePointer((void**)&s.h_block_dev, s.h_block, 0));
         }
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_done, kLaunchSlots * 16 * sizeof(uint32_t),
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(hipHostGetDevicePointer((void**)&ctx->h_done_dev, ctx->h_done, 0));
+        std::memset(ctx->h_done, 0, kLaunchSlots * 16 * sizeof(uint32_t));
         HIP_TRY(hipStreamCreateWithFlags(&ctx->upload_stream, hipStreamNonBlocking));
         HIP_TRY(hipHostMalloc((void**)&ctx->h_words, 2 * sizeof(uint32_t), hipHostMallocDefault));
         ctx->h_words[0] = 0u;
@@ -1117,7 +1246,7 @@ mc_status mc_destroy(mc_ctx* ctx)
     if (!ctx->validate_only) {
         quiet(hipSetDevice(ctx->device));
         for (auto& s : ctx->slots)
-            if (s.in_flight) quiet(hipEventSynchronize(s.ev_done));
+            if (s.in_flight && s.ev) quiet(hipEventSynchronize(s.ev->done));
     }
     for (auto& kv : ctx->requests) free_packed(kv.second.get());
     if (!ctx->validate_only) destroy_device(ctx);
@@ -1404,7 +1533,7 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
         ctx->blocks_per_cu32 = blocks_per_cu;
         // graphs bake the grid size in: recapture lazily
         for (auto& s : ctx->slots) {
-            if (s.in_flight) quiet(hipEventSynchronize(s.ev_done));
+            if (s.in_flight && s.ev) quiet(hipEventSynchronize(s.ev->done));
             if (s.graph) {
                 quiet(hipGraphExecDestroy(s.graph));
                 s.graph = nullptr;
@@ -1453,6 +1582,7 @@ static double time_batch(mc_ctx* ctx, const std::vector<mc_function>& fns, int32
     for (int guard = 0; guard < 64 && r->fns_done < r->fns.size(); ++guard) {
         if (mc_run(ctx, stream) != MC_OK) return -1.0;
         reap(ctx, 2);
+        collect_all_timing(ctx);
         total += ctx->last_main_ms;
     }
     std::vector<mc_result> out(fns.size());
@@ -1522,6 +1652,10 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
 mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!ctx->validate_only) {
+        quiet(hipSetDevice(ctx->device));
+        collect_all_timing(ctx);
+    }
     if (!ctx->have_timing) return fail(ctx, MC_NOT_READY, "no completed run yet");
     if (main_ms) *main_ms = ctx->last_main_ms;
     if (finalize_ms) *finalize_ms = ctx->last_fin_ms;
@@ -1531,6 +1665,11 @@ mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms)
 mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out)
 {
     if (!ctx || !out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (!ctx->validate_only) {
+        // timings of completed launches whose events the runtime had not yet released
+        quiet(hipSetDevice(ctx->device));
+        collect_all_timing(ctx);
+    }
     *out = ctx->stats;
     return MC_OK;
 }

@@ -39,6 +39,21 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(con
     batched_body<BuiltinDispatch<true>>(Ld, kKernelBuiltin64);
 }
 
+// First kernel of a launch: copy the staged descriptor, counters, tile list and
+// finalize records from pinned host memory into the slot's device block.  The
+// byte count is the descriptor's first field; `cap` (the block's size) bounds it.
+extern "C" __global__ __launch_bounds__(256) void zmc_stage(const uint4* __restrict__ src, uint4* __restrict__ dst,
+                                                            uint64_t cap)
+{
+    __shared__ uint64_t s_bytes;
+    if (threadIdx.x == 0) s_bytes = reinterpret_cast<const LaunchDesc*>(src)->stage_bytes;
+    __syncthreads();
+    const uint64_t bytes = s_bytes < cap ? s_bytes : cap;
+    const uint64_t n = bytes / sizeof(uint4);
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
+        dst[i] = src[i];
+}
+
 // Per-function second pass, one wave per function: the tile partials are summed
 // by repeated 64-wide butterflies over aligned chunks (compacted in place), which
 // is the pairwise tree over tile index; then mean and standard error in FP64.
@@ -47,7 +62,7 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
     const DevFn* fns = Ld->fns;
     const Fin* fins = Ld->fins;
     Partial* partials = Ld->partials;
-    DevResult* results = Ld->results;
+    DevResult* results = Ld->host_results;
     const uint32_t n_fins = Ld->n_fins;
     const uint32_t n_fns = Ld->n_fns;
     const uint64_t n_partials = Ld->n_partials;
@@ -100,6 +115,20 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
             r.status = aborted ? -10 : 0;
             r.precision = fn->precision;
             results[fin.res] = r;
+        }
+    }
+    // Publication: each wave counts itself once its results are out (system-scope
+    // fence first); the last wave copies the counters to host memory and then
+    // stores the launch's sequence number, which the host polls.
+    if (lane == 0) {
+        __threadfence_system();
+        const uint32_t done = atomicAdd(&counters[kCounterFinWaves], 1u);
+        if (done == nw - 1) {
+            __threadfence();
+            for (int i = 0; i < kNumCounters; ++i)
+                Ld->host_counters[i] = __hip_atomic_load(&counters[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            __threadfence_system();
+            __hip_atomic_store(Ld->host_done, Ld->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }
 }
@@ -193,6 +222,7 @@ extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* 
 
 const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
 const void* batched_kernel_ptr(bool fp64) { return fp64 ? (const void*)zmc_batched_fp64 : (const void*)zmc_batched_fp32; }
+const void* stage_kernel_ptr() { return (const void*)zmc_stage; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }
 
