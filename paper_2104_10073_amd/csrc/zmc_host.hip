@@ -343,6 +343,7 @@ struct Request {
     std::vector<mc_function> fns;     // caller's table (copied at submit)
     DevFn* packed = nullptr;          // packed table (pinned host memory on a device context)
     bool packed_pinned = false;
+    size_t packed_cap = 0;            // bytes of the pinned buffer (from the context's pool)
     std::vector<FnState> st;
     std::vector<mc_result> results;
     std::vector<uint32_t> order;      // functions by descending per-tile cost
@@ -445,6 +446,8 @@ struct mc_ctx {
     uint32_t* h_words = nullptr;       // pinned {0, 1}: sources for setting / clearing it
     uint32_t* h_done = nullptr;        // pinned fine-grained: one done word per launch slot (16 words apart)
     uint32_t* h_done_dev = nullptr;    // its device address
+    std::multimap<size_t, void*> pinned_free;  // pooled pinned buffers by capacity
+    size_t pinned_free_bytes = 0;
     std::vector<std::unique_ptr<EvSet>> ev_pool;
     std::vector<EvSet*> ev_free;
     std::deque<EvSet*> ev_pending;     // recorded sets, oldest first
@@ -550,17 +553,53 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
     return (n_segments + per_tile - 1) / per_tile;
 }
 
-void free_packed(Request* r)
+// Pinned host buffers (packed tables) are pooled by power-of-two capacity:
+// freeing pinned memory synchronizes the whole device, which would drain the
+// launch pipeline every time a request completes.
+constexpr size_t kPinnedPoolMax = 512ull << 20;
+
+void* pinned_get(mc_ctx* ctx, size_t bytes, size_t* cap)
+{
+    size_t c = 64 << 10;
+    while (c < bytes) c <<= 1;
+    *cap = c;
+    auto it = ctx->pinned_free.find(c);
+    if (it != ctx->pinned_free.end()) {
+        void* p = it->second;
+        ctx->pinned_free.erase(it);
+        ctx->pinned_free_bytes -= c;
+        return p;
+    }
+    void* p = nullptr;
+    const hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
+    if (e != hipSuccess) {
+        quiet(e);
+        return nullptr;
+    }
+    return p;
+}
+
+void pinned_put(mc_ctx* ctx, void* p, size_t cap)
+{
+    if (ctx->pinned_free_bytes + cap > kPinnedPoolMax) {
+        quiet(hipHostFree(p));
+        return;
+    }
+    ctx->pinned_free.emplace(cap, p);
+    ctx->pinned_free_bytes += cap;
+}
+
+void free_packed(mc_ctx* ctx, Request* r)
 {
     if (!r->packed) return;
-    if (r->packed_pinned) quiet(hipHostFree(r->packed));
+    if (r->packed_pinned) pinned_put(ctx, r->packed, r->packed_cap);
     else std::free(r->packed);
     r->packed = nullptr;
 }
 
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
-    free_packed(r);
+    free_packed(ctx, r);
     if (r->uploaded) {
         quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
@@ -1112,6 +1151,9 @@ void destroy_device(mc_ctx* ctx)
     ctx->ev_pool.clear();
     ctx->ev_free.clear();
     ctx->ev_pending.clear();
+    for (auto& kv : ctx->pinned_free) quiet(hipHostFree(kv.second));
+    ctx->pinned_free.clear();
+    ctx->pinned_free_bytes = 0;
     if (ctx->h_words) quiet(hipHostFree(ctx->h_words));
     if (ctx->h_done) quiet(hipHostFree(ctx->h_done));
     ctx->h_done = nullptr;
@@ -1248,7 +1290,7 @@ mc_status mc_destroy(mc_ctx* ctx)
         for (auto& s : ctx->slots)
             if (s.in_flight && s.ev) quiet(hipEventSynchronize(s.ev->done));
     }
-    for (auto& kv : ctx->requests) free_packed(kv.second.get());
+    for (auto& kv : ctx->requests) free_packed(ctx, kv.second.get());
     if (!ctx->validate_only) destroy_device(ctx);
     delete ctx;
     return MC_OK;
@@ -1266,17 +1308,18 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     std::unique_ptr<Request> r(new Request());
     r->precision = precision;
     r->fns.assign(fns, fns + n);
-    if (!ctx->validate_only && hipHostMalloc((void**)&r->packed, n * sizeof(DevFn), hipHostMallocDefault) == hipSuccess) {
+    if (!ctx->validate_only && (r->packed = (DevFn*)pinned_get(ctx, n * sizeof(DevFn), &r->packed_cap)) != nullptr) {
         r->packed_pinned = true;
     } else {
         r->packed = (DevFn*)std::malloc(n * sizeof(DevFn));
         if (!r->packed) return fail(ctx, MC_ERR_OUT_OF_MEMORY, "host allocation for %zu functions failed", n);
     }
     struct PackedGuard {
+        mc_ctx* ctx;
         Request* r;
         bool armed = true;
-        ~PackedGuard() { if (armed) free_packed(r); }
-    } guard{r.get()};
+        ~PackedGuard() { if (armed) free_packed(ctx, r); }
+    } guard{ctx, r.get()};
     r->st.resize(n);
     r->results.assign(n, mc_result{});
     uint64_t parts = 0;
