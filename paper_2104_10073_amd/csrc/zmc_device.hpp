@@ -104,8 +104,7 @@ struct DevResult {
 // Counters of one launch (zeroed by every descriptor upload).
 constexpr int kCounterAborted = 0;     // a workgroup stopped because the abort word was set
 constexpr int kCounterBadRecords = 1;  // tile or finalize records that failed their bounds checks
-constexpr int kCounterFinWaves = 2;    // finalize waves done (the last one publishes the launch)
-constexpr int kCounterTiles = 3;       // kMaxKernels words: next tile of each kernel
+constexpr int kCounterTiles = 2;       // kMaxKernels words: next tile of each kernel
 constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 
 // Everything one launch reads; lives in device memory at a fixed address per
@@ -114,16 +113,18 @@ constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 // pinned host memory; the launch's first kernel copies those `stage_bytes` into
 // device memory.  The tile list is cut into one contiguous part per kernel
 // (built-in FP32, built-in FP64, each run-time family in FP32 and FP64); every
-// kernel walks its part and writes into the same partial arena, then one
-// finalize kernel writes the results and counters straight into pinned host
-// memory and, last, the launch's sequence number into `host_done`.
+// kernel walks its part and writes into the same partial arena, one finalize
+// kernel turns partials into results, and a publish kernel copies results and
+// counters into pinned host memory and, last, stores the launch's sequence
+// number into `host_done`.
 struct alignas(64) LaunchDesc {
     uint64_t stage_bytes;                  // bytes from this descriptor on that the stage kernel copies
     const DevFn* fns;
     const Tile* tiles;
     Partial* partials;
     const Fin* fins;
-    DevResult* host_results;               // host memory: n_fins results
+    DevResult* results;                    // device: n_fins results (finalize)
+    DevResult* host_results;               // host memory: their copy (publish)
     uint32_t* counters;                    // device: kNumCounters words, right after this descriptor
     uint32_t* host_counters;               // host memory: copy of the counters at the end of the launch
     uint32_t* host_done;                   // host memory: receives `seq` once results and counters are out

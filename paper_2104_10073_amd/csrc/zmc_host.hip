@@ -35,6 +35,7 @@ const void* plain_kernel_ptr();
 const void* batched_kernel_ptr(bool fp64);
 const void* finalize_kernel_ptr();
 const void* stage_kernel_ptr();
+const void* publish_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
 // compiling caller-supplied families at run time.
@@ -891,6 +892,7 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
     if (events) HIP_TRY(hipEventRecord(e->main, stream));
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
     if (events) HIP_TRY(hipEventRecord(e->end, stream));
+    HIP_TRY(hipLaunchKernel(publish_kernel_ptr(), dim3(1), dim3(1024), args, 0, stream));
 }
 
 void capture_graph(mc_ctx* ctx, LaunchSlot& s)
@@ -1066,6 +1068,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     hd->tiles = (const Tile*)(ddesc + kDescBytes);
     hd->partials = ctx->d_partials;
     hd->fins = (const Fin*)(ddesc + kDescBytes) + s.n_tiles;
+    hd->results = (DevResult*)ddesc - s.n_fins;
     hd->host_results = (DevResult*)hdesc_dev - s.n_fins;
     hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));
     hd->host_counters = (uint32_t*)(hdesc_dev + sizeof(LaunchDesc));

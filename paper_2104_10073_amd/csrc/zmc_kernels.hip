@@ -62,7 +62,7 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
     const DevFn* fns = Ld->fns;
     const Fin* fins = Ld->fins;
     Partial* partials = Ld->partials;
-    DevResult* results = Ld->host_results;
+    DevResult* results = Ld->results;
     const uint32_t n_fins = Ld->n_fins;
     const uint32_t n_fns = Ld->n_fns;
     const uint64_t n_partials = Ld->n_partials;
@@ -117,20 +117,21 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
             results[fin.res] = r;
         }
     }
-    // Publication: each wave counts itself once its results are out (system-scope
-    // fence first); the last wave copies the counters to host memory and then
-    // stores the launch's sequence number, which the host polls.
-    if (lane == 0) {
-        __threadfence_system();
-        const uint32_t done = atomicAdd(&counters[kCounterFinWaves], 1u);
-        if (done == nw - 1) {
-            __threadfence();
-            for (int i = 0; i < kNumCounters; ++i)
-                Ld->host_counters[i] = __hip_atomic_load(&counters[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            __threadfence_system();
-            __hip_atomic_store(Ld->host_done, Ld->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
-        }
-    }
+}
+
+// Last kernel of a launch: copy the results and counters into pinned host
+// memory, then publish the launch's sequence number (system scope, after every
+// thread's copies are complete), which the host polls.
+extern "C" __global__ __launch_bounds__(1024) void zmc_publish(const LaunchDesc* __restrict__ Ld)
+{
+    const uint64_t words = (uint64_t)Ld->n_fins * (sizeof(DevResult) / sizeof(uint64_t));
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(Ld->results);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(Ld->host_results);
+    for (uint64_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
+    if (threadIdx.x < (uint32_t)kNumCounters) Ld->host_counters[threadIdx.x] = Ld->counters[threadIdx.x];
+    __threadfence_system();
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(Ld->host_done, Ld->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ---------------------------------------------------------------- plain FP64 path
@@ -223,6 +224,7 @@ extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* 
 const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
 const void* batched_kernel_ptr(bool fp64) { return fp64 ? (const void*)zmc_batched_fp64 : (const void*)zmc_batched_fp32; }
 const void* stage_kernel_ptr() { return (const void*)zmc_stage; }
+const void* publish_kernel_ptr() { return (const void*)zmc_publish; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }
 
