@@ -31,12 +31,6 @@ constexpr uint32_t kUserFamily0 = 16;                 // family id of the first 
 constexpr int kKernelBuiltin32 = 0;                   // kernel indices: built-in FP32, built-in FP64,
 constexpr int kKernelBuiltin64 = 1;                   //   then FP32 / FP64 of each run-time family
 constexpr int kMaxKernels = 2 + 2 * kMaxUserFamilies;
-// An MI355X has 8 XCDs, each with its own L2; a kernel's tiles are split into
-// one part per XCD (whole functions, balanced by cost), so a function's record
-// and partials stay in one L2.  Workgroups take tiles from their own XCD's part
-// first, then from the others'.
-constexpr int kNumXcd = 8;
-constexpr uint32_t kHwRegXccId = (3u << 11) | 20u;  // s_getreg operand: HW_REG_XCC_ID, bits [3:0]
 constexpr int kUserParams = 32;
 
 enum Family : uint32_t { HARMONIC = 0, ABS_LINEAR = 1, GAUSSIAN = 2, POLY_PRODUCT = 3 };
@@ -110,8 +104,8 @@ struct DevResult {
 // Counters of one launch (zeroed by every descriptor upload).
 constexpr int kCounterAborted = 0;     // a workgroup stopped because the abort word was set
 constexpr int kCounterBadRecords = 1;  // tile or finalize records that failed their bounds checks
-constexpr int kCounterTiles = 2;       // kMaxKernels x kNumXcd words: next tile of each (kernel, XCD) part
-constexpr int kNumCounters = kCounterTiles + kMaxKernels * kNumXcd;
+constexpr int kCounterTiles = 2;       // kMaxKernels words: next tile of each kernel
+constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 
 // Everything one launch reads; lives in device memory at a fixed address per
 // launch slot so a captured graph can be replayed with new contents.  The host
@@ -138,10 +132,10 @@ struct alignas(64) LaunchDesc {
     uint64_t n_partials;                   // size of the partial arena (bounds checks)
     uint32_t n_fns;                        // size of the function table (bounds checks)
     uint32_t n_fins;
-    uint32_t n_tiles;                      // length of the tile list (bounds checks)
     uint32_t seq;
-    // kernel k's tiles for XCD x are tiles[part[k][x] .. part[k][x + 1])
-    uint32_t part[kMaxKernels][kNumXcd + 1];
+    uint32_t pad_;
+    uint32_t tile_begin[kMaxKernels];
+    uint32_t tile_count[kMaxKernels];
 };
 
 }  // namespace zmc

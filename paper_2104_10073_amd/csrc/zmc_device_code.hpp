@@ -542,68 +542,49 @@ struct UserDispatch {
 // ---------------------------------------------------------------- persistent kernel body
 
 // Persistent batched kernel: every workgroup fetches tiles from its kernel's
-// part of the launch's tile list for its own XCD (one counter per part) and,
-// once that part is exhausted, from the other XCDs' parts in turn, until all are
-// exhausted (or the abort word in device memory is set); it evaluates each tile
-// and writes one partial per tile.  `Dispatch::run` evaluates a tile's segments
-// for the function's family (false: not a family this kernel knows).  Indices
-// read from the lists are checked against the launch's bounds; a bad record is
+// part of the launch's tile list through one counter until that part is
+// exhausted (or the abort word in device memory is set), evaluates them, and
+// writes one partial per tile.  `Dispatch::run` evaluates a tile's segments for
+// the function's family (false: not a family this kernel knows).  Indices read
+// from the lists are checked against the launch's bounds; a bad record is
 // skipped and counted instead of being dereferenced.
 template <class Dispatch>
 __device__ __forceinline__ void batched_body(const LaunchDesc* __restrict__ Ld, uint32_t kidx)
 {
-    constexpr uint32_t kNoTile = 0xFFFFFFFFu;
     __shared__ Partial s_seg[kBlockWaves << kMaxSegLog2];
     __shared__ uint32_t s_tile;
-    if (kidx >= (uint32_t)kMaxKernels) return;
-    const uint32_t* part = Ld->part[kidx];
-    if (part[kNumXcd] == part[0]) return;  // (uniform over the grid) no tiles for this kernel in this launch
     const DevFn* fns = Ld->fns;
-    const Tile* tiles = Ld->tiles;
-    const uint32_t n_tiles = Ld->n_tiles;
+    const bool kidx_ok = kidx < (uint32_t)kMaxKernels;
+    const Tile* tiles = Ld->tiles + (kidx_ok ? Ld->tile_begin[kidx] : 0u);
+    const uint32_t n_tiles = kidx_ok ? Ld->tile_count[kidx] : 0u;
+    if (n_tiles == 0) return;  // (uniform over the grid) no tiles for this kernel in this launch
     const uint32_t n_fns = Ld->n_fns;
     const uint64_t n_partials = Ld->n_partials;
     uint32_t* counters = Ld->counters;
-    uint32_t* part_counters = counters + kCounterTiles + kidx * kNumXcd;
     const uint32_t* abort_word = Ld->abort_word;
     Partial* partials = Ld->partials;
     const uint32_t lane = threadIdx.x & (kWave - 1);
     const uint32_t wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
-    const uint32_t home = __builtin_amdgcn_s_getreg(kHwRegXccId) & (kNumXcd - 1);
-    uint32_t step = 0;  // (thread 0) parts exhausted so far, starting at the home XCD
     for (uint32_t iter = 0;; ++iter) {
         if (threadIdx.x == 0) {
-            uint32_t ti = kNoTile;
+            uint32_t ti = n_tiles;
+            if (kidx_ok) ti = atomicAdd(&counters[kCounterTiles + kidx], 1u);
             if ((iter & 7u) == 0u &&
                 __hip_atomic_load(abort_word, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0u) {
                 atomicOr(&counters[kCounterAborted], 1u);
-                step = kNumXcd;
-            }
-            while (step < (uint32_t)kNumXcd) {
-                const uint32_t x = (home + step) & (kNumXcd - 1);
-                const uint32_t b = part[x], e = part[x + 1];
-                if (b < e) {
-                    const uint32_t k = atomicAdd(&part_counters[x], 1u);
-                    if (k < e - b) {
-                        ti = b + k;
-                        break;
-                    }
-                }
-                ++step;
+                ti = n_tiles;
             }
             s_tile = ti;
         }
         __syncthreads();
         const uint32_t ti = __builtin_amdgcn_readfirstlane(s_tile);
-        __syncthreads();  // every wave has read s_tile before thread 0 writes the next one
-        if (ti == kNoTile) break;
-        bool ok = ti < n_tiles;
-        const Tile t = tiles[ok ? ti : 0u];
+        if (ti >= n_tiles) break;
+        const Tile t = tiles[ti];
         const uint32_t fi = __builtin_amdgcn_readfirstlane(t.fn);
         const uint32_t seg0 = __builtin_amdgcn_readfirstlane(t.seg0);
         const uint32_t seg_log2 = __builtin_amdgcn_readfirstlane(t.seg_log2);
         const uint32_t out = __builtin_amdgcn_readfirstlane(t.out);
-        ok = ok && fi < n_fns && seg_log2 <= (uint32_t)kMaxSegLog2 && out < n_partials;
+        bool ok = fi < n_fns && seg_log2 <= (uint32_t)kMaxSegLog2 && out < n_partials;
         CDevFn* fn = scalar_view(fns + (ok ? fi : 0u));
         const uint32_t dim = fn->dim;
         ok = ok && dim >= 1 && dim <= (uint32_t)kMaxDim;

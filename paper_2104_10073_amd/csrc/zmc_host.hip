@@ -407,14 +407,13 @@ struct LaunchSlot {
     std::vector<Tile> kt[kMaxKernels];  // tiles of each kernel while the launch is built
     std::vector<Fin> fv;                // finalize records while the launch is built
     std::vector<TileRun> runs[kMaxKernels];  // each function's tiles in kt[], with their cost
-    uint32_t part[kMaxKernels][kNumXcd + 1] = {};  // per kernel: XCD part offsets in the tile list
-    uint32_t kernel_tiles(int k) const { return part[k][kNumXcd] - part[k][0]; }
+    uint32_t tile_begin[kMaxKernels] = {}, tile_count[kMaxKernels] = {};
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
     std::vector<Request*> touched;  // requests with tiles in this launch
 };
 
-constexpr size_t kDescBytes = 1536;  // LaunchDesc followed by its counters (zero padded)
+constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters (zero padded)
 static_assert(kUserFamily0 == (uint32_t)MC_FAMILY_USER0 && kMaxUserFamilies == MC_MAX_USER_FAMILIES,
               "run-time family ids");
 static_assert(sizeof(LaunchDesc) + kNumCounters * sizeof(uint32_t) <= kDescBytes, "launch descriptor size");
@@ -805,8 +804,8 @@ void reap(mc_ctx* ctx, int wait)
             s.ev->released = true;
             ctx->stats.launches++;
             for (int k = 0; k < kMaxKernels; ++k) {
-                if (k % 2 == 0) ctx->stats.tiles32 += s.kernel_tiles(k);
-                else ctx->stats.tiles64 += s.kernel_tiles(k);
+                if (k % 2 == 0) ctx->stats.tiles32 += s.tile_count[k];
+                else ctx->stats.tiles64 += s.tile_count[k];
             }
             ctx->stats.functions += s.n_fins;
             ctx->stats.samples += s.n_samples;
@@ -875,17 +874,17 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
     // a graph holds every built-in kernel (an empty one exits at once);
     // direct launches skip kernels without tiles
     if (events) HIP_TRY(hipEventRecord(e->start, stream));
-    if (!events || s.kernel_tiles(kKernelBuiltin32) != 0)
+    if (!events || s.tile_count[kKernelBuiltin32] != 0)
         HIP_TRY(hipLaunchKernel(batched_kernel_ptr(false), dim3(ctx->num_cus * ctx->blocks_per_cu32),
                                 dim3(kBlockThreads), args, 0, stream));
     if (events) HIP_TRY(hipEventRecord(e->mid, stream));
-    if (!events || s.kernel_tiles(kKernelBuiltin64) != 0)
+    if (!events || s.tile_count[kKernelBuiltin64] != 0)
         HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64),
                                 dim3(kBlockThreads), args, 0, stream));
     // run-time families: kernels with no tiles in this launch are skipped
     for (uint32_t u = 0; u < ctx->n_user; ++u)
         for (int p = 0; p < 2; ++p) {
-            if (s.kernel_tiles(2 + 2 * u + p) == 0) continue;
+            if (s.tile_count[2 + 2 * u + p] == 0) continue;
             const mc_ctx::UserFamily& uf = ctx->user[u];
             HIP_TRY(hipModuleLaunchKernel(uf.kernel[p], ctx->num_cus * uf.blocks_per_cu[p], 1, 1, kBlockThreads, 1, 1,
                                           0, stream, args, nullptr));
@@ -1018,38 +1017,21 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
     Tile* const htiles = (Tile*)(hdesc + kDescBytes);
     {
-        // Each kernel's tiles are split into one part per XCD: functions' runs,
-        // taken in descending tile cost, go whole to the XCD with the least work
-        // so far (so a function's record and partials stay in one L2, and each
-        // part still ends with its cheapest tiles: a short tail).  Workgroups
-        // steal from other parts once their own is done.  Results do not depend
-        // on the order or the split.
+        // Within a kernel's part, functions' runs go in descending tile cost, so
+        // the last tiles each workgroup fetches are the cheapest (a short tail).
+        // Results do not depend on the order.
         uint32_t off = 0;
         for (int k = 0; k < kMaxKernels; ++k) {
+            s.tile_begin[k] = off;
+            s.tile_count[k] = (uint32_t)s.kt[k].size();
             std::vector<TileRun>& rr = s.runs[k];
             std::stable_sort(rr.begin(), rr.end(), [](const TileRun& a, const TileRun& b) { return a.cost > b.cost; });
-            double load[kNumXcd] = {};
-            uint32_t count[kNumXcd] = {};
-            std::vector<uint8_t> home(rr.size());
-            for (size_t i = 0; i < rr.size(); ++i) {
-                int best = 0;
-                for (int x = 1; x < kNumXcd; ++x)
-                    if (load[x] < load[best]) best = x;
-                home[i] = (uint8_t)best;
-                load[best] += rr[i].cost * rr[i].count;
-                count[best] += rr[i].count;
+            uint32_t o = off;
+            for (const TileRun& run : rr) {
+                std::memcpy(htiles + o, s.kt[k].data() + run.begin, (size_t)run.count * sizeof(Tile));
+                o += run.count;
             }
-            uint32_t at[kNumXcd];
-            s.part[k][0] = off;
-            for (int x = 0; x < kNumXcd; ++x) {
-                at[x] = s.part[k][x];
-                s.part[k][x + 1] = s.part[k][x] + count[x];
-            }
-            for (size_t i = 0; i < rr.size(); ++i) {
-                std::memcpy(htiles + at[home[i]], s.kt[k].data() + rr[i].begin, (size_t)rr[i].count * sizeof(Tile));
-                at[home[i]] += rr[i].count;
-            }
-            off = s.part[k][kNumXcd];
+            off += s.tile_count[k];
         }
         if (s.n_fins) std::memcpy(htiles + s.n_tiles, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
     }
@@ -1095,8 +1077,10 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     hd->abort_word = ctx->d_abort_word;
     hd->n_partials = ctx->max_partials;
     hd->n_fns = ctx->max_functions;
-    std::memcpy(hd->part, s.part, sizeof(s.part));
-    hd->n_tiles = s.n_tiles;
+    for (int k = 0; k < kMaxKernels; ++k) {
+        hd->tile_begin[k] = s.tile_begin[k];
+        hd->tile_count[k] = s.tile_count[k];
+    }
     hd->n_fins = s.n_fins;
     s.stream = stream;
     // a launch graph holds the built-in kernels only: with run-time families
