@@ -93,24 +93,44 @@ def algorithmic_slots_per_eval(family: str, d: int) -> float:
     return philox + uniform + fam + 4.0
 
 
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(table, budget_s: float = 10.0):
     from oracle import oracle as O
     orc = O.default()
     threads = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    # one core: the first 20 functions (each is serial in the oracle anyway)
+    sub = np.ascontiguousarray(table[:20])
+    t1 = time.perf_counter()
+    orc.integrate(sub, 1)
+    one_core = float(sub["n_samples"].sum()) / (time.perf_counter() - t1)
     done = 0
     evals = 0
     used = 1
+    most = 1
     t0 = time.perf_counter()
     chunk = max(threads, 16)
     while done < len(table) and time.perf_counter() - t0 < budget_s:
         sub = np.ascontiguousarray(table[done:done + chunk])
         _, used = orc.integrate(sub, threads)
+        most = max(most, used)
         done += len(sub)
         evals += int(sub["n_samples"].sum())
     dt = time.perf_counter() - t0
-    return {"value": evals / dt, "unit": "integrand evals/s", "cores": int(used), "kind": "oracle",
+    return {"value": evals / dt, "unit": "integrand evals/s", "cores": int(most), "kind": "oracle",
             "sample": f"first {done} of {len(table)} functions of the seed-0 batch in full "
-                      f"({evals:.3g} evals, {dt:.1f} s wall, threads over functions)"}, orc, done
+                      f"({evals:.3g} evals, {dt:.1f} s wall, threads over functions)",
+            "one_core_value": one_core, "one_core_sample": "first 20 functions of the seed-0 batch",
+            "cpu_model": cpu_model(), "cpus_available": int(threads)}, orc, done
 
 
 def serving_leg(Z, W, stream, args):
@@ -126,14 +146,26 @@ def serving_leg(Z, W, stream, args):
     n = args.serve_requests
     reqs = W.serving_requests(n, gen_seed=5)
     flags = 0 if args.graph else Z.MC_NO_GRAPH
+    loads = sorted(set([args.serve_load] + [float(x) for x in args.serve_loads.split(",") if x]))
     with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 15,
                    max_functions=1 << 17, max_partials=1 << 24) as ctx:
         sat = serving.serve(ctx, reqs, np.zeros(n), stream)
         sat_qps = n / sat["wall_s"]
+        per_load = []
+        for lf in loads:
+            if lf == args.serve_load:
+                continue
+            arr = W.poisson_arrivals(n, lf * sat_qps, seed=5)
+            o = serving.serve(ctx, reqs, arr, stream)
+            sm = serving.summarize(o, arr)
+            sm.update({"load_fraction": lf, "offered_qps": lf * sat_qps})
+            per_load.append(sm)
+            log(f"serving at {lf:.2f} x saturated: p50 {sm['p50_ms']:.2f} ms, p99 {sm['p99_ms']:.2f} ms")
         qps = args.serve_load * sat_qps
         arrivals = W.poisson_arrivals(n, qps, seed=5)
         run = serving.serve(ctx, reqs, arrivals, stream, keep_results=True)
         summ = serving.summarize(run, arrivals)
+        log(f"serving at {args.serve_load:.2f} x saturated: p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms")
         # each result alone equals its result inside the mix
         rng = np.random.Generator(np.random.PCG64(23))
         picks = rng.choice(n, size=min(20, n), replace=False)
@@ -145,9 +177,46 @@ def serving_leg(Z, W, stream, args):
     summ.update({"offered_qps": qps, "saturated_qps": sat_qps, "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
                  "load_fraction": args.serve_load, "alone_equals_mix_bitwise": bool(same),
                  "requests_checked_alone": int(len(picks)),
+                 "other_loads": per_load,
                  "workload": "requests of floor(10^U(0,3)) functions, forms mixed, dims U{1..12}, "
                              "10^U(4,7) samples each, Poisson arrivals"})
     return summ
+
+
+def other_configs(Z, W, stream):
+    """Throughput of the other workloads (each run twice, the second timed): the
+    paper's Eq. (1) series (plain FP64 and batched FP32), the mixed-form batch
+    and the high-dimensional batch (batched FP32 with FP64 promotion)."""
+    import torch
+    out = {}
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t0
+
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as ctx:
+        eq1 = W.eq1_series(n_samples=10_000)
+        ev = W.total_evals(eq1)
+        _, tp = timed(lambda: ctx.plain_fp64(eq1, stream=stream))
+        _, tb = timed(lambda: ctx.integrate(eq1, Z.PREC_FP32, stream=stream))
+        out["eq1_100x1e4"] = {"evals": ev, "plain_fp64_ms": tp * 1e3, "batched_fp32_ms": tb * 1e3,
+                              "plain_fp64_evals_per_s": ev / tp, "batched_fp32_evals_per_s": ev / tb}
+        for name, table in (("mixed_2000_dims1to7", W.mixed_batch(2000)),
+                            ("highdim_500x1e7_dims8to12", W.high_dim_batch(500))):
+            ev = W.total_evals(table)
+            st0 = ctx.stats()
+            _, t = timed(lambda: ctx.integrate(table, Z.PREC_FP32, stream=stream))
+            st1 = ctx.stats()
+            half = {k: (st1[k] - st0[k]) / 2 for k in ("fp32_ms", "fp64_ms", "finalize_ms", "promoted", "launches")}
+            out[name] = {"evals": ev, "wall_ms": t * 1e3, "evals_per_s": ev / t,
+                         "kernel_ms": half["fp32_ms"] + half["fp64_ms"] + half["finalize_ms"],
+                         "promoted_to_fp64_per_run": half["promoted"], "launches_per_run": half["launches"]}
+            log(f"{name}: {ev / t:.3g} evals/s")
+    return out
 
 
 def main():
@@ -162,7 +231,10 @@ def main():
     ap.add_argument("--autotune", type=float, default=0.0, help="seconds of autotuning before timing")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured HIP graphs (then only whole-launch times are measured)")
-    ap.add_argument("--serve-requests", type=int, default=1000,
+    ap.add_argument("--serve-loads", default="0.25,0.75",
+                    help="further offered loads (fractions of saturated) reported beside the headline one")
+    ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
+    ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturated request rate")
@@ -206,8 +278,14 @@ def main():
     flags = 0 if args.graph else Z.MC_NO_GRAPH
     ctx = Z.Context(device=0, workspace="torch", flags=flags, policy=Z.MC_SCHED_FIFO,
                     max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
+    tuning = None
     if args.autotune > 0:
+        ta = time.perf_counter()
         ctx.autotune(Z.PREC_FP32, stream=stream, budget_seconds=args.autotune)
+        b, seg = ctx.get_tuning()
+        tuning = {"autotune_s": time.perf_counter() - ta, "blocks_per_cu": b,
+                  "tile_segments_log2_fp32_harmonic_d4": int(seg[0][0][3])}
+        log(f"autotuned: {tuning}")
     ids = [ctx.submit(b, Z.PREC_FP32) for b in batches]
     n = args.n_funcs
     # warmup steps (also captures the launch graphs)
@@ -257,7 +335,7 @@ def main():
         "config": {"workload": f"harmonic batch: {args.n_funcs} integrands a cos(k.x)+b sin(k.x) on [0,1]^4, "
                                f"a,b~U(0.5,2), k~U(5,30), {args.n_samples:.0e} samples each, one seed per step",
                    "functions": args.n_funcs, "samples_per_function": args.n_samples, "dim": 4,
-                   "precision": "fp32-eval"},
+                   "precision": "fp32-eval", "tuning": tuning or "default"},
         "roofline": roof,
     }
 
@@ -285,6 +363,10 @@ def main():
                                                               np.sqrt(r64["n"] * r64["sum_f2"]))),
         }
     ctx.close()
+
+    if not args.no_configs:
+        log("other workloads")
+        out["other_configs"] = other_configs(Z, W, stream)
 
     if args.serve_requests > 0:
         log("serving leg")
