@@ -228,7 +228,8 @@ def main():
     ap.add_argument("--n-samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
-    ap.add_argument("--autotune", type=float, default=0.0, help="seconds of autotuning before timing")
+    ap.add_argument("--autotune", type=float, default=5.0,
+                    help="seconds of autotuning (timed apart, before the timed steps); 0 keeps the defaults")
     ap.add_argument("--graph", action="store_true",
                     help="replay captured HIP graphs (then only whole-launch times are measured)")
     ap.add_argument("--serve-loads", default="0.25,0.75",
