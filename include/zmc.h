@@ -179,12 +179,16 @@ typedef struct mc_grid_axis {
 mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
                          int32_t precision, uint64_t* out_request_id);
 
-/* Admit what fits, then enqueue one launch of the batched path on `stream`:
- * a persistent kernel over the admitted (function, sample-segment) tiles and a
- * finalize kernel for every function whose last tile is in this launch, plus
- * the copy of those results to host memory.  Returns without waiting.  Launches
+/* Admit what fits, then enqueue one launch of the batched path on `stream`, as
+ * kernels only: a stage kernel that copies the launch's work list from pinned
+ * host memory, the persistent kernels over the admitted (function,
+ * sample-segment) tiles, a finalize kernel for every function whose last tile
+ * is in this launch, and a publish kernel that writes those results to pinned
+ * host memory and then marks the launch done.  Returns without waiting (the
+ * library reads completion from that mark, not from the stream).  Launches
  * nothing and returns MC_OK when no admitted work is pending, or MC_NOT_READY
- * when all launch slots are still in flight (call again later). */
+ * when all launch slots are still in flight (call again later).  The stream
+ * must stay valid until the launch has completed. */
 mc_status mc_run(mc_ctx* ctx, void* stream);
 
 /* Ids of requests that completed since the previous call (their results can be
