@@ -37,7 +37,7 @@ VALU_SLOT_PEAK = 256 * 128 * 2.4e9   # lane-slots per second
 
 # Sources that determine the persistent kernel's code; HBM counter figures are
 # used only while these are unchanged since the counters were taken.
-KERNEL_SOURCES = ["paper_2104_10073_amd/csrc/zmc_kernels.hip", "paper_2104_10073_amd/csrc/zmc_device_code.hpp",
+KERNEL_SOURCES = ["paper_2104_10073_amd/csrc/zmc_batched.hip", "paper_2104_10073_amd/csrc/zmc_device_code.hpp",
                   "paper_2104_10073_amd/csrc/zmc_device.hpp"]
 WORKLOAD_TAG = "harmonic1000x1e6"
 

@@ -1,6 +1,7 @@
 """Build the gfx950 library (libzmc.so) in-tree with hipcc.
 
-Two translation units: the kernels and the host runtime.  Flags:
+Three translation units: the batched kernels, the other kernels and the host
+runtime.  Flags:
 * --offload-arch=gfx950 only;
 * -ffp-contract=off: every fused multiply-add in the kernels is written out,
   so the FP64 path keeps the reference operation order;
@@ -23,7 +24,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 COMMON = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-ffp-contract=off",
           "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
           "-I" + INCLUDE, "-I" + CSRC, "-Wall", "-Wno-unused-result"]
-SOURCES = ["zmc_kernels.hip", "zmc_host.hip"]
+SOURCES = ["zmc_batched.hip", "zmc_kernels.hip", "zmc_host.hip"]
 
 
 def _run(cmd):
@@ -55,7 +56,7 @@ def _rtc_headers_object() -> str:
 
 
 def build(verbose: bool = False, incremental: bool = False) -> str:
-    """Compile both translation units (in parallel) and link libzmc.so.
+    """Compile the translation units (in parallel) and link libzmc.so.
 
     incremental=True skips an object that is newer than its source and the
     shared headers (for development; the default always recompiles)."""
@@ -63,6 +64,7 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     objs = []
     procs = []
     headers = [os.path.join(CSRC, "zmc_device.hpp"), os.path.join(CSRC, "zmc_device_code.hpp"),
+               os.path.join(CSRC, "zmc_pack.hpp"),
                os.path.join(INCLUDE, "zmc.h")]
     for src in SOURCES:
         obj = os.path.join(BUILD, src.replace(".hip", ".o"))

@@ -29,6 +29,7 @@
 
 #include "../../include/zmc.h"
 #include "zmc_device.hpp"
+#include "zmc_pack.hpp"
 
 namespace zmc {
 const void* plain_kernel_ptr();
@@ -36,6 +37,7 @@ const void* batched_kernel_ptr(bool fp64);
 const void* finalize_kernel_ptr();
 const void* stage_kernel_ptr();
 const void* publish_kernel_ptr();
+const void* pack_grid_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
 // compiling caller-supplied families at run time.
@@ -200,112 +202,7 @@ mc_status validate_one(const mc_function& f, uint32_t n_user, std::string* why)
 }
 
 // ---------------------------------------------------------------- packing
-
-float frac_to_float(long double x)
-{
-    long double r = x - std::floor(x);
-    float f = (float)r;
-    if (f >= 1.0f) f = 0.0f;
-    return f;
-}
-
-void pack_function(const mc_function& f, int precision, DevFn* d)
-{
-    std::memset(d, 0, sizeof(DevFn));
-    const uint32_t D = f.dim;
-    d->family = f.family;
-    d->kfam = f.family;
-    d->dim = D;
-    d->key0 = (uint32_t)(f.seed & 0xFFFFFFFFull);
-    d->key1 = (uint32_t)(f.seed >> 32);
-    d->n_samples = f.n_samples;
-    d->n_quads = (f.n_samples + 3) / 4;
-    d->n_segments = (uint32_t)((d->n_quads + kSegQuads - 1) / kSegQuads);
-    d->precision = (uint32_t)precision;
-    double vol = 1.0;
-    for (uint32_t j = 0; j < D; ++j) {
-        d->lo[j] = f.lo[j];
-        d->w[j] = f.hi[j] - f.lo[j];
-        d->v[j] = f.params[MC_PARAM_V0 + j];
-        vol *= d->w[j];
-    }
-    d->volume = vol;
-    d->s0 = f.params[0];
-    d->s1 = f.params[1];
-    if (f.family == MC_FAMILY_GAUSSIAN) d->h = 0.5 / (f.params[1] * f.params[1]);
-    if (f.family == MC_FAMILY_POLY_PRODUCT)
-        for (uint32_t j = 0; j < D; ++j) d->deg[j] = (int32_t)f.params[MC_PARAM_W0 + j];
-    d->scale1 = 1.0;
-    d->scale2 = 1.0;
-    if (f.family >= kUserFamily0) {
-        // run-time family: the point in the box and the raw parameters (both precisions)
-        for (int k = 0; k < kUserParams; ++k) {
-            d->up[k] = f.params[k];
-            d->up32[k] = (float)f.params[k];
-        }
-        for (uint32_t j = 0; j < D; ++j) {
-            d->fc[j] = (float)d->w[j];
-            d->fo[j] = (float)f.lo[j];
-        }
-        return;
-    }
-    if (precision == MC_PREC_FP64) return;
-
-    // FP32 evaluation: coefficients in t_j = u_j + C, C = 1 - 2^-24.
-    const long double C = 1.0L - std::ldexp(1.0L, -24);
-    switch (f.family) {
-    case MC_FAMILY_HARMONIC: {
-        const double a = f.params[0], b = f.params[1];
-        const double R = std::hypot(a, b);
-        const long double phi = (R > 0.0) ? (long double)std::atan2(b, a) : 0.0L;
-        long double off = -phi / (long double)kTwoPi;
-        for (uint32_t j = 0; j < D; ++j) {
-            const long double k = f.params[MC_PARAM_V0 + j];
-            const long double kappa = k * (long double)d->w[j] / (long double)kTwoPi;
-            d->fc[j] = (float)kappa;
-            off += k * (long double)f.lo[j] / (long double)kTwoPi - C * (long double)d->fc[j];
-        }
-        d->f0 = frac_to_float(off);
-        d->scale1 = R;
-        d->scale2 = R * R;
-        break;
-    }
-    case MC_FAMILY_ABS_LINEAR: {
-        long double off = f.params[1];
-        for (uint32_t j = 0; j < D; ++j) {
-            const long double c = f.params[MC_PARAM_V0 + j];
-            d->fc[j] = (float)(c * (long double)d->w[j]);
-            off += c * (long double)f.lo[j] - C * (long double)d->fc[j];
-        }
-        d->f0 = (float)off;
-        d->f0lo = (float)(off - (long double)d->f0);
-        d->scale1 = f.params[0];
-        d->scale2 = f.params[0] * f.params[0];
-        break;
-    }
-    case MC_FAMILY_GAUSSIAN: {
-        const long double sigma = f.params[1];
-        const long double hh = 1.4426950408889634073599246810019L / (2.0L * sigma * sigma);  // log2(e) / (2 s^2)
-        const long double sq = std::sqrt(hh);
-        for (uint32_t j = 0; j < D; ++j) {
-            d->fc[j] = (float)((long double)d->w[j] * sq);
-            d->fo[j] = (float)(C + ((long double)f.params[MC_PARAM_V0 + j] - (long double)f.lo[j]) /
-                                       (long double)d->w[j]);
-        }
-        d->scale1 = f.params[0];
-        d->scale2 = f.params[0] * f.params[0];
-        break;
-    }
-    default: {  // POLY_PRODUCT
-        for (uint32_t j = 0; j < D; ++j) {
-            d->fc[j] = (float)d->w[j];
-            d->fo[j] = (float)f.lo[j];
-            d->fp[j] = (float)f.params[MC_PARAM_V0 + j];
-        }
-        break;
-    }
-    }
-}
+// (zmc::pack_function, shared with the grid kernel: zmc_pack.hpp)
 
 // Relative VALU cost of one sample (full-rate issue slots), used to order tiles.
 double sample_cost(uint32_t family, uint32_t dim, int precision)
@@ -341,7 +238,18 @@ struct FnState {
 struct Request {
     uint64_t id;
     int32_t precision;
-    std::vector<mc_function> fns;     // caller's table (copied at submit)
+    std::vector<mc_function> fns;     // caller's table (copied at submit); empty for a grid
+    bool grid = false;                // records are built on the device from `spec`
+    GridSpec spec{};
+    uint64_t n = 0;                   // functions in the request
+    size_t count() const { return (size_t)n; }
+    mc_function at(size_t i) const
+    {
+        if (!grid) return fns[i];
+        mc_function f;
+        grid_function(spec.base, spec.axes, spec.n_axes, i, &f);
+        return f;
+    }
     DevFn* packed = nullptr;          // packed table (pinned host memory on a device context)
     bool packed_pinned = false;
     size_t packed_cap = 0;            // bytes of the pinned buffer (from the context's pool)
@@ -606,7 +514,7 @@ void free_request_resources(mc_ctx* ctx, Request* r)
         r->uploaded = nullptr;
     }
     if (!r->admitted) return;
-    ctx->fn_alloc.release(r->slot_base, r->fns.size());
+    ctx->fn_alloc.release(r->slot_base, r->count());
     ctx->part_alloc.release(r->part_base, r->part_count);
     r->admitted = false;
 }
@@ -637,7 +545,12 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     fs.f64 = true;
     fs.next_tile = 0;
     r->tiles_total += fs.n_tiles;
-    pack_function(r->fns[fi], MC_PREC_FP64, &r->packed[fi]);
+    if (!r->packed) {  // a grid: host records only for the functions promoted to FP64
+        r->packed = (DevFn*)pinned_get(ctx, r->count() * sizeof(DevFn), &r->packed_cap);
+        if (!r->packed) throw HipError{hipErrorOutOfMemory, "pinned buffer for promoted grid functions"};
+        r->packed_pinned = true;
+    }
+    pack_function(r->at(fi), MC_PREC_FP64, &r->packed[fi]);
     HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &r->packed[fi], sizeof(DevFn), hipMemcpyHostToDevice,
                            ctx->upload_stream));
     if (!r->uploaded) HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
@@ -795,7 +708,7 @@ void reap(mc_ctx* ctx, int wait)
             }
             if (out.status != MC_OK) fr.req->aborted = true;
             fr.req->fns_done++;
-            if (fr.req->fns_done == fr.req->fns.size()) {
+            if (fr.req->fns_done == fr.req->count()) {
                 free_request_resources(ctx, fr.req);
                 ctx->completed.push_back(fr.req->id);
             }
@@ -824,7 +737,7 @@ void admit(mc_ctx* ctx)
 {
     while (!ctx->pending.empty()) {
         Request* r = ctx->pending.front();
-        const uint64_t nf = r->fns.size();
+        const uint64_t nf = r->count();
         uint64_t parts = 0;
         for (auto& s : r->st) parts += s.n_tiles;
         uint64_t slot_off = 0, part_off = 0;
@@ -843,8 +756,16 @@ void admit(mc_ctx* ctx)
             p += r->st[i].n_tiles;
         }
         r->admitted = true;  // from here on the slots are released with the request
-        HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice,
-                               ctx->upload_stream));
+        if (r->grid) {
+            // records built on the device from the grid spec: no table crosses PCIe
+            DevFn* out = ctx->d_fns + slot_off;
+            void* args[] = {&r->spec, &out};
+            HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256), args, 0,
+                                    ctx->upload_stream));
+        } else {
+            HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice,
+                                   ctx->upload_stream));
+        }
         HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
         ctx->pending.pop_front();
@@ -929,12 +850,12 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         const bool in_order = r->order_pos < r->order.size();
         const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
         FnState& fs = r->st[fi];
-        const int kidx = kernel_index(r->fns[fi].family, fs.f64);
+        const int kidx = kernel_index(r->grid ? r->spec.base.family : r->fns[fi].family, fs.f64);
         std::vector<Tile>& out = s.kt[kidx];
         const size_t run_begin = out.size();
         const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
         const uint64_t tile_samples = (uint64_t)per_tile * kSegSamples;
-        const uint64_t fn_samples = r->fns[fi].n_samples;
+        const uint64_t fn_samples = r->grid ? r->spec.base.n_samples : r->fns[fi].n_samples;
         while (fs.next_tile < fs.n_tiles && s.n_tiles < ctx->tile_cap && taken < budget) {
             const uint64_t first = (uint64_t)fs.next_tile * tile_samples;
             s.n_samples += std::min<uint64_t>(tile_samples, fn_samples - first);
@@ -1112,15 +1033,15 @@ void finish_abort(mc_ctx* ctx)
 {
     reap(ctx, 2);
     auto cancel = [&](Request* r) {
-        for (uint32_t i = 0; i < r->fns.size(); ++i) {
+        for (uint32_t i = 0; i < r->count(); ++i) {
             mc_result& out = r->results[i];
             std::memset(&out, 0, sizeof out);
-            out.n = r->fns[i].n_samples;
+            out.n = r->grid ? r->spec.base.n_samples : r->fns[i].n_samples;
             out.status = MC_ERR_ABORTED;
             out.precision = (uint32_t)r->precision;
         }
         r->aborted = true;
-        r->fns_done = (uint32_t)r->fns.size();
+        r->fns_done = (uint32_t)r->count();
         r->order_pos = (uint32_t)r->order.size();
         r->redo_pos = (uint32_t)r->redo.size();
         free_request_resources(ctx, r);
@@ -1299,6 +1220,57 @@ mc_status mc_destroy(mc_ctx* ctx)
     return MC_OK;
 }
 
+namespace {
+
+// Scheduling state of function i (its packed record `d`), common to tables and grids.
+void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const DevFn& d)
+{
+    FnState& fs = r->st[i];
+    // run-time families take the harmonic family's tile size
+    const uint32_t tf = d.kfam < (uint32_t)kNumFamilies ? d.kfam : (uint32_t)MC_FAMILY_HARMONIC;
+    uint32_t L = ctx->seg_log2[r->precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
+    // no point in tiles larger than the function
+    while (L > 0 && ((uint32_t)kBlockWaves << (L - 1)) >= d.n_segments) --L;
+    fs.seg_log2 = L;
+    fs.n_tiles = tiles_for(d.n_segments, L);
+    fs.next_tile = 0;
+    fs.f64 = r->precision == MC_PREC_FP64;
+    fs.tile_cost = sample_cost(d.family, d.dim, r->precision) *
+                   (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
+    r->tiles_total += fs.n_tiles;
+}
+
+// Order, id and admission of a validated request.
+mc_status enqueue_request(mc_ctx* ctx, std::unique_ptr<Request> r, uint64_t* out_request_id)
+{
+    uint64_t parts = 0;
+    for (const FnState& fs : r->st) parts += fs.n_tiles;
+    if (parts > ctx->max_partials)
+        return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
+                    (unsigned long long)parts, (unsigned long long)ctx->max_partials);
+    const size_t n = r->count();
+    r->order.resize(n);
+    for (size_t i = 0; i < n; ++i) r->order[i] = (uint32_t)i;
+    Request* rq = r.get();
+    std::stable_sort(rq->order.begin(), rq->order.end(),
+                     [rq](uint32_t a, uint32_t b) { return rq->st[a].tile_cost > rq->st[b].tile_cost; });
+    r->id = ctx->next_id++;
+    *out_request_id = r->id;
+    ctx->requests.emplace(rq->id, std::move(r));
+    if (!ctx->validate_only) {
+        ctx->pending.push_back(rq);
+        try {
+            HIP_TRY(hipSetDevice(ctx->device));
+            admit(ctx);
+        } catch (const HipError& e) {
+            return fail_hip(ctx, e);
+        }
+    }
+    return MC_OK;
+}
+
+}  // namespace
+
 mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision, uint64_t* out_request_id)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
@@ -1311,6 +1283,7 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     std::unique_ptr<Request> r(new Request());
     r->precision = precision;
     r->fns.assign(fns, fns + n);
+    r->n = n;
     if (!ctx->validate_only && (r->packed = (DevFn*)pinned_get(ctx, n * sizeof(DevFn), &r->packed_cap)) != nullptr) {
         r->packed_pinned = true;
     } else {
@@ -1325,50 +1298,16 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     } guard{ctx, r.get()};
     r->st.resize(n);
     r->results.assign(n, mc_result{});
-    uint64_t parts = 0;
     for (size_t i = 0; i < n; ++i) {
         std::string why;
         mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
         pack_function(fns[i], precision, &r->packed[i]);
-        FnState& fs = r->st[i];
-        const DevFn& d = r->packed[i];
-        // run-time families take the harmonic family's tile size
-        const uint32_t tf = d.kfam < (uint32_t)kNumFamilies ? d.kfam : (uint32_t)MC_FAMILY_HARMONIC;
-        uint32_t L = ctx->seg_log2[precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
-        // no point in tiles larger than the function
-        while (L > 0 && ((uint32_t)kBlockWaves << (L - 1)) >= d.n_segments) --L;
-        fs.seg_log2 = L;
-        fs.n_tiles = tiles_for(d.n_segments, L);
-        fs.next_tile = 0;
-        fs.f64 = precision == MC_PREC_FP64;
-        fs.tile_cost = sample_cost(d.family, d.dim, precision) *
-                       (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
-        parts += fs.n_tiles;
-        r->tiles_total += fs.n_tiles;
+        init_fn_state(ctx, r.get(), i, r->packed[i]);
     }
-    if (parts > ctx->max_partials)
-        return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
-                    (unsigned long long)parts, (unsigned long long)ctx->max_partials);
-    r->order.resize(n);
-    for (size_t i = 0; i < n; ++i) r->order[i] = (uint32_t)i;
-    std::stable_sort(r->order.begin(), r->order.end(),
-                     [&](uint32_t a, uint32_t b) { return r->st[a].tile_cost > r->st[b].tile_cost; });
-    guard.armed = false;
-    r->id = ctx->next_id++;
-    *out_request_id = r->id;
-    Request* rp = r.get();
-    ctx->requests.emplace(rp->id, std::move(r));
-    if (!ctx->validate_only) {
-        ctx->pending.push_back(rp);
-        try {
-            HIP_TRY(hipSetDevice(ctx->device));
-            admit(ctx);
-        } catch (const HipError& e) {
-            return fail_hip(ctx, e);
-        }
-    }
-    return MC_OK;
+    const mc_status st = enqueue_request(ctx, std::move(r), out_request_id);
+    if (st == MC_OK) guard.armed = false;
+    return st;
 }
 
 mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
@@ -1376,6 +1315,8 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (!base || !axes || !out_request_id) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (precision != MC_PREC_FP32_EVAL && precision != MC_PREC_FP64)
+        return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
     if (n_axes < 1 || n_axes > MC_MAX_GRID_AXES)
         return fail(ctx, MC_ERR_INVALID_ARG, "n_axes %u outside 1..%d", n_axes, MC_MAX_GRID_AXES);
     uint64_t n = 1;
@@ -1393,17 +1334,43 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
     }
     if (base->seed > UINT64_MAX - (n - 1))
         return fail(ctx, MC_ERR_INVALID_ARG, "seed range of the grid wraps 2^64");
-    std::vector<mc_function> fns(n, *base);
-    for (uint64_t i = 0; i < n; ++i) {
-        uint64_t rest = i;
+    std::unique_ptr<Request> r(new Request());
+    r->precision = precision;
+    r->grid = true;
+    r->n = n;
+    r->spec.base = *base;
+    for (uint32_t a = 0; a < n_axes; ++a) r->spec.axes[a] = axes[a];
+    r->spec.n_axes = n_axes;
+    r->spec.precision = precision;
+    r->spec.n = n;
+    // Validity without expanding the grid: every constraint involves one
+    // parameter, so it suffices to check the grid's first point and, from
+    // there, every point of each axis alone.
+    {
+        uint64_t stride = 1;
+        std::string why;
+        mc_function f;
+        grid_function(r->spec.base, r->spec.axes, n_axes, 0, &f);
+        mc_status st = validate_one(f, ctx->n_user, &why);
+        if (st != MC_OK) return fail(ctx, st, "function 0: %s", why.c_str());
         for (uint32_t a = 0; a < n_axes; ++a) {
-            const uint64_t k = rest % axes[a].count;
-            rest /= axes[a].count;
-            fns[i].params[axes[a].param] = axes[a].start + (double)k * axes[a].step;
+            for (uint32_t k = 1; k < axes[a].count; ++k) {
+                grid_function(r->spec.base, r->spec.axes, n_axes, (uint64_t)k * stride, &f);
+                st = validate_one(f, ctx->n_user, &why);
+                if (st != MC_OK)
+                    return fail(ctx, st, "function %llu: %s", (unsigned long long)((uint64_t)k * stride), why.c_str());
+            }
+            stride *= axes[a].count;
         }
-        fns[i].seed = base->seed + i;
     }
-    return mc_submit(ctx, fns.data(), fns.size(), precision, out_request_id);
+    // all functions share family, dimension and sample count: one record gives
+    // everybody's schedule
+    DevFn d;
+    pack_function(r->spec.base, precision, &d);
+    r->st.resize(n);
+    r->results.assign(n, mc_result{});
+    for (uint64_t i = 0; i < n; ++i) init_fn_state(ctx, r.get(), i, d);
+    return enqueue_request(ctx, std::move(r), out_request_id);
 }
 
 mc_status mc_run(mc_ctx* ctx, void* stream)
@@ -1448,7 +1415,7 @@ mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles)
     uint64_t nr = 0, nt = 0;
     for (auto& kv : ctx->requests) {
         Request* r = kv.second.get();
-        if (r->fns_done < r->fns.size()) nr++;
+        if (r->fns_done < r->count()) nr++;
         nt += r->tiles_total - r->tiles_launched;
     }
     if (requests) *requests = nr;
@@ -1463,14 +1430,14 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
     if (it == ctx->requests.end())
         return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
     Request* r = it->second.get();
-    if (!out || n != r->fns.size())
+    if (!out || n != r->count())
         return fail(ctx, MC_ERR_INVALID_ARG, "request %llu has %zu functions, got n=%zu", (unsigned long long)request_id,
-                    r->fns.size(), n);
+                    r->count(), n);
     if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
     try {
         HIP_TRY(hipSetDevice(ctx->device));
         reap(ctx, 0);
-        while (r->fns_done < r->fns.size()) {
+        while (r->fns_done < r->count()) {
             if (!blocking) return MC_NOT_READY;
             if (r->tiles_launched < r->tiles_total || !r->admitted) {
                 mc_status st = mc_run(ctx, nullptr);
@@ -1625,7 +1592,7 @@ static double time_batch(mc_ctx* ctx, const std::vector<mc_function>& fns, int32
     double total = 0.0;
     auto it = ctx->requests.find(id);
     Request* r = it->second.get();
-    for (int guard = 0; guard < 64 && r->fns_done < r->fns.size(); ++guard) {
+    for (int guard = 0; guard < 64 && r->fns_done < r->count(); ++guard) {
         if (mc_run(ctx, stream) != MC_OK) return -1.0;
         reap(ctx, 2);
         collect_all_timing(ctx);

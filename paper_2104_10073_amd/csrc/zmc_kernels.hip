@@ -1,43 +1,14 @@
-// zmc_kernels.hip -- the built-in gfx950 kernels: the persistent batched kernels
-// for the four built-in families (FP32 and FP64 evaluation), the finalize pass,
-// and the plain one-launch-per-function FP64 path.  The device code itself is in
-// zmc_device_code.hpp.
+// zmc_kernels.hip -- the launch's other gfx950 kernels: staging of the work
+// list, the finalize pass, publication of results, the grid packer, and the
+// plain one-launch-per-function FP64 path.  The persistent batched kernels are
+// in zmc_batched.hip; the device code they share is in zmc_device_code.hpp.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "zmc_device_code.hpp"
+#include "zmc_pack.hpp"
 
 namespace zmc {
-
-// Family dispatch of the built-in kernels (a wave-uniform branch per tile).
-template <bool F64>
-struct BuiltinDispatch {
-    template <int FAM>
-    using Ev = typename std::conditional<F64, Eval64<FAM>, Eval32<FAM>>::type;
-    __device__ static __forceinline__ bool run(CDevFn* fn, uint32_t fam, uint32_t seg0, uint32_t seg_log2,
-                                               uint32_t wave, uint32_t lane, Partial* s_seg)
-    {
-        switch (fam) {
-        case HARMONIC: tile_segments<Ev<HARMONIC>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
-        case ABS_LINEAR: tile_segments<Ev<ABS_LINEAR>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
-        case GAUSSIAN: tile_segments<Ev<GAUSSIAN>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
-        case POLY_PRODUCT: tile_segments<Ev<POLY_PRODUCT>>(fn, seg0, seg_log2, wave, lane, s_seg); return true;
-        default: return false;
-        }
-    }
-};
-
-extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp32(const LaunchDesc* __restrict__ Ld)
-{
-    batched_body<BuiltinDispatch<false>>(Ld, kKernelBuiltin32);
-}
-
-extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(const LaunchDesc* __restrict__ Ld)
-{
-    batched_body<BuiltinDispatch<true>>(Ld, kKernelBuiltin64);
-}
 
 // First kernel of a launch: copy the staged descriptor, counters, tile list and
 // finalize records from pinned host memory into the slot's device block.  The
@@ -134,6 +105,18 @@ extern "C" __global__ __launch_bounds__(1024) void zmc_publish(const LaunchDesc*
     if (threadIdx.x == 0) __hip_atomic_store(Ld->host_done, Ld->seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// Records of a parameter grid, one thread per function (the paper's functional
+// mode: one integrand form over a large parameter space), written straight into
+// the request's function slots.
+extern "C" __global__ __launch_bounds__(256) void zmc_pack_grid(GridSpec spec, DevFn* __restrict__ out)
+{
+    const uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= spec.n) return;
+    mc_function f;
+    grid_function(spec.base, spec.axes, spec.n_axes, i, &f);
+    pack_function(f, spec.precision, &out[i]);
+}
+
 // ---------------------------------------------------------------- plain FP64 path
 
 // One thread per quad over a grid sized to the function's N, block sums in LDS,
@@ -222,9 +205,9 @@ extern "C" __global__ __launch_bounds__(256) void zmc_plain_reduce(const DevFn* 
 }
 
 const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
-const void* batched_kernel_ptr(bool fp64) { return fp64 ? (const void*)zmc_batched_fp64 : (const void*)zmc_batched_fp32; }
 const void* stage_kernel_ptr() { return (const void*)zmc_stage; }
 const void* publish_kernel_ptr() { return (const void*)zmc_publish; }
+const void* pack_grid_kernel_ptr() { return (const void*)zmc_pack_grid; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }
 

@@ -1,5 +1,6 @@
-"""Parameter-grid requests (functional mode) on an MI355X: a grid gives the
-same bits as the table it stands for, and matches the oracle on that table."""
+"""Parameter-grid requests (functional mode) on an MI355X: the device builds the
+records from the grid spec; the results equal those of the expanded table
+(FP64: bitwise) and match the oracle on that table."""
 
 import numpy as np
 import pytest
@@ -20,9 +21,15 @@ def test_grid_equals_table_and_oracle():
         for prec in (Z.PREC_FP64, Z.PREC_FP32):
             g = c.integrate_grid(base, axes, prec)
             t = c.integrate(table, prec)
-            for k in ("mean", "std_error", "sum_f", "sum_f2", "n"):
-                assert np.array_equal(g[k], t[k]), k
+            assert np.array_equal(g["n"], t["n"])
             if prec == Z.PREC_FP64:
+                # the FP64 record fields are exact functions of the inputs: same bits
+                for k in ("mean", "std_error", "sum_f", "sum_f2"):
+                    assert np.array_equal(g[k], t[k]), k
                 G.check_fp64(g, orc, "grid fp64")
             else:
+                # FP32 coefficients come from the device's libm instead of the
+                # host's (hypot, atan2 may differ in the last bit before rounding
+                # to float): far inside the FP32 bar
+                assert np.all(np.abs(g["mean"] - t["mean"]) <= 1e-3 * orc["stderr"])
                 G.check_fp32(g, orc, "grid fp32")

@@ -56,3 +56,28 @@ def test_grid_seed_wrap_rejected():
         with pytest.raises(Z.McError) as e:
             c.submit_grid(base, axes)
         assert e.value.status == -1
+
+
+def test_grid_validation_names_the_failing_point():
+    """Each constraint involves one parameter, so the grid is validated axis by
+    axis without expanding it; the first failing point is reported by its index."""
+    t = W.mixed_batch(40, gen_seed=3)
+    poly = t[t["family"] == W.POLY_PRODUCT][:1].copy()
+    assert len(poly) == 1
+    deg0 = W.W0  # degree of coordinate 0
+    # axis 0 over a harmless parameter (3 points), axis 1 over the degree: 1, 2.5 (bad), 3.5 (bad)
+    axes = [(W.V0, 3, 0.1, 0.1), (deg0, 3, 1.0, 1.5)]
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY) as c:
+        with pytest.raises(Z.McError) as e:
+            c.submit_grid(poly, axes)
+        assert e.value.status == -5
+        assert "function 3:" in str(e.value)  # point k = 1 of axis 1 is function 1 * 3
+
+
+def test_grid_axis_may_override_an_invalid_base_parameter():
+    t = W.mixed_batch(40, gen_seed=3)
+    g = t[t["family"] == W.GAUSSIAN][:1].copy()
+    g["params"][0, 1] = 0.0  # sigma 0 in the base, but every grid point sets it
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY) as c:
+        c.submit_grid(g, [(1, 4, 0.2, 0.1)])
+        assert c.validate_tiles() >= 4
