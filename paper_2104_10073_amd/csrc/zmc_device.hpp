@@ -82,6 +82,18 @@ struct Tile {
 };
 
 // Finalize record: function fn's tile partials are partials[part0 .. part0 + n_tiles).
+// Consecutive tiles of one function in a launch's tile list, as the host stages
+// them; the stage kernel expands each into `count` Tile records at `dst`.
+struct TileRun {
+    uint32_t fn;
+    uint32_t first;               // the function's tile index of the first one
+    uint32_t count;
+    uint32_t seg_log2;
+    uint32_t part0;               // partial slot of the function's tile 0
+    uint32_t dst;                 // position of the first one in the tile list
+    uint32_t pad_[2];
+};
+
 struct Fin {
     uint32_t fn;
     uint32_t part0;
@@ -119,6 +131,8 @@ constexpr int kNumCounters = kCounterTiles + kMaxKernels;
 // number into `host_done`.
 struct alignas(64) LaunchDesc {
     uint64_t stage_bytes;                  // bytes from this descriptor on that the stage kernel copies
+    uint32_t n_runs;                       // tile runs staged after the finalize records
+    uint32_t runs_off;                     // their byte offset from this descriptor (host block)
     const DevFn* fns;
     const Tile* tiles;
     Partial* partials;

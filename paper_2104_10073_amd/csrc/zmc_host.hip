@@ -270,9 +270,9 @@ struct Request {
 };
 
 // A function's consecutive tiles in one launch and the cost of one of them.
-struct TileRun {
+struct HostRun {
     double cost;
-    uint32_t begin, count;
+    TileRun run;
 };
 
 struct FinRef {
@@ -291,15 +291,17 @@ struct EvSet {
 };
 constexpr size_t kEvPoolMax = 256;
 
-// Staging of one launch: a device block and a pinned (fine-grained) host block
-// with the same layout:
-//   [results area | LaunchDesc + counters (kDescBytes) | tiles | finalize records]
-// The host writes the descriptor (counters zeroed), the tiles (one contiguous
-// part per kernel) and the finalize records after the results area; the stage
-// kernel copies them to the device block.  The finalize kernel writes the
-// launch's n_fins results into the end of the host block's results area (right
-// before the descriptor) and the counters after the host copy of the
-// descriptor, then the launch's sequence number into the slot's done word.
+// Staging of one launch: a device block and a pinned (fine-grained) host block:
+//   device [results area | LaunchDesc + counters (kDescBytes) | finalize records | tile list]
+//   host   [results area | LaunchDesc + counters (kDescBytes) | finalize records | tile runs]
+// The host writes the descriptor (counters zeroed), the finalize records and
+// one run per function with tiles in the launch (16 + 32 bytes per function,
+// not 16 per tile); the stage kernel copies descriptor and records to the
+// device block and expands the runs into the tile list, one contiguous part
+// per kernel.  The publish kernel writes the launch's n_fins results into the
+// end of the host block's results area (right before the descriptor) and the
+// counters after the host copy of the descriptor, then the launch's sequence
+// number into the slot's done word.
 struct LaunchSlot {
     uint8_t* d_block = nullptr;     // device
     uint8_t* h_block = nullptr;     // pinned host
@@ -312,9 +314,9 @@ struct LaunchSlot {
     bool graphed = false;             // this launch replayed the slot's graph
     uint64_t seq = 0;
     uint32_t n_tiles = 0, n_fins = 0;
-    std::vector<Tile> kt[kMaxKernels];  // tiles of each kernel while the launch is built
     std::vector<Fin> fv;                // finalize records while the launch is built
-    std::vector<TileRun> runs[kMaxKernels];  // each function's tiles in kt[], with their cost
+    std::vector<HostRun> runs[kMaxKernels];  // each kernel's tile runs while the launch is built
+    uint32_t n_runs = 0;
     uint32_t tile_begin[kMaxKernels] = {}, tile_count[kMaxKernels] = {};
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
@@ -427,7 +429,11 @@ Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t ti
     off = align_up(off + max_partials * sizeof(Partial), 256);
     L.slots = off;
     L.slot_res_bytes = align_up((uint64_t)fin_cap * sizeof(DevResult), 256);
-    L.slot_bytes = align_up(L.slot_res_bytes + kDescBytes + ((uint64_t)tile_cap + fin_cap) * sizeof(Tile), 256);
+    // device: descriptor, finalize records, tile list; host: descriptor, finalize
+    // records, tile runs (at most one per function slot)
+    L.slot_bytes = align_up(L.slot_res_bytes + kDescBytes + (uint64_t)fin_cap * sizeof(Fin) +
+                                std::max<uint64_t>((uint64_t)tile_cap * sizeof(Tile), (uint64_t)fin_cap * sizeof(TileRun)),
+                            256);
     off += kLaunchSlots * L.slot_bytes;
     L.abort_word = off;
     off = align_up(off + sizeof(uint32_t), 256);
@@ -787,8 +793,9 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
         // staging: descriptor, counters, tiles and finalize records, host -> device
         const uint8_t* src = s.h_block_dev + ctx->slot_res_bytes;
         uint8_t* dst = s.d_block + ctx->slot_res_bytes;
-        uint64_t cap = ctx->slot_bytes - ctx->slot_res_bytes;
-        void* sargs[] = {&src, &dst, &cap};
+        uint64_t cap = kDescBytes + (uint64_t)ctx->fin_cap * sizeof(Fin);
+        uint32_t tile_cap = ctx->tile_cap;
+        void* sargs[] = {&src, &dst, &cap, &tile_cap};
         HIP_TRY(hipLaunchKernel(stage_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(256), sargs, 0, stream));
     }
     EvSet* e = s.ev;
@@ -851,30 +858,29 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
         FnState& fs = r->st[fi];
         const int kidx = kernel_index(r->grid ? r->spec.base.family : r->fns[fi].family, fs.f64);
-        std::vector<Tile>& out = s.kt[kidx];
-        const size_t run_begin = out.size();
-        const uint32_t per_tile = (uint32_t)kBlockWaves << fs.seg_log2;
-        const uint64_t tile_samples = (uint64_t)per_tile * kSegSamples;
+        const uint64_t tile_samples = ((uint64_t)kBlockWaves << fs.seg_log2) * kSegSamples;
         const uint64_t fn_samples = r->grid ? r->spec.base.n_samples : r->fns[fi].n_samples;
-        while (fs.next_tile < fs.n_tiles && s.n_tiles < ctx->tile_cap && taken < budget) {
-            const uint64_t first = (uint64_t)fs.next_tile * tile_samples;
-            s.n_samples += std::min<uint64_t>(tile_samples, fn_samples - first);
-            out.emplace_back();
-            s.n_tiles++;
-            Tile& t = out.back();
-            t.fn = fs.slot;
-            t.seg0 = fs.next_tile * per_tile;
-            t.seg_log2 = fs.seg_log2;
-            t.out = (uint32_t)(fs.part0 + fs.next_tile);
-            fs.next_tile++;
-            r->tiles_launched++;
-            taken++;
+        // the function's next tiles, as many as the launch and the share allow, in one run
+        uint64_t take = fs.n_tiles - fs.next_tile;
+        take = std::min<uint64_t>(take, ctx->tile_cap - s.n_tiles);
+        take = std::min<uint64_t>(take, budget - std::min(budget, taken));
+        if (take > 0 && s.n_runs >= ctx->fin_cap) take = 0;  // run records are full
+        if (take > 0) {
+            const uint64_t a = fs.next_tile, b = a + take;
+            s.n_samples += std::min<uint64_t>(b * tile_samples, fn_samples) - a * tile_samples;
+            HostRun hr;
+            hr.cost = fs.tile_cost;
+            hr.run = TileRun{fs.slot, (uint32_t)a, (uint32_t)take, fs.seg_log2, (uint32_t)fs.part0, 0u, {0u, 0u}};
+            s.runs[kidx].push_back(hr);
+            s.n_runs++;
+            s.n_tiles += (uint32_t)take;
+            fs.next_tile = (uint32_t)b;
+            r->tiles_launched += take;
+            taken += take;
         }
-        if (out.size() > run_begin)
-            s.runs[kidx].push_back(TileRun{fs.tile_cost, (uint32_t)run_begin, (uint32_t)(out.size() - run_begin)});
         if (taken > 0 && (s.touched.empty() || s.touched.back() != r)) s.touched.push_back(r);
         if (fs.next_tile < fs.n_tiles) {
-            room = s.n_tiles < ctx->tile_cap;
+            room = s.n_tiles < ctx->tile_cap && s.n_runs < ctx->fin_cap;
             break;
         }
         if (s.n_fins >= ctx->fin_cap) {
@@ -913,8 +919,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         return false;
     }
     LaunchSlot& s = *slot;
-    s.n_tiles = s.n_fins = 0;
-    for (auto& v : s.kt) v.clear();
+    s.n_tiles = s.n_fins = s.n_runs = 0;
     for (auto& v : s.runs) v.clear();
     s.fv.clear();
     s.n_samples = 0;
@@ -933,30 +938,31 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     }
     ctx->active.swap(keep);
     if (s.n_tiles == 0 && s.n_fins == 0) return false;
-    // stage: the kernels' tiles one part after another, then the finalize records
+    // stage: finalize records after the descriptor, then the tile runs; the
+    // stage kernel expands the runs into the device tile list, the kernels'
+    // parts one after another
     uint8_t* const hdesc = s.h_block + ctx->slot_res_bytes;
     uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
-    Tile* const htiles = (Tile*)(hdesc + kDescBytes);
+    Fin* const hfins = (Fin*)(hdesc + kDescBytes);
+    TileRun* const hruns = (TileRun*)(hfins + s.n_fins);
+    if (s.n_fins) std::memcpy(hfins, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
     {
         // Within a kernel's part, functions' runs go in descending tile cost, so
         // the last tiles each workgroup fetches are the cheapest (a short tail).
         // Results do not depend on the order.
-        uint32_t off = 0;
+        uint32_t off = 0, nr = 0;
         for (int k = 0; k < kMaxKernels; ++k) {
             s.tile_begin[k] = off;
-            s.tile_count[k] = (uint32_t)s.kt[k].size();
-            std::vector<TileRun>& rr = s.runs[k];
-            std::stable_sort(rr.begin(), rr.end(), [](const TileRun& a, const TileRun& b) { return a.cost > b.cost; });
-            uint32_t o = off;
-            for (const TileRun& run : rr) {
-                std::memcpy(htiles + o, s.kt[k].data() + run.begin, (size_t)run.count * sizeof(Tile));
-                o += run.count;
+            std::vector<HostRun>& rr = s.runs[k];
+            std::stable_sort(rr.begin(), rr.end(), [](const HostRun& a, const HostRun& b) { return a.cost > b.cost; });
+            for (HostRun& hr : rr) {
+                hr.run.dst = off;
+                hruns[nr++] = hr.run;
+                off += hr.run.count;
             }
-            off += s.tile_count[k];
+            s.tile_count[k] = off - s.tile_begin[k];
         }
-        if (s.n_fins) std::memcpy(htiles + s.n_tiles, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
     }
-    static_assert(sizeof(Fin) == sizeof(Tile), "tiles and finalize records share the staging stride");
 
     // Launches may be enqueued on different streams; a function's tiles can span
     // launches, so each launch waits for the previous one, and for the uploads
@@ -984,11 +990,13 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     uint8_t* const hdesc_dev = s.h_block_dev + ctx->slot_res_bytes;
     LaunchDesc* hd = (LaunchDesc*)hdesc;
     std::memset(hdesc, 0, kDescBytes);
-    hd->stage_bytes = kDescBytes + ((uint64_t)s.n_tiles + s.n_fins) * sizeof(Tile);
+    hd->stage_bytes = kDescBytes + (uint64_t)s.n_fins * sizeof(Fin);
+    hd->n_runs = s.n_runs;
+    hd->runs_off = (uint32_t)(kDescBytes + (uint64_t)s.n_fins * sizeof(Fin));
     hd->fns = ctx->d_fns;
-    hd->tiles = (const Tile*)(ddesc + kDescBytes);
+    hd->tiles = (const Tile*)(ddesc + kDescBytes + (uint64_t)ctx->fin_cap * sizeof(Fin));
     hd->partials = ctx->d_partials;
-    hd->fins = (const Fin*)(ddesc + kDescBytes) + s.n_tiles;
+    hd->fins = (const Fin*)(ddesc + kDescBytes);
     hd->results = (DevResult*)ddesc - s.n_fins;
     hd->host_results = (DevResult*)hdesc_dev - s.n_fins;
     hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));

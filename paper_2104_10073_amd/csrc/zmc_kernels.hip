@@ -10,19 +10,39 @@
 
 namespace zmc {
 
-// First kernel of a launch: copy the staged descriptor, counters, tile list and
-// finalize records from pinned host memory into the slot's device block.  The
-// byte count is the descriptor's first field; `cap` (the block's size) bounds it.
+// First kernel of a launch: copy the staged descriptor, counters and finalize
+// records from pinned host memory into the slot's device block (their byte
+// count is the descriptor's first field, bounded by `cap`), and expand the
+// staged tile runs into the device tile list (bounded by `tile_cap`).
 extern "C" __global__ __launch_bounds__(256) void zmc_stage(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                                                            uint64_t cap)
+                                                            uint64_t cap, uint32_t tile_cap)
 {
     __shared__ uint64_t s_bytes;
-    if (threadIdx.x == 0) s_bytes = reinterpret_cast<const LaunchDesc*>(src)->stage_bytes;
+    __shared__ uint32_t s_runs, s_runs_off;
+    __shared__ Tile* s_tiles;
+    if (threadIdx.x == 0) {
+        const LaunchDesc* hd = reinterpret_cast<const LaunchDesc*>(src);
+        s_bytes = hd->stage_bytes;
+        s_runs = hd->n_runs;
+        s_runs_off = hd->runs_off;
+        s_tiles = const_cast<Tile*>(hd->tiles);
+    }
     __syncthreads();
     const uint64_t bytes = s_bytes < cap ? s_bytes : cap;
     const uint64_t n = bytes / sizeof(uint4);
     for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (uint64_t)gridDim.x * blockDim.x)
         dst[i] = src[i];
+    const TileRun* runs = reinterpret_cast<const TileRun*>(reinterpret_cast<const uint8_t*>(src) + s_runs_off);
+    Tile* tiles = s_tiles;
+    for (uint32_t r = blockIdx.x; r < s_runs; r += gridDim.x) {
+        const TileRun run = runs[r];
+        if (run.dst > tile_cap || run.count > tile_cap - run.dst || run.seg_log2 > (uint32_t)kMaxSegLog2) continue;
+        const uint32_t per_tile = (uint32_t)kBlockWaves << run.seg_log2;  // segments
+        for (uint32_t i = threadIdx.x; i < run.count; i += blockDim.x) {
+            const uint32_t t = run.first + i;
+            tiles[run.dst + i] = Tile{run.fn, t * per_tile, run.seg_log2, run.part0 + t};
+        }
+    }
 }
 
 // Per-function second pass, one wave per function: the tile partials are summed
