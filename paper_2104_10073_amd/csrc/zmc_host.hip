@@ -60,7 +60,6 @@ thread_local std::string g_thread_error;
 
 constexpr int kLaunchSlots = 3;
 constexpr uint64_t kMaxSamples = 1ull << 40;
-constexpr double kTwoPi = 6.283185307179586476925286766559;
 
 // ---------------------------------------------------------------- small helpers
 

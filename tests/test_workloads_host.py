@@ -1,5 +1,7 @@
 """Seeded workload generator and host-side planning (CPU only)."""
 
+import os
+
 import numpy as np
 import pytest
 
@@ -82,3 +84,14 @@ def test_serving_summary_math():
     assert s["measured"] == 90
     assert abs(s["p50_ms"] - np.percentile(lat[10:], 50) * 1e3) < 1e-9
     assert s["sustained_evals_per_s"] == 1e9
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py runs on one GPU; asking for more exits with a message (no GPU touched)."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert p.returncode == 2
+    assert "one GPU" in p.stderr
