@@ -248,6 +248,17 @@ typedef struct mc_stats {
 
 mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out);
 
+/* The points at which the library samples function `f` (direct Monte Carlo:
+ * uniform points in the box, paper "Solution method"): samples
+ * [first, first + count) as count x f->dim doubles, row-major, into the host
+ * array `out`, computed on the device by the batched kernels' Philox generator
+ * and FP64 mapping x = fma(hi - lo, u, lo).  The FP32 evaluation uses the same
+ * uniforms u.  For reproducing or auditing a result; synchronous on `stream`.
+ * Errors: as mc_submit's validation of f; MC_ERR_INVALID_ARG if the range is
+ * empty, leaves [0, n_samples) or holds more than 2^26 samples. */
+mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, uint64_t count, double* out,
+                           void* stream);
+
 /* Register an integrand family given as source text, compiled at run time for
  * gfx950 (hipRTC).  The paper's program integrates functions of arbitrary form
  * written by the user (program summary, "Nature of problem"; the multi-function

@@ -51,6 +51,7 @@ EXPORTS = [
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
     "mc_segment_samples", "mc_version", "mc_register_family", "mc_submit_grid",
+    "mc_sample_points",
 ]
 
 
@@ -125,6 +126,7 @@ def load(path: str = LIB_PATH):
     L.mc_last_run_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
     L.mc_get_stats.argtypes = [vp, ctypes.POINTER(McStats)]
     L.mc_last_error.argtypes = [vp]
+    L.mc_sample_points.argtypes = [vp, vp, ctypes.c_uint64, ctypes.c_uint64, vp, vp]
     L.mc_submit_grid.argtypes = [vp, vp, vp, ctypes.c_uint32, ctypes.c_int32, u64p]
     L.mc_register_family.argtypes = [vp, ctypes.c_char_p, ctypes.POINTER(ctypes.c_uint32)]
     L.mc_last_error.restype = ctypes.c_char_p
@@ -287,6 +289,16 @@ class Context:
         fam = ctypes.c_uint32()
         self._check(self.L.mc_register_family(self.h, source.encode(), ctypes.byref(fam)), self.h)
         return int(fam.value)
+
+    def sample_points(self, fn, first: int, count: int, stream=None) -> np.ndarray:
+        """Points of samples [first, first + count) of one function, shape (count, dim)."""
+        t = as_table(np.atleast_1d(fn))
+        if len(t) != 1:
+            raise ValueError("one function")
+        out = np.zeros((count, int(t["dim"][0])), dtype=np.float64)
+        self._check(self.L.mc_sample_points(self.h, t.ctypes.data, first, count, out.ctypes.data,
+                                            _stream_handle(stream)), self.h)
+        return out
 
     # -- plain baseline
     def plain_fp64(self, fns, stream=None):

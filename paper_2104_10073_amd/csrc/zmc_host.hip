@@ -38,6 +38,7 @@ const void* finalize_kernel_ptr();
 const void* stage_kernel_ptr();
 const void* publish_kernel_ptr();
 const void* pack_grid_kernel_ptr();
+const void* sample_points_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
 // compiling caller-supplied families at run time.
@@ -1524,6 +1525,43 @@ mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n,
     if (d_fns) quiet(hipFree(d_fns));
     if (d_parts) quiet(hipFree(d_parts));
     if (d_res) quiet(hipFree(d_res));
+    return status;
+}
+
+mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, uint64_t count, double* out,
+                           void* stream)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!f || !out || count == 0) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument or empty range");
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    std::string why;
+    const mc_status st = validate_one(*f, ctx->n_user, &why);
+    if (st != MC_OK) return fail(ctx, st, "function: %s", why.c_str());
+    if (count > (1ull << 26)) return fail(ctx, MC_ERR_INVALID_ARG, "count %llu above 2^26", (unsigned long long)count);
+    if (first >= f->n_samples || count > f->n_samples - first)
+        return fail(ctx, MC_ERR_INVALID_ARG, "samples [%llu, %llu) outside 0..%llu", (unsigned long long)first,
+                    (unsigned long long)(first + count), (unsigned long long)f->n_samples);
+    DevFn packed;
+    pack_function(*f, MC_PREC_FP64, &packed);
+    DevFn* d_fn = nullptr;
+    double* d_out = nullptr;
+    const size_t out_bytes = (size_t)count * f->dim * sizeof(double);
+    mc_status status = MC_OK;
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        HIP_TRY(hipMalloc(&d_fn, sizeof(DevFn)));
+        HIP_TRY(hipMalloc(&d_out, out_bytes));
+        HIP_TRY(hipMemcpyAsync(d_fn, &packed, sizeof(DevFn), hipMemcpyHostToDevice, s));
+        void* args[] = {&d_fn, &first, &count, &d_out};
+        HIP_TRY(hipLaunchKernel(sample_points_kernel_ptr(), dim3((unsigned)((count + 255) / 256)), dim3(256), args, 0, s));
+        HIP_TRY(hipMemcpyAsync(out, d_out, out_bytes, hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } catch (const HipError& e) {
+        status = fail_hip(ctx, e);
+    }
+    if (d_fn) quiet(hipFree(d_fn));
+    if (d_out) quiet(hipFree(d_out));
     return status;
 }
 

@@ -137,6 +137,27 @@ extern "C" __global__ __launch_bounds__(256) void zmc_pack_grid(GridSpec spec, D
     pack_function(f, spec.precision, &out[i]);
 }
 
+// The points of samples [first, first + count) of one function, row-major
+// (count x dim), from the batched kernels' generator and FP64 mapping: block
+// q*d + j of sample i = 4q + s gives coordinate j from its word s.
+extern "C" __global__ __launch_bounds__(256) void zmc_sample_points(const DevFn* __restrict__ fn_in, uint64_t first,
+                                                                    uint64_t count, double* __restrict__ out)
+{
+    const uint64_t t = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= count) return;
+    CDevFn* fn = scalar_view(fn_in);
+    const uint64_t i = first + t;
+    const uint64_t q = i >> 2;
+    const uint32_t s = (uint32_t)(i & 3u);
+    const uint32_t d = fn->dim;
+    for (uint32_t j = 0; j < d && j < (uint32_t)kMaxDim; ++j) {
+        const uint64_t b = q * d + j;
+        uint32_t w[4];
+        philox_block((uint32_t)b, (uint32_t)(b >> 32), fn->key0, fn->key1, w);
+        out[t * d + j] = fma(fn->w[j], word_to_u64(w[s]), fn->lo[j]);
+    }
+}
+
 // ---------------------------------------------------------------- plain FP64 path
 
 // One thread per quad over a grid sized to the function's N, block sums in LDS,
@@ -228,6 +249,7 @@ const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
 const void* stage_kernel_ptr() { return (const void*)zmc_stage; }
 const void* publish_kernel_ptr() { return (const void*)zmc_publish; }
 const void* pack_grid_kernel_ptr() { return (const void*)zmc_pack_grid; }
+const void* sample_points_kernel_ptr() { return (const void*)zmc_sample_points; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }
 
