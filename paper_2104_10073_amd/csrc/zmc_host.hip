@@ -61,6 +61,7 @@ thread_local std::string g_thread_error;
 
 constexpr int kLaunchSlots = 3;
 constexpr uint64_t kMaxSamples = 1ull << 40;
+constexpr uint32_t kTargetTilesPerFn = 1u << 16;
 
 // ---------------------------------------------------------------- small helpers
 
@@ -1237,8 +1238,11 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const DevFn& d)
     // run-time families take the harmonic family's tile size
     const uint32_t tf = d.kfam < (uint32_t)kNumFamilies ? d.kfam : (uint32_t)MC_FAMILY_HARMONIC;
     uint32_t L = ctx->seg_log2[r->precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
-    // no point in tiles larger than the function
+    // no point in tiles larger than the function; very large functions take
+    // larger tiles so their partials stay within kTargetTilesPerFn (results do
+    // not depend on the tile size)
     while (L > 0 && ((uint32_t)kBlockWaves << (L - 1)) >= d.n_segments) --L;
+    while (L < (uint32_t)kMaxSegLog2 && tiles_for(d.n_segments, L) > kTargetTilesPerFn) ++L;
     fs.seg_log2 = L;
     fs.n_tiles = tiles_for(d.n_segments, L);
     fs.next_tile = 0;

@@ -95,3 +95,15 @@ def test_bench_refuses_more_than_one_gpu():
                        text=True, timeout=120)
     assert p.returncode == 2
     assert "one GPU" in p.stderr
+
+
+def test_very_large_functions_take_larger_tiles():
+    """Tiles grow (up to 256 segments of 4096 samples) so that a function needs
+    at most 2^16 tile partials where it can: 2^36 samples -> 2^16 tiles, 2^40
+    samples -> 2^20 (the largest tile), both within the default partial space."""
+    import paper_2104_10073_amd as Z
+    for log2n, tiles in ((36, 1 << 16), (40, 1 << 20), (20, 64)):
+        row = W.harmonic_batch(1, n_samples=1 << log2n)
+        with Z.Context(flags=Z.MC_VALIDATE_ONLY) as c:
+            c.submit(row, Z.PREC_FP32)
+            assert c.validate_tiles() == tiles, log2n
