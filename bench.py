@@ -183,10 +183,25 @@ def serving_leg(Z, W, stream, args):
     return summ
 
 
+USER_RATIONAL_SRC = r"""
+template <class T>
+__device__ T mc_user_integrand(const T* x, const T* p, uint32_t d)
+{
+    T s = T(1);
+    for (uint32_t j = 0; j < d; ++j) {
+        const T t = p[2 + j] * x[j];
+        s += t * t;
+    }
+    return T(1) / s;
+}
+"""
+
+
 def other_configs(Z, W, stream):
     """Throughput of the other workloads (each run twice, the second timed): the
-    paper's Eq. (1) series (plain FP64 and batched FP32), the mixed-form batch
-    and the high-dimensional batch (batched FP32 with FP64 promotion)."""
+    paper's Eq. (1) series (plain FP64 and batched FP32), a parameter grid
+    (functional mode), a run-time compiled integrand, the mixed-form batch and
+    the high-dimensional batch (batched FP32 with FP64 promotion)."""
     import torch
     out = {}
 
@@ -205,6 +220,22 @@ def other_configs(Z, W, stream):
         _, tb = timed(lambda: ctx.integrate(eq1, Z.PREC_FP32, stream=stream))
         out["eq1_100x1e4"] = {"evals": ev, "plain_fp64_ms": tp * 1e3, "batched_fp32_ms": tb * 1e3,
                               "plain_fp64_evals_per_s": ev / tp, "batched_fp32_evals_per_s": ev / tb}
+        # functional mode: one harmonic form over a 64 x 16 parameter grid, records built on the device
+        base, axes = W.functional_grid(n_k=64, n_ab=16, n_samples=1_000_000)
+        ev = 64 * 16 * 1_000_000
+        _, tg = timed(lambda: ctx.integrate_grid(base, axes, Z.PREC_FP32, stream=stream))
+        out["grid_64x16_harmonic_1e6"] = {"evals": ev, "wall_ms": tg * 1e3, "evals_per_s": ev / tg}
+        log(f"grid_64x16_harmonic_1e6: {ev / tg:.3g} evals/s")
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as ctx:
+        # a caller-supplied integrand compiled at run time: 1 / (1 + sum_j (p_j x_j)^2)
+        fam = ctx.register_family(USER_RATIONAL_SRC)
+        table = W.mixed_batch(1000, dim_range=(1, 12), log10_samples=(6.0, 6.0), gen_seed=7)
+        table["family"] = fam
+        ev = W.total_evals(table)
+        _, tu = timed(lambda: ctx.integrate(table, Z.PREC_FP32, stream=stream))
+        out["user_family_1000x1e6_dims1to12"] = {"evals": ev, "wall_ms": tu * 1e3, "evals_per_s": ev / tu}
+        log(f"user_family_1000x1e6_dims1to12: {ev / tu:.3g} evals/s")
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as ctx:
         for name, table in (("mixed_2000_dims1to7", W.mixed_batch(2000)),
                             ("highdim_500x1e7_dims8to12", W.high_dim_batch(500))):
             ev = W.total_evals(table)
