@@ -782,10 +782,11 @@ void admit(mc_ctx* ctx)
 
 void capture_graph(mc_ctx* ctx, LaunchSlot& s);
 
-// The three kernels of a launch.  Direct launches bracket each kernel with
-// timing events; a captured graph holds the kernels only and is timed as a
-// whole from outside (events recorded inside captured graphs are not
-// reliable timing sources).
+// The kernels of a launch: stage, the batched kernels (built-in FP32 and FP64,
+// then those of run-time families with tiles), finalize, publish.  Direct
+// launches bracket the batched kernels and the finalize with timing events; a
+// captured graph holds the kernels only and is timed as a whole from outside
+// (events recorded inside captured graphs are not reliable timing sources).
 void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events)
 {
     LaunchDesc* dd = s.d_desc;
