@@ -363,11 +363,11 @@ def main():
         "metric": "integrand evals/sec + % FP32 VALU peak; serving p50/p99 latency at fixed QPS",
         "value": value, "unit": "integrand evals/s", "n_gpus": 1, "steps": K, "warmup": Wm,
         "ms_per_step": dt / K * 1e3, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32 eval / f64 reduce", "data": "synthetic (seeded PCG64 parameters, Philox samples)",
+        "dtype": "f32", "data": "synthetic (seeded PCG64 parameters, Philox samples)",
         "config": {"workload": f"harmonic batch: {args.n_funcs} integrands a cos(k.x)+b sin(k.x) on [0,1]^4, "
                                f"a,b~U(0.5,2), k~U(5,30), {args.n_samples:.0e} samples each, one seed per step",
                    "functions": args.n_funcs, "samples_per_function": args.n_samples, "dim": 4,
-                   "precision": "fp32-eval", "tuning": tuning or "default"},
+                   "precision": "fp32 evaluation, fp64 reductions and finalize", "tuning": tuning or "default"},
         "roofline": roof,
     }
 
