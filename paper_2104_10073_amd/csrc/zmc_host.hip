@@ -251,9 +251,6 @@ struct Request {
         grid_function(spec.base, spec.axes, spec.n_axes, i, &f);
         return f;
     }
-    DevFn* packed = nullptr;          // packed table (pinned host memory on a device context)
-    bool packed_pinned = false;
-    size_t packed_cap = 0;            // bytes of the pinned buffer (from the context's pool)
     std::vector<FnState> st;
     std::vector<mc_result> results;
     std::vector<uint32_t> order;      // functions by descending per-tile cost
@@ -263,7 +260,7 @@ struct Request {
     uint64_t part_base = 0, part_count = 0;
     uint32_t slot_base = 0;
     bool admitted = false;
-    hipEvent_t uploaded = nullptr;    // upload of the packed table (library upload stream)
+    hipEvent_t uploaded = nullptr;    // upload of the packed records (library upload stream)
     uint32_t fns_done = 0;
     uint64_t tiles_total = 0, tiles_launched = 0;
     bool aborted = false;
@@ -358,8 +355,8 @@ struct mc_ctx {
     uint32_t* h_words = nullptr;       // pinned {0, 1}: sources for setting / clearing it
     uint32_t* h_done = nullptr;        // pinned fine-grained: one done word per launch slot (16 words apart)
     uint32_t* h_done_dev = nullptr;    // its device address
-    std::multimap<size_t, void*> pinned_free;  // pooled pinned buffers by capacity
-    size_t pinned_free_bytes = 0;
+    DevFn* h_fns = nullptr;            // pinned host mirror of the function table (records are packed
+                                       // here at admission and uploaded from here)
     std::vector<std::unique_ptr<EvSet>> ev_pool;
     std::vector<EvSet*> ev_free;
     std::deque<EvSet*> ev_pending;     // recorded sets, oldest first
@@ -469,53 +466,8 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
     return (n_segments + per_tile - 1) / per_tile;
 }
 
-// Pinned host buffers (packed tables) are pooled by power-of-two capacity:
-// freeing pinned memory synchronizes the whole device, which would drain the
-// launch pipeline every time a request completes.
-constexpr size_t kPinnedPoolMax = 512ull << 20;
-
-void* pinned_get(mc_ctx* ctx, size_t bytes, size_t* cap)
-{
-    size_t c = 64 << 10;
-    while (c < bytes) c <<= 1;
-    *cap = c;
-    auto it = ctx->pinned_free.find(c);
-    if (it != ctx->pinned_free.end()) {
-        void* p = it->second;
-        ctx->pinned_free.erase(it);
-        ctx->pinned_free_bytes -= c;
-        return p;
-    }
-    void* p = nullptr;
-    const hipError_t e = hipHostMalloc(&p, c, hipHostMallocDefault);
-    if (e != hipSuccess) {
-        quiet(e);
-        return nullptr;
-    }
-    return p;
-}
-
-void pinned_put(mc_ctx* ctx, void* p, size_t cap)
-{
-    if (ctx->pinned_free_bytes + cap > kPinnedPoolMax) {
-        quiet(hipHostFree(p));
-        return;
-    }
-    ctx->pinned_free.emplace(cap, p);
-    ctx->pinned_free_bytes += cap;
-}
-
-void free_packed(mc_ctx* ctx, Request* r)
-{
-    if (!r->packed) return;
-    if (r->packed_pinned) pinned_put(ctx, r->packed, r->packed_cap);
-    else std::free(r->packed);
-    r->packed = nullptr;
-}
-
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
-    free_packed(ctx, r);
     if (r->uploaded) {
         quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
@@ -552,13 +504,9 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     fs.f64 = true;
     fs.next_tile = 0;
     r->tiles_total += fs.n_tiles;
-    if (!r->packed) {  // a grid: host records only for the functions promoted to FP64
-        r->packed = (DevFn*)pinned_get(ctx, r->count() * sizeof(DevFn), &r->packed_cap);
-        if (!r->packed) throw HipError{hipErrorOutOfMemory, "pinned buffer for promoted grid functions"};
-        r->packed_pinned = true;
-    }
-    pack_function(r->at(fi), MC_PREC_FP64, &r->packed[fi]);
-    HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &r->packed[fi], sizeof(DevFn), hipMemcpyHostToDevice,
+    // the slot's previous upload has completed (its FP32 result came back)
+    pack_function(r->at(fi), MC_PREC_FP64, &ctx->h_fns[fs.slot]);
+    HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &ctx->h_fns[fs.slot], sizeof(DevFn), hipMemcpyHostToDevice,
                            ctx->upload_stream));
     if (!r->uploaded) HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
@@ -770,8 +718,11 @@ void admit(mc_ctx* ctx)
             HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256), args, 0,
                                     ctx->upload_stream));
         } else {
-            HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, r->packed, nf * sizeof(DevFn), hipMemcpyHostToDevice,
-                                   ctx->upload_stream));
+            // records packed into the slots' part of the pinned mirror (whose
+            // previous uploads completed before those slots were released)
+            for (uint64_t i = 0; i < nf; ++i) pack_function(r->fns[i], r->precision, &ctx->h_fns[slot_off + i]);
+            HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
+                                   hipMemcpyHostToDevice, ctx->upload_stream));
         }
         HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
         HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
@@ -1085,9 +1036,8 @@ void destroy_device(mc_ctx* ctx)
     ctx->ev_pool.clear();
     ctx->ev_free.clear();
     ctx->ev_pending.clear();
-    for (auto& kv : ctx->pinned_free) quiet(hipHostFree(kv.second));
-    ctx->pinned_free.clear();
-    ctx->pinned_free_bytes = 0;
+    if (ctx->h_fns) quiet(hipHostFree(ctx->h_fns));
+    ctx->h_fns = nullptr;
     if (ctx->h_words) quiet(hipHostFree(ctx->h_words));
     if (ctx->h_done) quiet(hipHostFree(ctx->h_done));
     ctx->h_done = nullptr;
@@ -1195,6 +1145,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             HIP_TRY(hipHostMalloc((void**)&s.h_block, L.slot_bytes, hipHostMallocMapped | hipHostMallocCoherent));
             HIP_TRY(hipHostGetDevicePointer((void**)&s.h_block_dev, s.h_block, 0));
         }
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_fns, (size_t)ctx->max_functions * sizeof(DevFn), hipHostMallocDefault));
         HIP_TRY(hipHostMalloc((void**)&ctx->h_done, kLaunchSlots * 16 * sizeof(uint32_t),
                               hipHostMallocMapped | hipHostMallocCoherent));
         HIP_TRY(hipHostGetDevicePointer((void**)&ctx->h_done_dev, ctx->h_done, 0));
@@ -1224,7 +1175,6 @@ mc_status mc_destroy(mc_ctx* ctx)
         for (auto& s : ctx->slots)
             if (s.in_flight && s.ev) quiet(hipEventSynchronize(s.ev->done));
     }
-    for (auto& kv : ctx->requests) free_packed(ctx, kv.second.get());
     if (!ctx->validate_only) destroy_device(ctx);
     delete ctx;
     return MC_OK;
@@ -1232,12 +1182,16 @@ mc_status mc_destroy(mc_ctx* ctx)
 
 namespace {
 
-// Scheduling state of function i (its packed record `d`), common to tables and grids.
-void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const DevFn& d)
+// Scheduling state of function i, common to tables and grids.
+void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
 {
+    struct {
+        uint32_t family, dim, n_segments;
+        uint64_t n_samples;
+    } d{f.family, f.dim, (uint32_t)(((f.n_samples + 3) / 4 + kSegQuads - 1) / kSegQuads), f.n_samples};
     FnState& fs = r->st[i];
     // run-time families take the harmonic family's tile size
-    const uint32_t tf = d.kfam < (uint32_t)kNumFamilies ? d.kfam : (uint32_t)MC_FAMILY_HARMONIC;
+    const uint32_t tf = d.family < (uint32_t)kNumFamilies ? d.family : (uint32_t)MC_FAMILY_HARMONIC;
     uint32_t L = ctx->seg_log2[r->precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
     // no point in tiles larger than the function; very large functions take
     // larger tiles so their partials stay within kTargetTilesPerFn (results do
@@ -1297,30 +1251,16 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
     r->precision = precision;
     r->fns.assign(fns, fns + n);
     r->n = n;
-    if (!ctx->validate_only && (r->packed = (DevFn*)pinned_get(ctx, n * sizeof(DevFn), &r->packed_cap)) != nullptr) {
-        r->packed_pinned = true;
-    } else {
-        r->packed = (DevFn*)std::malloc(n * sizeof(DevFn));
-        if (!r->packed) return fail(ctx, MC_ERR_OUT_OF_MEMORY, "host allocation for %zu functions failed", n);
-    }
-    struct PackedGuard {
-        mc_ctx* ctx;
-        Request* r;
-        bool armed = true;
-        ~PackedGuard() { if (armed) free_packed(ctx, r); }
-    } guard{ctx, r.get()};
     r->st.resize(n);
     r->results.assign(n, mc_result{});
     for (size_t i = 0; i < n; ++i) {
         std::string why;
         mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
-        pack_function(fns[i], precision, &r->packed[i]);
-        init_fn_state(ctx, r.get(), i, r->packed[i]);
+        init_fn_state(ctx, r.get(), i, fns[i]);
     }
-    const mc_status st = enqueue_request(ctx, std::move(r), out_request_id);
-    if (st == MC_OK) guard.armed = false;
-    return st;
+    // (records are packed at admission, into the pinned mirror of their slots)
+    return enqueue_request(ctx, std::move(r), out_request_id);
 }
 
 mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
@@ -1376,13 +1316,11 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
             stride *= axes[a].count;
         }
     }
-    // all functions share family, dimension and sample count: one record gives
+    // all functions share family, dimension and sample count: the base gives
     // everybody's schedule
-    DevFn d;
-    pack_function(r->spec.base, precision, &d);
     r->st.resize(n);
     r->results.assign(n, mc_result{});
-    for (uint64_t i = 0; i < n; ++i) init_fn_state(ctx, r.get(), i, d);
+    for (uint64_t i = 0; i < n; ++i) init_fn_state(ctx, r.get(), i, r->spec.base);
     return enqueue_request(ctx, std::move(r), out_request_id);
 }
 

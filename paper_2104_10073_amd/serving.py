@@ -43,6 +43,9 @@ def serve(ctx: Context, requests, arrivals, stream=None, precision: int = PREC_F
             id_to_idx[rid] = next_i
             next_i += 1
             progressed = True
+            # launch as soon as there is work, so the GPU starts while later
+            # arrivals are still being submitted
+            ctx.run(stream)
         ctx.run(stream)
         for rid in ctx.poll():
             i = id_to_idx.pop(rid, None)
