@@ -113,9 +113,9 @@ typedef struct mc_result {
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */
     uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH */
-    uint32_t max_functions;      /* device function slots (0: 1 << 16) */
-    uint32_t max_tiles_per_run;  /* tiles one mc_run may launch; the rest waits for the next run (0: no cap) */
-    uint64_t max_partials;       /* device tile-partial slots, 16 bytes each (0: 1 << 22) */
+    uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16) */
+    uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20) */
+    uint64_t max_partials;       /* device tile-partial slots, 16 bytes each, at most 2^32 - 1 (0: 1 << 22) */
     uint64_t mem_budget_bytes;   /* upper bound on device memory the context holds (0: no bound) */
     void* workspace;             /* optional caller-owned device memory for every device buffer */
     uint64_t workspace_bytes;    /* its size; see mc_workspace_size */

@@ -1089,6 +1089,11 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
     ctx->promote = (cfg.flags & MC_NO_PROMOTE) == 0;
     ctx->device = cfg.device;
     if (cfg.policy > MC_SCHED_FIFO) return fail(nullptr, MC_ERR_INVALID_ARG, "unknown policy %u", cfg.policy);
+    // tiles, finalize records and partial indices are 32-bit; the pinned mirror holds 1 KiB per slot
+    if (cfg.max_partials > 0xFFFFFFFFull)
+        return fail(nullptr, MC_ERR_INVALID_ARG, "max_partials above 2^32 - 1");
+    if (cfg.max_functions > (1u << 24)) return fail(nullptr, MC_ERR_INVALID_ARG, "max_functions above 2^24");
+    if (cfg.max_tiles_per_run > (1u << 28)) return fail(nullptr, MC_ERR_INVALID_ARG, "max_tiles_per_run above 2^28");
     ctx->policy = cfg.policy;
     default_tuning(ctx.get());
     resolve_capacities(cfg, &ctx->max_functions, &ctx->max_partials, &ctx->tile_cap, &ctx->fin_cap);

@@ -139,3 +139,11 @@ def test_workspace_size_monotone(Z):
         assert L.mc_workspace_size(ctypes.byref(cfg), ctypes.byref(out)) == 0
         sizes.append(out.value)
     assert sizes[1] > sizes[0] > 0
+
+
+@pytest.mark.parametrize("kw", [{"max_partials": 1 << 32}, {"max_functions": (1 << 24) + 1},
+                                {"max_tiles_per_run": (1 << 28) + 1}])
+def test_config_limits_of_32bit_indices(Z, kw):
+    with pytest.raises(Z.McError) as e:
+        Z.Context(flags=Z.MC_VALIDATE_ONLY, **kw)
+    assert e.value.status == -1
