@@ -301,23 +301,32 @@ def main():
     batches = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=b) for b in range(K + Wm)]
     evals_per_step = W.total_evals(batches[0])
 
-    # One launch per step: FIFO scheduling with the per-launch tile cap set to one
-    # batch's tile count, so each mc_run takes exactly the next seed's batch.
-    probe = Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY)
-    probe.submit(batches[0], Z.PREC_FP32)
-    tiles_per_batch = probe.validate_tiles()
-    probe.close()
+    # Autotuning on a context of its own (timed apart); its choices are applied
+    # to the probe that sizes a launch and to the timed context.
     flags = 0 if args.graph else Z.MC_NO_GRAPH
-    ctx = Z.Context(device=0, workspace="torch", flags=flags, policy=Z.MC_SCHED_FIFO,
-                    max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
     tuning = None
+    tuned = None
     if args.autotune > 0:
         ta = time.perf_counter()
-        ctx.autotune(Z.PREC_FP32, stream=stream, budget_seconds=args.autotune)
-        b, seg = ctx.get_tuning()
+        with Z.Context(device=0, flags=flags) as tctx:
+            tctx.autotune(Z.PREC_FP32, stream=stream, budget_seconds=args.autotune)
+            tuned = tctx.get_tuning()
+        b, seg = tuned
         tuning = {"autotune_s": time.perf_counter() - ta, "blocks_per_cu": b,
                   "tile_segments_log2_fp32_harmonic_d4": int(seg[0][0][3])}
         log(f"autotuned: {tuning}")
+    # One launch per step: FIFO scheduling with the per-launch tile cap set to one
+    # batch's tile count, so each mc_run takes exactly the next seed's batch.
+    probe = Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY)
+    if tuned is not None:
+        probe.set_tuning(0, tuned[1])
+    probe.submit(batches[0], Z.PREC_FP32)
+    tiles_per_batch = probe.validate_tiles()
+    probe.close()
+    ctx = Z.Context(device=0, workspace="torch", flags=flags, policy=Z.MC_SCHED_FIFO,
+                    max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
+    if tuned is not None:
+        ctx.set_tuning(tuned[0], tuned[1])
     ids = [ctx.submit(b, Z.PREC_FP32) for b in batches]
     n = args.n_funcs
     # warmup steps (also captures the launch graphs)
