@@ -113,6 +113,27 @@ def test_torch_workspace_and_stream():
     _same(ref, got, "torch workspace + side stream")
 
 
+def test_launches_alternating_between_streams():
+    """A function's tiles spread over several launches enqueued on different
+    streams (each launch orders itself after the previous one across streams):
+    same bits as one stream."""
+    import torch
+    Z = _Z()
+    t = _batch()
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        ref = c.integrate(t, Z.PREC_FP32)
+    streams = [torch.cuda.Stream(), torch.cuda.Stream(), torch.cuda.current_stream()]
+    with Z.Context(flags=Z.MC_NO_GRAPH, max_tiles_per_run=97) as c:
+        rid = c.submit(t, Z.PREC_FP32)
+        i = 0
+        while c.pending()[1] > 0:
+            c.run(streams[i % len(streams)])
+            i += 1
+        got = c.results(rid, len(t))
+        assert i > 3
+    _same(ref, got, "launches on alternating streams")
+
+
 def test_promotion_of_nearly_constant_functions():
     """A nearly constant integrand cannot be resolved in FP32; it comes back from FP64."""
     Z = _Z()
