@@ -147,7 +147,7 @@ def serving_leg(Z, W, stream, args):
     reqs = W.serving_requests(n, gen_seed=5)
     flags = 0 if args.graph else Z.MC_NO_GRAPH
     loads = sorted(set([args.serve_load] + [float(x) for x in args.serve_loads.split(",") if x]))
-    with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 15,
+    with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 16,
                    max_functions=1 << 17, max_partials=1 << 24) as ctx:
         sat = serving.serve(ctx, reqs, np.zeros(n), stream)
         sat_qps = n / sat["wall_s"]
