@@ -28,6 +28,21 @@ def test_eq1_plain_fp64(ctx):
     G.check_fp64(ctx.plain_fp64(t), orc, "plain eq1")
 
 
+def test_eq1_plain_fp64_against_closed_forms(ctx):
+    """The paper's Eq. (1) series on the GPU's plain FP64 path, checked against
+    the exact box integrals: z = (F_hat - F) / SE over n = 1..100 has mean 0 and
+    mean square 1 (each |F| < SE / 4 here, so the batch carries the test), and
+    every SE is within 3 % of the exact one."""
+    import closed_forms as CF
+    t = W.eq1_series(n_samples=10_000)
+    r = ctx.plain_fp64(t)
+    z = np.array([(r["mean"][i] - CF.exact_integral(t, i)) / CF.exact_se(t, i) for i in range(len(t))])
+    ratio = np.array([r["std_error"][i] / CF.exact_se(t, i) for i in range(len(t))])
+    assert abs(np.mean(z)) < 0.4 and abs(np.mean(z * z) - 1.0) < 0.6, (np.mean(z), np.mean(z * z))
+    assert np.all(np.abs(z) < 4.5)
+    assert np.all(np.abs(ratio - 1.0) < 0.03)
+
+
 def test_eq1_batched_fp64_and_fp32(ctx):
     import paper_2104_10073_amd as Z
     t = W.eq1_series(n_samples=10_000)
