@@ -275,7 +275,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: the multi-GPU path (tiles sharded across GPUs, one gather "
-              "of tile partials) is not part of this build; use --gpus 1", file=sys.stderr)
+              "of tile partials) is not implemented; use --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -44,7 +44,7 @@ __device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint3
                                              uint32_t out[4])
 {
     uint32_t c0, c1, c2, c3;
-    {   // round 1: c2 = c3 = 0
+    {   // first Philox round: c2 = c3 = 0
         const uint64_t p0 = (uint64_t)kPhiloxM0 * b_lo;
         c0 = b_hi ^ k0;
         c1 = 0u;
@@ -53,7 +53,7 @@ __device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint3
     }
     k0 += kPhiloxW0;
     k1 += kPhiloxW1;
-    {   // round 2: c1 = 0
+    {   // second Philox round: c1 = 0
         const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
         const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
         const uint32_t n0 = (uint32_t)(p1 >> 32) ^ k0;
