@@ -220,6 +220,19 @@ def other_configs(Z, W, stream):
         _, tb = timed(lambda: ctx.integrate(eq1, Z.PREC_FP32, stream=stream))
         out["eq1_100x1e4"] = {"evals": ev, "plain_fp64_ms": tp * 1e3, "batched_fp32_ms": tb * 1e3,
                               "plain_fp64_evals_per_s": ev / tp, "batched_fp32_evals_per_s": ev / tb}
+        # the paper's Fig. 1 job: the Eq. (1) series at 10^6 samples, ten independent
+        # runs, each function reported as mean and spread over the runs
+        fig1 = W.eq1_series(n_samples=1_000_000)
+        ev = 10 * W.total_evals(fig1)
+        row = {"evals": ev, "runs": 10,
+               "paper_context": "about one minute per run (all 100 integrals) on one V100, precision not stated"}
+        for pname, prec in (("fp32", Z.PREC_FP32), ("fp64", Z.PREC_FP64)):
+            (_, sp), tf = timed(lambda: Z.runs.integrate_runs(ctx, fig1, runs=10, precision=prec, stream=stream))
+            row[pname] = {"wall_ms": tf * 1e3, "ms_per_run": tf * 1e3 / 10, "evals_per_s": ev / tf,
+                          "mean_spread2_over_se2": float(np.mean((sp["spread"] / sp["rms_se"]) ** 2))}
+        out["eq1_fig1_100x1e6_10runs"] = row
+        log(f"eq1_fig1_100x1e6_10runs: {row['fp32']['ms_per_run']:.3f} ms per run (fp32), "
+            f"{row['fp64']['ms_per_run']:.3f} ms (fp64)")
         # functional mode: one harmonic form over a 64 x 16 parameter grid, records built on the device
         base, axes = W.functional_grid(n_k=64, n_ab=16, n_samples=1_000_000)
         ev = 64 * 16 * 1_000_000
@@ -381,6 +394,18 @@ def main():
     }
 
     log(f"timed: {value:.4g} evals/s, fp32 kernel {avg_main_s * 1e3:.3f} ms/launch")
+    if K >= 2:
+        # the paper's error statistic over the timed steps (each step one seed of the
+        # same functions): the spread over runs against the per-run standard errors
+        sp = Z.runs.spread(results)
+        q = (sp["spread"] / sp["rms_se"]) ** 2
+        out["run_spread"] = {
+            "runs": K, "functions": n,
+            "statistic": "per function: mean and sample std (n-1) of the estimate over the timed runs",
+            "mean_spread2_over_se2": float(np.mean(q)),
+            "expected_sd_of_that_mean": float(np.sqrt(2.0 / (K - 1) / n)),
+            "median_spread_over_se": float(np.median(np.sqrt(q))),
+        }
     if not args.no_comparators:
         # batched FP64 and the plain one-launch-per-function FP64 path on the seed-0 batch
         b0 = batches[Wm]

@@ -227,6 +227,34 @@ def check_z_batch(orc, n_funcs=100):
         assert abs((z * z).mean() - 1.0) < 4.0 * math.sqrt(2.0 / m), ("z^2 mean", (z * z).mean())
 
 
+def check_run_spread(orc, runs=10, n_samples=2_000):
+    """The paper's error bar (Fig. 1) is the sample standard deviation of the
+    estimates over independent runs.  Over the Eq. (1) series, run r drawing the
+    streams of base r: per function, (spread / exact SE)^2 is chi^2 with runs - 1
+    degrees of freedom over runs - 1 (mean 1, sd sqrt(2 / (runs - 1))), and the
+    mean over runs sits around the exact integral with sd SE / sqrt(runs)."""
+    t0 = W.eq1_series(n_samples=n_samples)
+    m = len(t0)
+    est = []
+    for r in range(runs):
+        t = t0.copy()
+        for i in range(m):
+            t["seed"][i] = W.stream_seed(r, i)
+        res, _ = orc.integrate(t, threads=8)
+        est.append(res["mean"])
+    est = np.array(est)
+    fbar = est.mean(axis=0)
+    spread = est.std(axis=0, ddof=1)
+    ex = np.array([exact_integral(t0, i) for i in range(m)])
+    se = np.array([exact_se(t0, i) for i in range(m)])
+    ratio = (spread / se) ** 2
+    assert abs(ratio.mean() - 1.0) < 4.0 * math.sqrt(2.0 / (runs - 1)) / math.sqrt(m), ("spread^2 / SE^2",
+                                                                                       ratio.mean())
+    z = (fbar - ex) / (se / math.sqrt(runs))
+    assert abs(z.mean()) < 4.0 / math.sqrt(m), ("F-bar z mean", z.mean())
+    assert abs((z * z).mean() - 1.0) < 4.0 * math.sqrt(2.0 / m), ("F-bar z^2 mean", (z * z).mean())
+
+
 def check_special_cases(orc):
     # k = 0: f is the constant a; every sum is exact
     t = W.empty(3)
@@ -283,4 +311,5 @@ ALL_CHECKS = [
     ("special_cases", lambda o, r: check_special_cases(o)),
     ("closed_forms", lambda o, r: check_closed_forms_4sigma(o)),
     ("eq2", lambda o, r: check_eq2_worked_values(o)),
+    ("run_spread", lambda o, r: check_run_spread(o)),
 ]

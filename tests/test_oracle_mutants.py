@@ -29,6 +29,7 @@ MUTANTS = [
      "uint64_t q = i;"),
     ("counter words in 2-3", "{(uint32_t)b, (uint32_t)(b >> 32), 0u, 0u}", "{0u, 0u, (uint32_t)b, (uint32_t)(b >> 32)}"),
     ("key halves swapped", "{(uint32_t)seed, (uint32_t)(seed >> 32)}", "{(uint32_t)(seed >> 32), (uint32_t)seed}"),
+    ("key high word dropped", "{(uint32_t)seed, (uint32_t)(seed >> 32)}", "{(uint32_t)seed, 0u}"),
     ("mapping drops lo", "x[j] = fma(w, u, fn->lo[j]);", "x[j] = w * u;"),
     ("harmonic sin sign", "fma(p[0], cos(theta), p[1] * sin(theta))", "fma(p[0], cos(theta), -p[1] * sin(theta))"),
     ("harmonic a/b swapped", "fma(p[0], cos(theta), p[1] * sin(theta))", "fma(p[1], cos(theta), p[0] * sin(theta))"),

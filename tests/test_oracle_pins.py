@@ -46,6 +46,10 @@ def test_eq2_worked_values(orc):
     P.check_eq2_worked_values(orc)
 
 
+def test_spread_over_independent_runs(orc):
+    P.check_run_spread(orc)
+
+
 def test_eq1_closed_form_matches_compact_formula():
     """Eq. (1) on [0,1]^4 with equal k: F_n = (2 sin(k/2)/k)^4 (cos 2k + sin 2k) -- pins the product form."""
     import mpmath

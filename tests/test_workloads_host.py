@@ -1,5 +1,6 @@
 """Seeded workload generator and host-side planning (CPU only)."""
 
+import math
 import os
 
 import numpy as np
@@ -107,3 +108,29 @@ def test_very_large_functions_take_larger_tiles():
         with Z.Context(flags=Z.MC_VALIDATE_ONLY) as c:
             c.submit(row, Z.PREC_FP32)
             assert c.validate_tiles() == tiles, log2n
+
+
+def test_runs_reseed_and_spread():
+    """Run r of a table draws the streams of base r; the spread is the per-function
+    mean and sample standard deviation (n - 1) over runs."""
+    from paper_2104_10073_amd import runs as R
+    from paper_2104_10073_amd._native import RESULT_DTYPE
+    t = W.harmonic_batch(5, n_samples=1000, base=0)
+    u = R.reseeded(t, 7)
+    assert list(u["seed"]) == [W.stream_seed(7, i) for i in range(5)]
+    assert list(t["seed"]) == [W.stream_seed(0, i) for i in range(5)]
+    for k in ("family", "dim", "n_samples", "lo", "hi", "params"):
+        assert np.array_equal(t[k], u[k])
+    rs = []
+    for r, vals in enumerate(([1.0, 2.0], [3.0, 2.0], [5.0, 2.0])):
+        a = np.zeros(2, dtype=RESULT_DTYPE)
+        a["mean"] = vals
+        a["std_error"] = [r + 1.0, 0.0]
+        rs.append(a)
+    s = R.spread(rs)
+    assert s["runs"] == 3
+    assert list(s["mean"]) == [3.0, 2.0]
+    assert list(s["spread"]) == [2.0, 0.0]
+    assert abs(s["rms_se"][0] - math.sqrt(14.0 / 3.0)) < 1e-15 and s["rms_se"][1] == 0.0
+    with pytest.raises(ValueError):
+        R.spread(rs[:1])
