@@ -138,8 +138,10 @@ def serving_leg(Z, W, stream, args):
 
     Requests of floor(10^U(0,3)) functions (mixed forms, dims 1..12, 10^4..10^7
     samples each).  The saturated rate is measured first with every request
-    arriving at t = 0; the offered QPS is `serve_load` times it.  Latency is
-    arrival to results-on-host; the first 10 % of requests are warm-up.
+    arriving at t = 0 under the headline scheduling policy; the offered QPS is
+    `serve_load` times it.  Latency is arrival to results-on-host; the first
+    10 % of requests are warm-up.  The other policies are measured at the same
+    absolute arrival rates.
     """
     from paper_2104_10073_amd import serving
 
@@ -147,40 +149,64 @@ def serving_leg(Z, W, stream, args):
     reqs = W.serving_requests(n, gen_seed=5)
     flags = 0 if args.graph else Z.MC_NO_GRAPH
     loads = sorted(set([args.serve_load] + [float(x) for x in args.serve_loads.split(",") if x]))
-    with Z.Context(device=0, flags=flags, policy=Z.MC_SCHED_FAIR, max_tiles_per_run=1 << 16,
-                   max_functions=1 << 17, max_partials=1 << 24) as ctx:
+    head = args.serve_policy
+    others = [p for p in args.serve_compare.split(",") if p and p != head]
+
+    def make_ctx(name):
+        return Z.Context(device=0, flags=flags, policy=SERVE_POLICIES[name](Z), max_tiles_per_run=1 << 16,
+                         max_functions=1 << 17, max_partials=1 << 24)
+
+    with make_ctx(head) as ctx:
         sat = serving.serve(ctx, reqs, np.zeros(n), stream)
-        sat_qps = n / sat["wall_s"]
+    sat_qps = n / sat["wall_s"]
+    summ = None
+    compare = {}
+    for name in [head] + others:
         per_load = []
-        for lf in loads:
-            if lf == args.serve_load:
+        with make_ctx(name) as ctx:
+            for lf in loads:
+                if name == head and lf == args.serve_load:
+                    continue
+                arr = W.poisson_arrivals(n, lf * sat_qps, seed=5)
+                o = serving.serve(ctx, reqs, arr, stream)
+                sm = serving.summarize(o, arr)
+                sm.update({"load_fraction": lf, "offered_qps": lf * sat_qps})
+                per_load.append(sm)
+                log(f"serving ({name}) at {lf:.2f} x saturated: p50 {sm['p50_ms']:.2f} ms, p99 {sm['p99_ms']:.2f} ms")
+            if name != head:
+                compare[name] = per_load
                 continue
-            arr = W.poisson_arrivals(n, lf * sat_qps, seed=5)
-            o = serving.serve(ctx, reqs, arr, stream)
-            sm = serving.summarize(o, arr)
-            sm.update({"load_fraction": lf, "offered_qps": lf * sat_qps})
-            per_load.append(sm)
-            log(f"serving at {lf:.2f} x saturated: p50 {sm['p50_ms']:.2f} ms, p99 {sm['p99_ms']:.2f} ms")
-        qps = args.serve_load * sat_qps
-        arrivals = W.poisson_arrivals(n, qps, seed=5)
-        run = serving.serve(ctx, reqs, arrivals, stream, keep_results=True)
-        summ = serving.summarize(run, arrivals)
-        log(f"serving at {args.serve_load:.2f} x saturated: p50 {summ['p50_ms']:.2f} ms, p99 {summ['p99_ms']:.2f} ms")
-        # each result alone equals its result inside the mix
-        rng = np.random.Generator(np.random.PCG64(23))
-        picks = rng.choice(n, size=min(20, n), replace=False)
-        same = True
-        for i in picks:
-            alone = ctx.integrate(reqs[i], Z.PREC_FP32, stream=stream)
-            mixed = run["results"][i]
-            same = same and all(np.array_equal(alone[k], mixed[k]) for k in ("mean", "std_error", "sum_f", "sum_f2"))
-    summ.update({"offered_qps": qps, "saturated_qps": sat_qps, "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
+            qps = args.serve_load * sat_qps
+            arrivals = W.poisson_arrivals(n, qps, seed=5)
+            run = serving.serve(ctx, reqs, arrivals, stream, keep_results=True)
+            summ = serving.summarize(run, arrivals)
+            log(f"serving ({name}) at {args.serve_load:.2f} x saturated: p50 {summ['p50_ms']:.2f} ms, "
+                f"p99 {summ['p99_ms']:.2f} ms")
+            # each result alone equals its result inside the mix
+            rng = np.random.Generator(np.random.PCG64(23))
+            picks = rng.choice(n, size=min(20, n), replace=False)
+            same = True
+            for i in picks:
+                alone = ctx.integrate(reqs[i], Z.PREC_FP32, stream=stream)
+                mixed = run["results"][i]
+                same = same and all(np.array_equal(alone[k], mixed[k]) for k in ("mean", "std_error", "sum_f", "sum_f2"))
+            head_other = per_load
+    summ.update({"policy": head, "offered_qps": qps, "saturated_qps": sat_qps,
+                 "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
                  "load_fraction": args.serve_load, "alone_equals_mix_bitwise": bool(same),
                  "requests_checked_alone": int(len(picks)),
-                 "other_loads": per_load,
+                 "other_loads": head_other,
+                 "other_policies_same_arrivals": compare,
                  "workload": "requests of floor(10^U(0,3)) functions, forms mixed, dims U{1..12}, "
                              "10^U(4,7) samples each, Poisson arrivals"})
     return summ
+
+
+SERVE_POLICIES = {
+    "fair": lambda Z: Z.MC_SCHED_FAIR,
+    "fifo": lambda Z: Z.MC_SCHED_FIFO,
+    "srpt": lambda Z: Z.MC_SCHED_SRPT,
+}
 
 
 USER_RATIONAL_SRC = r"""
@@ -281,6 +307,10 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
     ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests in the serving measurement (0 skips it)")
+    ap.add_argument("--serve-policy", default="fair", choices=sorted(SERVE_POLICIES),
+                    help="scheduling policy of the headline serving measurement")
+    ap.add_argument("--serve-compare", default="fair,srpt",
+                    help="policies also measured at the same arrival rates (comma-separated)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturated request rate")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",

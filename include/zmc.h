@@ -120,12 +120,14 @@ typedef struct mc_config {
     void* workspace;             /* optional caller-owned device memory for every device buffer */
     uint64_t workspace_bytes;    /* its size; see mc_workspace_size */
     uint32_t blocks_per_cu;      /* persistent-kernel workgroups per CU (0: tuned/default) */
-    uint32_t policy;             /* MC_SCHED_FAIR (0) or MC_SCHED_FIFO: how mc_run shares a launch */
+    uint32_t policy;             /* MC_SCHED_FAIR (0), MC_SCHED_FIFO or MC_SCHED_SRPT: how mc_run shares a launch */
 } mc_config;
 
 /* Scheduling policies for the tiles of one launch (results never depend on them). */
 #define MC_SCHED_FAIR 0u  /* every active request gets an equal share of the launch (small requests finish fast) */
 #define MC_SCHED_FIFO 1u  /* fill the launch from the oldest request on */
+#define MC_SCHED_SRPT 2u  /* fill the launch from the request with the least remaining work on (estimated
+                             evaluation cost of its tiles not yet launched); ties go to the older request */
 
 typedef struct mc_ctx mc_ctx;
 

@@ -34,6 +34,7 @@ MC_NO_GRAPH = 0x2
 MC_NO_PROMOTE = 0x4
 MC_SCHED_FAIR = 0
 MC_SCHED_FIFO = 1
+MC_SCHED_SRPT = 2
 GRID_AXIS_DTYPE = np.dtype([("param", "<u4"), ("count", "<u4"), ("start", "<f8"), ("step", "<f8")])
 MC_MAX_GRID_AXES = 4
 MC_FAMILY_USER0 = 16        # first run-time family id (mc_register_family)

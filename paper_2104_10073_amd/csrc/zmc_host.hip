@@ -263,6 +263,7 @@ struct Request {
     hipEvent_t uploaded = nullptr;    // upload of the packed records (library upload stream)
     uint32_t fns_done = 0;
     uint64_t tiles_total = 0, tiles_launched = 0;
+    double work_left = 0.0;           // estimated cost of the tiles not yet launched
     bool aborted = false;
     uint32_t n_promoted = 0;
 };
@@ -504,8 +505,12 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     fs.f64 = true;
     fs.next_tile = 0;
     r->tiles_total += fs.n_tiles;
+    const mc_function f = r->at(fi);
+    fs.tile_cost = sample_cost(f.family, f.dim, MC_PREC_FP64) *
+                   (double)std::min<uint64_t>(f.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << fs.seg_log2));
+    r->work_left += fs.tile_cost * fs.n_tiles;
     // the slot's previous upload has completed (its FP32 result came back)
-    pack_function(r->at(fi), MC_PREC_FP64, &ctx->h_fns[fs.slot]);
+    pack_function(f, MC_PREC_FP64, &ctx->h_fns[fs.slot]);
     HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &ctx->h_fns[fs.slot], sizeof(DevFn), hipMemcpyHostToDevice,
                            ctx->upload_stream));
     if (!r->uploaded) HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
@@ -829,6 +834,7 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
             s.n_tiles += (uint32_t)take;
             fs.next_tile = (uint32_t)b;
             r->tiles_launched += take;
+            r->work_left = std::max(0.0, r->work_left - fs.tile_cost * (double)take);
             taken += take;
         }
         if (taken > 0 && (s.touched.empty() || s.touched.back() != r)) s.touched.push_back(r);
@@ -880,10 +886,16 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     s.touched.clear();
     // FIFO fills the launch from the oldest request; FAIR gives every active
     // request an equal share first, so a small request never waits behind a
-    // large one for more than one launch.
+    // large one for more than one launch; SRPT fills it from the request with
+    // the least work left (shortest remaining processing time first), which
+    // under heavy-tailed request sizes shortens the wait of nearly every
+    // request, the largest ones included, compared with equal sharing.
     const uint64_t n_active = ctx->active.size();
-    const uint64_t share = ctx->policy == MC_SCHED_FIFO ? UINT64_MAX
-                                                         : std::max<uint64_t>(ctx->tile_cap / n_active, 64);
+    const uint64_t share = ctx->policy == MC_SCHED_FAIR ? std::max<uint64_t>(ctx->tile_cap / n_active, 64)
+                                                        : UINT64_MAX;
+    if (ctx->policy == MC_SCHED_SRPT)
+        std::stable_sort(ctx->active.begin(), ctx->active.end(),
+                         [](const Request* a, const Request* b) { return a->work_left < b->work_left; });
     std::deque<Request*> keep;
     for (Request* r : ctx->active) {
         if (has_work(r)) take_tiles(ctx, s, r, share);
@@ -1088,7 +1100,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
     ctx->use_graph = (cfg.flags & MC_NO_GRAPH) == 0;
     ctx->promote = (cfg.flags & MC_NO_PROMOTE) == 0;
     ctx->device = cfg.device;
-    if (cfg.policy > MC_SCHED_FIFO) return fail(nullptr, MC_ERR_INVALID_ARG, "unknown policy %u", cfg.policy);
+    if (cfg.policy > MC_SCHED_SRPT) return fail(nullptr, MC_ERR_INVALID_ARG, "unknown policy %u", cfg.policy);
     // tiles, finalize records and partial indices are 32-bit; the pinned mirror holds 1 KiB per slot
     if (cfg.max_partials > 0xFFFFFFFFull)
         return fail(nullptr, MC_ERR_INVALID_ARG, "max_partials above 2^32 - 1");
@@ -1210,6 +1222,7 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
     fs.tile_cost = sample_cost(d.family, d.dim, r->precision) *
                    (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
     r->tiles_total += fs.n_tiles;
+    r->work_left += fs.tile_cost * fs.n_tiles;
 }
 
 // Order, id and admission of a validated request.

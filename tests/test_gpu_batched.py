@@ -79,6 +79,33 @@ def test_concurrent_requests_and_small_budget():
         _same(a, b, f"request {k}")
 
 
+@pytest.mark.parametrize("policy", ["MC_SCHED_SRPT", "MC_SCHED_FIFO"])
+def test_scheduling_order_and_results(policy):
+    """A small request submitted after a large one: shortest-remaining-work-first
+    completes it in the first launch, FIFO only after the large one; under both,
+    every result equals the request integrated alone (scheduling never changes
+    what a function sums)."""
+    Z = _Z()
+    big = W.harmonic_batch(4, n_samples=4_000_000, base=5)      # ~245 tiles per function
+    small = W.eq1_series(n_samples=10_000, n_funcs=4, base=6)   # one tile per function
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        alone = [c.integrate(big, Z.PREC_FP32), c.integrate(small, Z.PREC_FP32)]
+    with Z.Context(flags=Z.MC_NO_GRAPH, policy=getattr(Z, policy), max_tiles_per_run=64) as c:
+        ids = [c.submit(big, Z.PREC_FP32), c.submit(small, Z.PREC_FP32)]
+        order = []
+        for _ in range(10_000):
+            c.run()
+            order += c.poll()
+            if len(order) == 2:
+                break
+        assert sorted(order) == sorted(ids)
+        outs = [c.results(ids[0], len(big)), c.results(ids[1], len(small))]
+    want = [ids[1], ids[0]] if policy == "MC_SCHED_SRPT" else [ids[0], ids[1]]
+    assert order == want, (policy, order, ids)
+    _same(alone[0], outs[0], "large request")
+    _same(alone[1], outs[1], "small request")
+
+
 def test_abort_then_recover():
     """Abort while the persistent kernels run (~0.1 s of work): they stop at their next
     tile fetch, the request comes back aborted, and later work is unaffected."""
