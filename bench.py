@@ -153,7 +153,7 @@ def serving_leg(Z, W, stream, args):
     others = [p for p in args.serve_compare.split(",") if p and p != head]
 
     def make_ctx(name):
-        return Z.Context(device=0, flags=flags, policy=SERVE_POLICIES[name](Z), max_tiles_per_run=1 << 16,
+        return Z.Context(device=0, flags=flags, policy=SERVE_POLICIES[name](Z), max_tiles_per_run=1 << 15,
                          max_functions=1 << 17, max_partials=1 << 24)
 
     with make_ctx(head) as ctx:
@@ -307,7 +307,7 @@ def main():
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
     ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests in the serving measurement (0 skips it)")
-    ap.add_argument("--serve-policy", default="fair", choices=sorted(SERVE_POLICIES),
+    ap.add_argument("--serve-policy", default="srpt", choices=sorted(SERVE_POLICIES),
                     help="scheduling policy of the headline serving measurement")
     ap.add_argument("--serve-compare", default="fair,srpt",
                     help="policies also measured at the same arrival rates (comma-separated)")

@@ -127,7 +127,9 @@ typedef struct mc_config {
 #define MC_SCHED_FAIR 0u  /* every active request gets an equal share of the launch (small requests finish fast) */
 #define MC_SCHED_FIFO 1u  /* fill the launch from the oldest request on */
 #define MC_SCHED_SRPT 2u  /* fill the launch from the request with the least remaining work on (estimated
-                             evaluation cost of its tiles not yet launched); ties go to the older request */
+                             evaluation cost of its tiles not yet launched); ties go to the older request.
+                             Shortest waits below saturation; under sustained overload the largest requests
+                             can wait indefinitely (FAIR bounds every request's share) */
 
 typedef struct mc_ctx mc_ctx;
 

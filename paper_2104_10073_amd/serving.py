@@ -3,7 +3,7 @@
 Requests (function tables) arrive at given times; each is submitted when its
 arrival time has passed, the context admits it into device slots as soon as
 function slots and tile-partial memory allow, and every `mc_run` shares one
-launch among all admitted requests (FAIR policy).  A request's latency is the
+launch among all admitted requests (by the context's scheduling policy).  A request's latency is the
 time from its arrival to the moment its results are on the host.  The loop only
 marshals calls into the library; all integration work runs in its kernels.
 """
