@@ -77,9 +77,11 @@ typedef enum {
 
 typedef enum {
     MC_PREC_FP32_EVAL = 0,   /* FP32 sample mapping and evaluation, per-lane compensated FP32 sums,
-                                FP64 cross-lane reduction, variance and finalize.  A function whose
-                                spread is too small for FP32 to resolve (sigma / rms below
-                                400 * 2^-24 * sqrt(N)) is re-run in FP64; its result says so. */
+                                FP64 cross-lane reduction, variance and finalize.  A function FP32
+                                cannot resolve is re-run in FP64 and its result says so: spread too
+                                small (sigma / rms below 400 * 2^-24 * sqrt(N)), values or squares
+                                out of FP32 range (non-finite sums: |f| beyond about 2^60; mean
+                                square below 2^-120 or zero: |f| below about 2^-60). */
     MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
 } mc_precision;
 
@@ -108,7 +110,8 @@ typedef struct mc_result {
 /* Context flags. */
 #define MC_VALIDATE_ONLY 0x1u    /* host-only context: mc_submit validates and packs, no device is touched */
 #define MC_NO_GRAPH 0x2u         /* launch kernels directly instead of replaying captured HIP graphs */
-#define MC_NO_PROMOTE 0x4u       /* keep FP32 results of nearly constant integrands instead of re-running them in FP64 */
+#define MC_NO_PROMOTE 0x4u       /* keep every FP32 result instead of re-running unresolvable ones in FP64
+                                    (nearly constant or out-of-range integrands then come back as FP32 gave them) */
 
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */

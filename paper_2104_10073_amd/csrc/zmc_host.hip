@@ -484,16 +484,28 @@ bool has_work(const Request* r)
     return r->order_pos < r->order.size() || r->redo_pos < r->redo.size();
 }
 
-// FP32 evaluation rounds each sample to about 2^-24 of its size; a bias of a
-// few such units of the RMS value must stay below 0.01 of the standard error,
-// i.e. sigma / rms must exceed 100 * 4 * 2^-24 * sqrt(N).  Below that (nearly
-// constant integrands) the FP32 result cannot be trusted to that accuracy.
-bool fp32_unresolved(const mc_result& r)
+// Whether an FP32-evaluated result must be computed again in FP64.  `scale`
+// is the factor the FP32 path takes out of every sample (f = scale * g, the
+// sums scaled in FP64), so only g passes through FP32 arithmetic.
+// * Range: every g and g^2 is an FP32 value, summed in FP32 over 64 samples
+//   per lane before the FP64 reduction.  |g| beyond about 2^60 overflows those
+//   sums (non-finite S1 or S2); below about 2^-60 the squares underflow (mean
+//   of g^2 under 2^-120, or zero -- also when g itself rounds to 0 in FP32, so
+//   an integrand that is zero in FP32 everywhere with a nonzero scale is
+//   checked in FP64 too).  A zero scale means f == 0 exactly.
+// * Accuracy: FP32 evaluation rounds each sample to about 2^-24 of its size;
+//   a bias of a few such units of the RMS value must stay below 0.01 of the
+//   standard error, i.e. sigma / rms must exceed 100 * 4 * 2^-24 * sqrt(N).
+//   Below that (nearly constant integrands) the FP32 result cannot be
+//   trusted to that accuracy.
+bool fp32_unresolved(const mc_result& r, double scale)
 {
     const double n = (double)r.n;
     if (!(n >= 2.0)) return false;
+    if (!std::isfinite(r.sum_f) || !std::isfinite(r.sum_f2)) return true;
+    if (scale == 0.0) return false;
     const double rms2 = r.sum_f2 / n;
-    if (!(rms2 > 0.0)) return false;                 // f == 0 everywhere: exact in FP32
+    if (!(rms2 / (scale * scale) >= 0x1p-120)) return true;
     const double var = (r.sum_f2 - r.sum_f * r.sum_f / n) / (n - 1.0);
     const double ratio = var > 0.0 ? std::sqrt(var / rms2) : 0.0;
     return ratio < 400.0 * std::ldexp(1.0, -24) * std::sqrt(n);
@@ -662,7 +674,7 @@ void reap(mc_ctx* ctx, int wait)
             std::memcpy(&out, &hres[i], sizeof(mc_result));
             if (bad != 0) out.status = MC_ERR_HIP;
             if (out.status == MC_OK && out.precision == MC_PREC_FP32_EVAL && ctx->promote &&
-                fp32_unresolved(out)) {
+                fp32_unresolved(out, fr.req->grid ? fp32_scale(fr.req->at(fr.index)) : fp32_scale(fr.req->fns[fr.index]))) {
                 promote_to_fp64(ctx, fr.req, fr.index);
                 continue;
             }

@@ -33,6 +33,21 @@ __host__ __device__ inline float pack_frac_to_float(double x)
     return f;
 }
 
+// The factor the FP32 path takes out of every sample of a built-in family
+// (f = scale * g; S1 and S2 are scaled by it and its square in FP64 at
+// finalize): the amplitude for Eq. (1), |linear| and Gaussian forms, 1 for the
+// product polynomial and run-time families.
+__host__ __device__ inline double fp32_scale(const mc_function& f)
+{
+    if (f.family >= kUserFamily0) return 1.0;
+    switch (f.family) {
+    case MC_FAMILY_HARMONIC: return hypot(f.params[0], f.params[1]);
+    case MC_FAMILY_ABS_LINEAR:
+    case MC_FAMILY_GAUSSIAN: return f.params[0];
+    default: return 1.0;
+    }
+}
+
 // `f` must have passed validation; `precision` is MC_PREC_FP32_EVAL or MC_PREC_FP64.
 __host__ __device__ inline void pack_function(const mc_function& f, int precision, DevFn* d)
 {
@@ -84,7 +99,7 @@ __host__ __device__ inline void pack_function(const mc_function& f, int precisio
     switch (f.family) {
     case MC_FAMILY_HARMONIC: {
         const double a = f.params[0], b = f.params[1];
-        const double R = hypot(a, b);
+        const double R = fp32_scale(f);
         const double phi = (R > 0.0) ? atan2(b, a) : 0.0;
         double off = -phi / kPackTwoPi;
         for (uint32_t j = 0; j < D; ++j) {
@@ -106,8 +121,8 @@ __host__ __device__ inline void pack_function(const mc_function& f, int precisio
         }
         d->f0 = (float)off;
         d->f0lo = (float)(off - (double)d->f0);
-        d->scale1 = f.params[0];
-        d->scale2 = f.params[0] * f.params[0];
+        d->scale1 = fp32_scale(f);
+        d->scale2 = d->scale1 * d->scale1;
         break;
     }
     case MC_FAMILY_GAUSSIAN: {
@@ -118,8 +133,8 @@ __host__ __device__ inline void pack_function(const mc_function& f, int precisio
             d->fc[j] = (float)(d->w[j] * sq);
             d->fo[j] = (float)(C + (f.params[MC_PARAM_V0 + j] - f.lo[j]) / d->w[j]);
         }
-        d->scale1 = f.params[0];
-        d->scale2 = f.params[0] * f.params[0];
+        d->scale1 = fp32_scale(f);
+        d->scale2 = d->scale1 * d->scale1;
         break;
     }
     default: {  // POLY_PRODUCT

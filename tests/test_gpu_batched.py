@@ -161,6 +161,41 @@ def test_launches_alternating_between_streams():
     _same(ref, got, "launches on alternating streams")
 
 
+def test_values_outside_fp32_range_are_promoted():
+    """The FP32 path takes each family's amplitude out of the samples (applied in
+    FP64), so amplitudes far outside FP32's range (1e25, 1e-25, 1e-40, 1e-50)
+    stay FP32 and meet the FP32 bar; what FP32 cannot hold after that --
+    |linear| forms reaching 1e20 or only 1e-25, a Gaussian whose box lies
+    in the far tail (values below 1e-19), a polynomial reaching 1e79 --
+    comes back evaluated in FP64 at the FP64 bar.  An exactly zero integrand
+    (amplitude 0) stays FP32 and is exact."""
+    Z = _Z()
+    t = W.empty(10)
+    W.set_harmonic(t, 0, 3, 1e25, -2e25, [3.0, 4.0, 5.0], [0, -1, 0.5], [1, 0.5, 2])
+    W.set_harmonic(t, 1, 3, 1e-25, 2e-25, [3.0, 4.0, 5.0], [0, -1, 0.5], [1, 0.5, 2])
+    W.set_gaussian(t, 2, 2, 1e-40, 0.5, [0.3, 0.6], [0, 0], [1, 1])
+    W.set_abs_linear(t, 3, 4, 1e-50, 0.1, [1.0, -1.0, 1.0, 1.0], [0] * 4, [1] * 4)
+    W.set_abs_linear(t, 4, 2, 2.0, 0.0, [3e20, -1e20], [0, 0], [1, 1])
+    W.set_poly(t, 5, 2, [0.5, 0.5], [8, 8], [-1e5, -1e5], [1e5, 1e5])
+    W.set_abs_linear(t, 6, 2, 1.0, 0.0, [1e-25, 2e-25], [0, 0], [1, 1])
+    W.set_gaussian(t, 7, 2, 1.0, 0.3015, [3.0, 3.0], [0, 0], [1, 1])
+    W.set_harmonic(t, 8, 2, 0.0, 0.0, [1.0, 1.0], [0, 0], [1, 1])
+    W.set_harmonic(t, 9, 4, 1.0, 0.5, [20.0] * 4, [0] * 4, [1] * 4)
+    t["n_samples"][:] = 200_003
+    t["seed"][:] = [W.stream_seed(41, i) for i in range(len(t))]
+    orc = G.oracle_results(t)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        r = c.integrate(t, Z.PREC_FP32)
+        promoted = c.stats()["promoted"]
+    assert r["precision"].tolist() == [0, 0, 0, 0, 1, 1, 1, 1, 0, 0], r["precision"].tolist()
+    assert promoted == 4
+    fp32 = np.array([0, 1, 2, 3, 8, 9])
+    fp64 = np.array([4, 5, 6, 7])
+    G.check_fp32(r[fp32], orc[fp32], "amplitudes outside FP32 range")
+    G.check_fp64(r[fp64], orc[fp64], "values outside FP32 range")
+    assert r["mean"][8] == 0.0 and r["std_error"][8] == 0.0
+
+
 def test_promotion_of_nearly_constant_functions():
     """A nearly constant integrand cannot be resolved in FP32; it comes back from FP64."""
     Z = _Z()
