@@ -25,6 +25,7 @@ constexpr int kSegSamples = 4 * kSegQuads;            // 4096 samples
 constexpr int kBlockWaves = 4;                        // waves per workgroup
 constexpr int kBlockThreads = kWave * kBlockWaves;    // 256
 constexpr int kMaxSegLog2 = 6;                        // at most 64 segments per wave per tile
+constexpr int kMaxPolyDegree = 8;                     // product polynomial degrees are 0..8 (validated)
 constexpr int kNumFamilies = 4;                       // built-in families
 constexpr int kMaxUserFamilies = 8;                   // run-time compiled families
 constexpr uint32_t kUserFamily0 = 16;                 // family id of the first run-time family
@@ -91,8 +92,10 @@ struct TileRun {
     uint32_t seg_log2;
     uint32_t part0;               // partial slot of the function's tile 0
     uint32_t dst;                 // position of the first one in the tile list
-    uint32_t pad_[2];
+    uint32_t flags;               // kRunUploadRecord: copy the function's record from the host mirror first
+    uint32_t pad_;
 };
+constexpr uint32_t kRunUploadRecord = 1u;
 
 struct Fin {
     uint32_t fn;

@@ -219,7 +219,7 @@ template <> struct Eval32<POLY_PRODUCT> {
     __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
         const float c = fn->fc[j], o = fn->fo[j], p = fn->fp[j];
-        const int e = fn->deg[j];
+        const int e = fn->deg[j] < kMaxPolyDegree ? fn->deg[j] : kMaxPolyDegree;  // bounded whatever the record holds
         float x[4], xp[4];
 #pragma unroll
         for (int s = 0; s < 4; ++s) {
@@ -292,7 +292,7 @@ template <int FAM> struct Eval64 {
                 st[s] = fma(t, t, st[s]);
             }
         } else {
-            const int e = fn->deg[j];
+            const int e = fn->deg[j] < kMaxPolyDegree ? fn->deg[j] : kMaxPolyDegree;  // bounded whatever the record holds
             double xp[4] = {1.0, 1.0, 1.0, 1.0};
             for (int k = 0; k < e; ++k) {
 #pragma unroll

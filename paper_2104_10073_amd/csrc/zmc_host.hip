@@ -54,6 +54,7 @@ static_assert(sizeof(mc_config) == 56, "mc_config layout");
 static_assert(sizeof(mc_stats) == 88, "mc_stats layout");
 static_assert(sizeof(DevResult) == sizeof(mc_result), "result layout");
 static_assert(sizeof(Tile) == 16 && sizeof(Fin) == 16 && sizeof(Partial) == 16, "record layout");
+static_assert(sizeof(TileRun) == 32 && sizeof(DevFn) % 16 == 0, "staged record layout");
 
 namespace {
 
@@ -192,8 +193,9 @@ mc_status validate_one(const mc_function& f, uint32_t n_user, std::string* why)
     if (f.family == MC_FAMILY_POLY_PRODUCT) {
         for (uint32_t j = 0; j < f.dim; ++j) {
             const double d = f.params[MC_PARAM_W0 + j];
-            if (!(d >= 0.0 && d <= 8.0 && d == std::floor(d))) {
-                snprintf(buf, sizeof buf, "polynomial degree of coordinate %u must be an integer in 0..8", j);
+            if (!(d >= 0.0 && d <= (double)kMaxPolyDegree && d == std::floor(d))) {
+                snprintf(buf, sizeof buf, "polynomial degree of coordinate %u must be an integer in 0..%d", j,
+                         kMaxPolyDegree);
                 *why = buf;
                 return MC_ERR_BAD_PARAMS;
             }
@@ -234,6 +236,7 @@ struct FnState {
     uint64_t part0;       // first partial slot
     double tile_cost;
     bool f64;             // evaluated by the FP64 kernel (requested, or promoted from FP32)
+    bool needs_upload;    // record packed into the host mirror, not yet on the device
 };
 
 struct Request {
@@ -260,6 +263,7 @@ struct Request {
     uint64_t part_base = 0, part_count = 0;
     uint32_t slot_base = 0;
     bool admitted = false;
+    bool grid_packed = false;         // a grid's records have been built on the device
     hipEvent_t uploaded = nullptr;    // upload of the packed records (library upload stream)
     uint32_t fns_done = 0;
     uint64_t tiles_total = 0, tiles_launched = 0;
@@ -356,8 +360,9 @@ struct mc_ctx {
     uint32_t* h_words = nullptr;       // pinned {0, 1}: sources for setting / clearing it
     uint32_t* h_done = nullptr;        // pinned fine-grained: one done word per launch slot (16 words apart)
     uint32_t* h_done_dev = nullptr;    // its device address
-    DevFn* h_fns = nullptr;            // pinned host mirror of the function table (records are packed
-                                       // here at admission and uploaded from here)
+    DevFn* h_fns = nullptr;            // pinned fine-grained host mirror of the function table (records
+                                       // are packed here at admission and uploaded from here)
+    DevFn* h_fns_dev = nullptr;        // its device address (read by the stage kernel)
     std::vector<std::unique_ptr<EvSet>> ev_pool;
     std::vector<EvSet*> ev_free;
     std::deque<EvSet*> ev_pending;     // recorded sets, oldest first
@@ -521,12 +526,10 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     fs.tile_cost = sample_cost(f.family, f.dim, MC_PREC_FP64) *
                    (double)std::min<uint64_t>(f.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << fs.seg_log2));
     r->work_left += fs.tile_cost * fs.n_tiles;
-    // the slot's previous upload has completed (its FP32 result came back)
+    // the slot's previous upload has completed (its FP32 result came back); the
+    // FP64 record goes up with the first launch of its tiles
     pack_function(f, MC_PREC_FP64, &ctx->h_fns[fs.slot]);
-    HIP_TRY(hipMemcpyAsync(ctx->d_fns + fs.slot, &ctx->h_fns[fs.slot], sizeof(DevFn), hipMemcpyHostToDevice,
-                           ctx->upload_stream));
-    if (!r->uploaded) HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
-    HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+    fs.needs_upload = true;
     const bool was_active = has_work(r);
     r->redo.push_back(fi);
     r->n_promoted++;
@@ -673,7 +676,14 @@ void reap(mc_ctx* ctx, int wait)
             mc_result& out = fr.req->results[fr.index];
             std::memcpy(&out, &hres[i], sizeof(mc_result));
             if (bad != 0) out.status = MC_ERR_HIP;
-            if (out.status == MC_OK && out.precision == MC_PREC_FP32_EVAL && ctx->promote &&
+            // the host's own record of the precision decides (a result can be
+            // promoted once); a device record that disagrees is an error
+            const bool host_f64 = fr.req->st[fr.index].f64;
+            if (out.status == MC_OK && out.precision != (host_f64 ? (uint32_t)MC_PREC_FP64 : (uint32_t)MC_PREC_FP32_EVAL)) {
+                out.status = MC_ERR_HIP;
+                ctx->err = "a result came back in another precision than its function was scheduled in";
+            }
+            if (out.status == MC_OK && !host_f64 && ctx->promote &&
                 fp32_unresolved(out, fr.req->grid ? fp32_scale(fr.req->at(fr.index)) : fp32_scale(fr.req->fns[fr.index]))) {
                 promote_to_fp64(ctx, fr.req, fr.index);
                 continue;
@@ -702,11 +712,18 @@ void reap(mc_ctx* ctx, int wait)
     }
 }
 
-// Move pending requests into device slots while they fit (FIFO).  The packed
-// table goes up on the library's upload stream; launches that use a request
-// wait for its upload event.
+// Move pending requests into device slots while they fit (FIFO).  With no
+// launch in flight the records go up at once on the library's upload stream
+// (launches that use the request wait for its upload event); otherwise a copy
+// or kernel on another stream would wait for the running persistent kernels
+// to free their compute units, so each record goes up with the stage kernel
+// of the first launch that runs its tiles, and a grid's records are built in
+// the launch stream right before it.
 void admit(mc_ctx* ctx)
 {
+    bool idle = true;
+    for (const auto& sl : ctx->slots)
+        if (sl.in_flight) idle = false;
     while (!ctx->pending.empty()) {
         Request* r = ctx->pending.front();
         const uint64_t nf = r->count();
@@ -730,19 +747,27 @@ void admit(mc_ctx* ctx)
         r->admitted = true;  // from here on the slots are released with the request
         if (r->grid) {
             // records built on the device from the grid spec: no table crosses PCIe
-            DevFn* out = ctx->d_fns + slot_off;
-            void* args[] = {&r->spec, &out};
-            HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256), args, 0,
-                                    ctx->upload_stream));
+            if (idle) {
+                DevFn* out = ctx->d_fns + slot_off;
+                void* args[] = {&r->spec, &out};
+                HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256), args,
+                                        0, ctx->upload_stream));
+                r->grid_packed = true;
+            }
         } else {
             // records packed into the slots' part of the pinned mirror (whose
             // previous uploads completed before those slots were released)
             for (uint64_t i = 0; i < nf; ++i) pack_function(r->fns[i], r->precision, &ctx->h_fns[slot_off + i]);
-            HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
-                                   hipMemcpyHostToDevice, ctx->upload_stream));
+            if (idle)
+                HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
+                                       hipMemcpyHostToDevice, ctx->upload_stream));
+            else
+                for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = true;
         }
-        HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
-        HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+        if (idle) {
+            HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
+            HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+        }
         ctx->pending.pop_front();
         ctx->active.push_back(r);
     }
@@ -765,7 +790,10 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
         uint8_t* dst = s.d_block + ctx->slot_res_bytes;
         uint64_t cap = kDescBytes + (uint64_t)ctx->fin_cap * sizeof(Fin);
         uint32_t tile_cap = ctx->tile_cap;
-        void* sargs[] = {&src, &dst, &cap, &tile_cap};
+        const DevFn* mirror = ctx->h_fns_dev;
+        DevFn* fns = ctx->d_fns;
+        uint32_t n_fns = ctx->max_functions;
+        void* sargs[] = {&src, &dst, &cap, &tile_cap, &mirror, &fns, &n_fns};
         HIP_TRY(hipLaunchKernel(stage_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(256), sargs, 0, stream));
     }
     EvSet* e = s.ev;
@@ -840,7 +868,9 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
             s.n_samples += std::min<uint64_t>(b * tile_samples, fn_samples) - a * tile_samples;
             HostRun hr;
             hr.cost = fs.tile_cost;
-            hr.run = TileRun{fs.slot, (uint32_t)a, (uint32_t)take, fs.seg_log2, (uint32_t)fs.part0, 0u, {0u, 0u}};
+            hr.run = TileRun{fs.slot, (uint32_t)a, (uint32_t)take, fs.seg_log2, (uint32_t)fs.part0, 0u,
+                             fs.needs_upload ? kRunUploadRecord : 0u, 0u};
+            fs.needs_upload = false;
             s.runs[kidx].push_back(hr);
             s.n_runs++;
             s.n_tiles += (uint32_t)take;
@@ -960,6 +990,16 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
             if (q != hipErrorNotReady) throw HipError{q, "hipEventQuery(upload)"};
             HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
         }
+    }
+    // grids admitted while launches were in flight: their records are built in
+    // this stream, before the stage kernel (and any graph) reads them
+    for (Request* r : s.touched) {
+        if (!r->grid || r->grid_packed) continue;
+        DevFn* out = ctx->d_fns + r->slot_base;
+        void* args[] = {&r->spec, &out};
+        HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((r->n + 255) / 256)), dim3(256), args, 0,
+                                stream));
+        r->grid_packed = true;
     }
     EvSet& ev = *acquire_evset(ctx);
     s.ev = &ev;
@@ -1174,7 +1214,9 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             HIP_TRY(hipHostMalloc((void**)&s.h_block, L.slot_bytes, hipHostMallocMapped | hipHostMallocCoherent));
             HIP_TRY(hipHostGetDevicePointer((void**)&s.h_block_dev, s.h_block, 0));
         }
-        HIP_TRY(hipHostMalloc((void**)&ctx->h_fns, (size_t)ctx->max_functions * sizeof(DevFn), hipHostMallocDefault));
+        HIP_TRY(hipHostMalloc((void**)&ctx->h_fns, (size_t)ctx->max_functions * sizeof(DevFn),
+                              hipHostMallocMapped | hipHostMallocCoherent));
+        HIP_TRY(hipHostGetDevicePointer((void**)&ctx->h_fns_dev, ctx->h_fns, 0));
         HIP_TRY(hipHostMalloc((void**)&ctx->h_done, kLaunchSlots * 16 * sizeof(uint32_t),
                               hipHostMallocMapped | hipHostMallocCoherent));
         HIP_TRY(hipHostGetDevicePointer((void**)&ctx->h_done_dev, ctx->h_done, 0));
@@ -1231,6 +1273,7 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
     fs.n_tiles = tiles_for(d.n_segments, L);
     fs.next_tile = 0;
     fs.f64 = r->precision == MC_PREC_FP64;
+    fs.needs_upload = false;
     fs.tile_cost = sample_cost(d.family, d.dim, r->precision) *
                    (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
     r->tiles_total += fs.n_tiles;

@@ -12,10 +12,15 @@ namespace zmc {
 
 // First kernel of a launch: copy the staged descriptor, counters and finalize
 // records from pinned host memory into the slot's device block (their byte
-// count is the descriptor's first field, bounded by `cap`), and expand the
-// staged tile runs into the device tile list (bounded by `tile_cap`).
+// count is the descriptor's first field, bounded by `cap`), copy the function
+// records that runs flag from the host mirror of the function table
+// (`mirror`, fine-grained, `n_fns` records) into the device table `fns`, and
+// expand the staged tile runs into the device tile list (bounded by
+// `tile_cap`).
 extern "C" __global__ __launch_bounds__(256) void zmc_stage(const uint4* __restrict__ src, uint4* __restrict__ dst,
-                                                            uint64_t cap, uint32_t tile_cap)
+                                                            uint64_t cap, uint32_t tile_cap,
+                                                            const DevFn* __restrict__ mirror,
+                                                            DevFn* __restrict__ fns, uint32_t n_fns)
 {
     __shared__ uint64_t s_bytes;
     __shared__ uint32_t s_runs, s_runs_off;
@@ -36,6 +41,15 @@ extern "C" __global__ __launch_bounds__(256) void zmc_stage(const uint4* __restr
     Tile* tiles = s_tiles;
     for (uint32_t r = blockIdx.x; r < s_runs; r += gridDim.x) {
         const TileRun run = runs[r];
+        if ((run.flags & kRunUploadRecord) != 0u && run.fn < n_fns) {
+            // the function's record, packed on the host since its last use, goes up
+            // with the launch that first needs it (the batched kernels run after
+            // this kernel in the same stream)
+            const uint4* rs = reinterpret_cast<const uint4*>(mirror + run.fn);
+            uint4* rd = reinterpret_cast<uint4*>(fns + run.fn);
+            for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(DevFn) / sizeof(uint4)); i += blockDim.x)
+                rd[i] = rs[i];
+        }
         if (run.dst > tile_cap || run.count > tile_cap - run.dst || run.seg_log2 > (uint32_t)kMaxSegLog2) continue;
         const uint32_t per_tile = (uint32_t)kBlockWaves << run.seg_log2;  // segments
         for (uint32_t i = threadIdx.x; i < run.count; i += blockDim.x) {

@@ -106,6 +106,40 @@ def test_scheduling_order_and_results(policy):
     _same(alone[1], outs[1], "small request")
 
 
+def test_admission_while_launches_are_in_flight():
+    """Requests admitted while a launch is in flight: their records go up with the
+    stage kernel of the first launch that runs them, a parameter grid's records are
+    built in the launch stream, and a promoted function's FP64 record follows the
+    same way -- every result equals the request integrated alone."""
+    Z = _Z()
+    busy = W.harmonic_batch(64, n_samples=2_000_000, base=3)
+    small = [W.mixed_batch(30, dim_range=(1, 12), log10_samples=(3.0, 5.0), gen_seed=300 + k, base=k)
+             for k in range(3)]
+    W.set_poly(small[1], 7, 3, [1e-9] * 3, [2, 2, 2], [0] * 3, [1] * 3)   # nearly constant: promoted
+    small[1]["n_samples"][7] = 300_000
+    base, axes = W.functional_grid(n_k=8, n_ab=4, n_samples=50_000)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        alone = [c.integrate(t, Z.PREC_FP32) for t in small]
+        alone_grid = c.integrate_grid(base, axes, Z.PREC_FP32)
+        alone_busy = c.integrate(busy, Z.PREC_FP32)
+    assert alone[1]["precision"][7] == 1
+    with Z.Context(flags=Z.MC_NO_GRAPH, max_tiles_per_run=1024) as c:
+        rb = c.submit(busy, Z.PREC_FP32)
+        assert c.run()                       # a launch is in flight from here on
+        ids = [c.submit(t, Z.PREC_FP32) for t in small]
+        rg = c.submit_grid(base, axes, Z.PREC_FP32)
+        c.run()
+        got = [c.results(rid, len(t)) for rid, t in zip(ids, small)]
+        got_grid = c.results(rg, len(alone_grid))
+        got_busy = c.results(rb, len(busy))
+        st = c.stats()
+    assert st["promoted"] >= 1
+    for k in range(len(small)):
+        _same(alone[k], got[k], f"request {k}")
+    _same(alone_grid, got_grid, "grid")
+    _same(alone_busy, got_busy, "busy request")
+
+
 def test_abort_then_recover():
     """Abort while the persistent kernels run (~0.1 s of work): they stop at their next
     tile fetch, the request comes back aborted, and later work is unaffected."""
