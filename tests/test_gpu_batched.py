@@ -106,11 +106,13 @@ def test_scheduling_order_and_results(policy):
     _same(alone[1], outs[1], "small request")
 
 
-def test_admission_while_launches_are_in_flight():
+@pytest.mark.parametrize("graph", [False, True], ids=["direct", "graph"])
+def test_admission_while_launches_are_in_flight(graph):
     """Requests admitted while a launch is in flight: their records go up with the
     stage kernel of the first launch that runs them, a parameter grid's records are
     built in the launch stream, and a promoted function's FP64 record follows the
-    same way -- every result equals the request integrated alone."""
+    same way -- every result equals the request integrated alone (direct launches
+    and captured launch graphs)."""
     Z = _Z()
     busy = W.harmonic_batch(64, n_samples=2_000_000, base=3)
     small = [W.mixed_batch(30, dim_range=(1, 12), log10_samples=(3.0, 5.0), gen_seed=300 + k, base=k)
@@ -123,7 +125,7 @@ def test_admission_while_launches_are_in_flight():
         alone_grid = c.integrate_grid(base, axes, Z.PREC_FP32)
         alone_busy = c.integrate(busy, Z.PREC_FP32)
     assert alone[1]["precision"][7] == 1
-    with Z.Context(flags=Z.MC_NO_GRAPH, max_tiles_per_run=1024) as c:
+    with Z.Context(flags=0 if graph else Z.MC_NO_GRAPH, max_tiles_per_run=1024) as c:
         rb = c.submit(busy, Z.PREC_FP32)
         assert c.run()                       # a launch is in flight from here on
         ids = [c.submit(t, Z.PREC_FP32) for t in small]
