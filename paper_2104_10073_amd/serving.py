@@ -18,8 +18,13 @@ from ._native import PREC_FP32, Context
 
 
 def serve(ctx: Context, requests, arrivals, stream=None, precision: int = PREC_FP32,
-          keep_results: bool = False, idle_sleep: float = 50e-6):
+          keep_results: bool = False, idle_sleep: float = 0.0):
     """Run `requests` (list of tables) arriving at `arrivals` (seconds from start).
+
+    The loop busy-polls for arrivals and completions by default (one host core,
+    as a latency-sensitive server thread would); a positive `idle_sleep` sleeps
+    that long when nothing happened instead (the OS rounds short sleeps up to
+    about 60 us, which adds that much to the time a completion is noticed).
 
     Returns a dict with per-request latency (s), completion times, total
     evaluations, wall time and, if asked, the results of every request.
