@@ -281,13 +281,22 @@ def other_configs(Z, W, stream):
                             ("highdim_500x1e7_dims8to12", W.high_dim_batch(500))):
             ev = W.total_evals(table)
             st0 = ctx.stats()
-            _, t = timed(lambda: ctx.integrate(table, Z.PREC_FP32, stream=stream))
+            r32, t = timed(lambda: ctx.integrate(table, Z.PREC_FP32, stream=stream))
             st1 = ctx.stats()
             half = {k: (st1[k] - st0[k]) / 2 for k in ("fp32_ms", "fp64_ms", "finalize_ms", "promoted", "launches")}
+            r64 = ctx.integrate(table, Z.PREC_FP64, stream=stream)
+            # FP32-evaluation error per function against the FP64 path (itself equal
+            # to the oracle's sums within 1e-12 of sum|f|), in units of the SE
+            err = np.abs(r32["mean"] - r64["mean"]) / np.maximum(r64["std_error"], 1e-300)
+            near_zero = np.abs(r64["mean"]) < 1e-4
             out[name] = {"evals": ev, "wall_ms": t * 1e3, "evals_per_s": ev / t,
                          "kernel_ms": half["fp32_ms"] + half["fp64_ms"] + half["finalize_ms"],
-                         "promoted_to_fp64_per_run": half["promoted"], "launches_per_run": half["launches"]}
-            log(f"{name}: {ev / t:.3g} evals/s")
+                         "promoted_to_fp64_per_run": half["promoted"], "launches_per_run": half["launches"],
+                         "fp32_vs_fp64_max_dF_over_SE": float(err.max()),
+                         "fp32_vs_fp64_median_dF_over_SE": float(np.median(err)),
+                         "near_zero_functions": int(near_zero.sum()),
+                         "near_zero_max_dF_over_SE": float(err[near_zero].max()) if near_zero.any() else None}
+            log(f"{name}: {ev / t:.3g} evals/s, FP32 vs FP64 max |dF|/SE {err.max():.2e}")
     return out
 
 
