@@ -103,7 +103,8 @@ typedef struct mc_result {
     double sum_f;                /* S1 = sum f(x_i) */
     double sum_f2;               /* S2 = sum f(x_i)^2 */
     uint64_t n;                  /* N */
-    int32_t status;              /* MC_OK or MC_ERR_ABORTED */
+    int32_t status;              /* MC_OK, MC_ERR_ABORTED, or MC_ERR_HIP if the launch's records failed the
+                                    kernels' checks or the result's precision disagrees with its schedule */
     uint32_t precision;          /* mc_precision the result was computed in */
 } mc_result;
 
@@ -115,7 +116,7 @@ typedef struct mc_result {
 
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */
-    uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH */
+    uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH | MC_NO_PROMOTE */
     uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16) */
     uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20) */
     uint64_t max_partials;       /* device tile-partial slots, 16 bytes each, at most 2^32 - 1 (0: 1 << 22) */
@@ -154,8 +155,10 @@ mc_status mc_destroy(mc_ctx* ctx);
  * The whole request is rejected on the first invalid function (its index is in
  * mc_last_error); nothing partial is queued.  Requests are admitted to the device
  * in submission order as function slots and partial memory free up (at submit
- * if they fit, else in a later mc_run); admission uploads the packed table on
- * the library's own upload stream.  A request that could never fit returns
+ * if they fit, else in a later mc_run).  Admission packs the table into pinned
+ * host memory; with no launch in flight it is uploaded at once on the library's
+ * own upload stream, otherwise each record goes up with the stage kernel of the
+ * first launch that runs that function.  A request that could never fit returns
  * MC_ERR_ADMISSION.  *out_request_id identifies it. */
 mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision,
                     uint64_t* out_request_id);
@@ -187,8 +190,10 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
                          int32_t precision, uint64_t* out_request_id);
 
 /* Admit what fits, then enqueue one launch of the batched path on `stream`, as
- * kernels only: a stage kernel that copies the launch's work list from pinned
- * host memory, the persistent kernels over the admitted (function,
+ * kernels only: a stage kernel that copies the launch's work list (and the
+ * records of functions admitted or promoted while launches were in flight) from
+ * pinned host memory, preceded by the record-building kernel of any parameter
+ * grid admitted under load, the persistent kernels over the admitted (function,
  * sample-segment) tiles, a finalize kernel for every function whose last tile
  * is in this launch, and a publish kernel that writes those results to pinned
  * host memory and then marks the launch done.  Returns without waiting (the
@@ -250,7 +255,7 @@ typedef struct mc_stats {
     double fp32_ms;              /* direct launches: sum of FP32 persistent-kernel time (HIP events on the launch stream) */
     double fp64_ms;              /* direct launches: sum of FP64 persistent-kernel time */
     double finalize_ms;          /* direct launches: sum of finalize time */
-    double graph_ms;             /* graph launches: sum of whole-graph time (all three kernels) */
+    double graph_ms;             /* graph launches: sum of whole-graph time (every kernel of the launch) */
 } mc_stats;
 
 mc_status mc_get_stats(mc_ctx* ctx, mc_stats* out);
@@ -294,7 +299,8 @@ mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_o
 /* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */
 const char* mc_last_error(mc_ctx* ctx);
 
-/* Library constants: samples per segment (the unit each wave reduces), wave size. */
+/* Samples per segment (the unit each wave reduces; a function's reduction tree
+ * is built over its segments), and the library's version string. */
 uint32_t mc_segment_samples(void);
 const char* mc_version(void);
 
