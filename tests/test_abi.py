@@ -147,3 +147,20 @@ def test_config_limits_of_32bit_indices(Z, kw):
     with pytest.raises(Z.McError) as e:
         Z.Context(flags=Z.MC_VALIDATE_ONLY, **kw)
     assert e.value.status == -1
+
+
+def test_c_client_links_and_checks_its_input(tmp_path):
+    """The tests' plain C client compiles against include/zmc.h, links libzmc.so, and
+    rejects a wrong command line or a file that is not whole 472-byte records before
+    it touches a device."""
+    import subprocess
+    import __graft_entry__ as g
+    exe = os.path.join(g.ROOT, "tests", "c_client", "zmc_c_client")
+    if not os.path.exists(exe):
+        g._build_c_client()
+    p = subprocess.run([exe], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 2 and "usage" in p.stderr
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"\0" * 471)
+    p = subprocess.run([exe, str(bad), str(tmp_path / "out.bin")], capture_output=True, text=True, timeout=60)
+    assert p.returncode == 2 and "472-byte records" in p.stderr
