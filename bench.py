@@ -135,6 +135,37 @@ def cpu_baseline(table, budget_s: float = 10.0):
             "cpu_model": cpu_model(), "cpus_available": int(threads)}, orc, np.concatenate(parts)
 
 
+def timed_steps(ctx, batches, n, K, Wm, stream):
+    """Submit every batch, run Wm untimed launches (which also capture launch
+    graphs), then time K launches, one batch each.  Launches are enqueued two
+    steps ahead of the results being collected, so the host's work-list building
+    and result handling overlap the GPU.  Returns (stats before, seconds,
+    results of the K timed batches, stats after)."""
+    import torch
+    import paper_2104_10073_amd as Z
+    ids = [ctx.submit(b, Z.PREC_FP32) for b in batches]
+    for i in range(Wm):
+        ctx.run(stream)
+        ctx.results(ids[i], n)
+    torch.cuda.synchronize()
+    log(f"warmup done; timing {K} steps")
+    st0 = ctx.stats()
+    t0 = time.perf_counter()
+    results = []
+    nxt = Wm
+    for _ in range(min(2, K)):
+        ctx.run(stream)
+        nxt += 1
+    for i in range(Wm, Wm + K):
+        if nxt < Wm + K:
+            ctx.run(stream)
+            nxt += 1
+        results.append(ctx.results(ids[i], n))
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    return st0, dt, results, ctx.stats()
+
+
 def serving_leg(Z, W, stream, args):
     """Continuous batching under open-loop Poisson arrivals at a fixed QPS.
 
@@ -381,31 +412,8 @@ def main():
                     max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs))
     if tuned is not None:
         ctx.set_tuning(tuned[0], tuned[1])
-    ids = [ctx.submit(b, Z.PREC_FP32) for b in batches]
     n = args.n_funcs
-    # warmup steps (also captures the launch graphs)
-    for i in range(Wm):
-        ctx.run(stream)
-        ctx.results(ids[i], n)
-    torch.cuda.synchronize()
-    log(f"warmup done; timing {K} steps")
-    st0 = ctx.stats()
-    t0 = time.perf_counter()
-    results = []
-    # launches are enqueued two steps ahead of the results being collected, so the
-    # host's work-list building and result handling overlap the GPU
-    nxt = Wm
-    for _ in range(min(2, K)):
-        ctx.run(stream)
-        nxt += 1
-    for i in range(Wm, Wm + K):
-        if nxt < Wm + K:
-            ctx.run(stream)
-            nxt += 1
-        results.append(ctx.results(ids[i], n))
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
-    st1 = ctx.stats()
+    st0, dt, results, st1 = timed_steps(ctx, batches, n, K, Wm, stream)
     value = evals_per_step * K / dt
     launches = st1["launches"] - st0["launches"]
     assert launches == K and st1["samples"] - st0["samples"] == evals_per_step * K, (st0, st1)
@@ -470,6 +478,21 @@ def main():
                                                               np.sqrt(r64["n"] * r64["sum_f2"]))),
         }
     ctx.close()
+    if not args.no_comparators and not args.graph:
+        # the same steps replayed as captured launch graphs (the context default)
+        with Z.Context(device=0, workspace="torch", flags=0, policy=Z.MC_SCHED_FIFO,
+                       max_tiles_per_run=tiles_per_batch, max_functions=max(65536, 2 * args.n_funcs)) as gctx:
+            if tuned is not None:
+                gctx.set_tuning(tuned[0], tuned[1])
+            # three warm-up launches, so every launch slot has captured its graph
+            # before the clock starts; then the same K seeds as the direct run
+            warm = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=1000 + b) for b in range(3)]
+            _, gdt, gres, _ = timed_steps(gctx, warm + batches[Wm:], n, K, 3, stream)
+        same = all(np.array_equal(a[f], b[f]) for a, b in zip(results, gres)
+                   for f in ("mean", "std_error", "sum_f", "sum_f2"))
+        out["comparators"]["graph_replay"] = {"evals_per_s": evals_per_step * K / gdt, "ms_per_step": gdt / K * 1e3,
+                                              "results_equal_direct_bitwise": bool(same)}
+        log(f"graph replay: {evals_per_step * K / gdt:.4g} evals/s, results equal: {same}")
 
     if not args.no_configs:
         log("other workloads")
