@@ -117,7 +117,8 @@ typedef struct mc_result {
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */
     uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH | MC_NO_PROMOTE */
-    uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16) */
+    uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16); each also takes
+                                    1 KiB of pinned host memory (the packed-record mirror) */
     uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20) */
     uint64_t max_partials;       /* device tile-partial slots, 16 bytes each, at most 2^32 - 1 (0: 1 << 22) */
     uint64_t mem_budget_bytes;   /* upper bound on device memory the context holds (0: no bound) */
