@@ -164,3 +164,14 @@ def test_c_client_links_and_checks_its_input(tmp_path):
     bad.write_bytes(b"\0" * 471)
     p = subprocess.run([exe, str(bad), str(tmp_path / "out.bin")], capture_output=True, text=True, timeout=60)
     assert p.returncode == 2 and "472-byte records" in p.stderr
+
+
+def test_unknown_policy_and_empty_request(Z):
+    with pytest.raises(Z.McError) as e:
+        Z.Context(flags=Z.MC_VALIDATE_ONLY, policy=3)
+    assert e.value.status == -1 and "policy" in str(e.value)
+    c = Z.Context(flags=Z.MC_VALIDATE_ONLY)
+    with pytest.raises(Z.McError) as e:
+        c.submit(W.eq1_series(n_funcs=1)[:0])
+    assert e.value.status == -1
+    c.close()
