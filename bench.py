@@ -340,6 +340,8 @@ def main():
     ap.add_argument("--n-samples", type=int, default=1_000_000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-comparators", action="store_true")
+    ap.add_argument("--blocks-per-cu", type=int, default=0,
+                    help="with --autotune 0: persistent-kernel workgroups per CU for the timed contexts")
     ap.add_argument("--autotune", type=float, default=5.0,
                     help="seconds of autotuning (timed apart, before the timed steps); 0 keeps the defaults")
     ap.add_argument("--graph", action="store_true",
@@ -400,6 +402,12 @@ def main():
         tuning = {"autotune_s": time.perf_counter() - ta, "blocks_per_cu": b,
                   "tile_segments_log2_fp32_harmonic_d4": int(seg[0][0][3])}
         log(f"autotuned: {tuning}")
+    elif args.blocks_per_cu > 0:
+        # a fixed launch shape (for profiles of the tuned configuration without the
+        # autotuner's own launches in the trace); tile sizes keep their defaults
+        with Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY) as vctx:
+            tuned = (args.blocks_per_cu, vctx.get_tuning()[1])
+        tuning = {"blocks_per_cu": args.blocks_per_cu, "fixed": True}
     # One launch per step: FIFO scheduling with the per-launch tile cap set to one
     # batch's tile count, so each mc_run takes exactly the next seed's batch.
     probe = Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY)
