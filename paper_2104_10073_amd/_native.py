@@ -202,6 +202,7 @@ class Context:
         return st
 
     def close(self):
+        """mc_destroy: wait for outstanding work and free the context."""
         if getattr(self, "h", None):
             self.L.mc_destroy(self.h)
             self.h = None
@@ -221,6 +222,7 @@ class Context:
 
     # -- batched path
     def submit(self, fns, precision: int = PREC_FP32) -> int:
+        """mc_submit: validate and queue a table (numpy FUNC_DTYPE array) as one request; returns its id."""
         t = as_table(fns)
         rid = ctypes.c_uint64()
         self._check(self.L.mc_submit(self.h, t.ctypes.data, len(t), precision, ctypes.byref(rid)), self.h)
@@ -241,6 +243,7 @@ class Context:
         return int(rid.value)
 
     def integrate_grid(self, base, axes, precision: int = PREC_FP32, stream=None):
+        """submit_grid, one mc_run on `stream`, then the blocking results (prod(count) of them)."""
         n = int(np.prod([a[1] for a in axes]))
         rid = self.submit_grid(base, axes, precision)
         self.run(stream)
@@ -262,11 +265,13 @@ class Context:
         return self.pending()[1]
 
     def pending(self):
+        """mc_pending: (requests not yet complete, tiles still waiting for a launch)."""
         r, t = ctypes.c_uint64(), ctypes.c_uint64()
         self._check(self.L.mc_pending(self.h, ctypes.byref(r), ctypes.byref(t)), self.h)
         return int(r.value), int(t.value)
 
     def results(self, request_id: int, n: int, blocking: bool = True, allow_aborted: bool = False):
+        """mc_results: the n results of a request (RESULT_DTYPE); None if not blocking and not ready."""
         out = np.zeros(n, dtype=RESULT_DTYPE)
         st = self.L.mc_results(self.h, request_id, out.ctypes.data, n, 1 if blocking else 0)
         if st == MC_NOT_READY:
@@ -277,12 +282,14 @@ class Context:
         return out
 
     def integrate(self, fns, precision: int = PREC_FP32, stream=None):
+        """submit, one mc_run on `stream`, then the blocking results."""
         t = as_table(fns)
         rid = self.submit(t, precision)
         self.run(stream)
         return self.results(rid, len(t), blocking=True)
 
     def abort(self):
+        """mc_abort: stop the running persistent kernels; queued requests complete as aborted."""
         self._check(self.L.mc_abort(self.h), self.h)
 
     def register_family(self, source: str) -> int:
@@ -303,6 +310,7 @@ class Context:
 
     # -- plain baseline
     def plain_fp64(self, fns, stream=None):
+        """mc_integrate_plain_fp64: the one-launch-per-function FP64 comparator (synchronous)."""
         t = as_table(fns)
         out = np.zeros(len(t), dtype=RESULT_DTYPE)
         self._check(self.L.mc_integrate_plain_fp64(self.h, t.ctypes.data, len(t), out.ctypes.data,
@@ -311,12 +319,14 @@ class Context:
 
     # -- tuning
     def get_tuning(self):
+        """mc_get_tuning: (workgroups per CU, seg_log2 array [precision][family][dim - 1])."""
         b = ctypes.c_uint32()
         seg = np.zeros((2, 4, 12), dtype=np.uint8)
         self._check(self.L.mc_get_tuning(self.h, ctypes.byref(b), seg.ctypes.data), self.h)
         return int(b.value), seg
 
     def set_tuning(self, blocks_per_cu: int = 0, seg_log2=None):
+        """mc_set_tuning: 0 / None keep the current value."""
         ptr = None
         if seg_log2 is not None:
             seg = np.ascontiguousarray(seg_log2, dtype=np.uint8).reshape(2, 4, 12)
@@ -324,14 +334,17 @@ class Context:
         self._check(self.L.mc_set_tuning(self.h, blocks_per_cu, ptr), self.h)
 
     def autotune(self, precision: int = PREC_FP32, stream=None, budget_seconds: float = 10.0):
+        """mc_autotune: time candidate tunings on synthetic batches and keep the fastest."""
         self._check(self.L.mc_autotune(self.h, precision, _stream_handle(stream), budget_seconds), self.h)
 
     def stats(self) -> dict:
+        """mc_get_stats: cumulative counters of the context."""
         st = McStats()
         self._check(self.L.mc_get_stats(self.h, ctypes.byref(st)), self.h)
         return st.as_dict()
 
     def last_run_timing(self):
+        """mc_last_run_timing: (persistent kernels ms, finalize ms) of the last direct launch."""
         a, b = ctypes.c_double(), ctypes.c_double()
         st = self.L.mc_last_run_timing(self.h, ctypes.byref(a), ctypes.byref(b))
         if st != MC_OK:

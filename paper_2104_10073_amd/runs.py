@@ -1,7 +1,8 @@
 """Repeated independent runs and the spread statistic of the paper's results.
 
-Sec. 3 reports each integral as the mean over independent runs with the
-standard deviation over those runs as its error bar (Fig. 1).  Each run
+The paper's test on GPUs (Fig. 1 and its caption) reports each integral as
+the mean over independent runs with the standard deviation over those runs as
+its error bar.  Each run
 of one table differs only in the sample streams: function i of run r takes
 the seed ``workloads.stream_seed(base + r, i)``.  Per run, the library's
 own per-function standard error estimates the same spread, so over many
