@@ -39,10 +39,11 @@ def test_result_queries():
 
 
 def test_run_with_every_slot_in_flight():
-    """Three launches of ~10^9 samples each fill the ring of launch slots; a fourth
-    mc_run right after them finds no free slot and returns MC_NOT_READY (False)."""
+    """Three launches of ~10^9 samples in 8..12 dimensions (several ms each) fill the
+    ring of launch slots; a fourth mc_run right after them finds no free slot and
+    returns MC_NOT_READY (False)."""
     import paper_2104_10073_amd as Z
-    t = W.harmonic_batch(400, n_samples=10_000_000, base=2)
+    t = W.high_dim_batch(500, n_samples=10_000_000)
     with Z.Context(flags=Z.MC_NO_GRAPH, max_tiles_per_run=1 << 16) as c:
         rid = c.submit(t, Z.PREC_FP32)
         launched = [c.run() for _ in range(4)]
