@@ -81,7 +81,10 @@ typedef enum {
                                 cannot resolve is re-run in FP64 and its result says so: spread too
                                 small (sigma / rms below 400 * 2^-24 * sqrt(N)), values or squares
                                 out of FP32 range (non-finite sums: |f| beyond about 2^60; mean
-                                square below 2^-120 or zero: |f| below about 2^-60). */
+                                square below 2^-120 or zero: |f| below about 2^-60).  An Eq. (1)
+                                function whose phase bound 1 + 2 sum_j |k_j| (hi_j - lo_j) / 2 pi
+                                exceeds 4096 revolutions is evaluated in FP64 from the start (for a
+                                parameter grid: the whole grid, if any point exceeds it). */
     MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
 } mc_precision;
 

@@ -757,7 +757,8 @@ void admit(mc_ctx* ctx)
         } else {
             // records packed into the slots' part of the pinned mirror (whose
             // previous uploads completed before those slots were released)
-            for (uint64_t i = 0; i < nf; ++i) pack_function(r->fns[i], r->precision, &ctx->h_fns[slot_off + i]);
+            for (uint64_t i = 0; i < nf; ++i)
+                pack_function(r->fns[i], r->st[i].f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &ctx->h_fns[slot_off + i]);
             if (idle)
                 HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
                                        hipMemcpyHostToDevice, ctx->upload_stream));
@@ -1253,8 +1254,26 @@ mc_status mc_destroy(mc_ctx* ctx)
 
 namespace {
 
-// Scheduling state of function i, common to tables and grids.
-void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
+// Largest phase, in revolutions, that the FP32 evaluation of Eq. (1) carries:
+// theta = f0 + sum_j kappa_j t_j with f0 in [0, 1), t_j in [1, 2) and
+// kappa_j = k_j w_j / 2 pi, so |theta| < 1 + 2 sum_j |kappa_j|.  Its FP32
+// rounding grows with it (measured: about 2.2e-7 * theta standard errors on
+// the estimate, whatever N), so beyond kFp32MaxPhaseRev (about 1e-3 SE) the
+// function is evaluated in FP64 instead.  0 for the other families.
+constexpr double kFp32MaxPhaseRev = 4096.0;
+
+double fp32_phase_bound(const mc_function& f)
+{
+    if (f.family != MC_FAMILY_HARMONIC) return 0.0;
+    double th = 1.0;
+    for (uint32_t j = 0; j < f.dim && j < (uint32_t)MC_MAX_DIM; ++j)
+        th += 2.0 * std::fabs(f.params[MC_PARAM_V0 + j] * (f.hi[j] - f.lo[j])) / kPackTwoPi;
+    return th;
+}
+
+// Scheduling state of function i, common to tables and grids; `f64`: evaluated
+// by the FP64 kernels.
+void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f, bool f64)
 {
     struct {
         uint32_t family, dim, n_segments;
@@ -1263,7 +1282,7 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
     FnState& fs = r->st[i];
     // run-time families take the harmonic family's tile size
     const uint32_t tf = d.family < (uint32_t)kNumFamilies ? d.family : (uint32_t)MC_FAMILY_HARMONIC;
-    uint32_t L = ctx->seg_log2[r->precision == MC_PREC_FP64 ? 1 : 0][tf][d.dim - 1];
+    uint32_t L = ctx->seg_log2[f64 ? 1 : 0][tf][d.dim - 1];
     // no point in tiles larger than the function; very large functions take
     // larger tiles so their partials stay within kTargetTilesPerFn (results do
     // not depend on the tile size)
@@ -1272,9 +1291,9 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f)
     fs.seg_log2 = L;
     fs.n_tiles = tiles_for(d.n_segments, L);
     fs.next_tile = 0;
-    fs.f64 = r->precision == MC_PREC_FP64;
+    fs.f64 = f64;
     fs.needs_upload = false;
-    fs.tile_cost = sample_cost(d.family, d.dim, r->precision) *
+    fs.tile_cost = sample_cost(d.family, d.dim, f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL) *
                    (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
     r->tiles_total += fs.n_tiles;
     r->work_left += fs.tile_cost * fs.n_tiles;
@@ -1330,7 +1349,8 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
         std::string why;
         mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
-        init_fn_state(ctx, r.get(), i, fns[i]);
+        const bool f64 = precision == MC_PREC_FP64 || fp32_phase_bound(fns[i]) > kFp32MaxPhaseRev;
+        init_fn_state(ctx, r.get(), i, fns[i], f64);
     }
     // (records are packed at admission, into the pinned mirror of their slots)
     return enqueue_request(ctx, std::move(r), out_request_id);
@@ -1389,11 +1409,24 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
             stride *= axes[a].count;
         }
     }
+    // FP32 phase bound over the whole grid: each parameter at the end of its
+    // axis with the larger magnitude (the bound grows with every |k_j|); a grid
+    // that exceeds it anywhere is evaluated in FP64 throughout
+    bool grid_f64 = precision == MC_PREC_FP64;
+    if (!grid_f64) {
+        mc_function fmax = r->spec.base;
+        for (uint32_t a = 0; a < n_axes; ++a) {
+            const double v0 = axes[a].start, v1 = axes[a].start + (double)(axes[a].count - 1) * axes[a].step;
+            fmax.params[axes[a].param] = std::fabs(v1) > std::fabs(v0) ? v1 : v0;
+        }
+        grid_f64 = fp32_phase_bound(fmax) > kFp32MaxPhaseRev;
+        if (grid_f64) r->spec.precision = MC_PREC_FP64;
+    }
     // all functions share family, dimension and sample count: the base gives
     // everybody's schedule
     r->st.resize(n);
     r->results.assign(n, mc_result{});
-    for (uint64_t i = 0; i < n; ++i) init_fn_state(ctx, r.get(), i, r->spec.base);
+    for (uint64_t i = 0; i < n; ++i) init_fn_state(ctx, r.get(), i, r->spec.base, grid_f64);
     return enqueue_request(ctx, std::move(r), out_request_id);
 }
 

@@ -232,6 +232,38 @@ def test_values_outside_fp32_range_are_promoted():
     assert r["mean"][8] == 0.0 and r["std_error"][8] == 0.0
 
 
+def test_large_phases_run_in_fp64():
+    """Eq. (1) functions whose FP32 phase bound 1 + 2 sum |k_j w_j| / 2 pi exceeds 4096
+    revolutions run in FP64 from the start (FP32 rounding of the phase costs about
+    2.2e-7 * theta standard errors); below it they stay FP32 and meet the FP32 bar.
+    A parameter grid whose k axis reaches such phases runs in FP64 throughout and
+    equals the expanded table evaluated in FP64."""
+    Z = _Z()
+    t = W.empty(4)
+    W.set_harmonic(t, 0, 2, 1.0, 0.5, [2e4, -1e4], [0, 0], [1, 1])               # ~9.5e3 rev
+    W.set_harmonic(t, 1, 1, 1.0, 0.0, [2e5], [-1.0], [1.0])                       # ~1.3e5 rev
+    W.set_harmonic(t, 2, 3, 1.0, 1.0, [300.0] * 3, [0] * 3, [1] * 3)              # ~290 rev
+    W.set_harmonic(t, 3, 4, 0.7, -0.3, [1e4, 1.0, 1.0, 1.0], [0] * 4, [1] * 4)    # ~3.2e3 rev
+    t["n_samples"][:] = 300_003
+    t["seed"][:] = [W.stream_seed(43, i) for i in range(len(t))]
+    orc = G.oracle_results(t)
+    base = W.empty(1)
+    W.set_harmonic(base, 0, 2, 1.0, 0.5, [10.0, 3.0], [0, 0], [1, 1])
+    base["n_samples"][0] = 100_003
+    base["seed"][0] = W.stream_seed(44, 0)
+    axes = [(W.V0, 8, 10.0, 3000.0)]                                              # k_0 up to 21010: ~6.7e3 rev
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        r = c.integrate(t, Z.PREC_FP32)
+        assert c.stats()["promoted"] == 0                                          # decided at submit, not re-run
+        rg = c.integrate_grid(base, axes, Z.PREC_FP32)
+        r64 = c.integrate(W.expand_grid(base, axes), Z.PREC_FP64)
+    assert r["precision"].tolist() == [1, 1, 0, 0]
+    G.check_fp64(r[:2], orc[:2], "large phases")
+    G.check_fp32(r[2:], orc[2:], "phases below the limit")
+    assert np.all(rg["precision"] == 1)
+    _same(rg, r64, "grid reaching large phases")
+
+
 def test_promotion_of_nearly_constant_functions():
     """A nearly constant integrand cannot be resolved in FP32; it comes back from FP64."""
     Z = _Z()
