@@ -83,8 +83,11 @@ typedef enum {
                                 out of FP32 range (non-finite sums: |f| beyond about 2^60; mean
                                 square below 2^-120 or zero: |f| below about 2^-60).  An Eq. (1)
                                 function whose phase bound 1 + 2 sum_j |k_j| (hi_j - lo_j) / 2 pi
-                                exceeds 4096 revolutions is evaluated in FP64 from the start (for a
-                                parameter grid: the whole grid, if any point exceeds it). */
+                                exceeds 4096 revolutions, and a product-polynomial or run-time-family
+                                function (which sees x in FP32 absolute coordinates) with
+                                K sqrt(N) > 24200, K = max_j max(|lo_j|, |hi_j|) / (hi_j - lo_j), are
+                                evaluated in FP64 from the start (for a parameter grid: the whole grid,
+                                if any point exceeds it). */
     MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
 } mc_precision;
 

@@ -1271,6 +1271,33 @@ double fp32_phase_bound(const mc_function& f)
     return th;
 }
 
+// The product polynomial and run-time families see the sample point in FP32
+// absolute coordinates, x_j = fma(w_j, u_j, lo_j) with lo_j and w_j rounded to
+// float: a shift common to all samples of about 2^-25 max(|lo_j|, |hi_j|),
+// which against the box width biases the estimate by about
+// 2^-25 sqrt(12) K sqrt(N) standard errors, K = max_j max(|lo_j|, |hi_j|) / w_j
+// (measured on the GPU: K = 100, N = 1e6, a factor with its root in the box:
+// 1.1e-2 SE, against 1.0e-2 predicted).  Where that exceeds 0.0025 SE, i.e.
+// K sqrt(N) > kFp32MaxOffsetRootN, the function is evaluated in FP64 instead.
+// 0 for the families evaluated in local coordinates.
+constexpr double kFp32MaxOffsetRootN = 24200.0;
+
+double fp32_offset_ratio(const mc_function& f)
+{
+    if (f.family <= (uint32_t)MC_FAMILY_GAUSSIAN) return 0.0;
+    double k = 0.0;
+    for (uint32_t j = 0; j < f.dim && j < (uint32_t)MC_MAX_DIM; ++j)
+        k = std::max(k, std::max(std::fabs(f.lo[j]), std::fabs(f.hi[j])) / (f.hi[j] - f.lo[j]));
+    return k;
+}
+
+// Whether FP32 evaluation of f can meet 0.01 SE at all (checked at submit).
+bool fp32_hopeless(const mc_function& f)
+{
+    return fp32_phase_bound(f) > kFp32MaxPhaseRev ||
+           fp32_offset_ratio(f) * std::sqrt((double)f.n_samples) > kFp32MaxOffsetRootN;
+}
+
 // Scheduling state of function i, common to tables and grids; `f64`: evaluated
 // by the FP64 kernels.
 void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f, bool f64)
@@ -1349,7 +1376,7 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
         std::string why;
         mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
-        const bool f64 = precision == MC_PREC_FP64 || fp32_phase_bound(fns[i]) > kFp32MaxPhaseRev;
+        const bool f64 = precision == MC_PREC_FP64 || fp32_hopeless(fns[i]);
         init_fn_state(ctx, r.get(), i, fns[i], f64);
     }
     // (records are packed at admission, into the pinned mirror of their slots)
@@ -1419,7 +1446,7 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
             const double v0 = axes[a].start, v1 = axes[a].start + (double)(axes[a].count - 1) * axes[a].step;
             fmax.params[axes[a].param] = std::fabs(v1) > std::fabs(v0) ? v1 : v0;
         }
-        grid_f64 = fp32_phase_bound(fmax) > kFp32MaxPhaseRev;
+        grid_f64 = fp32_hopeless(fmax);
         if (grid_f64) r->spec.precision = MC_PREC_FP64;
     }
     // all functions share family, dimension and sample count: the base gives

@@ -264,6 +264,27 @@ def test_large_phases_run_in_fp64():
     _same(rg, r64, "grid reaching large phases")
 
 
+def test_far_narrow_boxes_of_the_polynomial_run_in_fp64():
+    """The product polynomial sees x in FP32 absolute coordinates: a box far from the
+    origin relative to its width (K = max|x| / w) biases the FP32 estimate by about
+    2^-25 sqrt(12) K sqrt(N) SE, so K sqrt(N) > 24200 runs in FP64 from submit.  A
+    factor with its root inside a box 1000 widths out (K sqrt(N) = 1e6) comes back
+    FP64 at the FP64 bar; the same form near the origin stays FP32 at the FP32 bar."""
+    Z = _Z()
+    t = W.empty(3)
+    W.set_poly(t, 0, 1, [-1.0 / 100.03], [1], [100.0], [100.1])                    # K ~ 1000
+    W.set_poly(t, 1, 2, [-0.8, 0.5], [1, 3], [50.0, -1.0], [50.5, 1.0])            # K = 101
+    W.set_poly(t, 2, 1, [-1.0 / 1.7], [1], [1.0], [3.0])                            # K = 1.5
+    t["n_samples"][:] = 1_000_000
+    t["seed"][:] = [W.stream_seed(45, i) for i in range(len(t))]
+    orc = G.oracle_results(t)
+    with Z.Context(flags=Z.MC_NO_GRAPH) as c:
+        r = c.integrate(t, Z.PREC_FP32)
+    assert r["precision"].tolist() == [1, 1, 0]
+    G.check_fp64(r[:2], orc[:2], "far narrow boxes")
+    G.check_fp32(r[2:], orc[2:], "box near the origin")
+
+
 def test_promotion_of_nearly_constant_functions():
     """A nearly constant integrand cannot be resolved in FP32; it comes back from FP64."""
     Z = _Z()
