@@ -384,6 +384,9 @@ def main():
         return
     stream = torch.cuda.current_stream()
     K, Wm = args.steps, args.warmup
+    if args.graph:
+        # every launch slot captures its graph on first use: warm all three
+        Wm = max(Wm, 3)
     log(f"building {K + Wm} batches of {args.n_funcs} functions")
     batches = [W.harmonic_batch(args.n_funcs, n_samples=args.n_samples, base=b) for b in range(K + Wm)]
     evals_per_step = W.total_evals(batches[0])
