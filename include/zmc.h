@@ -289,7 +289,10 @@ mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, ui
  * x[0..dim) is the sample point inside the function's box, p[0..32) its
  * mc_function.params, T = float for MC_PREC_FP32_EVAL and double for MC_PREC_FP64
  * (FP32 evaluation sees x and p rounded to float; sums and the finalize stay as
- * for the built-in families, including FP32 -> FP64 promotion).  HIP device math
+ * for the built-in families, including FP32 -> FP64 promotion and the
+ * absolute-coordinate rule of MC_PREC_FP32_EVAL; what the caller's code itself
+ * loses in FP32 -- e.g. sin of a large argument -- the library cannot see, so such
+ * integrands should be submitted in MC_PREC_FP64).  HIP device math
  * (sinf, exp, ...) is available.  The source is copied; the id written to
  * *family_out (MC_FAMILY_USER0 + k, k < MC_MAX_USER_FAMILIES, in registration
  * order) goes into mc_function.family for mc_submit on this context only.
