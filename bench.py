@@ -436,10 +436,19 @@ def main():
     avg_main_s = (st1[key] - st0[key]) / launches * 1e-3
     slots = algorithmic_slots_per_eval("harmonic", 4) * evals_per_step
     achieved = slots / avg_main_s
+    # secondary fractions of the same kernel time: FP32 FLOPs (d = 4 harmonic: 4 phase
+    # FMAs = 8 flops, fract, cos, 4 for the pairwise and compensated sums: ~14 per
+    # evaluation) against the 157.3 TFLOP/s FP32-vector peak, and one v_cos_f32 per
+    # evaluation against the transcendental issue rate (a quarter of the full
+    # 32-bit lane rate)
+    evals_per_s_kernel = evals_per_step / avg_main_s
+    secondary = {"fp32_flop_frac": 14.0 * evals_per_s_kernel / 157.3e12,
+                 "transcendental_frac": evals_per_s_kernel / (VALU_SLOT_PEAK / 4.0),
+                 "flops_per_eval": 14.0, "transcendentals_per_eval": 1.0}
     roof = {"bound": "alu", "achieved": achieved / 1e12, "peak": VALU_SLOT_PEAK / 1e12,
             "unit": "T lane-slots/s (full-rate VALU issue)", "frac": achieved / VALU_SLOT_PEAK,
             "traffic": measured_traffic("zmc_batched_fp32"), "kernel": "zmc_batched_fp32", "kernel_ms": avg_main_s * 1e3,
-            "slots_per_eval": algorithmic_slots_per_eval("harmonic", 4)}
+            "slots_per_eval": algorithmic_slots_per_eval("harmonic", 4), "secondary": secondary}
 
     out = {
         "metric": "integrand evals/sec + % FP32 VALU peak; serving p50/p99 latency at fixed QPS",
