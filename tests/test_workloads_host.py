@@ -134,3 +134,28 @@ def test_runs_reseed_and_spread():
     assert abs(s["rms_se"][0] - math.sqrt(14.0 / 3.0)) < 1e-15 and s["rms_se"][1] == 0.0
     with pytest.raises(ValueError):
         R.spread(rs[:1])
+
+
+def test_bench_roofline_helpers(monkeypatch):
+    """The roofline's algorithmic work (77 lane-slots per d = 4 harmonic evaluation:
+    Philox 60, uniforms 4, phase and cos 9, sums 4) and the committed HBM counter
+    summary, which is used only while the kernel sources match its hash."""
+    import bench
+    assert bench.algorithmic_slots_per_eval("harmonic", 4) == 77.0
+    assert bench.algorithmic_slots_per_eval("harmonic", 8) == 60 * 2 + 8 + 13 + 4
+    traffic = bench.measured_traffic("zmc_batched_fp32")
+    assert traffic is None or 3e6 < traffic < 1e8           # None once the sources differ from the profile's
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: "0" * 16)
+    assert bench.measured_traffic("zmc_batched_fp32") is None
+    assert bench.measured_traffic("no_such_kernel") is None
+
+
+def test_bench_help_lists_the_contract_options():
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    p = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--help"], capture_output=True, text=True,
+                       timeout=120)
+    assert p.returncode == 0
+    for opt in ("--gpus", "--steps", "--warmup", "--serve-policy", "--blocks-per-cu", "--graph"):
+        assert opt in p.stdout, opt
