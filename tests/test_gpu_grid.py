@@ -33,3 +33,45 @@ def test_grid_equals_table_and_oracle():
                 # to float): far inside the FP32 bar
                 assert np.all(np.abs(g["mean"] - t["mean"]) <= 1e-3 * orc["stderr"])
                 G.check_fp32(g, orc, "grid fp32")
+
+
+def _base(family):
+    b = W.empty(1)
+    if family == "abs_linear":
+        W.set_abs_linear(b, 0, 3, 1.0, 0.2, [1.0, -1.0, 0.5], [-0.5, 0.0, 0.2], [0.5, 1.5, 1.0])
+        axes = [(0, 3, 0.5, 0.75), (W.V0 + 1, 4, -2.0, 1.3)]
+    elif family == "gaussian":
+        W.set_gaussian(b, 0, 2, 1.5, 0.4, [0.3, 0.6], [0.0, 0.0], [1.0, 1.2])
+        axes = [(1, 3, 0.2, 0.3), (W.V0, 5, 0.1, 0.2)]
+    elif family == "poly":
+        W.set_poly(b, 0, 3, [0.5, -0.4, 0.9], [2, 1, 3], [-1.0, 0.0, 0.5], [1.0, 2.0, 1.5])
+        axes = [(W.V0, 4, -1.0, 0.6), (W.W0 + 2, 3, 1.0, 2.0)]            # degrees 1, 3, 5
+    else:
+        W.set_harmonic(b, 0, 4, 1.0, 0.5, [3.0, 5.0, 7.0, 2.0], [0.0] * 4, [1.0] * 4)
+        axes = [(0, 2, 0.5, 1.0), (1, 2, -1.0, 2.0), (W.V0 + 3, 3, 2.0, 5.0)]
+    b["n_samples"][0] = 20_001
+    b["seed"][0] = W.stream_seed(12, 0)
+    return b, axes
+
+
+@pytest.mark.parametrize("family", ["abs_linear", "gaussian", "poly", "harmonic_three_axes"])
+def test_grids_of_every_family(family):
+    """Grids with axes on scalar, per-dimension and degree parameters: FP64 results
+    equal the expanded table's bit for bit and match the oracle; FP32 results meet
+    the FP32 bar."""
+    import paper_2104_10073_amd as Z
+    base, axes = _base(family)
+    table = W.expand_grid(base, axes)
+    orc = G.oracle_results(table)
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as c:
+        g64 = c.integrate_grid(base, axes, Z.PREC_FP64)
+        t64 = c.integrate(table, Z.PREC_FP64)
+        g32 = c.integrate_grid(base, axes, Z.PREC_FP32)
+    for k in ("mean", "std_error", "sum_f", "sum_f2", "n", "precision"):
+        assert np.array_equal(g64[k], t64[k]), k
+    G.check_fp64(g64, orc, f"{family} grid fp64")
+    f32 = g32["precision"] == 0
+    assert f32.any()
+    G.check_fp32(g32[f32], orc[f32], f"{family} grid fp32")
+    if (~f32).any():
+        G.check_fp64(g32[~f32], orc[~f32], f"{family} grid promoted")
