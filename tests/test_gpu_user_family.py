@@ -95,3 +95,19 @@ def test_plain_path_rejects_user_family(setup):
     with pytest.raises(Z.McError) as e:
         c.plain_fp64(t[30:32])
     assert e.value.status == -2
+
+
+def test_user_family_far_narrow_box_runs_in_fp64(setup):
+    """A run-time family sees x in FP32 absolute coordinates, so a box far from the
+    origin relative to its width (K sqrt(N) > 24200) runs in FP64 from submit and
+    matches the oracle at the FP64 bar; the same function near the origin stays FP32."""
+    import paper_2104_10073_amd as Z
+    c, _, _, (fa, fb) = setup
+    t = U.user_table(2, fb, gen_seed=905, log10_samples=(5.0, 5.0), dim_range=(2, 2), base=4)
+    t["lo"][0, :2] = [200.0, -0.5]
+    t["hi"][0, :2] = [200.05, 0.5]                      # K = 4001, K sqrt(N) ~ 1.3e6
+    r = c.integrate(t, Z.PREC_FP32)
+    assert r["precision"].tolist() == [1, 0]
+    orc = O.default().integrate_user(t, U.rational_np)
+    G.check_fp64(r[:1], orc[:1], "far box, run-time family")
+    G.check_fp32(r[1:], orc[1:], "box near the origin, run-time family")
