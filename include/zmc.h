@@ -87,7 +87,8 @@ typedef enum {
                                 function (which sees x in FP32 absolute coordinates) with
                                 K sqrt(N) > 24200, K = max_j max(|lo_j|, |hi_j|) / (hi_j - lo_j), are
                                 evaluated in FP64 from the start (for a parameter grid: the whole grid,
-                                if any point exceeds it). */
+                                if any point exceeds it), as is every function of N >= 1.8e9, which the
+                                sigma / rms check would always send to FP64. */
     MC_PREC_FP64 = 1         /* FP64 evaluation in the reference operation order, FP64 sums */
 } mc_precision;
 
@@ -117,8 +118,8 @@ typedef struct mc_result {
 /* Context flags. */
 #define MC_VALIDATE_ONLY 0x1u    /* host-only context: mc_submit validates and packs, no device is touched */
 #define MC_NO_GRAPH 0x2u         /* launch kernels directly instead of replaying captured HIP graphs */
-#define MC_NO_PROMOTE 0x4u       /* keep every FP32 result instead of re-running unresolvable ones in FP64
-                                    (nearly constant or out-of-range integrands then come back as FP32 gave them) */
+#define MC_NO_PROMOTE 0x4u       /* evaluate every function of an FP32 request in FP32: no FP64 re-runs and no
+                                    FP64 choice at submit (unresolvable integrands come back as FP32 gave them) */
 
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */

@@ -1291,10 +1291,16 @@ double fp32_offset_ratio(const mc_function& f)
     return k;
 }
 
+// From this many samples on the check after an FP32 run (fp32_unresolved:
+// sigma / rms below 400 * 2^-24 * sqrt(N), a bound above 1 + 1/N here) re-runs
+// every function in FP64, since sigma / rms never exceeds that; such functions
+// go to FP64 at submit instead, with the same result and no FP32 pass.
+constexpr double kFp32MaxSamples = 1.8e9;
+
 // Whether FP32 evaluation of f can meet 0.01 SE at all (checked at submit).
 bool fp32_hopeless(const mc_function& f)
 {
-    return fp32_phase_bound(f) > kFp32MaxPhaseRev ||
+    return (double)f.n_samples >= kFp32MaxSamples || fp32_phase_bound(f) > kFp32MaxPhaseRev ||
            fp32_offset_ratio(f) * std::sqrt((double)f.n_samples) > kFp32MaxOffsetRootN;
 }
 
@@ -1376,7 +1382,7 @@ mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t preci
         std::string why;
         mc_status st = validate_one(fns[i], ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
-        const bool f64 = precision == MC_PREC_FP64 || fp32_hopeless(fns[i]);
+        const bool f64 = precision == MC_PREC_FP64 || (ctx->promote && fp32_hopeless(fns[i]));
         init_fn_state(ctx, r.get(), i, fns[i], f64);
     }
     // (records are packed at admission, into the pinned mirror of their slots)
@@ -1440,7 +1446,7 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
     // axis with the larger magnitude (the bound grows with every |k_j|); a grid
     // that exceeds it anywhere is evaluated in FP64 throughout
     bool grid_f64 = precision == MC_PREC_FP64;
-    if (!grid_f64) {
+    if (!grid_f64 && ctx->promote) {
         mc_function fmax = r->spec.base;
         for (uint32_t a = 0; a < n_axes; ++a) {
             const double v0 = axes[a].start, v1 = axes[a].start + (double)(axes[a].count - 1) * axes[a].step;

@@ -35,7 +35,7 @@ def test_max_size_functions_match_exact_integrals():
         print("max size: 2 functions x 2^36 samples, d = 12", flush=True)
         r64 = c.integrate(t, Z.PREC_FP64)
         # at 6.9e10 samples FP32 evaluation cannot reach 0.01 SE: the FP32 request
-        # comes back re-run in FP64
+        # runs in FP64 (decided at submit; MC_NO_PROMOTE keeps FP32)
         r32p = c.integrate(t, Z.PREC_FP32)
     with Z.Context(device=0, flags=Z.MC_NO_GRAPH | Z.MC_NO_PROMOTE) as c:
         r32 = c.integrate(t, Z.PREC_FP32)
