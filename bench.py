@@ -10,9 +10,18 @@ tile reductions), the FP64 finalize pass and the copy of the 1000 results.
 
 Prints one JSON line.  `value` is integrand evaluations per second over the
 timed steps (inputs resident before the clock starts).  `roofline` prices the
-persistent kernel's algorithmic VALU work against the chip's VALU issue peak;
-`cpu_baseline` is the serial FP64 CPU oracle on a bounded sample of the same
-workload, all host cores.
+persistent kernel's algorithmic VALU work against the chip's VALU issue peak
+(with the FP32 FLOP and transcendental fractions beside it and the HBM bytes
+of the committed counter summary); `run_spread` is the paper's error bar over
+the timed seeds.  Beside them: `comparators` (the batched FP64 path, the plain
+one-launch-per-function FP64 path, graph replays of the same steps),
+`other_configs` (the paper's Eq. (1) cases including the Fig. 1 job, a
+parameter grid, a run-time compiled family, the mixed and high-dimensional
+batches with their FP32 errors), `serving` (open-loop Poisson arrivals at a
+fixed rate under SRPT, FAIR at the same rates, alone-vs-mix equality),
+`cpu_baseline` (the serial FP64 CPU oracle on a bounded sample of the same
+workload, all host cores) and `oracle_check` (the timed FP32 results against
+that oracle).
 """
 
 from __future__ import annotations
