@@ -282,6 +282,14 @@ def other_configs(Z, W, stream):
         return r, time.perf_counter() - t0
 
     with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as ctx:
+        # the headline batch end to end from a host table: validation, packing, the
+        # PCIe upload of 1000 records, the launch and the results back (the
+        # PCIe-inclusive rate; the headline value has the records resident)
+        hb = W.harmonic_batch(1000, n_samples=1_000_000, base=77)
+        ev = W.total_evals(hb)
+        _, th = timed(lambda: ctx.integrate(hb, Z.PREC_FP32, stream=stream))
+        out["harmonic_1000x1e6_from_host_table"] = {"evals": ev, "wall_ms": th * 1e3, "evals_per_s": ev / th}
+        log(f"harmonic_1000x1e6_from_host_table: {ev / th:.3g} evals/s")
         eq1 = W.eq1_series(n_samples=10_000)
         ev = W.total_evals(eq1)
         _, tp = timed(lambda: ctx.plain_fp64(eq1, stream=stream))
