@@ -49,7 +49,7 @@ typedef enum {
     MC_ERR_BAD_DIM = -3,           /* dim outside 1..12 */
     MC_ERR_BAD_BOUNDS = -4,        /* lo/hi not finite or lo >= hi */
     MC_ERR_BAD_PARAMS = -5,        /* non-finite parameter, sigma <= 0, bad degree */
-    MC_ERR_OUT_OF_MEMORY = -6,     /* device or pinned allocation failed */
+    MC_ERR_OUT_OF_MEMORY = -6,     /* device or pinned allocation failed (any HIP call returning out of memory) */
     MC_ERR_ADMISSION = -7,         /* request can never fit the context's capacity */
     MC_ERR_HIP = -8,               /* a HIP runtime call failed (message has the HIP string) */
     MC_ERR_NO_DEVICE = -9,         /* no usable gfx950 device, or device call on a validate-only context */

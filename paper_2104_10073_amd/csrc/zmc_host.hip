@@ -412,9 +412,11 @@ mc_status fail(mc_ctx* ctx, mc_status st, const char* fmt, ...)
     return st;
 }
 
+// An allocation the runtime refuses is reported as such, whichever call made it.
 mc_status fail_hip(mc_ctx* ctx, const HipError& e)
 {
-    return fail(ctx, MC_ERR_HIP, "%s failed: %s", e.what, hipGetErrorString(e.e));
+    const mc_status st = e.e == hipErrorOutOfMemory ? MC_ERR_OUT_OF_MEMORY : MC_ERR_HIP;
+    return fail(ctx, st, "%s failed: %s", e.what, hipGetErrorString(e.e));
 }
 
 uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
