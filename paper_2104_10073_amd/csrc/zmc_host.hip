@@ -597,11 +597,17 @@ EvSet* acquire_evset(mc_ctx* ctx)
     if (ctx->ev_free.empty() && ctx->ev_pool.size() >= kEvPoolMax) collect_pending(ctx, true);
     if (ctx->ev_free.empty()) {
         std::unique_ptr<EvSet> e(new EvSet());
-        HIP_TRY(hipEventCreate(&e->start));
-        HIP_TRY(hipEventCreate(&e->mid));
-        HIP_TRY(hipEventCreate(&e->main));
-        HIP_TRY(hipEventCreate(&e->end));
-        HIP_TRY(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+        try {
+            HIP_TRY(hipEventCreate(&e->start));
+            HIP_TRY(hipEventCreate(&e->mid));
+            HIP_TRY(hipEventCreate(&e->main));
+            HIP_TRY(hipEventCreate(&e->end));
+            HIP_TRY(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+        } catch (const HipError&) {
+            for (hipEvent_t x : {e->start, e->mid, e->main, e->end, e->done})
+                if (x) quiet(hipEventDestroy(x));
+            throw;
+        }
         ctx->ev_free.push_back(e.get());
         ctx->ev_pool.push_back(std::move(e));
     }
@@ -610,6 +616,13 @@ EvSet* acquire_evset(mc_ctx* ctx)
     e->pending = false;
     e->released = false;
     return e;
+}
+
+bool any_in_flight(const mc_ctx* ctx)
+{
+    for (const auto& s : ctx->slots)
+        if (s.in_flight) return true;
+    return false;
 }
 
 uint32_t load_done(const mc_ctx* ctx, const LaunchSlot& s)
@@ -922,6 +935,9 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         *no_slot = true;
         return false;
     }
+    // the one resource a launch creates, taken before any request's state
+    // changes, so that its failure leaves every request as it was
+    EvSet* const evp = acquire_evset(ctx);
     LaunchSlot& s = *slot;
     s.n_tiles = s.n_fins = s.n_runs = 0;
     for (auto& v : s.runs) v.clear();
@@ -947,7 +963,10 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         if (has_work(r)) keep.push_back(r);
     }
     ctx->active.swap(keep);
-    if (s.n_tiles == 0 && s.n_fins == 0) return false;
+    if (s.n_tiles == 0 && s.n_fins == 0) {
+        ctx->ev_free.push_back(evp);
+        return false;
+    }
     // stage: finalize records after the descriptor, then the tile runs; the
     // stage kernel expands the runs into the device tile list, the kernels'
     // parts one after another
@@ -1004,7 +1023,7 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
                                 stream));
         r->grid_packed = true;
     }
-    EvSet& ev = *acquire_evset(ctx);
+    EvSet& ev = *evp;
     s.ev = &ev;
     const uint64_t seq = ctx->launch_seq + 1;
     uint8_t* const hdesc_dev = s.h_block_dev + ctx->slot_res_bytes;
@@ -1531,12 +1550,17 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
         reap(ctx, 0);
         while (r->fns_done < r->count()) {
             if (!blocking) return MC_NOT_READY;
-            if (r->tiles_launched < r->tiles_total || !r->admitted) {
+            if (r->tiles_launched < r->tiles_total || has_work(r) || !r->admitted) {
                 mc_status st = mc_run(ctx, nullptr);
                 if (st == MC_NOT_READY) reap(ctx, 1);  // all slots busy: wait for the oldest launch
                 else if (st != MC_OK) return st;
-            } else {
+            } else if (any_in_flight(ctx)) {
                 reap(ctx, 1);
+            } else {
+                // every tile was handed to a launch and every launch has been
+                // reaped: the rest went to a launch that failed to enqueue
+                return fail(ctx, MC_ERR_HIP, "request %llu cannot complete: its work was in a launch that failed",
+                            (unsigned long long)request_id);
             }
         }
     } catch (const HipError& e) {
