@@ -935,10 +935,19 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         *no_slot = true;
         return false;
     }
-    // the one resource a launch creates, taken before any request's state
-    // changes, so that its failure leaves every request as it was
+    // what a launch may have to create (its event set, the slot's graph on
+    // first use; neither depends on the launch's contents) is made before any
+    // request's state changes, so that a failure leaves every request as it was
     EvSet* const evp = acquire_evset(ctx);
     LaunchSlot& s = *slot;
+    if (ctx->use_graph && ctx->n_user == 0 && !s.graph) {
+        try {
+            capture_graph(ctx, s);
+        } catch (const HipError&) {
+            ctx->ev_free.push_back(evp);
+            throw;
+        }
+    }
     s.n_tiles = s.n_fins = s.n_runs = 0;
     for (auto& v : s.runs) v.clear();
     s.fv.clear();
