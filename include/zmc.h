@@ -224,8 +224,9 @@ mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
  * the null stream as needed and waits.  Results can be taken once; the
  * request's device resources are released when it completes.  If an mc_run
  * failed with MC_ERR_HIP after handing part of this request's work to its
- * launch (a kernel launch or stream wait refused), that work is lost and the
- * blocking call returns MC_ERR_HIP instead of waiting for it.  A failure to
+ * launch (a kernel launch or stream wait refused), that work is lost: the
+ * blocking call returns MC_ERR_HIP instead of waiting for it and releases the
+ * request (its id is then unknown).  A failure to
  * create the launch's events or the slot's graph happens before any work is
  * handed over: the next mc_run launches the request as if nothing had happened. */
 mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking);

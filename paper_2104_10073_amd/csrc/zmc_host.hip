@@ -1567,7 +1567,10 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
                 reap(ctx, 1);
             } else {
                 // every tile was handed to a launch and every launch has been
-                // reaped: the rest went to a launch that failed to enqueue
+                // reaped: the rest went to a launch that failed to enqueue.
+                // Nothing in flight refers to the request, so it is released.
+                free_request_resources(ctx, r);
+                ctx->requests.erase(it);
                 return fail(ctx, MC_ERR_HIP, "request %llu cannot complete: its work was in a launch that failed",
                             (unsigned long long)request_id);
             }
