@@ -153,13 +153,21 @@ mc_status mc_workspace_size(const mc_config* cfg, uint64_t* bytes);
 
 /* Create a context on cfg->device.  Allocates the function table, tile-partial
  * arena, staging buffers and (unless MC_NO_GRAPH) captures the launch graphs.
- * With MC_VALIDATE_ONLY nothing touches a device. */
+ * With MC_VALIDATE_ONLY nothing touches a device.  Paper, "Solution method":
+ * the integrations run on the GPU; a context is the device state (one GPU)
+ * that every later call of the path uses.  *out is owned by the caller until
+ * mc_destroy.  Errors: MC_ERR_INVALID_ARG (NULL or out-of-range config field),
+ * MC_ERR_NO_DEVICE, MC_ERR_OUT_OF_MEMORY, MC_ERR_HIP; nothing is left
+ * allocated on failure. */
 mc_status mc_create(const mc_config* cfg, mc_ctx** out);
 
 /* Wait for the context's outstanding work and free everything it owns. */
 mc_status mc_destroy(mc_ctx* ctx);
 
 /* Validate and queue n functions as one request evaluated in `precision`.
+ * Paper, "Multi-function Integrations" (Eq. (1), Eq. (2)): a batch of
+ * integrands that differ in form, dimension and domain, each one row of the
+ * caller's table (family, dim, params, box, n_samples, seed).
  * The whole request is rejected on the first invalid function (its index is in
  * mc_last_error); nothing partial is queued.  Requests are admitted to the device
  * in submission order as function slots and partial memory free up (at submit
@@ -197,7 +205,9 @@ typedef struct mc_grid_axis {
 mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axis* axes, uint32_t n_axes,
                          int32_t precision, uint64_t* out_request_id);
 
-/* Admit what fits, then enqueue one launch of the batched path on `stream`, as
+/* Paper, "Solution method": direct Monte Carlo of every admitted function on
+ * the GPU (uniform samples in its box, sum f and sum f^2 per function).
+ * Admit what fits, then enqueue one launch of the batched path on `stream`, as
  * kernels only: a stage kernel that copies the launch's work list (and the
  * records of functions admitted or promoted while launches were in flight) from
  * pinned host memory, preceded by the record-building kernel of any parameter
@@ -218,7 +228,11 @@ mc_status mc_poll(mc_ctx* ctx, uint64_t* completed, size_t cap, size_t* n);
 /* Number of requests submitted but not yet complete, and tiles still waiting for a launch. */
 mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
 
-/* Copy the n results of a request into out (n must equal the request size).
+/* Paper, Fig. 1 caption and "Solution method": each integral comes back as a
+ * value with an error bar -- mean V * S1 / N and standard error
+ * V * sqrt((S2 - S1^2 / N) / ((N - 1) N)) (mc_result, with S1, S2, N and the
+ * precision used).
+ * Copy the n results of a request into out (n must equal the request size).
  * blocking = 0: MC_NOT_READY if the request is not finished (runs are still
  * needed, or launched work has not completed).  blocking != 0: calls mc_run on
  * the null stream as needed and waits.  Results can be taken once; the

@@ -2,6 +2,8 @@
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 from oracle import oracle as O
@@ -9,6 +11,7 @@ from paper_2104_10073_amd import workloads as W
 
 FP64_REL = 1e-12      # FP64 paths: |S_gpu - S_oracle| <= 1e-12 * sum|f|  (S2: <= 1e-12 * S2)
 FP32_SE_FRAC = 1e-2   # FP32-eval path: |F_gpu - F_oracle| <= 0.01 * SE_oracle
+PREC_FP32, PREC_FP64 = 0, 1  # mc_precision values in results
 
 
 def oracle_results(table, threads=16):
@@ -35,21 +38,120 @@ def check_fp64(gpu, orc, label=""):
     return float(np.max(d1 / (orc["sum_abs"] + 1e-300)))
 
 
-def check_fp32(gpu, orc, label=""):
-    assert np.all(gpu["status"] == 0), label
-    assert np.array_equal(gpu["n"], orc["n"]), label
-    err = np.abs(gpu["mean"] - orc["mean"])
-    se = orc["stderr"]
+# The library's stated rules for running a function of an FP32 request in FP64
+# (header, MC_PREC_FP32_EVAL), restated from that documentation: at submit, by
+# phase bound, absolute-coordinate offset and sample count; after the FP32 run,
+# by spread and range of its sums.
+FP32_MAX_PHASE_REV = 4096.0
+FP32_MAX_OFFSET_ROOT_N = 24200.0
+FP32_MAX_SAMPLES = 1.8e9
+
+
+def _fp32_scale(table, i):
+    fam = int(table["family"][i])
+    p = table["params"][i]
+    if fam == W.HARMONIC:
+        return math.hypot(float(p[0]), float(p[1]))
+    if fam in (W.ABS_LINEAR, W.GAUSSIAN):
+        return abs(float(p[0]))
+    return 1.0
+
+
+def expected_promotion(table, orc, margin=2.0):
+    """(must, may): rows of an FP32 request the documented rules send to FP64.
+
+    `must` rows have to come back in FP64, rows outside `may` in FP32; rows in
+    `may` but not `must` sit within a factor `margin` of a post-run threshold,
+    where the FP32 sums and the oracle's may fall on either side.  The post-run
+    quantities are taken from the oracle's sums."""
+    n_rows = len(table)
+    must = np.zeros(n_rows, dtype=bool)
+    may = np.zeros(n_rows, dtype=bool)
+    for i in range(n_rows):
+        fam = int(table["family"][i])
+        d = int(table["dim"][i])
+        n = float(table["n_samples"][i])
+        lo = table["lo"][i, :d].astype(np.float64)
+        hi = table["hi"][i, :d].astype(np.float64)
+        p = table["params"][i]
+        hopeless = n >= FP32_MAX_SAMPLES
+        if fam == W.HARMONIC:
+            theta = 1.0 + float(np.sum(2.0 * np.abs(p[W.V0:W.V0 + d] * (hi - lo)) / (2.0 * math.pi)))
+            hopeless |= theta > FP32_MAX_PHASE_REV
+        if fam >= W.POLY_PRODUCT:
+            k = float(np.max(np.maximum(np.abs(lo), np.abs(hi)) / (hi - lo)))
+            hopeless |= k * math.sqrt(n) > FP32_MAX_OFFSET_ROOT_N
+        if hopeless:
+            must[i] = may[i] = True
+            continue
+        scale = _fp32_scale(table, i)
+        if scale == 0.0:
+            continue
+        s1, s2 = float(orc["sum_f"][i]), float(orc["sum_f2"][i])
+        rms2 = s2 / n
+        tiny = rms2 / (scale * scale)
+        # FP32 range: g beyond ~2^60 overflows the per-lane sums of g^2
+        if not math.isfinite(tiny) or tiny > 2.0 ** 128:
+            must[i] = may[i] = True
+            continue
+        if tiny > 2.0 ** 80:
+            may[i] = True
+        if tiny < 2.0 ** -120 / margin ** 2:
+            must[i] = may[i] = True
+            continue
+        if tiny < 2.0 ** -120 * margin ** 2:
+            may[i] = True
+        var = (s2 - s1 * s1 / n) / (n - 1.0)
+        ratio = math.sqrt(var / rms2) if var > 0.0 and rms2 > 0.0 else 0.0
+        bound = 400.0 * 2.0 ** -24 * math.sqrt(n)
+        if ratio < bound / margin:
+            must[i] = may[i] = True
+        elif ratio < bound * margin:
+            may[i] = True
+    return must, may
+
+
+def check_fp32(gpu, orc, label="", table=None):
+    """Grade an FP32 request by the precision each result reports.
+
+    Without `table` every row must have stayed FP32.  With `table`, rows the
+    library ran in FP64 (promotion) are graded by the FP64 bar, and must be
+    exactly the rows the documented promotion rules call for (`expected_promotion`).
+    Rows that stayed FP32 are graded by the FP32 bar.  Returns
+    {"max_ratio", "fp32", "fp64"}: the worst |dF| / SE over FP32 rows and the
+    row counts."""
+    prec = np.asarray(gpu["precision"])
+    f64 = prec == PREC_FP64
+    assert np.all((prec == PREC_FP32) | f64), f"{label}: unknown precision values {np.unique(prec)}"
+    if table is None:
+        assert not np.any(f64), f"{label}: rows {np.nonzero(f64)[0][:10]} came back in FP64"
+    else:
+        must, may = expected_promotion(table, orc)
+        late = np.nonzero(must & ~f64)[0]
+        extra = np.nonzero(f64 & ~may)[0]
+        assert late.size == 0, f"{label}: rows {late[:10]} should have been run in FP64"
+        assert extra.size == 0, f"{label}: rows {extra[:10]} were run in FP64 without a documented reason"
+    n32 = int(np.count_nonzero(~f64))
+    print(f"{label}: {n32} of {len(prec)} rows stayed FP32, {len(prec) - n32} ran in FP64", flush=True)
+    if np.any(f64):
+        check_fp64(gpu[f64], orc[f64], label + " (promoted to FP64)")
+    g, o = gpu[~f64], orc[~f64]
+    if len(g) == 0:
+        return {"max_ratio": 0.0, "fp32": 0, "fp64": len(prec)}
+    assert np.all(g["status"] == 0), label
+    assert np.array_equal(g["n"], o["n"]), label
+    err = np.abs(g["mean"] - o["mean"])
+    se = o["stderr"]
     exact_zero = se == 0.0
     ratio = np.where(exact_zero, 0.0, err / np.where(exact_zero, 1.0, se))
     bad = np.nonzero(ratio > FP32_SE_FRAC)[0]
     assert bad.size == 0, f"{label}: |F32 - F64| / SE above 0.01 at {bad[:10]}: {ratio[bad[:10]]}"
     # constant integrands (SE = 0) must come out exact to FP32 evaluation of a constant
     if np.any(exact_zero):
-        assert np.all(np.abs(err[exact_zero]) <= 1e-6 * np.abs(orc["mean"][exact_zero]) + 1e-300), label
-    se_ratio = np.where(exact_zero, 1.0, gpu["std_error"] / np.where(exact_zero, 1.0, se))
+        assert np.all(np.abs(err[exact_zero]) <= 1e-6 * np.abs(o["mean"][exact_zero]) + 1e-300), label
+    se_ratio = np.where(exact_zero, 1.0, g["std_error"] / np.where(exact_zero, 1.0, se))
     assert np.all(np.abs(se_ratio - 1.0) < 1e-3), f"{label}: SE ratio {se_ratio[np.abs(se_ratio - 1) >= 1e-3][:5]}"
-    return float(np.max(ratio))
+    return {"max_ratio": float(np.max(ratio)), "fp32": n32, "fp64": len(prec) - n32}
 
 
 def edge_table():

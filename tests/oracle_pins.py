@@ -10,7 +10,8 @@ Sources of truth used here, none of them the oracle's own code:
 * rocRAND's Philox4x32-10 run on the host (an independent implementation),
 * exact rational arithmetic for the uniform construction and the box mapping,
 * 40-digit mpmath evaluation of each integrand at a point,
-* math.fsum brute force of the sums on tiny sample counts,
+* math.fsum brute force of the sums on tiny sample counts, and exactly
+  rounded sums where a plain running sum drifts (N up to 10^7),
 * closed-form box integrals (tests/closed_forms.py): the estimate must sit
   within a few standard errors of the exact value, the standard errors must
   match the exact ones, and batches of z-scores must look standard normal,
@@ -179,6 +180,49 @@ def check_brute_force_sums(orc, rocrand_ref):
             assert abs(se - se_ref) <= 1e-6 * se_ref + 1e-12 * V * math.sqrt(s2_ref / n) / n, ("finalize se", i)
 
 
+def check_compensated_sums(orc):
+    """The oracle's sums are the accurate side of every parity bar (paper, "Solution
+    method": one direct Monte Carlo sum per integrand over up to ~10^7 samples).
+
+    Two cases where an uncompensated running sum visibly drifts, each against an
+    exactly rounded sum computed outside the oracle:
+    * a constant integrand with a non-dyadic value (Eq. (1) with k = 0: f = a
+      exactly) over N = 10^7 + 3 samples -- S1 and sum|f| must equal N * fl(0.1)
+      rounded once, S2 likewise N * fl(fl(0.1)^2) (a plain running sum is off by
+      about 1.6e-10 relative here);
+    * a high-frequency Eq. (1) term, f = cos(k x) on [0, 1] with k = 1000.5, over
+      2^20 samples: positive and negative values cancel so that |S1| is about
+      sqrt(N) while sum|f| is about 0.64 N.  The values are recomputed here from
+      the oracle's sample points with Python's float arithmetic and libm cos (the
+      same operations, each rounded once) and summed exactly with math.fsum (a
+      plain running sum is off by ~10^3 ulp of S1)."""
+    t = W.empty(2)
+    n_const = 10_000_003
+    W.set_harmonic(t, 0, 1, 0.1, 0.7, [0.0], [0.0], [1.0])
+    W.set_harmonic(t, 1, 1, 1.0, 0.0, [1000.5], [0.0], [1.0])
+    t["n_samples"][:] = [n_const, 1 << 20]
+    t["seed"][:] = [11, 12]
+
+    s1, s2, sa = orc.partial_sums(t, 0, 0, n_const)
+    want1 = float(Fraction(0.1) * n_const)
+    want2 = float(Fraction(0.1 * 0.1) * n_const)
+    assert abs(s1 - want1) <= math.ulp(want1), ("compensated S1, constant", s1, want1)
+    assert abs(sa - want1) <= math.ulp(want1), ("compensated sum|f|, constant", sa, want1)
+    assert abs(s2 - want2) <= math.ulp(want2), ("compensated S2, constant", s2, want2)
+
+    n = int(t["n_samples"][1])
+    xs = orc.sample_points(t, 1, 0, n)[:, 0]
+    fs = [math.cos(1000.5 * float(x)) for x in xs]
+    want1 = math.fsum(fs)
+    want2 = math.fsum(v * v for v in fs)
+    wanta = math.fsum(abs(v) for v in fs)
+    s1, s2, sa = orc.partial_sums(t, 1, 0, n)
+    assert abs(want1) < 4.0 * math.sqrt(n) and wanta > 0.5 * n, "the case must cancel"
+    assert abs(s1 - want1) <= 2.0 * math.ulp(want1), ("compensated S1, cancelling", s1, want1)
+    assert abs(s2 - want2) <= 2.0 * math.ulp(want2), ("compensated S2, cancelling", s2, want2)
+    assert abs(sa - wanta) <= 2.0 * math.ulp(wanta), ("compensated sum|f|, cancelling", sa, wanta)
+
+
 def check_finalize_textbook(orc):
     """f = 1, 2, 3, 4 on a box of volume 2: mean 5, sample variance 5/3."""
     mean, se = orc.finalize(2.0, 4, 10.0, 30.0)
@@ -312,4 +356,5 @@ ALL_CHECKS = [
     ("closed_forms", lambda o, r: check_closed_forms_4sigma(o)),
     ("eq2", lambda o, r: check_eq2_worked_values(o)),
     ("run_spread", lambda o, r: check_run_spread(o)),
+    ("compensated_sums", lambda o, r: check_compensated_sums(o)),
 ]

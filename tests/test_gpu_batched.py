@@ -227,6 +227,8 @@ def test_values_outside_fp32_range_are_promoted():
     assert promoted == 4
     fp32 = np.array([0, 1, 2, 3, 8, 9])
     fp64 = np.array([4, 5, 6, 7])
+    must, may = G.expected_promotion(t, orc)
+    assert must[fp64].all() and not may[fp32].any(), (must, may)
     G.check_fp32(r[fp32], orc[fp32], "amplitudes outside FP32 range")
     G.check_fp64(r[fp64], orc[fp64], "values outside FP32 range")
     assert r["mean"][8] == 0.0 and r["std_error"][8] == 0.0

@@ -48,7 +48,7 @@ def test_mixed_batch_full_size():
     sub = np.concatenate([order[:12], order[-2:], np.arange(0, 2000, 250)])
     sub = np.unique(sub)
     orc = G.oracle_results(t[sub])
-    G.check_fp32(r32[sub], orc, "mixed fp32")
+    G.check_fp32(r32[sub], orc, "mixed fp32", table=t[sub])
     G.check_fp64(r64[sub], orc, "mixed fp64")
     err = np.abs(r32["mean"] - r64["mean"]) / np.maximum(r64["std_error"], 1e-300)
     assert err.max() < 1e-2, (err.max(), int(np.argmax(err)))
@@ -63,7 +63,7 @@ def test_high_dim_full_size_sampled():
         r64 = c.integrate(t, Z.PREC_FP64)
     sub = np.array([0, 1, 9, 19])   # harmonic, Gaussian, two near-zero
     orc = G.oracle_results(t[sub])
-    G.check_fp32(r32[sub], orc, "high-dim fp32")
+    G.check_fp32(r32[sub], orc, "high-dim fp32", table=t[sub])
     G.check_fp64(r64[sub], orc, "high-dim fp64")
     err = np.abs(r32["mean"] - r64["mean"]) / np.maximum(r64["std_error"], 1e-300)
     assert err.max() < 1e-2, (err.max(), int(np.argmax(err)))

@@ -32,7 +32,7 @@ def test_grid_equals_table_and_oracle():
                 # host's (hypot, atan2 may differ in the last bit before rounding
                 # to float): far inside the FP32 bar
                 assert np.all(np.abs(g["mean"] - t["mean"]) <= 1e-3 * orc["stderr"])
-                G.check_fp32(g, orc, "grid fp32")
+                G.check_fp32(g, orc, "grid fp32", table=table)
 
 
 def _base(family):

@@ -65,7 +65,15 @@ def test_edge_cases_all_paths(ctx):
     orc = G.oracle_results(t)
     G.check_fp64(ctx.plain_fp64(t), orc, "plain edges")
     G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "batched fp64 edges")
-    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "batched fp32 edges")
+    r32 = ctx.integrate(t, Z.PREC_FP32)
+    info = G.check_fp32(r32, orc, "batched fp32 edges", table=t)
+    # the last four rows are the degenerate ones, all promoted: k = 0 and p = 0
+    # (constants), a Gaussian centred far outside its box (values below 2^-60,
+    # squares below FP32's range), sigma = 1e3 (nearly constant); no other row
+    assert r32["precision"][-4:].tolist() == [1, 1, 1, 1]
+    must, may = G.expected_promotion(t, orc)
+    assert int(np.count_nonzero(must)) <= info["fp64"] <= int(np.count_nonzero(may)), info
+    assert info["fp64"] == 4 and info["fp32"] == len(t) - 4, info
 
 
 def test_mixed_small_batch(ctx):
@@ -74,7 +82,9 @@ def test_mixed_small_batch(ctx):
     t = W.mixed_batch(300, dim_range=(1, 12), log10_samples=(2.0, 5.3), gen_seed=101)
     orc = G.oracle_results(t)
     G.check_fp64(ctx.integrate(t, Z.PREC_FP64), orc, "mixed fp64")
-    G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "mixed fp32")
+    info = G.check_fp32(ctx.integrate(t, Z.PREC_FP32), orc, "mixed fp32", table=t)
+    must, may = G.expected_promotion(t, orc)
+    assert int(np.count_nonzero(must)) <= info["fp64"] <= int(np.count_nonzero(may)), info
 
 
 def test_eq1_full_fp32_matches_oracle_sampled(ctx):

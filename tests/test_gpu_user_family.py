@@ -62,7 +62,9 @@ def test_user_families_fp32(setup):
     import paper_2104_10073_amd as Z
     c, t, orc, _ = setup
     print("user families fp32: functions", len(t), flush=True)
-    G.check_fp32(c.integrate(t, Z.PREC_FP32), orc, "user fp32")
+    info = G.check_fp32(c.integrate(t, Z.PREC_FP32), orc, "user fp32", table=t)
+    must, may = G.expected_promotion(t, orc)
+    assert int(np.count_nonzero(must)) <= info["fp64"] <= int(np.count_nonzero(may)), info
 
 
 def test_user_family_alone_equals_mixed(setup):

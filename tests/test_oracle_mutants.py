@@ -40,6 +40,10 @@ MUTANTS = [
     ("gaussian centre sign", "double t = x[j] - p[ORC_V0 + j];", "double t = x[j] + p[ORC_V0 + j];"),
     ("poly degree off by one", "for (int e = 0; e < deg; ++e)", "for (int e = 0; e <= deg; ++e)"),
     ("S2 sums f", "nsum_add(&a2, f * f);", "nsum_add(&a2, f);"),
+    ("compensation dropped", "static double nsum_value(const orc_sum* a) { return a->s + a->c; }",
+     "static double nsum_value(const orc_sum* a) { return a->s; }"),
+    ("compensation branch swapped", "if (fabs(a->s) >= fabs(x))", "if (fabs(a->s) < fabs(x))"),
+    ("compensation term sign", "a->c += (a->s - t) + x;", "a->c -= (a->s - t) + x;"),
     ("variance denominator N", "/ (dn - 1.0);", "/ dn;"),
     ("SE without volume", "*se = volume * sqrt(var / dn);", "*se = sqrt(var / dn);"),
     ("mean without volume", "*mean = volume * (s1 / dn);", "*mean = s1 / dn;"),

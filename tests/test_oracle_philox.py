@@ -3,8 +3,9 @@
 rocRAND is an independent implementation of Philox4x32-10 (Salmon et al., SC'11).
 Its host-side generator, seeded with the 64-bit function seed and read from
 subsequence 0, produces word g of the stream from counter (g/4 lo, g/4 hi, 0, 0)
-and key (seed lo, seed hi) -- exactly the layout the oracle defines (coordinate
-j of sample i uses word g = i*d + j).  The tests compare bit for bit.
+and key (seed lo, seed hi).  The oracle takes samples in quads: coordinate j
+of sample i is word i mod 4 of block (i / 4) * d + j, i.e. stream word
+g = 4 * ((i / 4) * d + j) + (i mod 4).  The tests compare bit for bit.
 """
 
 import numpy as np

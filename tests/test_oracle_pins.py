@@ -26,6 +26,10 @@ def test_brute_force_sums(orc, rocrand_ref):
     P.check_brute_force_sums(orc, rocrand_ref)
 
 
+def test_compensated_sums(orc):
+    P.check_compensated_sums(orc)
+
+
 def test_finalize_textbook(orc):
     P.check_finalize_textbook(orc)
 
