@@ -258,6 +258,21 @@ mc_status mc_abort(mc_ctx* ctx);
 mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out,
                                   void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): mc_integrate_plain_fp64
+ * with the same arguments and bitwise the same results, but calling no
+ * hipMalloc, hipFree or other allocating routine.  Its working set (the copied
+ * table, the packed records, the results and the block partials) lives in a
+ * fixed 24 MiB array in the library's code object, one per GPU, held until the
+ * process ends; mc_create looks up its address on the context's device.
+ * Limits: n <= 4096 functions, n_samples <= 2^30 per function (larger inputs
+ * return MC_ERR_INVALID_ARG and run nothing).  The array is shared by every
+ * call on a GPU and keeps the last call's contents: calls that overlap on one
+ * GPU (from several threads, contexts or streams) race and must be serialized
+ * by the caller.  Synchronous on `stream`; errors as mc_integrate_plain_fp64. */
+mc_status mc_integrate_plain_fp64_noalloc(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out,
+                                          void* stream);
+
 /* Tuning of the batched path: workgroups per CU for the persistent kernel and,
  * per (precision, family, dim), log2 of the segments each wave takes per tile.
  * Results never depend on these (the reduction tree is fixed per function). */

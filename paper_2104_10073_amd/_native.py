@@ -52,7 +52,7 @@ EXPORTS = [
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
     "mc_segment_samples", "mc_version", "mc_register_family", "mc_submit_grid",
-    "mc_sample_points",
+    "mc_sample_points", "mc_integrate_plain_fp64_noalloc",
 ]
 
 
@@ -121,6 +121,7 @@ def load(path: str = LIB_PATH):
     L.mc_results.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.c_int]
     L.mc_abort.argtypes = [vp]
     L.mc_integrate_plain_fp64.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
+    L.mc_integrate_plain_fp64_noalloc.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.mc_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
     L.mc_set_tuning.argtypes = [vp, ctypes.c_uint32, vp]
     L.mc_autotune.argtypes = [vp, ctypes.c_int32, vp, ctypes.c_double]
@@ -315,6 +316,15 @@ class Context:
         out = np.zeros(len(t), dtype=RESULT_DTYPE)
         self._check(self.L.mc_integrate_plain_fp64(self.h, t.ctypes.data, len(t), out.ctypes.data,
                                                    _stream_handle(stream)), self.h)
+        return out
+
+    def plain_fp64_noalloc(self, fns, stream=None):
+        """mc_integrate_plain_fp64_noalloc: the plain FP64 path with its working set in the
+        library's fixed per-GPU array (no device allocation; synchronous)."""
+        t = as_table(fns)
+        out = np.zeros(len(t), dtype=RESULT_DTYPE)
+        self._check(self.L.mc_integrate_plain_fp64_noalloc(self.h, t.ctypes.data, len(t), out.ctypes.data,
+                                                           _stream_handle(stream)), self.h)
         return out
 
     # -- tuning

@@ -23,6 +23,7 @@
 #include <deque>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <unordered_map>
 #include <vector>
@@ -38,6 +39,7 @@ const void* finalize_kernel_ptr();
 const void* stage_kernel_ptr();
 const void* publish_kernel_ptr();
 const void* pack_grid_kernel_ptr();
+const void* pack_table_kernel_ptr();
 const void* sample_points_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
@@ -47,6 +49,15 @@ extern const char* const kRtcHeaderCode;
 }  // namespace zmc
 
 using namespace zmc;
+
+// Device memory of mc_integrate_plain_fp64_noalloc, for callers that cannot
+// allocate: a fixed array in the library's code object, one copy per GPU,
+// held until the process ends.  In host code `scratch` is only a host-side
+// stand-in; its address on each GPU is looked up once per device
+// (scratch_address, called by mc_create with that device current) and only
+// that address is ever passed to kernels or copies.
+constexpr uint64_t kScratchBytes = 24ull << 20;
+static __device__ __align__(256) uint8_t scratch[kScratchBytes];
 
 static_assert(sizeof(mc_function) == 472, "mc_function layout");
 static_assert(sizeof(mc_result) == 48, "mc_result layout");
@@ -59,6 +70,36 @@ static_assert(sizeof(TileRun) == 32 && sizeof(DevFn) % 16 == 0, "staged record l
 namespace {
 
 thread_local std::string g_thread_error;
+
+// Limits of the no-allocation path (its whole working set lives in `scratch`).
+constexpr uint32_t kNoAllocMaxFunctions = 4096;
+constexpr uint64_t kNoAllocMaxBlocks = 1ull << 20;  // plain-kernel blocks of one function: N <= 2^30
+constexpr uint64_t align256(uint64_t x) { return (x + 255) & ~255ull; }
+static_assert(align256(kNoAllocMaxFunctions * sizeof(mc_function)) + kNoAllocMaxFunctions * sizeof(DevFn) +
+                      align256(kNoAllocMaxFunctions * sizeof(DevResult)) + kNoAllocMaxBlocks * sizeof(Partial) <=
+                  kScratchBytes,
+              "no-allocation working set");
+
+constexpr int kMaxScratchDevices = 256;
+std::mutex g_scratch_mu;
+uint8_t* g_scratch_dev[kMaxScratchDevices] = {};
+
+// Device address of `scratch` on device `dev`, which must be current; looked up
+// with hipGetSymbolAddress on the first call for that device, then cached.
+hipError_t scratch_address(int dev, uint8_t** out)
+{
+    if (dev < 0 || dev >= kMaxScratchDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (p == nullptr) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (uint8_t*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
+}
 
 constexpr int kLaunchSlots = 3;
 constexpr uint64_t kMaxSamples = 1ull << 40;
@@ -350,6 +391,7 @@ struct mc_ctx {
     uint64_t slot_bytes = 0;      // whole block
 
     // device memory
+    uint8_t* scratch = nullptr;   // device address of the static `scratch` array on this device
     bool owns_memory = true;
     void* mem_base = nullptr;
     uint64_t mem_bytes = 0;
@@ -1209,6 +1251,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             return fail(nullptr, MC_ERR_NO_DEVICE, "device %d is %s; this library is built for gfx950", cfg.device,
                         prop.gcnArchName);
         ctx->num_cus = prop.multiProcessorCount;
+        HIP_TRY(scratch_address(cfg.device, &ctx->scratch));
         int occ32 = 0, occ64 = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, batched_kernel_ptr(false), kBlockThreads, 0));
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ64, batched_kernel_ptr(true), kBlockThreads, 0));
@@ -1646,6 +1689,65 @@ mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n,
     if (d_parts) quiet(hipFree(d_parts));
     if (d_res) quiet(hipFree(d_res));
     return status;
+}
+
+mc_status mc_integrate_plain_fp64_noalloc(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out,
+                                          void* stream)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    if (!fns || !out || n == 0) return fail(ctx, MC_ERR_INVALID_ARG, "empty request or NULL argument");
+    if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    if (n > kNoAllocMaxFunctions)
+        return fail(ctx, MC_ERR_INVALID_ARG, "%zu functions exceed the no-allocation limit of %u", n,
+                    kNoAllocMaxFunctions);
+    uint64_t max_blocks = 1;
+    for (size_t i = 0; i < n; ++i) {
+        std::string why;
+        const mc_status st = validate_one(fns[i], 0, &why);  // built-in families only
+        if (st != MC_OK) return fail(ctx, st, "function %zu: %s", i, why.c_str());
+        const uint64_t blocks = ((fns[i].n_samples + 3) / 4 + 255) / 256;
+        if (blocks > kNoAllocMaxBlocks)
+            return fail(ctx, MC_ERR_INVALID_ARG, "function %zu: %llu samples exceed the no-allocation limit of 2^30", i,
+                        (unsigned long long)fns[i].n_samples);
+        max_blocks = std::max(max_blocks, blocks);
+    }
+    // working set in `scratch`: [caller's table | records | results | block partials]
+    const uint64_t rec_off = align256((uint64_t)n * sizeof(mc_function));
+    const uint64_t res_off = rec_off + (uint64_t)n * sizeof(DevFn);
+    const uint64_t part_off = res_off + align256((uint64_t)n * sizeof(DevResult));
+    if (part_off + max_blocks * sizeof(Partial) > kScratchBytes)
+        return fail(ctx, MC_ERR_INVALID_ARG, "no-allocation working set exceeds %llu bytes",
+                    (unsigned long long)kScratchBytes);
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        hipStream_t s = (hipStream_t)stream;
+        uint8_t* const base = ctx->scratch;
+        mc_function* d_table = (mc_function*)base;
+        DevFn* d_fns = (DevFn*)(base + rec_off);
+        DevResult* d_res = (DevResult*)(base + res_off);
+        Partial* d_parts = (Partial*)(base + part_off);
+        HIP_TRY(hipMemcpyAsync(d_table, fns, n * sizeof(mc_function), hipMemcpyHostToDevice, s));
+        uint32_t n32 = (uint32_t)n;
+        int32_t prec = MC_PREC_FP64;
+        void* pa[] = {&d_table, &n32, &prec, &d_fns};
+        HIP_TRY(hipLaunchKernel(pack_table_kernel_ptr(), dim3((n32 + 255) / 256), dim3(256), pa, 0, s));
+        // every block of the plain kernel writes its partial and the reduction
+        // reads exactly those: nothing in `scratch` has to start at zero
+        for (size_t i = 0; i < n; ++i) {
+            const DevFn* f = d_fns + i;
+            const uint32_t blocks = (uint32_t)(((fns[i].n_samples + 3) / 4 + 255) / 256);
+            void* a1[] = {&f, &d_parts};
+            HIP_TRY(hipLaunchKernel(plain_kernel_ptr(), dim3(blocks), dim3(256), a1, 0, s));
+            DevResult* r = d_res + i;
+            void* a2[] = {&f, &d_parts, (void*)&blocks, &r};
+            HIP_TRY(hipLaunchKernel(plain_reduce_kernel_ptr(), dim3(1), dim3(256), a2, 0, s));
+        }
+        HIP_TRY(hipMemcpyAsync(out, d_res, n * sizeof(DevResult), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    return MC_OK;
 }
 
 mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, uint64_t count, double* out,

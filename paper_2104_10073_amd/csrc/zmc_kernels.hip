@@ -151,6 +151,17 @@ extern "C" __global__ __launch_bounds__(256) void zmc_pack_grid(GridSpec spec, D
     pack_function(f, spec.precision, &out[i]);
 }
 
+// Records of a validated function table already in device memory, one thread
+// per function (the same packing code the host runs for tables).
+extern "C" __global__ __launch_bounds__(256) void zmc_pack_table(const mc_function* __restrict__ fns, uint32_t n,
+                                                                 int32_t precision, DevFn* __restrict__ out)
+{
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const mc_function f = fns[i];
+    pack_function(f, precision, &out[i]);
+}
+
 // The points of samples [first, first + count) of one function, row-major
 // (count x dim), from the batched kernels' generator and FP64 mapping: block
 // q*d + j of sample i = 4q + s gives coordinate j from its word s.
@@ -263,6 +274,7 @@ const void* plain_kernel_ptr() { return (const void*)zmc_plain_fp64; }
 const void* stage_kernel_ptr() { return (const void*)zmc_stage; }
 const void* publish_kernel_ptr() { return (const void*)zmc_publish; }
 const void* pack_grid_kernel_ptr() { return (const void*)zmc_pack_grid; }
+const void* pack_table_kernel_ptr() { return (const void*)zmc_pack_table; }
 const void* sample_points_kernel_ptr() { return (const void*)zmc_sample_points; }
 const void* finalize_kernel_ptr() { return (const void*)zmc_finalize; }
 const void* plain_reduce_kernel_ptr() { return (const void*)zmc_plain_reduce; }

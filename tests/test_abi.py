@@ -111,6 +111,9 @@ def test_validate_only_has_no_device_calls(Z):
     with pytest.raises(Z.McError) as e:
         c.plain_fp64(W.eq1_series(n_funcs=2))
     assert e.value.status == -9
+    with pytest.raises(Z.McError) as e:
+        c.plain_fp64_noalloc(W.eq1_series(n_funcs=2))
+    assert e.value.status == -9
     c.close()
 
 
