@@ -27,6 +27,11 @@
  *   - `stream` arguments are hipStream_t values passed as void* (NULL = the
  *     null stream).  Work is enqueued asynchronously on that stream.
  *   - A context is externally synchronized: one thread at a time.
+ *   - Testing aid for the error paths: MC_FAULT_HIP=n in the environment when a
+ *     context is created makes the n-th checked HIP runtime call the library
+ *     makes from then on report failure without being made (out of memory for
+ *     allocations, hipErrorUnknown otherwise), once; every mc_create re-arms
+ *     the countdown from the variable or, without it, disarms it.
  */
 #ifndef ZMC_H
 #define ZMC_H
@@ -175,7 +180,10 @@ mc_status mc_destroy(mc_ctx* ctx);
  * host memory; with no launch in flight it is uploaded at once on the library's
  * own upload stream, otherwise each record goes up with the stage kernel of the
  * first launch that runs that function.  A request that could never fit returns
- * MC_ERR_ADMISSION.  *out_request_id identifies it. */
+ * MC_ERR_ADMISSION.  *out_request_id identifies it.  Once validated the request
+ * is queued: if a HIP call of the admission tried at submit fails, the request
+ * stays queued, unadmitted, and the next mc_run tries again (and reports a
+ * failure that persists). */
 mc_status mc_submit(mc_ctx* ctx, const mc_function* fns, size_t n, int32_t precision,
                     uint64_t* out_request_id);
 
@@ -218,7 +226,9 @@ mc_status mc_submit_grid(mc_ctx* ctx, const mc_function* base, const mc_grid_axi
  * library reads completion from that mark, not from the stream).  Launches
  * nothing and returns MC_OK when no admitted work is pending, or MC_NOT_READY
  * when all launch slots are still in flight (call again later).  The stream
- * must stay valid until the launch has completed. */
+ * must stay valid until the launch has completed.  MC_ERR_HIP /
+ * MC_ERR_OUT_OF_MEMORY: a HIP call failed; what happens to the launch being
+ * built is described at mc_results. */
 mc_status mc_run(mc_ctx* ctx, void* stream);
 
 /* Ids of requests that completed since the previous call (their results can be
@@ -236,13 +246,16 @@ mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
  * blocking = 0: MC_NOT_READY if the request is not finished (runs are still
  * needed, or launched work has not completed).  blocking != 0: calls mc_run on
  * the null stream as needed and waits.  Results can be taken once; the
- * request's device resources are released when it completes.  If an mc_run
- * failed with MC_ERR_HIP after handing part of this request's work to its
- * launch (a kernel launch or stream wait refused), that work is lost: the
- * blocking call returns MC_ERR_HIP instead of waiting for it and releases the
- * request (its id is then unknown).  A failure to
- * create the launch's events or the slot's graph happens before any work is
- * handed over: the next mc_run launches the request as if nothing had happened. */
+ * request's device resources are released when it completes.
+ * After an mc_run that failed with MC_ERR_HIP: if the failure came before the
+ * launch's finalize kernel was handed to the stream, the launch is taken back
+ * (kernels already handed over are waited for) and every request is as it was:
+ * the next mc_run launches the same work, with bitwise the same results.  A
+ * failure from the finalize kernel on, or one after which the stream cannot be
+ * drained, loses the work of every request in that launch: those requests take
+ * no further launches, and mc_results (blocking or not) returns MC_ERR_HIP for
+ * them once no launch in flight refers to them, and releases them (their ids
+ * are then unknown). */
 mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking);
 
 /* Ask running persistent kernels to stop fetching tiles.  Every request submitted

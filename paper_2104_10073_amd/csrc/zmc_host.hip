@@ -14,6 +14,7 @@
 #include <time.h>
 
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstdarg>
@@ -121,10 +122,39 @@ inline void quiet(hipError_t e)
     if (e != hipSuccess) (void)hipGetLastError();
 }
 
-#define HIP_TRY(expr)                                   \
-    do {                                                \
-        hipError_t e_ = (expr);                         \
-        if (e_ != hipSuccess) throw HipError{e_, #expr}; \
+// Failure injection (a testing aid for the error paths): when a context is
+// created with MC_FAULT_HIP=n in the environment, the n-th checked HIP call the
+// library makes from then on (in any thread) reports failure without being
+// made: out of memory for allocations, hipErrorUnknown otherwise.  Each
+// mc_create re-arms the countdown from the variable, or disarms it when the
+// variable is absent or 0.  Unchecked calls (cleanup, completion polling) are
+// never failed.
+std::atomic<int64_t> g_fault_countdown{0};
+
+void arm_fault_injection()
+{
+    const char* v = std::getenv("MC_FAULT_HIP");
+    const long long n = v ? std::atoll(v) : 0;
+    g_fault_countdown.store(n > 0 ? (int64_t)n : 0, std::memory_order_relaxed);
+}
+
+inline bool fault_due()
+{
+    if (g_fault_countdown.load(std::memory_order_relaxed) <= 0) return false;
+    return g_fault_countdown.fetch_sub(1, std::memory_order_relaxed) == 1;
+}
+
+inline hipError_t injected_error(const char* what)
+{
+    return std::strncmp(what, "hipMalloc", 9) == 0 || std::strncmp(what, "hipHostMalloc", 13) == 0
+               ? hipErrorOutOfMemory
+               : hipErrorUnknown;
+}
+
+#define HIP_TRY(expr)                                                    \
+    do {                                                                 \
+        hipError_t e_ = fault_due() ? injected_error(#expr) : (expr);    \
+        if (e_ != hipSuccess) throw HipError{e_, #expr};                 \
     } while (0)
 
 // First-fit range allocator over [0, capacity) with coalescing free list.
@@ -310,6 +340,8 @@ struct Request {
     uint64_t tiles_total = 0, tiles_launched = 0;
     double work_left = 0.0;           // estimated cost of the tiles not yet launched
     bool aborted = false;
+    bool lost = false;                // part of its work went to a launch that failed after handing
+                                      // finalize records to kernels: it completes with MC_ERR_HIP
     uint32_t n_promoted = 0;
 };
 
@@ -322,6 +354,21 @@ struct HostRun {
 struct FinRef {
     Request* req;
     uint32_t index;
+};
+
+// What building a launch changes, kept so that a launch that fails before its
+// finalize kernel is enqueued can be taken back.
+struct TakeUndo {
+    Request* req;
+    uint32_t index;
+    uint32_t next_tile;
+    bool needs_upload;
+};
+struct RequestUndo {
+    Request* req;
+    uint32_t order_pos, redo_pos;
+    uint64_t tiles_launched;
+    double work_left;
 };
 
 // Timing events of one launch.  They are read once the runtime reports them
@@ -365,6 +412,7 @@ struct LaunchSlot {
     uint64_t n_samples = 0;             // integrand evaluations in this launch's tiles
     std::vector<FinRef> fin_refs;
     std::vector<Request*> touched;  // requests with tiles in this launch
+    std::vector<TakeUndo> undo;     // function states before this launch took their tiles
 };
 
 constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters (zero padded)
@@ -740,7 +788,7 @@ void reap(mc_ctx* ctx, int wait)
                 out.status = MC_ERR_HIP;
                 ctx->err = "a result came back in another precision than its function was scheduled in";
             }
-            if (out.status == MC_OK && !host_f64 && ctx->promote &&
+            if (out.status == MC_OK && !host_f64 && ctx->promote && !fr.req->lost &&
                 fp32_unresolved(out, fr.req->grid ? fp32_scale(fr.req->at(fr.index)) : fp32_scale(fr.req->fns[fr.index]))) {
                 promote_to_fp64(ctx, fr.req, fr.index);
                 continue;
@@ -802,29 +850,49 @@ void admit(mc_ctx* ctx)
             p += r->st[i].n_tiles;
         }
         r->admitted = true;  // from here on the slots are released with the request
-        if (r->grid) {
-            // records built on the device from the grid spec: no table crosses PCIe
-            if (idle) {
-                DevFn* out = ctx->d_fns + slot_off;
-                void* args[] = {&r->spec, &out};
-                HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256), args,
-                                        0, ctx->upload_stream));
-                r->grid_packed = true;
+        bool enqueued = false;
+        try {
+            if (r->grid) {
+                // records built on the device from the grid spec: no table crosses PCIe
+                if (idle) {
+                    DevFn* out = ctx->d_fns + slot_off;
+                    void* args[] = {&r->spec, &out};
+                    enqueued = true;
+                    HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((nf + 255) / 256)), dim3(256),
+                                            args, 0, ctx->upload_stream));
+                    r->grid_packed = true;
+                }
+            } else {
+                // records packed into the slots' part of the pinned mirror (whose
+                // previous uploads completed before those slots were released)
+                for (uint64_t i = 0; i < nf; ++i)
+                    pack_function(r->fns[i], r->st[i].f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL,
+                                  &ctx->h_fns[slot_off + i]);
+                if (idle) {
+                    enqueued = true;
+                    HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
+                                           hipMemcpyHostToDevice, ctx->upload_stream));
+                } else {
+                    for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = true;
+                }
             }
-        } else {
-            // records packed into the slots' part of the pinned mirror (whose
-            // previous uploads completed before those slots were released)
-            for (uint64_t i = 0; i < nf; ++i)
-                pack_function(r->fns[i], r->st[i].f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &ctx->h_fns[slot_off + i]);
-            if (idle)
-                HIP_TRY(hipMemcpyAsync(ctx->d_fns + slot_off, ctx->h_fns + slot_off, nf * sizeof(DevFn),
-                                       hipMemcpyHostToDevice, ctx->upload_stream));
-            else
-                for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = true;
-        }
-        if (idle) {
-            HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
-            HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+            if (idle) {
+                HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
+                HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
+            }
+        } catch (const HipError&) {
+            // the request stays first in the queue, unadmitted, and is admitted
+            // again later; an upload already handed to the stream finishes
+            // before its slots can be handed to anyone else
+            if (enqueued) quiet(hipStreamSynchronize(ctx->upload_stream));
+            if (r->uploaded) {
+                quiet(hipEventDestroy(r->uploaded));
+                r->uploaded = nullptr;
+            }
+            for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = false;
+            r->grid_packed = false;
+            free_request_resources(ctx, r);
+            throw;
         }
         ctx->pending.pop_front();
         ctx->active.push_back(r);
@@ -838,7 +906,9 @@ void capture_graph(mc_ctx* ctx, LaunchSlot& s);
 // launches bracket the batched kernels and the finalize with timing events; a
 // captured graph holds the kernels only and is timed as a whole from outside
 // (events recorded inside captured graphs are not reliable timing sources).
-void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events)
+// *progress: 1 once the stage kernel is handed to the stream, 2 once the
+// finalize kernel is (from then on the launch's finalize records are in use).
+void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events, int* progress)
 {
     LaunchDesc* dd = s.d_desc;
     void* args[] = {&dd};
@@ -852,6 +922,7 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
         DevFn* fns = ctx->d_fns;
         uint32_t n_fns = ctx->max_functions;
         void* sargs[] = {&src, &dst, &cap, &tile_cap, &mirror, &fns, &n_fns};
+        *progress = std::max(*progress, 1);
         HIP_TRY(hipLaunchKernel(stage_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(256), sargs, 0, stream));
     }
     EvSet* e = s.ev;
@@ -874,6 +945,7 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
                                           0, stream, args, nullptr));
         }
     if (events) HIP_TRY(hipEventRecord(e->main, stream));
+    *progress = 2;
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
     if (events) HIP_TRY(hipEventRecord(e->end, stream));
     HIP_TRY(hipLaunchKernel(publish_kernel_ptr(), dim3(1), dim3(1024), args, 0, stream));
@@ -888,18 +960,23 @@ void capture_graph(mc_ctx* ctx, LaunchSlot& s)
     hipStream_t cs;
     HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
     hipGraph_t g = nullptr;
+    bool capturing = false;
     try {
         HIP_TRY(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        enqueue_kernels(ctx, s, cs, false);
+        capturing = true;
+        int progress = 0;  // (nothing runs while capturing)
+        enqueue_kernels(ctx, s, cs, false, &progress);
+        capturing = false;
         HIP_TRY(hipStreamEndCapture(cs, &g));
         HIP_TRY(hipGraphInstantiate(&s.graph, g, nullptr, nullptr, 0));
     } catch (...) {
+        if (capturing) quiet(hipStreamEndCapture(cs, &g));  // leave capture mode before the stream goes
         if (g) quiet(hipGraphDestroy(g));
         quiet(hipStreamDestroy(cs));
         throw;
     }
     quiet(hipGraphDestroy(g));
-    HIP_TRY(hipStreamDestroy(cs));
+    quiet(hipStreamDestroy(cs));
 }
 
 // Put up to `budget` tiles of request r into launch slot s (functions in
@@ -922,6 +999,7 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         take = std::min<uint64_t>(take, budget - std::min(budget, taken));
         if (take > 0 && s.n_runs >= ctx->fin_cap) take = 0;  // run records are full
         if (take > 0) {
+            s.undo.push_back(TakeUndo{r, fi, fs.next_tile, fs.needs_upload});
             const uint64_t a = fs.next_tile, b = a + take;
             s.n_samples += std::min<uint64_t>(b * tile_samples, fn_samples) - a * tile_samples;
             HostRun hr;
@@ -959,6 +1037,63 @@ bool take_tiles(mc_ctx* ctx, LaunchSlot& s, Request* r, uint64_t budget)
         if (has_work(r) && taken >= budget) break;
     }
     return room;
+}
+
+// A launch whose enqueueing failed after it took its tiles.  Kernels it did
+// hand to the stream (progress > 0) are drained first, so that none of them
+// still reads the slot's blocks or writes partials when they are used again,
+// and the launch's sequence number, which its publish kernel may have stored
+// in the slot's done word, is never reused.  Before its finalize kernel was
+// enqueued (progress < 2) the take is undone: every request is as it was and
+// the next launch takes the same tiles, whose partials it rewrites with the
+// same values.  After that (finalize compacts partials in place), or if the
+// stream cannot be drained, the work of every request in the launch is lost:
+// those requests complete with MC_ERR_HIP and take no more launches.
+void abandon_launch(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, int progress,
+                    const std::vector<RequestUndo>& req_undo, const std::deque<Request*>& active_before)
+{
+    bool drained = true;
+    if (progress > 0) {
+        const hipError_t q = hipStreamSynchronize(stream);
+        quiet(q);
+        drained = q == hipSuccess;
+        ctx->launch_seq++;
+    }
+    if (progress < 2 && drained) {
+        for (auto it = s.undo.rbegin(); it != s.undo.rend(); ++it) {
+            FnState& fs = it->req->st[it->index];
+            fs.next_tile = it->next_tile;
+            fs.needs_upload = it->needs_upload;
+        }
+        for (const RequestUndo& u : req_undo) {
+            u.req->order_pos = u.order_pos;
+            u.req->redo_pos = u.redo_pos;
+            u.req->tiles_launched = u.tiles_launched;
+            u.req->work_left = u.work_left;
+        }
+        ctx->active = active_before;
+    } else {
+        std::vector<Request*> lost(s.touched.begin(), s.touched.end());
+        for (const FinRef& fr : s.fin_refs) lost.push_back(fr.req);
+        for (Request* r : lost) {
+            if (r->lost) continue;
+            r->lost = true;
+            r->order_pos = (uint32_t)r->order.size();
+            r->redo_pos = (uint32_t)r->redo.size();
+            r->tiles_launched = r->tiles_total;
+            r->work_left = 0.0;
+        }
+        std::deque<Request*> keep;
+        for (Request* r : ctx->active)
+            if (!r->lost) keep.push_back(r);
+        ctx->active.swap(keep);
+    }
+    s.n_tiles = s.n_fins = s.n_runs = 0;
+    for (auto& v : s.runs) v.clear();
+    s.fv.clear();
+    s.fin_refs.clear();
+    s.touched.clear();
+    s.undo.clear();
 }
 
 // Build and enqueue one launch.  Returns false if nothing was launched (no
@@ -1008,6 +1143,13 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     if (ctx->policy == MC_SCHED_SRPT)
         std::stable_sort(ctx->active.begin(), ctx->active.end(),
                          [](const Request* a, const Request* b) { return a->work_left < b->work_left; });
+    // what taking tiles changes, so that a launch that fails early can be taken back
+    const std::deque<Request*> active_before = ctx->active;
+    std::vector<RequestUndo> req_undo;
+    req_undo.reserve(ctx->active.size());
+    for (Request* r : ctx->active)
+        req_undo.push_back(RequestUndo{r, r->order_pos, r->redo_pos, r->tiles_launched, r->work_left});
+    s.undo.clear();
     std::deque<Request*> keep;
     for (Request* r : ctx->active) {
         if (has_work(r)) take_tiles(ctx, s, r, share);
@@ -1018,107 +1160,119 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
         ctx->ev_free.push_back(evp);
         return false;
     }
-    // stage: finalize records after the descriptor, then the tile runs; the
-    // stage kernel expands the runs into the device tile list, the kernels'
-    // parts one after another
-    uint8_t* const hdesc = s.h_block + ctx->slot_res_bytes;
-    uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
-    Fin* const hfins = (Fin*)(hdesc + kDescBytes);
-    TileRun* const hruns = (TileRun*)(hfins + s.n_fins);
-    if (s.n_fins) std::memcpy(hfins, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
-    {
-        // Within a kernel's part, functions' runs go in descending tile cost, so
-        // the last tiles each workgroup fetches are the cheapest (a short tail).
-        // Results do not depend on the order.
-        uint32_t off = 0, nr = 0;
-        for (int k = 0; k < kMaxKernels; ++k) {
-            s.tile_begin[k] = off;
-            std::vector<HostRun>& rr = s.runs[k];
-            std::stable_sort(rr.begin(), rr.end(), [](const HostRun& a, const HostRun& b) { return a.cost > b.cost; });
-            for (HostRun& hr : rr) {
-                hr.run.dst = off;
-                hruns[nr++] = hr.run;
-                off += hr.run.count;
+    int progress = 0;  // 1: kernels of this launch are in the stream; 2: its finalize kernel is too
+    try {
+        // stage: finalize records after the descriptor, then the tile runs; the
+        // stage kernel expands the runs into the device tile list, the kernels'
+        // parts one after another
+        uint8_t* const hdesc = s.h_block + ctx->slot_res_bytes;
+        uint8_t* const ddesc = s.d_block + ctx->slot_res_bytes;
+        Fin* const hfins = (Fin*)(hdesc + kDescBytes);
+        TileRun* const hruns = (TileRun*)(hfins + s.n_fins);
+        if (s.n_fins) std::memcpy(hfins, s.fv.data(), (size_t)s.n_fins * sizeof(Fin));
+        {
+            // Within a kernel's part, functions' runs go in descending tile cost, so
+            // the last tiles each workgroup fetches are the cheapest (a short tail).
+            // Results do not depend on the order.
+            uint32_t off = 0, nr = 0;
+            for (int k = 0; k < kMaxKernels; ++k) {
+                s.tile_begin[k] = off;
+                std::vector<HostRun>& rr = s.runs[k];
+                std::stable_sort(rr.begin(), rr.end(), [](const HostRun& a, const HostRun& b) { return a.cost > b.cost; });
+                for (HostRun& hr : rr) {
+                    hr.run.dst = off;
+                    hruns[nr++] = hr.run;
+                    off += hr.run.count;
+                }
+                s.tile_count[k] = off - s.tile_begin[k];
             }
-            s.tile_count[k] = off - s.tile_begin[k];
         }
-    }
 
-    // Launches may be enqueued on different streams; a function's tiles can span
-    // launches, so each launch waits for the previous one, and for the uploads
-    // of the function tables it reads.
-    // (A launch on the same stream is ordered already: a cross-stream wait on an
-    // event of the same stream only adds latency.)
-    for (auto& o : ctx->slots)
-        if (&o != &s && o.in_flight && o.seq == ctx->launch_seq && o.stream != stream)
-            HIP_TRY(hipStreamWaitEvent(stream, o.ev->done, 0));
-    for (Request* r : s.touched) {
-        if (!r->uploaded) continue;
-        const hipError_t q = hipEventQuery(r->uploaded);
-        if (q == hipSuccess) {  // upload finished: nothing to wait for from now on
-            quiet(hipEventDestroy(r->uploaded));
-            r->uploaded = nullptr;
-        } else {
-            quiet(q);
-            if (q != hipErrorNotReady) throw HipError{q, "hipEventQuery(upload)"};
-            HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
+        // Launches may be enqueued on different streams; a function's tiles can span
+        // launches, so each launch waits for the previous one, and for the uploads
+        // of the function tables it reads.
+        // (A launch on the same stream is ordered already: a cross-stream wait on an
+        // event of the same stream only adds latency.)
+        {
+            const LaunchSlot* newest = nullptr;
+            for (const auto& o : ctx->slots)
+                if (&o != &s && o.in_flight && (!newest || o.seq > newest->seq)) newest = &o;
+            if (newest && newest->stream != stream) HIP_TRY(hipStreamWaitEvent(stream, newest->ev->done, 0));
         }
+        for (Request* r : s.touched) {
+            if (!r->uploaded) continue;
+            const hipError_t q = hipEventQuery(r->uploaded);
+            if (q == hipSuccess) {  // upload finished: nothing to wait for from now on
+                quiet(hipEventDestroy(r->uploaded));
+                r->uploaded = nullptr;
+            } else {
+                quiet(q);
+                if (q != hipErrorNotReady) throw HipError{q, "hipEventQuery(upload)"};
+                HIP_TRY(hipStreamWaitEvent(stream, r->uploaded, 0));
+            }
+        }
+        // grids admitted while launches were in flight: their records are built in
+        // this stream, before the stage kernel (and any graph) reads them
+        for (Request* r : s.touched) {
+            if (!r->grid || r->grid_packed) continue;
+            DevFn* out = ctx->d_fns + r->slot_base;
+            void* args[] = {&r->spec, &out};
+            progress = std::max(progress, 1);
+            HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((r->n + 255) / 256)), dim3(256), args, 0,
+                                    stream));
+            r->grid_packed = true;
+        }
+        EvSet& ev = *evp;
+        s.ev = &ev;
+        const uint64_t seq = ctx->launch_seq + 1;
+        uint8_t* const hdesc_dev = s.h_block_dev + ctx->slot_res_bytes;
+        LaunchDesc* hd = (LaunchDesc*)hdesc;
+        std::memset(hdesc, 0, kDescBytes);
+        hd->stage_bytes = kDescBytes + (uint64_t)s.n_fins * sizeof(Fin);
+        hd->n_runs = s.n_runs;
+        hd->runs_off = (uint32_t)(kDescBytes + (uint64_t)s.n_fins * sizeof(Fin));
+        hd->fns = ctx->d_fns;
+        hd->tiles = (const Tile*)(ddesc + kDescBytes + (uint64_t)ctx->fin_cap * sizeof(Fin));
+        hd->partials = ctx->d_partials;
+        hd->fins = (const Fin*)(ddesc + kDescBytes);
+        hd->results = (DevResult*)ddesc - s.n_fins;
+        hd->host_results = (DevResult*)hdesc_dev - s.n_fins;
+        hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));
+        hd->host_counters = (uint32_t*)(hdesc_dev + sizeof(LaunchDesc));
+        hd->host_done = ctx->h_done_dev + 16 * (&s - ctx->slots);
+        hd->seq = (uint32_t)seq;
+        hd->abort_word = ctx->d_abort_word;
+        hd->n_partials = ctx->max_partials;
+        hd->n_fns = ctx->max_functions;
+        for (int k = 0; k < kMaxKernels; ++k) {
+            hd->tile_begin[k] = s.tile_begin[k];
+            hd->tile_count[k] = s.tile_count[k];
+        }
+        hd->n_fins = s.n_fins;
+        s.stream = stream;
+        // a launch graph holds the built-in kernels only: with run-time families
+        // registered, launches are enqueued directly
+        s.graphed = ctx->use_graph && ctx->n_user == 0;
+        ev.graphed = s.graphed;
+        if (s.graphed) {
+            if (!s.graph) capture_graph(ctx, s);
+            HIP_TRY(hipEventRecord(ev.start, stream));
+            progress = 2;  // a graph launch hands every kernel over at once
+            HIP_TRY(hipGraphLaunch(s.graph, stream));
+            HIP_TRY(hipEventRecord(ev.end, stream));
+        } else {
+            enqueue_kernels(ctx, s, stream, true, &progress);
+        }
+        // (orders launches on other streams after this one; completion itself is
+        // read from the done word)
+        HIP_TRY(hipEventRecord(ev.done, stream));
+    } catch (const HipError&) {
+        abandon_launch(ctx, s, stream, progress, req_undo, active_before);
+        ctx->ev_free.push_back(evp);
+        throw;
     }
-    // grids admitted while launches were in flight: their records are built in
-    // this stream, before the stage kernel (and any graph) reads them
-    for (Request* r : s.touched) {
-        if (!r->grid || r->grid_packed) continue;
-        DevFn* out = ctx->d_fns + r->slot_base;
-        void* args[] = {&r->spec, &out};
-        HIP_TRY(hipLaunchKernel(pack_grid_kernel_ptr(), dim3((unsigned)((r->n + 255) / 256)), dim3(256), args, 0,
-                                stream));
-        r->grid_packed = true;
-    }
-    EvSet& ev = *evp;
-    s.ev = &ev;
-    const uint64_t seq = ctx->launch_seq + 1;
-    uint8_t* const hdesc_dev = s.h_block_dev + ctx->slot_res_bytes;
-    LaunchDesc* hd = (LaunchDesc*)hdesc;
-    std::memset(hdesc, 0, kDescBytes);
-    hd->stage_bytes = kDescBytes + (uint64_t)s.n_fins * sizeof(Fin);
-    hd->n_runs = s.n_runs;
-    hd->runs_off = (uint32_t)(kDescBytes + (uint64_t)s.n_fins * sizeof(Fin));
-    hd->fns = ctx->d_fns;
-    hd->tiles = (const Tile*)(ddesc + kDescBytes + (uint64_t)ctx->fin_cap * sizeof(Fin));
-    hd->partials = ctx->d_partials;
-    hd->fins = (const Fin*)(ddesc + kDescBytes);
-    hd->results = (DevResult*)ddesc - s.n_fins;
-    hd->host_results = (DevResult*)hdesc_dev - s.n_fins;
-    hd->counters = (uint32_t*)(ddesc + sizeof(LaunchDesc));
-    hd->host_counters = (uint32_t*)(hdesc_dev + sizeof(LaunchDesc));
-    hd->host_done = ctx->h_done_dev + 16 * (&s - ctx->slots);
-    hd->seq = (uint32_t)seq;
-    hd->abort_word = ctx->d_abort_word;
-    hd->n_partials = ctx->max_partials;
-    hd->n_fns = ctx->max_functions;
-    for (int k = 0; k < kMaxKernels; ++k) {
-        hd->tile_begin[k] = s.tile_begin[k];
-        hd->tile_count[k] = s.tile_count[k];
-    }
-    hd->n_fins = s.n_fins;
-    s.stream = stream;
-    // a launch graph holds the built-in kernels only: with run-time families
-    // registered, launches are enqueued directly
-    s.graphed = ctx->use_graph && ctx->n_user == 0;
-    ev.graphed = s.graphed;
-    if (s.graphed) {
-        if (!s.graph) capture_graph(ctx, s);
-        HIP_TRY(hipEventRecord(ev.start, stream));
-        HIP_TRY(hipGraphLaunch(s.graph, stream));
-        HIP_TRY(hipEventRecord(ev.end, stream));
-    } else {
-        enqueue_kernels(ctx, s, stream, true);
-    }
-    // (orders launches on other streams after this one; completion itself is
-    // read from the done word)
-    HIP_TRY(hipEventRecord(ev.done, stream));
-    ev.pending = true;
-    ctx->ev_pending.push_back(&ev);
+    evp->pending = true;
+    ctx->ev_pending.push_back(evp);
     s.in_flight = true;
     s.seq = ++ctx->launch_seq;
     return true;
@@ -1240,6 +1394,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         *out = ctx.release();
         return MC_OK;
     }
+    arm_fault_injection();
     try {
         int ndev = 0;
         if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= cfg.device || cfg.device < 0)
@@ -1273,8 +1428,15 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             ctx->owns_memory = false;
             ctx->mem_base = cfg.workspace;
         } else {
-            if (hipMalloc(&ctx->mem_base, L.total) != hipSuccess)
-                return fail(nullptr, MC_ERR_OUT_OF_MEMORY, "hipMalloc of %llu bytes failed", (unsigned long long)L.total);
+            const hipError_t e = fault_due() ? hipErrorOutOfMemory : hipMalloc(&ctx->mem_base, L.total);
+            if (e != hipSuccess) {
+                quiet(e);
+                ctx->mem_base = nullptr;
+                mc_status st = fail(nullptr, MC_ERR_OUT_OF_MEMORY, "hipMalloc of %llu bytes failed",
+                                    (unsigned long long)L.total);
+                destroy_device(ctx.get());
+                return st;
+            }
         }
         ctx->mem_bytes = L.total;
         uint8_t* base = (uint8_t*)ctx->mem_base;
@@ -1424,11 +1586,13 @@ mc_status enqueue_request(mc_ctx* ctx, std::unique_ptr<Request> r, uint64_t* out
     ctx->requests.emplace(rq->id, std::move(r));
     if (!ctx->validate_only) {
         ctx->pending.push_back(rq);
+        // The request is queued.  Admission is tried at once; if a HIP call of it
+        // fails, the requests it was admitting stay queued as they were and the
+        // next mc_run (which reports such failures) tries again.
         try {
             HIP_TRY(hipSetDevice(ctx->device));
             admit(ctx);
-        } catch (const HipError& e) {
-            return fail_hip(ctx, e);
+        } catch (const HipError&) {
         }
     }
     return MC_OK;
@@ -1601,6 +1765,14 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
         HIP_TRY(hipSetDevice(ctx->device));
         reap(ctx, 0);
         while (r->fns_done < r->count()) {
+            if (r->lost && !any_in_flight(ctx)) {
+                // part of its work was lost with a failed launch; nothing in flight
+                // refers to it any more, so it is released
+                free_request_resources(ctx, r);
+                ctx->requests.erase(it);
+                return fail(ctx, MC_ERR_HIP, "request %llu cannot complete: its work was in a launch that failed",
+                            (unsigned long long)request_id);
+            }
             if (!blocking) return MC_NOT_READY;
             if (r->tiles_launched < r->tiles_total || has_work(r) || !r->admitted) {
                 mc_status st = mc_run(ctx, nullptr);

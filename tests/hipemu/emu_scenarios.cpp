@@ -1,0 +1,512 @@
+// emu_scenarios.cpp -- the library's host runtime driven through its C ABI on
+// the CPU emulation of HIP (test infrastructure only; see hipemu.cpp).
+//
+// Usage: emu_scenarios <scenario> ...   (or "all").  Prints "ok <scenario>" per
+// passing scenario; exits non-zero on the first failure.  Every result the
+// library reports as MC_OK is compared field by field with the result the
+// emulation defines for that function (hipemu::expected_batched / plain).
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "hipemu.hpp"
+#include "zmc.h"
+
+namespace {
+
+int g_failures = 0;
+
+#define CHECK(cond, ...)                                                          \
+    do {                                                                          \
+        if (!(cond)) {                                                            \
+            std::fprintf(stderr, "%s:%d: check failed: %s: ", __FILE__, __LINE__, #cond); \
+            std::fprintf(stderr, __VA_ARGS__);                                    \
+            std::fprintf(stderr, "\n");                                           \
+            ++g_failures;                                                         \
+            return false;                                                         \
+        }                                                                         \
+    } while (0)
+
+// A function of one of the built-in families on a box, amplitude 1 unless given.
+mc_function make_fn(uint32_t family, uint32_t dim, uint64_t n, uint64_t seed, double amp = 1.0)
+{
+    mc_function f;
+    std::memset(&f, 0, sizeof f);
+    f.family = family;
+    f.dim = dim;
+    f.n_samples = n;
+    f.seed = seed;
+    for (uint32_t j = 0; j < dim; ++j) {
+        f.lo[j] = -0.5 + 0.1 * j;
+        f.hi[j] = f.lo[j] + 1.0 + 0.05 * j;
+    }
+    f.params[0] = amp;
+    switch (family) {
+    case MC_FAMILY_HARMONIC:
+        f.params[1] = 0.0;
+        for (uint32_t j = 0; j < dim; ++j) f.params[MC_PARAM_V0 + j] = 2.0 + j;
+        break;
+    case MC_FAMILY_ABS_LINEAR:
+        f.params[1] = 0.25;
+        for (uint32_t j = 0; j < dim; ++j) f.params[MC_PARAM_V0 + j] = (j & 1) ? -1.0 : 1.0;
+        break;
+    case MC_FAMILY_GAUSSIAN:
+        f.params[1] = 0.5;
+        for (uint32_t j = 0; j < dim; ++j) f.params[MC_PARAM_V0 + j] = 0.1;
+        break;
+    default:
+        f.params[0] = 0.0;
+        for (uint32_t j = 0; j < dim; ++j) {
+            f.params[MC_PARAM_V0 + j] = 0.5;
+            f.params[MC_PARAM_W0 + j] = 1 + j % 4;
+        }
+        break;
+    }
+    return f;
+}
+
+// A mixed table: every family, dimensions 1..12, sizes from 2 samples to several
+// segments and tiles with ragged tails.  Rows with `constant_every` > 0 and
+// index % constant_every == 1 have seed bit 63 set (constant in the emulated
+// FP32 kernel, so an FP32 request promotes them).
+std::vector<mc_function> mixed_table(size_t n, uint64_t base, size_t constant_every = 0)
+{
+    static const uint64_t sizes[] = {2, 3, 5, 64, 4095, 4096, 4097, 16385, 70001, 300003, 1000001};
+    std::vector<mc_function> t;
+    for (size_t i = 0; i < n; ++i) {
+        uint64_t seed = (base << 32) | i;
+        if (constant_every && i % constant_every == 1) seed |= 1ull << 63;
+        t.push_back(make_fn((uint32_t)(i % 4), 1 + (uint32_t)(i % 12), sizes[(i * 7) % 11], seed));
+    }
+    return t;
+}
+
+bool same_result(const mc_result& a, const mc_result& b)
+{
+    return std::memcmp(&a, &b, sizeof a) == 0;
+}
+
+// Results of an FP32 (fp64 = false) or FP64 request against the emulation's values.
+bool check_results(const std::vector<mc_function>& t, const std::vector<mc_result>& r, bool fp64, const char* label)
+{
+    CHECK(t.size() == r.size(), "%s: sizes", label);
+    for (size_t i = 0; i < t.size(); ++i) {
+        const bool promoted = !fp64 && (t[i].seed >> 63) != 0;
+        const mc_result want = hipemu::expected_batched(t[i], fp64 || promoted);
+        CHECK(same_result(r[i], want), "%s: function %zu: got (%.17g, %.17g, %.17g, n %llu, status %d, prec %u) "
+              "want (%.17g, %.17g, %.17g, prec %u)", label, i, r[i].mean, r[i].sum_f, r[i].sum_f2,
+              (unsigned long long)r[i].n, r[i].status, r[i].precision, want.mean, want.sum_f, want.sum_f2,
+              want.precision);
+    }
+    return true;
+}
+
+mc_ctx* create(uint32_t flags, uint32_t max_tiles = 0, uint32_t policy = MC_SCHED_FAIR, uint32_t max_functions = 0,
+               uint64_t max_partials = 0)
+{
+    mc_config cfg;
+    mc_config_init(&cfg);
+    cfg.flags = flags;
+    cfg.max_tiles_per_run = max_tiles;
+    cfg.policy = policy;
+    cfg.max_functions = max_functions;
+    cfg.max_partials = max_partials;
+    mc_ctx* ctx = nullptr;
+    if (mc_create(&cfg, &ctx) != MC_OK) return nullptr;
+    return ctx;
+}
+
+bool run_request(mc_ctx* ctx, const std::vector<mc_function>& t, bool fp64, const char* label)
+{
+    uint64_t id = 0;
+    CHECK(mc_submit(ctx, t.data(), t.size(), fp64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id) == MC_OK, "%s: %s", label,
+          mc_last_error(ctx));
+    std::vector<mc_result> r(t.size());
+    CHECK(mc_results(ctx, id, r.data(), r.size(), 1) == MC_OK, "%s: %s", label, mc_last_error(ctx));
+    return check_results(t, r, fp64, label);
+}
+
+// ---------------------------------------------------------------- scenarios
+
+bool basic()
+{
+    for (uint32_t flags : {0u, (uint32_t)MC_NO_GRAPH}) {
+        mc_ctx* ctx = create(flags);
+        CHECK(ctx, "create");
+        const std::vector<mc_function> t = mixed_table(60, 1, 7);
+        if (!run_request(ctx, t, false, "fp32") || !run_request(ctx, t, true, "fp64")) return false;
+        mc_stats st;
+        CHECK(mc_get_stats(ctx, &st) == MC_OK && st.bad_records == 0, "stats");
+        CHECK(st.promoted == 9, "promoted %llu", (unsigned long long)st.promoted);
+        mc_destroy(ctx);
+    }
+    return true;
+}
+
+// Launches of a few tiles each: functions span many launches, under every policy.
+bool many_launches()
+{
+    for (uint32_t policy : {MC_SCHED_FAIR, MC_SCHED_FIFO, MC_SCHED_SRPT})
+        for (uint32_t flags : {0u, (uint32_t)MC_NO_GRAPH}) {
+            mc_ctx* ctx = create(flags, 5, policy);
+            CHECK(ctx, "create");
+            std::vector<std::vector<mc_function>> reqs = {mixed_table(12, 2, 5), mixed_table(3, 3), mixed_table(30, 4)};
+            std::vector<uint64_t> ids;
+            for (size_t k = 0; k < reqs.size(); ++k) {
+                uint64_t id = 0;
+                CHECK(mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id) ==
+                          MC_OK, "submit");
+                ids.push_back(id);
+            }
+            // drive with mc_run / mc_poll only, as a serving loop would
+            std::map<uint64_t, bool> done;
+            for (int guard = 0; guard < 100000 && done.size() < ids.size(); ++guard) {
+                const mc_status st = mc_run(ctx, nullptr);
+                CHECK(st == MC_OK || st == MC_NOT_READY, "run %d: %s", (int)st, mc_last_error(ctx));
+                uint64_t got[8];
+                size_t n = 0;
+                CHECK(mc_poll(ctx, got, 8, &n) == MC_OK, "poll");
+                for (size_t i = 0; i < n; ++i) done[got[i]] = true;
+            }
+            CHECK(done.size() == ids.size(), "requests did not all complete");
+            for (size_t k = 0; k < reqs.size(); ++k) {
+                std::vector<mc_result> r(reqs[k].size());
+                CHECK(mc_results(ctx, ids[k], r.data(), r.size(), 0) == MC_OK, "results");
+                if (!check_results(reqs[k], r, k == 1, "many launches")) return false;
+            }
+            uint64_t pr = 1, pt = 1;
+            CHECK(mc_pending(ctx, &pr, &pt) == MC_OK && pr == 0 && pt == 0, "pending %llu %llu", (unsigned long long)pr,
+                  (unsigned long long)pt);
+            mc_destroy(ctx);
+        }
+    return true;
+}
+
+// Requests wait for function slots and partial space; ones that never fit are refused.
+bool admission()
+{
+    mc_ctx* ctx = create(0, 64, MC_SCHED_FIFO, 16, 400);  // one request of 10 at a time
+    CHECK(ctx, "create");
+    std::vector<std::vector<mc_function>> reqs;
+    std::vector<uint64_t> ids;
+    for (int k = 0; k < 6; ++k) {
+        reqs.push_back(mixed_table(10, 10 + k));
+        uint64_t id = 0;
+        CHECK(mc_submit(ctx, reqs.back().data(), 10, MC_PREC_FP32_EVAL, &id) == MC_OK, "submit %d: %s", k,
+              mc_last_error(ctx));
+        ids.push_back(id);
+    }
+    uint64_t id = 0;
+    const std::vector<mc_function> big = mixed_table(17, 30);
+    CHECK(mc_submit(ctx, big.data(), big.size(), MC_PREC_FP32_EVAL, &id) == MC_ERR_ADMISSION, "17 functions");
+    std::vector<mc_function> wide(1, make_fn(MC_FAMILY_HARMONIC, 2, 401ull * 4 * 4096, 5));
+    CHECK(mc_submit(ctx, wide.data(), 1, MC_PREC_FP32_EVAL, &id) == MC_ERR_ADMISSION, "401 partials");
+    for (size_t k = ids.size(); k-- > 0;) {  // newest first: blocking calls drive the queue
+        std::vector<mc_result> r(10);
+        CHECK(mc_results(ctx, ids[k], r.data(), 10, 1) == MC_OK, "results %zu: %s", k, mc_last_error(ctx));
+        if (!check_results(reqs[k], r, false, "admission")) return false;
+    }
+    mc_destroy(ctx);
+    return true;
+}
+
+bool grid()
+{
+    mc_ctx* ctx = create(0, 9);
+    CHECK(ctx, "create");
+    const mc_function base = make_fn(MC_FAMILY_HARMONIC, 3, 50001, 7ull << 32, 1.5);
+    mc_grid_axis axes[2] = {{MC_PARAM_V0, 5, 1.0, 0.5}, {0, 3, 0.5, 0.25}};
+    for (int prec : {MC_PREC_FP32_EVAL, MC_PREC_FP64}) {
+        uint64_t id = 0;
+        CHECK(mc_submit_grid(ctx, &base, axes, 2, prec, &id) == MC_OK, "grid: %s", mc_last_error(ctx));
+        std::vector<mc_result> r(15);
+        CHECK(mc_results(ctx, id, r.data(), 15, 1) == MC_OK, "grid results");
+        std::vector<mc_function> t;
+        for (uint64_t i = 0; i < 15; ++i) {
+            mc_function f = base;
+            f.params[MC_PARAM_V0] = 1.0 + (double)(i % 5) * 0.5;
+            f.params[0] = 0.5 + (double)(i / 5) * 0.25;
+            f.seed = base.seed + i;
+            t.push_back(f);
+        }
+        if (!check_results(t, r, prec == MC_PREC_FP64, "grid")) return false;
+    }
+    mc_destroy(ctx);
+    return true;
+}
+
+bool abort_and_continue()
+{
+    mc_ctx* ctx = create(MC_NO_GRAPH, 4);
+    CHECK(ctx, "create");
+    const std::vector<mc_function> t = mixed_table(24, 40);
+    uint64_t id = 0;
+    CHECK(mc_submit(ctx, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+    CHECK(mc_run(ctx, nullptr) == MC_OK, "run");
+    CHECK(mc_abort(ctx) == MC_OK, "abort");
+    std::vector<mc_result> r(t.size());
+    CHECK(mc_results(ctx, id, r.data(), r.size(), 1) == MC_ERR_ABORTED, "aborted request");
+    size_t ok = 0;
+    for (size_t i = 0; i < t.size(); ++i) {
+        if (r[i].status == MC_OK) {
+            ++ok;
+            CHECK(same_result(r[i], hipemu::expected_batched(t[i], false)), "finished before the abort: %zu", i);
+        } else {
+            CHECK(r[i].status == MC_ERR_ABORTED, "status %d", r[i].status);
+        }
+    }
+    CHECK(ok < t.size(), "nothing was aborted");
+    if (!run_request(ctx, mixed_table(8, 41), false, "after abort")) return false;
+    mc_destroy(ctx);
+    return true;
+}
+
+bool errors()
+{
+    mc_ctx* ctx = create(0);
+    CHECK(ctx, "create");
+    std::vector<mc_function> t = mixed_table(5, 50);
+    uint64_t id = 0;
+    struct Bad {
+        int field;
+        mc_status code;
+    } bads[] = {{0, MC_ERR_BAD_DIM}, {1, MC_ERR_BAD_BOUNDS}, {2, MC_ERR_BAD_PARAMS}, {3, MC_ERR_INVALID_ARG},
+                {4, MC_ERR_UNSUPPORTED_FAMILY}};
+    for (const Bad& b : bads) {
+        std::vector<mc_function> u = t;
+        switch (b.field) {
+        case 0: u[3].dim = 13; break;
+        case 1: u[3].hi[0] = u[3].lo[0]; break;
+        case 2: u[3].params[20] = NAN; break;
+        case 3: u[3].n_samples = 1; break;
+        default: u[3].family = 9; break;
+        }
+        CHECK(mc_submit(ctx, u.data(), u.size(), MC_PREC_FP32_EVAL, &id) == b.code, "invalid field %d", b.field);
+        CHECK(std::strstr(mc_last_error(ctx), "function 3") != nullptr, "message names the row: %s", mc_last_error(ctx));
+    }
+    CHECK(mc_submit(ctx, t.data(), t.size(), 7, &id) == MC_ERR_INVALID_ARG, "precision");
+    CHECK(mc_submit(ctx, t.data(), 0, MC_PREC_FP64, &id) == MC_ERR_INVALID_ARG, "empty");
+    std::vector<mc_result> r(t.size());
+    CHECK(mc_results(ctx, 12345, r.data(), r.size(), 1) == MC_ERR_UNKNOWN_REQUEST, "unknown id");
+    CHECK(mc_submit(ctx, t.data(), t.size(), MC_PREC_FP64, &id) == MC_OK, "submit");
+    CHECK(mc_results(ctx, id, r.data(), r.size() - 1, 1) == MC_ERR_INVALID_ARG, "wrong n");
+    CHECK(mc_results(ctx, id, r.data(), r.size(), 1) == MC_OK, "results");
+    CHECK(mc_results(ctx, id, r.data(), r.size(), 1) == MC_ERR_UNKNOWN_REQUEST, "taken twice");
+    uint32_t fam = 0;
+    CHECK(mc_register_family(ctx, "template <class T> __device__ T mc_user_integrand(const T*, const T*, uint32_t)"
+                                  " { return T(1); }", &fam) == MC_ERR_COMPILE, "no compiler in the emulation");
+    mc_destroy(ctx);
+    mc_config cfg;
+    mc_config_init(&cfg);
+    cfg.policy = 3;
+    mc_ctx* bad = nullptr;
+    CHECK(mc_create(&cfg, &bad) == MC_ERR_INVALID_ARG && bad == nullptr, "policy");
+    mc_ctx* v = create(MC_VALIDATE_ONLY);
+    CHECK(v, "validate-only");
+    CHECK(mc_submit(v, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "validate-only submit");
+    CHECK(mc_run(v, nullptr) == MC_ERR_NO_DEVICE, "validate-only run");
+    mc_destroy(v);
+    return true;
+}
+
+bool plain_paths()
+{
+    mc_ctx* ctx = create(0);
+    CHECK(ctx, "create");
+    for (size_t n : {40, 7}) {  // a smaller table second: the fixed array keeps the first call's contents
+        const std::vector<mc_function> t = mixed_table(n, 60 + n);
+        std::vector<mc_result> a(n), b(n);
+        CHECK(mc_integrate_plain_fp64(ctx, t.data(), n, a.data(), nullptr) == MC_OK, "plain: %s", mc_last_error(ctx));
+        CHECK(mc_integrate_plain_fp64_noalloc(ctx, t.data(), n, b.data(), nullptr) == MC_OK, "noalloc: %s",
+              mc_last_error(ctx));
+        for (size_t i = 0; i < n; ++i) {
+            const mc_result want = hipemu::expected_plain(t[i]);
+            CHECK(same_result(a[i], want) && same_result(b[i], want), "plain function %zu", i);
+        }
+    }
+    std::vector<mc_function> over(4097, make_fn(MC_FAMILY_HARMONIC, 1, 10, 1));
+    std::vector<mc_result> r(4097);
+    CHECK(mc_integrate_plain_fp64_noalloc(ctx, over.data(), over.size(), r.data(), nullptr) == MC_ERR_INVALID_ARG,
+          "4097 functions");
+    over.resize(2);
+    over[1].n_samples = (1ull << 30) + 1;
+    CHECK(mc_integrate_plain_fp64_noalloc(ctx, over.data(), 2, r.data(), nullptr) == MC_ERR_INVALID_ARG, "2^30 + 1");
+    mc_destroy(ctx);
+    return true;
+}
+
+bool two_contexts()
+{
+    mc_ctx* a = create(0, 6);
+    mc_ctx* b = create(MC_NO_GRAPH, 11, MC_SCHED_SRPT);
+    CHECK(a && b, "create");
+    const std::vector<mc_function> ta = mixed_table(20, 70), tb = mixed_table(25, 71, 3);
+    uint64_t ia = 0, ib = 0;
+    CHECK(mc_submit(a, ta.data(), ta.size(), MC_PREC_FP32_EVAL, &ia) == MC_OK, "submit a");
+    CHECK(mc_submit(b, tb.data(), tb.size(), MC_PREC_FP32_EVAL, &ib) == MC_OK, "submit b");
+    for (int i = 0; i < 3; ++i) {
+        CHECK(mc_run(a, nullptr) != MC_ERR_HIP && mc_run(b, nullptr) != MC_ERR_HIP, "run");
+    }
+    std::vector<mc_result> ra(ta.size()), rb(tb.size());
+    CHECK(mc_results(b, ib, rb.data(), rb.size(), 1) == MC_OK, "b");
+    CHECK(mc_results(a, ia, ra.data(), ra.size(), 1) == MC_OK, "a");
+    if (!check_results(ta, ra, false, "context a") || !check_results(tb, rb, false, "context b")) return false;
+    mc_destroy(a);
+    mc_destroy(b);
+    return true;
+}
+
+// One run of the failure-injection workload: three requests (FP32 with promoted
+// rows, FP64, a grid) in launches of a few tiles, driven by mc_run and
+// non-blocking mc_results.  Every call may fail; a request that returns MC_OK
+// must hold exactly the expected results, every other one must end with
+// MC_ERR_HIP or MC_ERR_OUT_OF_MEMORY.  *clean: nothing failed.
+bool fault_workload(uint32_t flags, bool* clean)
+{
+    *clean = true;
+    mc_ctx* ctx = create(flags, 6, MC_SCHED_FAIR, 64, 4096);
+    if (!ctx) {
+        *clean = false;
+        const std::string e = mc_last_error(nullptr);
+        CHECK(e.find("failed") != std::string::npos, "create failed without a message");
+        return true;
+    }
+    std::vector<std::vector<mc_function>> reqs = {mixed_table(14, 80, 4), mixed_table(5, 81)};
+    const mc_function base = make_fn(MC_FAMILY_GAUSSIAN, 2, 9001, 82ull << 32);
+    mc_grid_axis axis = {MC_PARAM_V0, 4, 0.0, 0.25};
+    std::vector<mc_function> grid_t;
+    for (uint64_t i = 0; i < 4; ++i) {
+        mc_function f = base;
+        f.params[MC_PARAM_V0] = (double)i * 0.25;
+        f.seed = base.seed + i;
+        grid_t.push_back(f);
+    }
+    std::vector<uint64_t> ids(3, 0);
+    std::vector<int> state(3, 0);  // 0 not submitted, 1 pending, 2 done
+    for (int k = 0; k < 3; ++k) {
+        mc_status st = k < 2 ? mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL,
+                                         &ids[k])
+                             : mc_submit_grid(ctx, &base, &axis, 1, MC_PREC_FP32_EVAL, &ids[k]);
+        if (st == MC_OK) {
+            state[k] = 1;
+        } else {
+            *clean = false;
+            CHECK(st == MC_ERR_HIP || st == MC_ERR_OUT_OF_MEMORY, "submit %d: status %d", k, (int)st);
+            state[k] = 2;
+        }
+    }
+    for (int guard = 0; guard < 20000; ++guard) {
+        bool all = true;
+        for (int k = 0; k < 3; ++k) all = all && state[k] == 2;
+        if (all) break;
+        const mc_status st = mc_run(ctx, nullptr);
+        if (st != MC_OK && st != MC_NOT_READY) {
+            *clean = false;
+            CHECK(st == MC_ERR_HIP || st == MC_ERR_OUT_OF_MEMORY, "run: status %d", (int)st);
+        }
+        for (int k = 0; k < 3; ++k) {
+            if (state[k] != 1) continue;
+            const std::vector<mc_function>& t = k < 2 ? reqs[k] : grid_t;
+            std::vector<mc_result> r(t.size());
+            const mc_status rs = mc_results(ctx, ids[k], r.data(), r.size(), guard > 10000);
+            if (rs == MC_NOT_READY) continue;
+            state[k] = 2;
+            if (rs == MC_OK) {
+                if (!check_results(t, r, k == 1, "after injected failures")) return false;
+            } else {
+                *clean = false;
+                CHECK(rs == MC_ERR_HIP || rs == MC_ERR_OUT_OF_MEMORY, "results %d: status %d", k, (int)rs);
+            }
+        }
+    }
+    for (int k = 0; k < 3; ++k) CHECK(state[k] == 2, "request %d never finished", k);
+    // the context still works: a new request completes (the injected failure
+    // fires once, so if it lands here the second attempt must succeed)
+    const std::vector<mc_function> after = mixed_table(6, 83);
+    bool done = false;
+    for (int attempt = 0; attempt < 2 && !done; ++attempt) {
+        uint64_t id = 0;
+        mc_status rs = mc_submit(ctx, after.data(), after.size(), MC_PREC_FP32_EVAL, &id);
+        std::vector<mc_result> r(after.size());
+        if (rs == MC_OK) rs = mc_results(ctx, id, r.data(), r.size(), 1);
+        if (rs == MC_OK) {
+            if (!check_results(after, r, false, "after the failures")) return false;
+            done = true;
+        } else {
+            *clean = false;
+            CHECK(attempt == 0 && (rs == MC_ERR_HIP || rs == MC_ERR_OUT_OF_MEMORY),
+                  "a request after the failures: status %d: %s", (int)rs, mc_last_error(ctx));
+            if (id != 0) mc_results(ctx, id, r.data(), r.size(), 1);  // release it if it is still queued
+        }
+    }
+    CHECK(done, "no request completed after the failures");
+    mc_destroy(ctx);
+    return true;
+}
+
+// Fail the n-th checked HIP call, for every n the workload makes, with and without graphs.
+bool fault_sweep()
+{
+    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u}) {
+        unsetenv("MC_FAULT_HIP");
+        bool clean = false;
+        const uint64_t c0 = hipemu::api_calls();
+        if (!fault_workload(flags, &clean)) return false;
+        CHECK(clean, "the workload fails without injected failures");
+        const int calls = (int)(hipemu::api_calls() - c0);
+        int failed_runs = 0;
+        for (int n = 1; n <= calls + 2; ++n) {
+            char buf[32];
+            std::snprintf(buf, sizeof buf, "%d", n);
+            setenv("MC_FAULT_HIP", buf, 1);
+            clean = true;
+            if (!fault_workload(flags, &clean)) {
+                std::fprintf(stderr, "fault sweep: failing call %d (flags %u)\n", n, flags);
+                unsetenv("MC_FAULT_HIP");
+                return false;
+            }
+            failed_runs += clean ? 0 : 1;
+        }
+        unsetenv("MC_FAULT_HIP");
+        CHECK(failed_runs > calls / 4, "only %d of %d runs saw a failure", failed_runs, calls + 2);
+        std::printf("fault sweep (flags %u): each of the first %d checked HIP calls failed in turn; %d runs saw an "
+                    "error\n", flags, calls + 2, failed_runs);
+    }
+    return true;
+}
+
+}  // namespace
+
+int main(int argc, char** argv)
+{
+    const std::map<std::string, bool (*)()> all = {
+        {"basic", basic},     {"many_launches", many_launches}, {"admission", admission},
+        {"grid", grid},       {"abort", abort_and_continue},    {"errors", errors},
+        {"plain", plain_paths}, {"two_contexts", two_contexts}, {"fault_sweep", fault_sweep},
+    };
+    std::vector<std::string> names;
+    for (int i = 1; i < argc; ++i) {
+        if (std::string(argv[i]) == "all")
+            for (const auto& kv : all) names.push_back(kv.first);
+        else
+            names.push_back(argv[i]);
+    }
+    for (const std::string& s : names) {
+        auto it = all.find(s);
+        if (it == all.end()) {
+            std::fprintf(stderr, "unknown scenario %s\n", s.c_str());
+            return 2;
+        }
+        if (!it->second()) {
+            std::fprintf(stderr, "FAILED %s\n", s.c_str());
+            return 1;
+        }
+        std::printf("ok %s\n", s.c_str());
+        std::fflush(stdout);
+    }
+    return g_failures == 0 ? 0 : 1;
+}
