@@ -21,7 +21,8 @@ batches with their FP32 errors), `serving` (open-loop Poisson arrivals at a
 fixed rate under SRPT, FAIR at the same rates, alone-vs-mix equality),
 `cpu_baseline` (the serial FP64 CPU oracle on a bounded sample of the same
 workload, all host cores) and `oracle_check` (the timed FP32 results against
-that oracle).
+that oracle, and every function of the mixed and high-dimensional batches in
+both precisions).
 """
 
 from __future__ import annotations
@@ -85,21 +86,49 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def algorithmic_slots_per_eval(family: str, d: int) -> float:
-    """Full-rate VALU lane-slots one sample needs (the method's own work, no overheads).
+def algorithmic_slots_per_eval(family: str, d: int, degrees=None) -> float:
+    """Full-rate VALU lane-slots one sample of the FP32 path needs (the method's own
+    work, no overheads).
 
     Philox4x32-10: 10 rounds x (2 products at half rate = 4 slots + 2 three-input
     xors = 2 slots) = 60 slots per block, d/4 blocks per sample.  Uniform: 1 slot
-    per coordinate.  Harmonic: d FMAs, fract, cos (a transcendental, 4 slots).
-    Accumulation: 4 slots (pairwise quad sums, square, compensated add).
+    per coordinate.  Accumulation: 4 slots (pairwise quad sums, square,
+    compensated add).  A transcendental (cos, exp) issues at a quarter of the
+    full rate: 4 slots.  Per family:
+      harmonic      d FMAs + fract + cos                      d + 5
+      |linear|      d FMAs + the offset's low part            d + 1
+      Gaussian      per coordinate sub, mul, FMA; exp         3 d + 4
+      polynomial    per coordinate sub, FMA (x), n_j - 1 multiplies (x^n),
+                    FMA (1 + p x^n), multiply into the product  sum_j (4 + n_j)
     """
     philox = 60.0 * d / 4.0
     uniform = float(d)
     if family == "harmonic":
         fam = d + 1 + 4
+    elif family == "abs_linear":
+        fam = d + 1
+    elif family == "gaussian":
+        fam = 3 * d + 4
+    elif family == "poly_product":
+        degs = [2.5] * d if degrees is None else list(degrees)[:d]
+        fam = sum(4.0 + n for n in degs)
     else:
         raise ValueError(family)
     return philox + uniform + fam + 4.0
+
+
+FAMILY_NAMES = ("harmonic", "abs_linear", "gaussian", "poly_product")
+
+
+def algorithmic_slots(table) -> float:
+    """Sum over a table's functions of N x the algorithmic slots per sample."""
+    total = 0.0
+    for i in range(len(table)):
+        d = int(table["dim"][i])
+        fam = FAMILY_NAMES[int(table["family"][i])]
+        degs = table["params"][i, 14:14 + d] if fam == "poly_product" else None
+        total += float(table["n_samples"][i]) * algorithmic_slots_per_eval(fam, d, degs)
+    return total
 
 
 def cpu_model() -> str:
@@ -265,11 +294,39 @@ __device__ T mc_user_integrand(const T* x, const T* p, uint32_t d)
 """
 
 
-def other_configs(Z, W, stream):
+def family_table(Z, W, stream, dims=(1, 2, 4, 8, 12), n_funcs=256, n_samples=1 << 22):
+    """FP32 persistent-kernel throughput per (family, dimension): 256 functions of
+    one family and dimension, 2^22 samples each (parameters and boxes drawn as in
+    the mixed-form batch), one launch; kernel time from HIP events (the second of
+    two runs), algorithmic VALU slots from `algorithmic_slots`."""
+    rows = []
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH, max_tiles_per_run=1 << 20) as ctx:
+        for fam, name in enumerate(FAMILY_NAMES):
+            for d in dims:
+                t = W.family_batch(fam, d, n_funcs, n_samples)
+                ctx.integrate(t, Z.PREC_FP32, stream=stream)
+                st0 = ctx.stats()
+                ctx.integrate(t, Z.PREC_FP32, stream=stream)
+                st1 = ctx.stats()
+                ms = st1["fp32_ms"] - st0["fp32_ms"]
+                ev = W.total_evals(t)
+                slots = algorithmic_slots(t)
+                rows.append({"family": name, "dim": d, "evals": ev, "kernel_ms": ms,
+                             "evals_per_s": ev / (ms * 1e-3), "slots_per_eval": slots / ev,
+                             "valu_frac": slots / (ms * 1e-3) / VALU_SLOT_PEAK,
+                             "promoted": st1["promoted"] - st0["promoted"]})
+                log(f"family table: {name} d={d}: {ev / (ms * 1e-3):.3g} evals/s, "
+                    f"VALU fraction {rows[-1]['valu_frac']:.3f}")
+    return rows
+
+
+def other_configs(Z, W, stream, keep=None):
     """Throughput of the other workloads (each run twice, the second timed): the
     paper's Eq. (1) series (plain FP64 and batched FP32), a parameter grid
     (functional mode), a run-time compiled integrand, the mixed-form batch and
-    the high-dimensional batch (batched FP32 with FP64 promotion)."""
+    the high-dimensional batch (batched FP32 with FP64 promotion).  `keep`
+    receives the mixed and high-dimensional tables with their FP32 and FP64
+    results, for the check against the oracle."""
     import torch
     out = {}
 
@@ -333,19 +390,75 @@ def other_configs(Z, W, stream):
             st1 = ctx.stats()
             half = {k: (st1[k] - st0[k]) / 2 for k in ("fp32_ms", "fp64_ms", "finalize_ms", "promoted", "launches")}
             r64 = ctx.integrate(table, Z.PREC_FP64, stream=stream)
+            if keep is not None:
+                keep[name] = (table, r32, r64)
             # FP32-evaluation error per function against the FP64 path (itself equal
             # to the oracle's sums within 1e-12 of sum|f|), in units of the SE
             err = np.abs(r32["mean"] - r64["mean"]) / np.maximum(r64["std_error"], 1e-300)
             near_zero = np.abs(r64["mean"]) < 1e-4
             out[name] = {"evals": ev, "wall_ms": t * 1e3, "evals_per_s": ev / t,
                          "kernel_ms": half["fp32_ms"] + half["fp64_ms"] + half["finalize_ms"],
+                         "fp32_kernel_ms": half["fp32_ms"],
+                         "fp32_kernel_valu_frac": algorithmic_slots(table) / (half["fp32_ms"] * 1e-3) / VALU_SLOT_PEAK,
                          "promoted_to_fp64_per_run": half["promoted"], "launches_per_run": half["launches"],
                          "fp32_vs_fp64_max_dF_over_SE": float(err.max()),
                          "fp32_vs_fp64_median_dF_over_SE": float(np.median(err)),
                          "near_zero_functions": int(near_zero.sum()),
                          "near_zero_max_dF_over_SE": float(err[near_zero].max()) if near_zero.any() else None}
-            log(f"{name}: {ev / t:.3g} evals/s, FP32 vs FP64 max |dF|/SE {err.max():.2e}")
+            log(f"{name}: {ev / t:.3g} evals/s, FP32 vs FP64 max |dF|/SE {err.max():.2e}, "
+                f"FP32 kernel VALU fraction {out[name]['fp32_kernel_valu_frac']:.3f}")
+    out["family_table"] = family_table(Z, W, stream)
     return out
+
+
+def full_oracle_check(orc, table, r32, r64, threads):
+    """Every function of a batch against the CPU oracle on the same samples.
+
+    FP32 request: rows that stayed FP32 against the FP32 bar (|dF| <= 0.01 SE of
+    the oracle, and the SE ratio), rows the library promoted to FP64 against the
+    FP64 bar; FP64 request: S1 within 1e-12 of sum|f| and S2 within 1e-12 of
+    itself.  Near-zero integrals (|F_oracle| < 1e-4) are reported apart."""
+    t0 = time.perf_counter()
+    parts, used = [], 1
+    chunk = 8 * threads
+    for i0 in range(0, len(table), chunk):
+        res, u = orc.integrate(np.ascontiguousarray(table[i0:i0 + chunk]), threads)
+        parts.append(res)
+        used = max(used, u)
+        log(f"  oracle: {min(i0 + chunk, len(table))} of {len(table)} functions, {time.perf_counter() - t0:.0f} s")
+    o = np.concatenate(parts)
+    dt = time.perf_counter() - t0
+    promoted = r32["precision"] == 1
+    se = o["stderr"]
+    exact = se == 0.0
+    f32 = ~promoted & ~exact
+    err = np.abs(r32["mean"] - o["mean"]) / np.where(exact, 1.0, se)
+    se_dev = np.abs(r32["std_error"] / np.where(exact, 1.0, se) - 1.0)
+    near_zero = np.abs(o["mean"]) < 1e-4
+    sabs = np.maximum(o["sum_abs"], 1e-300)
+    s2 = np.maximum(o["sum_f2"], 1e-300)
+    d1_64 = np.abs(r64["sum_f"] - o["sum_f"]) / sabs
+    d2_64 = np.abs(r64["sum_f2"] - o["sum_f2"]) / s2
+    d1_p = (np.abs(r32["sum_f"] - o["sum_f"]) / sabs)[promoted]
+    d2_p = (np.abs(r32["sum_f2"] - o["sum_f2"]) / s2)[promoted]
+
+    def mx(a):
+        return float(np.max(a)) if a.size else None
+
+    res = {
+        "functions": int(len(table)), "oracle_s": dt, "oracle_threads": int(used),
+        "fp32_rows": int(f32.sum()), "promoted_rows": int(promoted.sum()), "constant_rows": int(exact.sum()),
+        "fp32_max_dF_over_SE": mx(err[f32]), "fp32_median_dF_over_SE": float(np.median(err[f32])) if f32.any() else None,
+        "fp32_max_SE_ratio_dev": mx(se_dev[f32]),
+        "near_zero_functions": int(near_zero.sum()), "near_zero_fp32_max_dF_over_SE": mx(err[f32 & near_zero]),
+        "promoted_max_dS1_over_sum_abs": mx(d1_p), "promoted_max_dS2_over_S2": mx(d2_p),
+        "fp64_max_dS1_over_sum_abs": mx(d1_64), "fp64_max_dS2_over_S2": mx(d2_64),
+        "bars": {"fp32_dF_over_SE": 0.01, "fp32_SE_ratio_dev": 1e-3, "fp64_rel": 1e-12},
+    }
+    worst64 = max([v for v in (mx(d1_64), mx(d2_64), mx(d1_p), mx(d2_p)) if v is not None] or [0.0])
+    res["pass"] = bool((res["fp32_max_dF_over_SE"] or 0.0) <= 0.01 and (res["fp32_max_SE_ratio_dev"] or 0.0) < 1e-3
+                       and worst64 <= 1e-12 and np.all(r32["status"] == 0) and np.all(r64["status"] == 0))
+    return res
 
 
 def main():
@@ -366,6 +479,8 @@ def main():
     ap.add_argument("--serve-loads", default="0.25,0.75",
                     help="further offered loads (fractions of saturated) reported beside the headline one")
     ap.add_argument("--no-configs", action="store_true", help="skip the other workloads' throughput lines")
+    ap.add_argument("--no-oracle-full", action="store_true",
+                    help="skip the check of every mixed and high-dimensional function against the CPU oracle")
     ap.add_argument("--serve-requests", type=int, default=3000,
                     help="requests in the serving measurement (0 skips it)")
     ap.add_argument("--serve-policy", default="srpt", choices=sorted(SERVE_POLICIES),
@@ -531,9 +646,10 @@ def main():
                                               "results_equal_direct_bitwise": bool(same)}
         log(f"graph replay: {evals_per_step * K / gdt:.4g} evals/s, results equal: {same}")
 
+    kept = {}
     if not args.no_configs:
         log("other workloads")
-        out["other_configs"] = other_configs(Z, W, stream)
+        out["other_configs"] = other_configs(Z, W, stream, kept)
 
     if args.serve_requests > 0:
         log("serving leg")
@@ -557,6 +673,13 @@ def main():
         out["oracle_check"] = {"functions": int(checked), "first_step_functions": int(len(ores)),
                                "later_steps": int(K - 1), "later_step_fraction": 0.1,
                                "max_dF_over_SE": worst, "bar": 0.01}
+        if not args.no_oracle_full:
+            # the mixed-form and high-dimensional batches, every function
+            for name, key in (("mixed_2000_dims1to7", "mixed"), ("highdim_500x1e7_dims8to12", "highdim")):
+                if name in kept:
+                    log(f"oracle check of every function: {name}")
+                    out["oracle_check"][key] = full_oracle_check(orc, *kept[name], threads)
+                    log(f"  {key}: {json.dumps(out['oracle_check'][key])}")
     print(json.dumps(out))
 
 

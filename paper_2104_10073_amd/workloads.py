@@ -192,9 +192,11 @@ def harmonic_batch(n_funcs: int = 1000, n_samples: int = 1_000_000, base: int = 
     return t
 
 
-def _draw_mixed(rng, t, i, dim):
-    """One function of the mixed-form batch: family uniform over the four families."""
-    fam = int(rng.integers(0, 4))
+def _draw_mixed(rng, t, i, dim, fam=None):
+    """One function of the mixed-form batch: family uniform over the four families
+    (or the given one), parameters and box drawn as for that batch."""
+    if fam is None:
+        fam = int(rng.integers(0, 4))
     lo = rng.uniform(-1.0, 1.0, dim)
     w = rng.uniform(0.5, 2.0, dim)
     hi = lo + w
@@ -230,6 +232,20 @@ def mixed_batch(n_funcs: int = 2000, dim_range=(1, 7), log10_samples=(4.0, 7.0),
         _draw_mixed(rng, t, i, dim)
         n = _log_uniform_count(rng, *log10_samples)
         t["n_samples"][i] = max(2, int(n * sample_scale))
+        t["seed"][i] = stream_seed(base, i)
+    return t
+
+
+def family_batch(family: int, dim: int, n_funcs: int = 256, n_samples: int = 1 << 22, base: int = 0,
+                 gen_seed: int = 9) -> np.ndarray:
+    """Functions of one family and one dimension, parameters and boxes drawn as in
+    the mixed-form batch, all with the same sample count (for per-(family, d)
+    throughput)."""
+    rng = np.random.Generator(np.random.PCG64(gen_seed + 97 * family + dim))
+    t = empty(n_funcs)
+    for i in range(n_funcs):
+        _draw_mixed(rng, t, i, dim, family)
+        t["n_samples"][i] = n_samples
         t["seed"][i] = stream_seed(base, i)
     return t
 

@@ -159,3 +159,40 @@ def test_bench_help_lists_the_contract_options():
     assert p.returncode == 0
     for opt in ("--gpus", "--steps", "--warmup", "--serve-policy", "--blocks-per-cu", "--graph"):
         assert opt in p.stdout, opt
+
+
+def test_bench_full_oracle_check_grades_by_precision():
+    """bench.full_oracle_check: results equal to the oracle's pass; an FP32 row off by
+    0.02 SE or an FP64 sum off by 1e-11 relative fails; promoted rows are graded by
+    the FP64 bar."""
+    import importlib.util
+    from oracle import oracle as O
+    from paper_2104_10073_amd import _native
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(root, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    t = W.mixed_batch(24, dim_range=(1, 5), log10_samples=(3.0, 3.5), gen_seed=17)
+    o, _ = O.default().integrate(t, 4)
+
+    def as_gpu(prec):
+        r = np.zeros(len(t), dtype=_native.RESULT_DTYPE)
+        for f in ("mean", "sum_f", "sum_f2", "n"):
+            r[f] = o[f]
+        r["std_error"] = o["stderr"]
+        r["precision"] = prec
+        return r
+
+    r32, r64 = as_gpu(0), as_gpu(1)
+    r32["precision"][3] = 1
+    res = bench.full_oracle_check(O.default(), t, r32, r64, 4)
+    assert res["pass"] and res["promoted_rows"] == 1 and res["fp32_rows"] == len(t) - 1
+    bad = r32.copy()
+    bad["mean"][5] += 0.02 * o["stderr"][5]
+    assert not bench.full_oracle_check(O.default(), t, bad, r64, 4)["pass"]
+    bad = r64.copy()
+    bad["sum_f"][7] += 1e-11 * o["sum_abs"][7]
+    assert not bench.full_oracle_check(O.default(), t, r32, bad, 4)["pass"]
+    bad = r32.copy()
+    bad["sum_f"][3] += 1e-11 * o["sum_abs"][3]
+    assert not bench.full_oracle_check(O.default(), t, bad, r64, 4)["pass"]
