@@ -82,6 +82,64 @@ __device__ __forceinline__ void philox_block(uint32_t b_lo, uint32_t b_hi, uint3
     out[3] = c3;
 }
 
+// The same block at counter (b, 0, 0, 0), for functions whose block indices fit
+// in 32 bits.  With the counter's second word zero, the first round leaves
+// c0 = k0 and c1 = 0, so the second round's first product M0 * k0 and the xor
+// terms it feeds are wave-uniform: they are formed on the scalar unit, and
+// every VALU xor takes at most one scalar operand (gfx950 reads one scalar
+// operand per vector instruction; a second would cost a copy).
+__device__ __forceinline__ void philox_block_narrow(uint32_t b, uint32_t k0, uint32_t k1, uint32_t out[4])
+{
+    uint32_t c0, c1, c2, c3;
+    // first round: counter (b, 0, 0, 0)
+    const uint64_t p = (uint64_t)kPhiloxM0 * b;
+    c2 = (uint32_t)(p >> 32) ^ k1;
+    c3 = (uint32_t)p;
+    // second round: counter (k0, 0, c2, c3); M0 * k0 is wave-uniform
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    const uint64_t u = (uint64_t)kPhiloxM0 * (k0 - kPhiloxW0);
+    const uint32_t u_hi_k1 = (uint32_t)(u >> 32) ^ k1;
+    const uint32_t u_lo = (uint32_t)u;
+    {
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        c0 = (uint32_t)(p1 >> 32) ^ k0;
+        c1 = (uint32_t)p1;
+        c2 = c3 ^ u_hi_k1;
+    }
+    // third round: c3 = u_lo is wave-uniform
+    k0 += kPhiloxW0;
+    k1 += kPhiloxW1;
+    {
+        const uint32_t lo_k1 = u_lo ^ k1;
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = (uint32_t)(p0 >> 32) ^ lo_k1;
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+#pragma unroll
+    for (int r = 3; r < 10; ++r) {
+        k0 += kPhiloxW0;
+        k1 += kPhiloxW1;
+        const uint64_t p0 = (uint64_t)kPhiloxM0 * c0;
+        const uint64_t p1 = (uint64_t)kPhiloxM1 * c2;
+        const uint32_t n0 = xor3((uint32_t)(p1 >> 32), c1, k0);
+        const uint32_t n2 = xor3((uint32_t)(p0 >> 32), c3, k1);
+        c1 = (uint32_t)p1;
+        c3 = (uint32_t)p0;
+        c0 = n0;
+        c2 = n2;
+    }
+    out[0] = c0;
+    out[1] = c1;
+    out[2] = c2;
+    out[3] = c3;
+}
+
 // ---------------------------------------------------------------- function records
 
 // Function records are read-only while kernels run.  Reading them through the
@@ -111,19 +169,28 @@ __device__ __forceinline__ double word_to_u64(uint32_t r)
     return (double)(((r & 0x007FFFFFu) << 1) | 1u) * 0x1p-24;
 }
 
-// One quad q of samples: d Philox blocks q*d .. q*d + d - 1, block j giving
-// coordinate j of the four samples, folded into the samples' states as soon as
-// it is produced (the built-in families need no more than one state per sample).
-template <class Ev, class T>
-__device__ __forceinline__ void stream_quad(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, T g[4])
+// One quad of samples whose first Philox block is b0 = q*d: blocks b0 .. b0 + d - 1,
+// block b0 + j giving coordinate j of the four samples, folded into the samples'
+// states as soon as it is produced (the built-in families need no more than one
+// state per sample).  B is uint32_t when every block index of the function fits
+// in 32 bits: the counter's second word is then the constant 0, which makes part
+// of the first two Philox rounds wave-uniform (scalar) work; otherwise uint64_t.
+template <class B>
+__device__ __forceinline__ void philox_at(B b, uint32_t k0, uint32_t k1, uint32_t w[4])
+{
+    if constexpr (sizeof(B) == 4) philox_block_narrow(b, k0, k1, w);
+    else philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+}
+
+template <class Ev, class T, class B>
+__device__ __forceinline__ void stream_quad(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1, B b0, T g[4])
 {
     T st[4];
-    ev.init(st);
-    const uint64_t b0 = q * (uint64_t)d;
-    for (uint32_t j = 0; j < d; ++j) {
-        const uint64_t b = b0 + j;
-        uint32_t w[4];
-        philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+    uint32_t w[4];
+    philox_at<B>(b0, k0, k1, w);
+    ev.first(st, w);  // d >= 1
+    for (uint32_t j = 1; j < d; ++j) {
+        philox_at<B>(b0 + j, k0, k1, w);
         ev.add(st, j, w);
     }
 #pragma unroll
@@ -133,8 +200,10 @@ __device__ __forceinline__ void stream_quad(const Ev& ev, uint32_t d, uint32_t k
 // ---------------------------------------------------------------- FP32 integrands
 
 // An evaluator holds a function (wave-uniform pointer) and works on the four
-// samples of a quad: init() sets their states, add(st, j, w) folds coordinate j
-// from the block's four words, finish() returns g with f = scale1 * g (scale1
+// samples of a quad: first(st, w) sets their states from coordinate 0 (the
+// state an empty sum would start from, folded into the first operation), add(st,
+// j, w) folds coordinate j from the block's four words, finish() returns g with
+// f = scale1 * g (scale1
 // and scale2 = scale1^2 are applied in FP64 at finalize).  Coefficients were
 // derived on the host in FP64 and rounded once; they are read with scalar loads.
 
@@ -146,11 +215,16 @@ template <int FAM> struct Eval32;
 template <> struct Eval32<HARMONIC> {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const;
-    __device__ __forceinline__ void init(float st[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, B b0, float g[4]) const
     {
-        const float f0 = fn->f0;
-        for (int s = 0; s < 4; ++s) st[s] = f0;
+        stream_quad(*this, d, k0, k1, b0, g);
+    }
+    __device__ __forceinline__ void first(float st[4], const uint32_t w[4]) const
+    {
+        const float c = fn->fc[0], f0 = fn->f0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), f0);
     }
     __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
@@ -169,11 +243,16 @@ template <> struct Eval32<HARMONIC> {
 template <> struct Eval32<ABS_LINEAR> {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const;
-    __device__ __forceinline__ void init(float st[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, B b0, float g[4]) const
     {
-        const float f0 = fn->f0;
-        for (int s = 0; s < 4; ++s) st[s] = f0;
+        stream_quad(*this, d, k0, k1, b0, g);
+    }
+    __device__ __forceinline__ void first(float st[4], const uint32_t w[4]) const
+    {
+        const float c = fn->fc[0], f0 = fn->f0;
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] = fmaf(c, word_to_t(w[s]), f0);
     }
     __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
@@ -189,10 +268,19 @@ template <> struct Eval32<ABS_LINEAR> {
 template <> struct Eval32<GAUSSIAN> {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const;
-    __device__ __forceinline__ void init(float st[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, B b0, float g[4]) const
     {
-        for (int s = 0; s < 4; ++s) st[s] = 0.0f;
+        stream_quad(*this, d, k0, k1, b0, g);
+    }
+    __device__ __forceinline__ void first(float st[4], const uint32_t w[4]) const
+    {
+        const float c = fn->fc[0], m = fn->fo[0];
+#pragma unroll
+        for (int s = 0; s < 4; ++s) {
+            const float y = c * (word_to_t(w[s]) - m);
+            st[s] = fmaf(y, y, 0.0f);
+        }
     }
     __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
     {
@@ -211,12 +299,12 @@ template <> struct Eval32<GAUSSIAN> {
 template <> struct Eval32<POLY_PRODUCT> {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const;
-    __device__ __forceinline__ void init(float st[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, B b0, float g[4]) const
     {
-        for (int s = 0; s < 4; ++s) st[s] = 1.0f;
+        stream_quad(*this, d, k0, k1, b0, g);
     }
-    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
+    __device__ __forceinline__ void factors(uint32_t j, const uint32_t w[4], float fac[4]) const
     {
         const float c = fn->fc[j], o = fn->fo[j], p = fn->fp[j];
         const int e = fn->deg[j] < kMaxPolyDegree ? fn->deg[j] : kMaxPolyDegree;  // bounded whatever the record holds
@@ -231,33 +319,18 @@ template <> struct Eval32<POLY_PRODUCT> {
             for (int s = 0; s < 4; ++s) xp[s] *= x[s];
         }
 #pragma unroll
-        for (int s = 0; s < 4; ++s) st[s] *= fmaf(p, xp[s], 1.0f);
+        for (int s = 0; s < 4; ++s) fac[s] = fmaf(p, xp[s], 1.0f);
+    }
+    __device__ __forceinline__ void first(float st[4], const uint32_t w[4]) const { factors(0, w, st); }
+    __device__ __forceinline__ void add(float st[4], uint32_t j, const uint32_t w[4]) const
+    {
+        float fac[4];
+        factors(j, w, fac);
+#pragma unroll
+        for (int s = 0; s < 4; ++s) st[s] *= fac[s];
     }
     __device__ __forceinline__ float finish(float g) const { return g; }
 };
-
-template <int FAM>
-__device__ __forceinline__ void eval32_quad(const Eval32<FAM>& ev, uint32_t d, uint32_t k0, uint32_t k1, uint64_t q,
-                                            float g[4])
-{
-    stream_quad(ev, d, k0, k1, q, g);
-}
-__device__ __forceinline__ void Eval32<HARMONIC>::quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
-{
-    eval32_quad(*this, d, k0, k1, q, g);
-}
-__device__ __forceinline__ void Eval32<ABS_LINEAR>::quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
-{
-    eval32_quad(*this, d, k0, k1, q, g);
-}
-__device__ __forceinline__ void Eval32<GAUSSIAN>::quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
-{
-    eval32_quad(*this, d, k0, k1, q, g);
-}
-__device__ __forceinline__ void Eval32<POLY_PRODUCT>::quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
-{
-    eval32_quad(*this, d, k0, k1, q, g);
-}
 
 // ---------------------------------------------------------------- FP64 integrands
 
@@ -265,16 +338,18 @@ __device__ __forceinline__ void Eval32<POLY_PRODUCT>::quad(uint32_t d, uint32_t 
 template <int FAM> struct Eval64 {
     CDevFn* fn;
     typedef double Value;
-    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, uint64_t q, double g[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t d, uint32_t k0, uint32_t k1, B b0, double g[4]) const
     {
-        stream_quad(*this, d, k0, k1, q, g);
+        stream_quad(*this, d, k0, k1, b0, g);
     }
-    __device__ __forceinline__ void init(double st[4]) const
+    __device__ __forceinline__ void first(double st[4], const uint32_t w[4]) const
     {
         double v = 0.0;
         if constexpr (FAM == ABS_LINEAR) v = fn->s1;
         if constexpr (FAM == POLY_PRODUCT) v = 1.0;
         for (int s = 0; s < 4; ++s) st[s] = v;
+        add(st, 0, w);
     }
     __device__ __forceinline__ void add(double st[4], uint32_t j, const uint32_t w[4]) const
     {
@@ -339,21 +414,25 @@ __device__ __forceinline__ void kahan_add(float& s, float& c, float x)
 
 // ---------------------------------------------------------------- one segment
 
-// Lane sums over the lane's 16 quads of one segment.  `tail` marks the
-// function's last segment, the only one that can hold quads or samples past N.
-template <class Ev>
+// Lane sums over the lane's 16 quads of one segment, quads quad0 + 64 k; b0 is
+// the first Philox block of the lane's current quad, advanced by 64 d per quad.
+// TAIL marks a segment that can hold quads or samples past N (the function's
+// last one, or any segment of a function whose block indices need 64 bits).
+template <bool TAIL, class B, class Ev>
 __device__ __forceinline__ void segment_fp32(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1,
-                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
+                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples,
                                              double& out1, double& out2)
 {
     float s1 = 0.0f, c1 = 0.0f, s2 = 0.0f, c2 = 0.0f;
+    B b0 = (B)(quad0 * d);
+    const B step = (B)kWave * (B)d;
 #pragma unroll 1
-    for (int k = 0; k < kQuadsPerLane; ++k) {
+    for (int k = 0; k < kQuadsPerLane; ++k, b0 += step) {
         const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (tail && q >= n_quads) break;
+        if (TAIL && q >= n_quads) break;
         float g[4];
-        ev.quad(d, k0, k1, q, g);
-        if (tail) {
+        ev.quad(d, k0, k1, b0, g);
+        if (TAIL) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 if (4 * q + (uint64_t)s >= n_samples) g[s] = 0.0f;
@@ -367,19 +446,21 @@ __device__ __forceinline__ void segment_fp32(const Ev& ev, uint32_t d, uint32_t 
     out2 = (double)s2 - (double)c2;
 }
 
-template <class Ev>
+template <bool TAIL, class B, class Ev>
 __device__ __forceinline__ void segment_fp64(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1,
-                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples, bool tail,
+                                             uint64_t quad0, uint64_t n_quads, uint64_t n_samples,
                                              double& out1, double& out2)
 {
     double s1 = 0.0, s2 = 0.0;
+    B b0 = (B)(quad0 * d);
+    const B step = (B)kWave * (B)d;
 #pragma unroll 1
-    for (int k = 0; k < kQuadsPerLane; ++k) {
+    for (int k = 0; k < kQuadsPerLane; ++k, b0 += step) {
         const uint64_t q = quad0 + (uint64_t)(k * kWave);
-        if (tail && q >= n_quads) break;
+        if (TAIL && q >= n_quads) break;
         double f[4];
-        ev.quad(d, k0, k1, q, f);
-        if (tail) {
+        ev.quad(d, k0, k1, b0, f);
+        if (TAIL) {
 #pragma unroll
             for (int s = 0; s < 4; ++s)
                 if (4 * q + (uint64_t)s >= n_samples) f[s] = 0.0;
@@ -389,6 +470,16 @@ __device__ __forceinline__ void segment_fp64(const Ev& ev, uint32_t d, uint32_t 
     }
     out1 = s1;
     out2 = s2;
+}
+
+template <bool TAIL, class B, class Ev>
+__device__ __forceinline__ void segment_sums(const Ev& ev, uint32_t d, uint32_t k0, uint32_t k1, uint64_t quad0,
+                                             uint64_t n_quads, uint64_t n_samples, double& out1, double& out2)
+{
+    if constexpr (sizeof(typename Ev::Value) == 8)
+        segment_fp64<TAIL, B>(ev, d, k0, k1, quad0, n_quads, n_samples, out1, out2);
+    else
+        segment_fp32<TAIL, B>(ev, d, k0, k1, quad0, n_quads, n_samples, out1, out2);
 }
 
 // ---------------------------------------------------------------- one tile
@@ -407,6 +498,8 @@ __device__ __forceinline__ void tile_segments(CDevFn* fn, uint32_t seg0, uint32_
     const uint32_t d = fn->dim;
     const uint32_t k0 = fn->key0, k1 = fn->key1;
     const uint32_t first = seg0 + wave * per_wave;
+    // every block index q*d + j of the function below 2^32: 32-bit counters
+    const bool narrow = n_quads * (uint64_t)d <= 0x100000000ull;
     const Ev ev{fn};
     for (uint32_t i = 0; i < per_wave; ++i) {
         const uint32_t seg = first + i;
@@ -414,10 +507,12 @@ __device__ __forceinline__ void tile_segments(CDevFn* fn, uint32_t seg0, uint32_
         if (seg < n_seg) {
             const uint64_t quad0 = (uint64_t)seg * kSegQuads + lane;
             const bool tail = (uint64_t)(seg + 1) * kSegSamples > n_samples;
-            if constexpr (sizeof(typename Ev::Value) == 8)
-                segment_fp64(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
+            if (!narrow)
+                segment_sums<true, uint64_t>(ev, d, k0, k1, quad0, n_quads, n_samples, a, b);
+            else if (tail)
+                segment_sums<true, uint32_t>(ev, d, k0, k1, quad0, n_quads, n_samples, a, b);
             else
-                segment_fp32(ev, d, k0, k1, quad0, n_quads, n_samples, tail, a, b);
+                segment_sums<false, uint32_t>(ev, d, k0, k1, quad0, n_quads, n_samples, a, b);
             a = wave_sum(a);
             b = wave_sum(b);
         }
@@ -459,15 +554,14 @@ template <class F, uint32_t D>
 struct EvalUser32 {
     CDevFn* fn;
     typedef float Value;
-    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, uint64_t q, float g[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, B b0, float g[4]) const
     {
         float x[4][D];
-        const uint64_t b0 = q * (uint64_t)D;
 #pragma unroll
         for (uint32_t j = 0; j < D; ++j) {
-            const uint64_t b = b0 + (uint64_t)j;
             uint32_t w[4];
-            philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+            philox_at<B>(b0 + j, k0, k1, w);
             const float c = fn->fc[j], o = fn->fo[j];
 #pragma unroll
             for (int s = 0; s < 4; ++s) x[s][j] = fmaf(c, word_to_t(w[s]) - kTShift, o);
@@ -484,15 +578,14 @@ template <class F, uint32_t D>
 struct EvalUser64 {
     CDevFn* fn;
     typedef double Value;
-    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, uint64_t q, double g[4]) const
+    template <class B>
+    __device__ __forceinline__ void quad(uint32_t, uint32_t k0, uint32_t k1, B b0, double g[4]) const
     {
         double x[4][D];
-        const uint64_t b0 = q * (uint64_t)D;
 #pragma unroll
         for (uint32_t j = 0; j < D; ++j) {
-            const uint64_t b = b0 + (uint64_t)j;
             uint32_t w[4];
-            philox_block((uint32_t)b, (uint32_t)(b >> 32), k0, k1, w);
+            philox_at<B>(b0 + j, k0, k1, w);
             const double lo = fn->lo[j], wd = fn->w[j];
 #pragma unroll
             for (int s = 0; s < 4; ++s) x[s][j] = fma(wd, word_to_u64(w[s]), lo);

@@ -191,7 +191,7 @@ template <int FAM>
 __device__ __forceinline__ void plain_quad(CDevFn* fn, uint64_t q, double f[4])
 {
     const Eval64<FAM> ev{fn};
-    ev.quad(fn->dim, fn->key0, fn->key1, q, f);
+    ev.quad(fn->dim, fn->key0, fn->key1, q * (uint64_t)fn->dim, f);
 }
 
 extern "C" __global__ __launch_bounds__(256) void zmc_plain_fp64(const DevFn* __restrict__ fn_in,
