@@ -293,7 +293,14 @@ mc_status mc_get_tuning(mc_ctx* ctx, uint32_t* blocks_per_cu, uint8_t* seg_log2 
 mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_log2 /* [2][4][12] or NULL */);
 
 /* Time candidate tunings on synthetic functions of every (family, dim) in
- * `precision` and keep the fastest.  Blocks until done; uses `stream`. */
+ * `precision` and keep the fastest: workgroups per CU (FP32 kernel) first, then
+ * the tile size per (family, dim), stopping when `budget_seconds` is spent (a
+ * trial in progress finishes).  Blocks until done; uses `stream`; call it on a
+ * context with no requests of its own in flight.  Results never change.
+ * With MC_TUNE_CACHE naming a text file in the environment, a line for this
+ * device kind, compute-unit count, library version and precision is taken
+ * from the file instead of timing (the last matching line wins; malformed
+ * lines are ignored), and a tuning that was timed is appended to it. */
 mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
 
 /* Kernel timing of the most recent completed direct-launch mc_run (persistent

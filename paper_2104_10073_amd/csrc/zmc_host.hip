@@ -428,6 +428,7 @@ struct mc_ctx {
     bool use_graph = true;
     int device = 0;
     int num_cus = 0;
+    std::string device_name;  // gcnArchName (keys the tuning cache)
     std::string err;
 
     // capacities
@@ -1337,11 +1338,16 @@ void destroy_device(mc_ctx* ctx)
     ctx->mem_base = nullptr;
 }
 
+// Tile size before any tuning: 4 segments per workgroup (one per wave) from
+// d = 3 on; at d = 1 and 2 a segment is so short that the per-tile fetch,
+// barriers and tree would dominate (measured at d = 1: 0.45 of the VALU
+// roofline with one segment per wave, 0.65 with four), so such tiles hold 4
+// and 2 segments per wave.
 void default_tuning(mc_ctx* ctx)
 {
     for (int p = 0; p < 2; ++p)
         for (int f = 0; f < kNumFamilies; ++f)
-            for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = 0;
+            for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = d == 0 ? 2 : d == 1 ? 1 : 0;
 }
 
 }  // namespace
@@ -1406,6 +1412,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
             return fail(nullptr, MC_ERR_NO_DEVICE, "device %d is %s; this library is built for gfx950", cfg.device,
                         prop.gcnArchName);
         ctx->num_cus = prop.multiProcessorCount;
+        ctx->device_name = prop.gcnArchName;
         HIP_TRY(scratch_address(cfg.device, &ctx->scratch));
         int occ32 = 0, occ64 = 0;
         HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ32, batched_kernel_ptr(false), kBlockThreads, 0));
@@ -2042,12 +2049,99 @@ static double time_batch(mc_ctx* ctx, const std::vector<mc_function>& fns, int32
     return total;
 }
 
+}  // extern "C"
+
+namespace {
+
+mc_status autotune_run(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
+
+// Tuning cache (MC_TUNE_CACHE names a text file): one line per device kind,
+// compute-unit count, library version and precision,
+//   zmc-tune 1 <arch> <CUs> <version> <precision> <blocks per CU> <48 seg_log2 values>
+// where the values are the [2][4][12] table of mc_get_tuning.  Results never
+// depend on the tuning, so a stale or foreign line can only cost speed.
+std::string tune_key(const mc_ctx* ctx, int precision)
+{
+    char buf[256];
+    snprintf(buf, sizeof buf, "zmc-tune 1 %s %d %s %d", ctx->device_name.c_str(), ctx->num_cus, mc_version(), precision);
+    for (char& c : buf)
+        if (c == '\n') c = ' ';
+    return buf;
+}
+
+bool load_tuning(mc_ctx* ctx, const char* path, int precision)
+{
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    const std::string key = tune_key(ctx, precision);
+    // later lines override earlier ones (a re-tuned context appends)
+    bool found = false;
+    uint32_t blocks = 0;
+    uint8_t seg[2 * 4 * kMaxDim] = {};
+    char line[1024];
+    while (std::fgets(line, sizeof line, f)) {
+        std::string l(line);
+        if (l.compare(0, key.size(), key) != 0 || l.size() <= key.size() || l[key.size()] != ' ') continue;
+        const char* q = l.c_str() + key.size();
+        char* end = nullptr;
+        const unsigned long b = std::strtoul(q, &end, 10);
+        if (end == q || b < 1 || b > 32) continue;
+        uint8_t v[2 * 4 * kMaxDim];
+        bool ok = true;
+        for (int i = 0; i < 2 * 4 * kMaxDim && ok; ++i) {
+            q = end;
+            const unsigned long x = std::strtoul(q, &end, 10);
+            ok = end != q && x <= (unsigned long)kMaxSegLog2;
+            v[i] = (uint8_t)x;
+        }
+        if (!ok) continue;
+        found = true;
+        blocks = (uint32_t)b;
+        std::memcpy(seg, v, sizeof seg);
+    }
+    std::fclose(f);
+    if (!found) return false;
+    // the cached line holds the tuned precision's rows; keep the other precision's
+    uint8_t cur[2 * 4 * kMaxDim];
+    mc_get_tuning(ctx, nullptr, cur);
+    const int p = precision == MC_PREC_FP64 ? 1 : 0;
+    std::memcpy(cur + p * 4 * kMaxDim, seg + p * 4 * kMaxDim, 4 * kMaxDim);
+    return mc_set_tuning(ctx, precision == MC_PREC_FP32_EVAL ? blocks : 0, cur) == MC_OK;
+}
+
+void store_tuning(mc_ctx* ctx, const char* path, int precision)
+{
+    uint32_t blocks = 0;
+    uint8_t seg[2 * 4 * kMaxDim];
+    mc_get_tuning(ctx, &blocks, seg);
+    std::string text = tune_key(ctx, precision) + " " + std::to_string(blocks);
+    for (int i = 0; i < 2 * 4 * kMaxDim; ++i) text += " " + std::to_string((unsigned)seg[i]);
+    text += "\n";
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;  // the cache is an optimisation: a file that cannot be written is ignored
+    std::fputs(text.c_str(), f);
+    std::fclose(f);
+}
+
+}  // namespace
+
 extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
     if (precision != MC_PREC_FP32_EVAL && precision != MC_PREC_FP64)
         return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
+    const char* cache = std::getenv("MC_TUNE_CACHE");
+    if (cache && *cache && load_tuning(ctx, cache, precision)) return MC_OK;
+    const mc_status st = autotune_run(ctx, precision, stream, budget_seconds);
+    if (st == MC_OK && cache && *cache) store_tuning(ctx, cache, precision);
+    return st;
+}
+
+namespace {
+
+mc_status autotune_run(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds)
+{
     const auto t0 = std::chrono::steady_clock::now();
     auto elapsed = [&] { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); };
     hipStream_t s = (hipStream_t)stream;
@@ -2110,6 +2204,10 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
     }
     return MC_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms)
 {

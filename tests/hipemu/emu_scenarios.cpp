@@ -5,6 +5,8 @@
 // passing scenario; exits non-zero on the first failure.  Every result the
 // library reports as MC_OK is compared field by field with the result the
 // emulation defines for that function (hipemu::expected_batched / plain).
+#include <unistd.h>
+
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -203,7 +205,7 @@ bool admission()
     uint64_t id = 0;
     const std::vector<mc_function> big = mixed_table(17, 30);
     CHECK(mc_submit(ctx, big.data(), big.size(), MC_PREC_FP32_EVAL, &id) == MC_ERR_ADMISSION, "17 functions");
-    std::vector<mc_function> wide(1, make_fn(MC_FAMILY_HARMONIC, 2, 401ull * 4 * 4096, 5));
+    std::vector<mc_function> wide(1, make_fn(MC_FAMILY_HARMONIC, 3, 401ull * 4 * 4096, 5));  // 401 tiles of 4 segments
     CHECK(mc_submit(ctx, wide.data(), 1, MC_PREC_FP32_EVAL, &id) == MC_ERR_ADMISSION, "401 partials");
     for (size_t k = ids.size(); k-- > 0;) {  // newest first: blocking calls drive the queue
         std::vector<mc_result> r(10);
@@ -479,6 +481,67 @@ bool fault_sweep()
     return true;
 }
 
+// The tuning cache: a tuned context appends its choice to MC_TUNE_CACHE; a new
+// context on the same device kind takes the cached line (the last matching one)
+// instead of timing again; malformed or foreign lines are ignored; results do
+// not depend on the tuning.
+bool autotune_cache()
+{
+    char path[] = "/tmp/zmc_tune_XXXXXX";
+    const int fd = mkstemp(path);
+    CHECK(fd >= 0, "mkstemp");
+    close(fd);
+    setenv("MC_TUNE_CACHE", path, 1);
+    bool ok = [&]() -> bool {
+        mc_ctx* a = create(0);
+        CHECK(a, "create");
+        const std::vector<mc_function> t = mixed_table(20, 90);
+        uint64_t id = 0;
+        std::vector<mc_result> before(t.size()), after(t.size());
+        CHECK(mc_submit(a, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+        CHECK(mc_results(a, id, before.data(), before.size(), 1) == MC_OK, "results");
+        CHECK(mc_autotune(a, MC_PREC_FP32_EVAL, nullptr, 0.5) == MC_OK, "autotune: %s", mc_last_error(a));
+        CHECK(mc_submit(a, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+        CHECK(mc_results(a, id, after.data(), after.size(), 1) == MC_OK, "results");
+        for (size_t i = 0; i < t.size(); ++i) CHECK(same_result(before[i], after[i]), "result %zu changed", i);
+        mc_destroy(a);
+        // the cache holds one line; rewrite its values, add noise around it
+        FILE* f = std::fopen(path, "r");
+        CHECK(f, "cache file");
+        char line[2048] = {};
+        CHECK(std::fgets(line, sizeof line, f) != nullptr, "cache line");
+        char extra[16];
+        CHECK(std::fgets(extra, sizeof extra, f) == nullptr, "one line");
+        std::fclose(f);
+        std::string l(line);
+        size_t pos = 0;
+        for (int field = 0; field < 7; ++field) pos = l.find(' ', pos) + 1;  // up to "<blocks per CU>"
+        std::string edited = l.substr(0, pos) + "3";
+        for (int i = 0; i < 96; ++i) edited += i < 48 ? " 2" : " 1";
+        f = std::fopen(path, "w");
+        std::fputs("garbage line\n", f);
+        std::fputs((l.substr(0, pos) + "99 1 2 3\n").c_str(), f);  // blocks out of range: ignored
+        std::fputs((edited + "\n").c_str(), f);
+        std::fputs("zmc-tune 1 gfx000 8 other 0 5 0 0\n", f);     // another device: ignored
+        std::fclose(f);
+        mc_ctx* b = create(0);
+        CHECK(b, "create");
+        uint32_t blocks = 0;
+        uint8_t defaults[96], seg[96];
+        CHECK(mc_get_tuning(b, &blocks, defaults) == MC_OK, "default tuning");
+        CHECK(mc_autotune(b, MC_PREC_FP32_EVAL, nullptr, 0.5) == MC_OK, "cached autotune");
+        CHECK(mc_get_tuning(b, &blocks, seg) == MC_OK, "get tuning");
+        CHECK(blocks == 3, "blocks per CU from the cache: %u", blocks);
+        // FP32 rows from the cache, the FP64 rows untouched
+        for (int i = 0; i < 96; ++i) CHECK(seg[i] == (i < 48 ? 2 : defaults[i]), "seg %d = %u", i, (unsigned)seg[i]);
+        mc_destroy(b);
+        return true;
+    }();
+    unsetenv("MC_TUNE_CACHE");
+    std::remove(path);
+    return ok;
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -487,6 +550,7 @@ int main(int argc, char** argv)
         {"basic", basic},     {"many_launches", many_launches}, {"admission", admission},
         {"grid", grid},       {"abort", abort_and_continue},    {"errors", errors},
         {"plain", plain_paths}, {"two_contexts", two_contexts}, {"fault_sweep", fault_sweep},
+        {"autotune_cache", autotune_cache},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {
