@@ -125,13 +125,16 @@ typedef struct mc_result {
 #define MC_NO_GRAPH 0x2u         /* launch kernels directly instead of replaying captured HIP graphs */
 #define MC_NO_PROMOTE 0x4u       /* evaluate every function of an FP32 request in FP32: no FP64 re-runs and no
                                     FP64 choice at submit (unresolvable integrands come back as FP32 gave them) */
+#define MC_RESIDENT 0x8u         /* serve through one resident kernel instead of launches: see "Resident
+                                    contexts" below */
 
 typedef struct mc_config {
     int32_t device;              /* HIP device ordinal */
-    uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH | MC_NO_PROMOTE */
+    uint32_t flags;              /* MC_VALIDATE_ONLY | MC_NO_GRAPH | MC_NO_PROMOTE | MC_RESIDENT */
     uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16); each also takes
                                     1 KiB of pinned host memory (the packed-record mirror) */
-    uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20) */
+    uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20).
+                                    MC_RESIDENT: ring entries that may wait unread (0: one per workgroup) */
     uint64_t max_partials;       /* device tile-partial slots, 16 bytes each, at most 2^32 - 1 (0: 1 << 22) */
     uint64_t mem_budget_bytes;   /* upper bound on device memory the context holds (0: no bound) */
     void* workspace;             /* optional caller-owned device memory for every device buffer */

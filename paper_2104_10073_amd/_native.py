@@ -32,6 +32,7 @@ PREC_FP64 = 1
 MC_VALIDATE_ONLY = 0x1
 MC_NO_GRAPH = 0x2
 MC_NO_PROMOTE = 0x4
+MC_RESIDENT = 0x8          # serve through one resident kernel (include/zmc.h)
 MC_SCHED_FAIR = 0
 MC_SCHED_FIFO = 1
 MC_SCHED_SRPT = 2

@@ -155,4 +155,69 @@ struct alignas(64) LaunchDesc {
     uint32_t tile_count[kMaxKernels];
 };
 
+// ---------------------------------------------------------------- resident engine
+//
+// A context created with MC_RESIDENT keeps one persistent kernel on the GPU
+// while work keeps coming.  The host appends chunks -- up to kChunkTiles
+// consecutive tiles of one function -- to a ring in pinned, fine-grained host
+// memory and publishes the count in a control word.  A workgroup takes a
+// ticket (an atomic add on a device counter) and processes ring entry
+// `ticket` once the control word shows it; the workgroup that counts a
+// function's last tile reduces its partials with the finalize tree, writes the
+// result into pinned host memory and then stores the run's token into the
+// slot's done word the host polls.  Nothing is launched per batch of work.
+//
+// Records are read through the scalar cache, which is only invalidated when a
+// kernel starts, so a record address is never written twice within one launch:
+// every run gets a fresh position in a record arena (its first chunk copies the
+// record there from the host mirror), and the host relaunches the kernel before
+// it reuses a position read in the current launch.
+//
+// Stopping.  The control word's top bit asks workgroups to leave; once it is
+// set (by the host, or by a workgroup that waited `idle_polls` times for its
+// ticket) the device's copy of the word never changes again, so every
+// workgroup sees the same final count: tickets below it are processed, the rest
+// are left, and the processed entries are exactly a prefix of the ring that
+// the host finds from the entries' acknowledgement words.
+constexpr uint32_t kChunkTiles = 8;
+constexpr uint32_t kChunkUpload = 1u;         // copy the record from the host mirror into the arena first
+constexpr uint64_t kCtlStop = 1ull << 63;     // in the control word: leave
+
+struct Chunk {
+    uint32_t fn;                  // function slot (counters, result and done word)
+    uint32_t rec;                 // record arena position of this run
+    uint32_t first;               // the function's tile index of the first tile
+    uint32_t count;               // tiles, 1..kChunkTiles
+    uint32_t part0;               // partial slot of the function's tile 0
+    uint32_t n_tiles;             // the run's tiles (its result is out when all are counted)
+    uint32_t token;               // nonzero, unique per run: reported in the done word
+    uint32_t seg_flags;           // seg_log2 in bits 0..7, kChunkUpload << 8
+};
+
+struct alignas(64) ResidentDesc {
+    const Chunk* ring;            // host: ring_mask + 1 entries
+    uint64_t* ack;                // host: per entry, its position + 1 once a workgroup has read it
+    const uint64_t* host_ctl;     // host: entries written (bits 0..62), kCtlStop
+    uint32_t* host_exit;          // host: the launch's epoch, stored by the last workgroup to leave;
+                                  // the word after it receives the bad-chunk count first
+    DevResult* host_results;      // host: per function slot
+    uint32_t* host_done;          // host: per function slot, the token of the run whose result is out
+    const DevFn* mirror;          // host: packed records by function slot
+    DevFn* arena;                 // device: record arena
+    Partial* partials;
+    uint64_t* pos;                // device: [0] tickets issued, [1] control word as last seen (top bit: stop)
+    uint32_t* running;            // device: workgroups of the launch not yet gone
+    uint32_t* tiles_done;         // device: per function slot, tiles counted in the current run
+    uint32_t* ready;              // device: per arena position, token of the run whose record is in place
+    uint32_t* slot_err;           // device: per function slot, token of a run that met a bad chunk or a timeout
+    uint32_t* bad_records;        // device: chunks that failed their checks
+    uint64_t n_partials;
+    uint32_t n_fns;
+    uint32_t n_arena;
+    uint32_t ring_mask;
+    uint32_t idle_polls;          // polls for a ticket's entry before the workgroup stops the launch
+    uint32_t ready_polls;         // polls of a record's ready word before the chunk is given up
+    uint32_t leader_every;        // workgroups with blockIdx % leader_every == 0 read the host's control word
+};
+
 }  // namespace zmc

@@ -544,6 +544,49 @@ __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, 
     if (lane == 0) *out = Partial{a, b};
 }
 
+// ---------------------------------------------------------------- one function's result
+
+// The per-function second pass, run by one wave: the tile partials P[0 .. n)
+// are summed by repeated 64-wide butterflies over aligned chunks (compacted in
+// place), which is the pairwise tree over tile index; then mean and standard
+// error in FP64.  Every lane returns the result.
+__device__ __forceinline__ DevResult finalize_function(CDevFn* fn, Partial* P, uint32_t n, uint32_t lane,
+                                                       int32_t status)
+{
+    while (n > 1) {
+        const uint32_t chunks = (n + kWave - 1) / kWave;
+        for (uint32_t c = 0; c < chunks; ++c) {
+            const uint32_t i = c * kWave + lane;
+            double a = 0.0, b = 0.0;
+            if (i < n) {
+                a = P[i].s1;
+                b = P[i].s2;
+            }
+            a = wave_sum(a);
+            b = wave_sum(b);
+            if (lane == 0) P[c] = Partial{a, b};
+            __threadfence_block();
+        }
+        n = chunks;
+    }
+    const double g1 = P[0].s1, g2 = P[0].s2;
+    const double S1 = fn->scale1 * g1;
+    const double S2 = fn->scale2 * g2;
+    const uint64_t N = fn->n_samples;
+    const double dn = (double)N;
+    double var = (S2 - S1 * S1 / dn) / (dn - 1.0);
+    if (!(var > 0.0)) var = 0.0;
+    DevResult r;
+    r.mean = fn->volume * (S1 / dn);
+    r.std_error = fn->volume * sqrt(var / dn);
+    r.sum_f = S1;
+    r.sum_f2 = S2;
+    r.n = N;
+    r.status = status;
+    r.precision = fn->precision;
+    return r;
+}
+
 // ---------------------------------------------------------------- caller-supplied integrands
 
 // A run-time compiled family calls F::f(x, p, d) once per sample, with x the

@@ -43,6 +43,7 @@ const void* pack_grid_kernel_ptr();
 const void* pack_table_kernel_ptr();
 const void* sample_points_kernel_ptr();
 const void* plain_reduce_kernel_ptr();
+const void* resident_kernel_ptr();
 // Texts of zmc_device.hpp and zmc_device_code.hpp (generated at build time) for
 // compiling caller-supplied families at run time.
 extern const char* const kRtcHeaderDevice;
@@ -308,6 +309,8 @@ struct FnState {
     double tile_cost;
     bool f64;             // evaluated by the FP64 kernel (requested, or promoted from FP32)
     bool needs_upload;    // record packed into the host mirror, not yet on the device
+    uint32_t token;       // resident engine: the current run's token and record arena position
+    uint32_t rec;
 };
 
 struct Request {
@@ -415,6 +418,57 @@ struct LaunchSlot {
     std::vector<TakeUndo> undo;     // function states before this launch took their tiles
 };
 
+// Resident engine (MC_RESIDENT).  Host side of the ring, the record arena and
+// the runs whose chunks have been pushed.
+constexpr uint32_t kRingEntries = 1u << 16;   // ring entries (power of two)
+constexpr uint32_t kIdlePolls = 30000;        // a workgroup's polls for its entry (~0.1 s) before the launch stops
+constexpr uint32_t kReadyPolls = 400000;      // polls of a record's ready word (~0.1 s) before a chunk is given up
+constexpr uint32_t kLeaderEvery = 8;          // one workgroup in 8 reads the host's control word
+constexpr uint32_t kArenaScan = 64;           // arena positions tried per new run while a launch runs
+
+struct ResRun {
+    Request* req;
+    uint32_t index;  // function of the request
+    uint32_t slot;
+    uint32_t token;
+    uint32_t rec;
+};
+
+struct ResidentState {
+    bool on = false;
+    hipStream_t stream = nullptr;
+    uint32_t grid = 0;             // workgroups per launch
+    uint32_t backlog = 0;          // entries the ring may hold that no workgroup has read yet
+    // pinned, fine-grained host block
+    uint8_t* h_block = nullptr;
+    uint8_t* h_block_dev = nullptr;
+    Chunk* ring = nullptr;
+    uint64_t* ack = nullptr;
+    uint64_t* ctl = nullptr;
+    uint32_t* exit_word = nullptr;
+    uint64_t* stage = nullptr;     // start values of a launch: tickets, control word, workgroups
+    DevResult* results = nullptr;  // per function slot
+    uint32_t* done = nullptr;      // per function slot
+    // device
+    ResidentDesc* d_desc = nullptr;
+    uint64_t* d_pos = nullptr;
+    uint32_t* d_running = nullptr;
+    uint32_t* d_bad = nullptr;
+    uint32_t* d_tiles_done = nullptr;
+    uint32_t n_arena = 0;
+    // ring positions: [0, acked) read by workgroups (or dropped by an abort), [acked, pushed) waiting
+    uint64_t pushed = 0, acked = 0;
+    uint32_t epoch = 0;            // of the last launch (the first is 1)
+    bool live = false;             // the last launch has not stored its exit word yet
+    bool stopping = false;         // the host asked it to stop
+    bool flush = false;            // no arena position free until the running launch ends
+    uint32_t next_token = 0;
+    uint32_t cursor = 0;           // next arena position to try
+    std::vector<uint32_t> arena_epoch;  // per position: the last launch that may have read it
+    std::vector<uint8_t> arena_busy;    // per position: used by a run whose result is not in
+    std::vector<ResRun> runs;           // runs with chunks pushed whose result is not in
+};
+
 constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters (zero padded)
 static_assert(kUserFamily0 == (uint32_t)MC_FAMILY_USER0 && kMaxUserFamilies == MC_MAX_USER_FAMILIES,
               "run-time family ids");
@@ -487,6 +541,8 @@ struct mc_ctx {
     };
     UserFamily user[kMaxUserFamilies];
     uint32_t n_user = 0;
+
+    ResidentState res;
 };
 
 namespace {
@@ -514,12 +570,44 @@ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 struct Layout {
     uint64_t fns, partials, slots, slot_res_bytes, slot_bytes, abort_word, total;
+    // resident contexts: descriptor and counters, per-slot words, ready words, record arena
+    uint64_t res_desc, res_tiles_done, res_slot_err, res_ready, res_arena;
+    uint32_t n_arena;
 };
 
-Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap)
+// Record arena of a resident context: twice the function slots (a run holds
+// one position until its result is in, and positions read by the running
+// launch wait for the next), at least 8192 and at most 2^17 (128 MiB).
+uint32_t arena_positions(uint32_t max_functions)
+{
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(2ull * max_functions, 8192), 1u << 17);
+}
+
+Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap,
+                      bool resident)
 {
     Layout L{};
     uint64_t off = 0;
+    if (resident) {
+        // no launch slots and no per-slot table: records live in the arena
+        L.n_arena = arena_positions(max_functions);
+        L.partials = off;
+        off = align_up(off + max_partials * sizeof(Partial), 256);
+        L.res_desc = off;
+        off += 512;  // ResidentDesc, then tickets and control word, workgroups, bad-chunk count
+        L.res_tiles_done = off;
+        off = align_up(off + (uint64_t)max_functions * sizeof(uint32_t), 256);
+        L.res_slot_err = off;
+        off = align_up(off + (uint64_t)max_functions * sizeof(uint32_t), 256);
+        L.res_ready = off;
+        off = align_up(off + (uint64_t)L.n_arena * sizeof(uint32_t), 256);
+        L.res_arena = off;
+        off += (uint64_t)L.n_arena * sizeof(DevFn);
+        L.abort_word = off;
+        off = align_up(off + sizeof(uint32_t), 256);
+        L.total = off;
+        return L;
+    }
     L.fns = off;
     off = align_up(off + (uint64_t)max_functions * sizeof(DevFn), 256);
     L.partials = off;
@@ -549,7 +637,7 @@ void resolve_capacities(const mc_config& cfg, uint32_t* max_functions, uint64_t*
     } else {
         *max_partials = 1ull << 22;
         if (cfg.mem_budget_bytes) {
-            Layout fixed = compute_layout(*max_functions, 0, *tile_cap, *fin_cap);
+            Layout fixed = compute_layout(*max_functions, 0, *tile_cap, *fin_cap, (cfg.flags & MC_RESIDENT) != 0);
             if (cfg.mem_budget_bytes > fixed.total + 4096)
                 *max_partials = std::min<uint64_t>(*max_partials, (cfg.mem_budget_bytes - fixed.total - 4096) / sizeof(Partial));
             else
@@ -749,6 +837,33 @@ void wait_done(mc_ctx* ctx, LaunchSlot& s)
     }
 }
 
+// A function's result is in: store it, send an FP32 result that cannot be
+// trusted to FP64, and complete the request with its last function.
+void complete_function(mc_ctx* ctx, Request* req, uint32_t index, const DevResult& res, bool bad)
+{
+    mc_result& out = req->results[index];
+    std::memcpy(&out, &res, sizeof(mc_result));
+    if (bad) out.status = MC_ERR_HIP;
+    // the host's own record of the precision decides (a result can be promoted
+    // once); a device record that disagrees is an error
+    const bool host_f64 = req->st[index].f64;
+    if (out.status == MC_OK && out.precision != (host_f64 ? (uint32_t)MC_PREC_FP64 : (uint32_t)MC_PREC_FP32_EVAL)) {
+        out.status = MC_ERR_HIP;
+        ctx->err = "a result came back in another precision than its function was scheduled in";
+    }
+    if (out.status == MC_OK && !host_f64 && ctx->promote && !req->lost &&
+        fp32_unresolved(out, req->grid ? fp32_scale(req->at(index)) : fp32_scale(req->fns[index]))) {
+        promote_to_fp64(ctx, req, index);
+        return;
+    }
+    if (out.status != MC_OK) req->aborted = true;
+    req->fns_done++;
+    if (req->fns_done == req->count()) {
+        free_request_resources(ctx, req);
+        ctx->completed.push_back(req->id);
+    }
+}
+
 // Collect finished launches (oldest first): scatter their results into the
 // requests.  wait = 0: only what has completed; 1: wait for the oldest launch
 // in flight first; 2: wait for every launch in flight.
@@ -779,27 +894,7 @@ void reap(mc_ctx* ctx, int wait)
         }
         for (uint32_t i = 0; i < s.n_fins; ++i) {
             const FinRef& fr = s.fin_refs[i];
-            mc_result& out = fr.req->results[fr.index];
-            std::memcpy(&out, &hres[i], sizeof(mc_result));
-            if (bad != 0) out.status = MC_ERR_HIP;
-            // the host's own record of the precision decides (a result can be
-            // promoted once); a device record that disagrees is an error
-            const bool host_f64 = fr.req->st[fr.index].f64;
-            if (out.status == MC_OK && out.precision != (host_f64 ? (uint32_t)MC_PREC_FP64 : (uint32_t)MC_PREC_FP32_EVAL)) {
-                out.status = MC_ERR_HIP;
-                ctx->err = "a result came back in another precision than its function was scheduled in";
-            }
-            if (out.status == MC_OK && !host_f64 && ctx->promote && !fr.req->lost &&
-                fp32_unresolved(out, fr.req->grid ? fp32_scale(fr.req->at(fr.index)) : fp32_scale(fr.req->fns[fr.index]))) {
-                promote_to_fp64(ctx, fr.req, fr.index);
-                continue;
-            }
-            if (out.status != MC_OK) fr.req->aborted = true;
-            fr.req->fns_done++;
-            if (fr.req->fns_done == fr.req->count()) {
-                free_request_resources(ctx, fr.req);
-                ctx->completed.push_back(fr.req->id);
-            }
+            complete_function(ctx, fr.req, fr.index, hres[i], bad != 0);
         }
         {
             s.ev->released = true;
@@ -824,13 +919,43 @@ void reap(mc_ctx* ctx, int wait)
 // or kernel on another stream would wait for the running persistent kernels
 // to free their compute units, so each record goes up with the stage kernel
 // of the first launch that runs its tiles, and a grid's records are built in
-// the launch stream right before it.
+// the launch stream right before it.  A resident context packs every record
+// into the mirror (grids too, on the host): the first chunk of each run copies
+// it to the device, so admission enqueues nothing.
 void admit(mc_ctx* ctx)
 {
     bool idle = true;
     for (const auto& sl : ctx->slots)
         if (sl.in_flight) idle = false;
     while (!ctx->pending.empty()) {
+        if (ctx->res.on) {
+            Request* r = ctx->pending.front();
+            const uint64_t nf = r->count();
+            uint64_t parts = 0;
+            for (auto& st : r->st) parts += st.n_tiles;
+            uint64_t slot_off = 0, part_off = 0;
+            if (!ctx->fn_alloc.alloc(nf, &slot_off)) return;
+            if (!ctx->part_alloc.alloc(parts, &part_off)) {
+                ctx->fn_alloc.release(slot_off, nf);
+                return;
+            }
+            r->slot_base = (uint32_t)slot_off;
+            r->part_base = part_off;
+            r->part_count = parts;
+            uint64_t p = part_off;
+            for (uint32_t i = 0; i < nf; ++i) {
+                FnState& fs = r->st[i];
+                fs.slot = (uint32_t)slot_off + i;
+                fs.part0 = p;
+                p += fs.n_tiles;
+                pack_function(r->at(i), fs.f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &ctx->h_fns[fs.slot]);
+            }
+            r->admitted = true;
+            r->grid_packed = true;
+            ctx->pending.pop_front();
+            ctx->active.push_back(r);
+            continue;
+        }
         Request* r = ctx->pending.front();
         const uint64_t nf = r->count();
         uint64_t parts = 0;
@@ -1310,8 +1435,340 @@ void finish_abort(mc_ctx* ctx)
     ctx->abort_requested = false;
 }
 
+// ---------------------------------------------------------------- resident engine
+
+void res_publish(ResidentState& R)
+{
+    __atomic_store_n(R.ctl, R.pushed | (R.stopping ? kCtlStop : 0ull), __ATOMIC_RELEASE);
+}
+
+// Advance `acked` over the entries workgroups have read, in ring order.
+void res_scan_acks(ResidentState& R)
+{
+    while (R.acked < R.pushed &&
+           __atomic_load_n(&R.ack[R.acked & (kRingEntries - 1)], __ATOMIC_ACQUIRE) == R.acked + 1)
+        R.acked++;
+}
+
+// Whether the last launch has gone.  Every workgroup acknowledges what it read
+// before it leaves, and the last one stores the exit word after that, so from
+// here on the entries read are exactly [0, acked) (a stopping launch reads a
+// prefix of the ring) and no workgroup touches the ring or a record again.
+bool res_exited(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    if (!R.live) return true;
+    if (__atomic_load_n(R.exit_word, __ATOMIC_ACQUIRE) != R.epoch) return false;
+    R.live = false;
+    R.stopping = false;
+    R.flush = false;
+    res_scan_acks(R);
+    ctx->stats.bad_records = __atomic_load_n(R.exit_word + 1, __ATOMIC_RELAXED);  // (cumulative on the device)
+    return true;
+}
+
+// Ask the running launch to end (its workgroups finish the entries below the
+// count as it stands, then leave).  No entry is pushed until it has gone.
+void res_request_stop(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    if (!R.live || R.stopping) return;
+    R.stopping = true;
+    res_publish(R);
+}
+
+// Start a launch if entries wait and none runs.
+void res_launch(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    if (!res_exited(ctx) || R.pushed == R.acked) return;
+    uint32_t epoch = ++R.epoch;  // (a number whose launch failed is not reused)
+    R.stage[0] = R.acked;
+    R.stage[1] = R.pushed;
+    R.stage[2] = R.grid;
+    res_publish(R);
+    bool enqueued = false;
+    try {
+        enqueued = true;
+        HIP_TRY(hipMemcpyAsync(R.d_pos, R.stage, 2 * sizeof(uint64_t), hipMemcpyHostToDevice, R.stream));
+        HIP_TRY(hipMemcpyAsync(R.d_running, &R.stage[2], sizeof(uint32_t), hipMemcpyHostToDevice, R.stream));
+        ResidentDesc* d = R.d_desc;
+        void* args[] = {&d, &epoch};
+        HIP_TRY(hipLaunchKernel(resident_kernel_ptr(), dim3(R.grid), dim3(kBlockThreads), args, 0, R.stream));
+    } catch (const HipError&) {
+        // the staged start values are rewritten by the next attempt: let what
+        // was enqueued finish first
+        if (enqueued) quiet(hipStreamSynchronize(R.stream));
+        throw;
+    }
+    R.live = true;
+    ctx->stats.launches++;
+}
+
+// A record arena position for a new run.  Records are read through the
+// scalar cache, which a kernel does not see invalidated while it runs, so a
+// position may only be written again by a launch that started after every
+// launch that read it: free means no run uses it and the launch the new run
+// will be read in (the running one, or the next) has not read it.
+bool res_alloc_rec(ResidentState& R, uint32_t* out)
+{
+    const uint32_t first_reader = R.live && !R.stopping ? R.epoch : R.epoch + 1;
+    const uint32_t tries = R.live ? std::min(kArenaScan, R.n_arena) : R.n_arena;
+    for (uint32_t k = 0; k < tries; ++k) {
+        const uint32_t p = R.cursor;
+        R.cursor = R.cursor + 1 == R.n_arena ? 0 : R.cursor + 1;
+        if (!R.arena_busy[p] && R.arena_epoch[p] < first_reader) {
+            *out = p;
+            return true;
+        }
+    }
+    return false;
+}
+
+bool res_room(const ResidentState& R)
+{
+    return !R.stopping && R.pushed - R.acked < R.backlog && R.pushed < R.acked + kRingEntries;
+}
+
+// Push request r's next chunk into the ring (not yet published).  The first
+// chunk of a run takes a token and an arena position and carries the upload
+// flag.  Returns false if nothing was pushed.
+bool res_push_chunk(mc_ctx* ctx, Request* r)
+{
+    ResidentState& R = ctx->res;
+    if (!has_work(r) || !res_room(R)) return false;
+    const bool in_order = r->order_pos < r->order.size();
+    const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
+    FnState& fs = r->st[fi];
+    const bool first = fs.next_tile == 0;
+    if (first) {
+        uint32_t rec = 0;
+        if (R.flush || !res_alloc_rec(R, &rec)) {
+            R.flush = true;
+            return false;
+        }
+        if (++R.next_token == 0) ++R.next_token;
+        fs.token = R.next_token;
+        fs.rec = rec;
+        R.arena_busy[rec] = 1;
+        R.runs.push_back(ResRun{r, fi, fs.slot, fs.token, rec});
+    }
+    // one tile per chunk until a function has more tiles than the launch has
+    // workgroups: a request's tiles spread over as many workgroups as possible
+    const uint32_t left = fs.n_tiles - fs.next_tile;
+    const uint32_t count = std::min(std::min(left, kChunkTiles), std::max(1u, left / R.grid));
+    R.ring[R.pushed & (kRingEntries - 1)] =
+        Chunk{fs.slot, fs.rec, fs.next_tile, count, (uint32_t)fs.part0, fs.n_tiles, fs.token,
+              fs.seg_log2 | (first ? kChunkUpload << 8 : 0u)};
+    R.pushed++;
+    fs.next_tile += count;
+    fs.needs_upload = false;
+    r->tiles_launched += count;
+    r->work_left = std::max(0.0, r->work_left - fs.tile_cost * (double)count);
+    if (fs.f64) ctx->stats.tiles64 += count;
+    else ctx->stats.tiles32 += count;
+    if (fs.next_tile == fs.n_tiles) {
+        if (in_order) r->order_pos++;
+        else r->redo_pos++;
+    }
+    return true;
+}
+
+// Fill the ring up to the backlog by the scheduling policy: FIFO from the
+// oldest request, SRPT from the request with the least work left, FAIR one
+// chunk per request in turn.
+void res_feed(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    res_scan_acks(R);
+    if (!res_room(R) || ctx->active.empty()) return;
+    const uint64_t before = R.pushed;
+    if (ctx->policy == MC_SCHED_SRPT)
+        std::stable_sort(ctx->active.begin(), ctx->active.end(),
+                         [](const Request* a, const Request* b) { return a->work_left < b->work_left; });
+    if (ctx->policy == MC_SCHED_FAIR) {
+        for (bool any = true; any && res_room(R);) {
+            any = false;
+            for (Request* r : ctx->active)
+                if (res_push_chunk(ctx, r)) any = true;
+        }
+    } else {
+        for (Request* r : ctx->active) {
+            while (res_push_chunk(ctx, r)) {
+            }
+            if (!res_room(R) || R.flush) break;
+        }
+    }
+    std::deque<Request*> keep;
+    for (Request* r : ctx->active)
+        if (has_work(r)) keep.push_back(r);
+    ctx->active.swap(keep);
+    if (R.pushed != before) res_publish(R);
+    // arena positions of the running launch are exhausted: end it, so that
+    // the next one may reuse them
+    if (R.flush) res_request_stop(ctx);
+}
+
+// Results of runs whose done word shows their token.
+void res_reap(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    size_t w = 0;
+    const size_t n = R.runs.size();
+    for (size_t i = 0; i < n; ++i) {
+        const ResRun run = R.runs[i];
+        if (__atomic_load_n(&R.done[run.slot], __ATOMIC_ACQUIRE) != run.token) {
+            R.runs[w++] = run;
+            continue;
+        }
+        DevResult res;
+        std::memcpy(&res, &R.results[run.slot], sizeof res);
+        R.arena_busy[run.rec] = 0;
+        R.arena_epoch[run.rec] = R.epoch;
+        ctx->stats.functions++;
+        ctx->stats.samples += res.n;
+        complete_function(ctx, run.req, run.index, res, false);
+    }
+    R.runs.resize(w);
+}
+
+void res_fail(mc_ctx* ctx);
+
+// Wait until the last launch has gone.  The kernel leaves by itself (a
+// stopping launch within a chunk per workgroup, an idle one within its poll
+// bound); a stream that reports an error, or that is idle while the exit word
+// never came, is an error.
+void res_wait_exit(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    for (uint64_t i = 0; !res_exited(ctx); ++i) {
+        if (i < 4096) continue;
+        if (i < 65536) {
+            sched_yield();
+            continue;
+        }
+        if ((i & 255) == 0) {
+            const hipError_t q = hipStreamQuery(R.stream);
+            quiet(q);
+            if (q != hipErrorNotReady) {
+                if (res_exited(ctx)) return;
+                res_fail(ctx);
+                if (q != hipSuccess) throw HipError{q, "hipStreamQuery(resident launch)"};
+                throw HipError{hipErrorUnknown, "resident launch finished without its exit word"};
+            }
+        }
+        struct timespec ts{0, 20000};
+        nanosleep(&ts, nullptr);
+    }
+}
+
+// The resident launch failed (an error from its stream, or it never stored its
+// exit word): every run in the ring is lost and its request completes with
+// MC_ERR_HIP; with the stream idle nothing refers to their slots any more.
+void res_fail(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    for (const ResRun& run : R.runs) {
+        Request* r = run.req;
+        R.arena_busy[run.rec] = 0;
+        R.arena_epoch[run.rec] = R.epoch;
+        if (r->lost) continue;
+        r->lost = true;
+        r->order_pos = (uint32_t)r->order.size();
+        r->redo_pos = (uint32_t)r->redo.size();
+        r->tiles_launched = r->tiles_total;
+        r->work_left = 0.0;
+    }
+    R.runs.clear();
+    std::deque<Request*> keep;
+    for (Request* r : ctx->active)
+        if (!r->lost) keep.push_back(r);
+    ctx->active.swap(keep);
+    R.live = false;
+    R.stopping = false;
+    R.flush = false;
+    R.acked = R.pushed;
+    __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
+}
+
+// After mc_abort on a resident context: the launch has been asked to stop;
+// once it has gone, results that came in complete normally, every other
+// request completes as aborted, the unread entries are dropped and the slot
+// counters the cancelled runs leave behind are cleared.
+void res_finish_abort(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    res_request_stop(ctx);
+    res_wait_exit(ctx);
+    res_reap(ctx);
+    std::vector<Request*> cancel;
+    for (const ResRun& run : R.runs) {
+        R.arena_busy[run.rec] = 0;
+        R.arena_epoch[run.rec] = R.epoch;
+        cancel.push_back(run.req);
+    }
+    R.runs.clear();
+    for (Request* r : ctx->active) cancel.push_back(r);
+    for (Request* r : ctx->pending) cancel.push_back(r);
+    ctx->active.clear();
+    ctx->pending.clear();
+    for (Request* r : cancel) {
+        if (r->fns_done == r->count()) continue;  // (listed twice)
+        for (uint32_t i = 0; i < r->count(); ++i) {
+            mc_result& out = r->results[i];
+            std::memset(&out, 0, sizeof out);
+            out.n = r->grid ? r->spec.base.n_samples : r->fns[i].n_samples;
+            out.status = MC_ERR_ABORTED;
+            out.precision = (uint32_t)r->precision;
+        }
+        r->aborted = true;
+        r->fns_done = (uint32_t)r->count();
+        r->order_pos = (uint32_t)r->order.size();
+        r->redo_pos = (uint32_t)r->redo.size();
+        r->tiles_launched = r->tiles_total;
+        r->work_left = 0.0;
+        free_request_resources(ctx, r);
+        ctx->completed.push_back(r->id);
+    }
+    R.acked = R.pushed;
+    __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
+    HIP_TRY(hipMemsetAsync(R.d_tiles_done, 0, (size_t)ctx->max_functions * sizeof(uint32_t), R.stream));
+    HIP_TRY(hipStreamSynchronize(R.stream));
+    ctx->abort_requested = false;
+}
+
+// One step of a resident context: collect results, admit, feed the ring and
+// (re)launch the kernel if entries wait and it has gone.
+void res_step(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    res_exited(ctx);
+    res_reap(ctx);
+    if (ctx->abort_requested) res_finish_abort(ctx);
+    admit(ctx);
+    res_feed(ctx);
+    if (!R.live) res_launch(ctx);
+}
+
+// Whether the resident launch is known to have failed; checks the stream.
+bool res_stream_failed(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    if (!R.live) return false;
+    const hipError_t q = hipStreamQuery(R.stream);
+    quiet(q);
+    if (q == hipErrorNotReady) return false;
+    if (res_exited(ctx)) return false;
+    return true;  // an error, or idle without the exit word
+}
+
 void destroy_device(mc_ctx* ctx)
 {
+    ResidentState& R = ctx->res;
+    if (R.stream) quiet(hipStreamDestroy(R.stream));
+    R.stream = nullptr;
+    if (R.h_block) quiet(hipHostFree(R.h_block));
+    R.h_block = nullptr;
     for (auto& s : ctx->slots) {
         if (s.graph) quiet(hipGraphExecDestroy(s.graph));
         if (s.h_block) quiet(hipHostFree(s.h_block));
@@ -1350,6 +1807,123 @@ void default_tuning(mc_ctx* ctx)
             for (int d = 0; d < kMaxDim; ++d) ctx->seg_log2[p][f][d] = d == 0 ? 2 : d == 1 ? 1 : 0;
 }
 
+// Device state of a resident context: its stream, the pinned host block
+//   [ring | acknowledgements | control word | exit word | start values | results | done words]
+// and, in device memory, the descriptor, counters, per-slot words, ready words
+// (zeroed: tokens start at 1) and the record arena.
+void create_resident(mc_ctx* ctx, const Layout& L, uint8_t* base)
+{
+    ResidentState& R = ctx->res;
+    const mc_config& cfg = ctx->cfg;
+    int occ = 0;
+    HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resident_kernel_ptr(), kBlockThreads, 0));
+    R.grid = (uint32_t)ctx->num_cus * (cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ));
+    R.backlog = cfg.max_tiles_per_run ? std::min<uint32_t>(cfg.max_tiles_per_run, kRingEntries / 2)
+                                      : std::min<uint32_t>(R.grid, kRingEntries / 2);
+    R.n_arena = L.n_arena;
+    R.arena_epoch.assign(R.n_arena, 0u);
+    R.arena_busy.assign(R.n_arena, 0u);
+    const uint64_t ring_off = 0;
+    const uint64_t ack_off = ring_off + (uint64_t)kRingEntries * sizeof(Chunk);
+    const uint64_t ctl_off = ack_off + (uint64_t)kRingEntries * sizeof(uint64_t);
+    const uint64_t exit_off = ctl_off + 64;
+    const uint64_t stage_off = exit_off + 64;
+    const uint64_t res_off = stage_off + 256;
+    const uint64_t done_off = res_off + (uint64_t)ctx->max_functions * sizeof(DevResult);
+    const uint64_t bytes = done_off + (uint64_t)ctx->max_functions * sizeof(uint32_t);
+    HIP_TRY(hipHostMalloc((void**)&R.h_block, bytes, hipHostMallocMapped | hipHostMallocCoherent));
+    HIP_TRY(hipHostGetDevicePointer((void**)&R.h_block_dev, R.h_block, 0));
+    std::memset(R.h_block, 0, bytes);
+    R.ring = (Chunk*)(R.h_block + ring_off);
+    R.ack = (uint64_t*)(R.h_block + ack_off);
+    R.ctl = (uint64_t*)(R.h_block + ctl_off);
+    R.exit_word = (uint32_t*)(R.h_block + exit_off);
+    R.stage = (uint64_t*)(R.h_block + stage_off);
+    R.results = (DevResult*)(R.h_block + res_off);
+    R.done = (uint32_t*)(R.h_block + done_off);
+    HIP_TRY(hipStreamCreateWithFlags(&R.stream, hipStreamNonBlocking));
+    R.d_desc = (ResidentDesc*)(base + L.res_desc);
+    R.d_pos = (uint64_t*)(base + L.res_desc + 256);
+    R.d_running = (uint32_t*)(base + L.res_desc + 256 + 16);
+    R.d_bad = (uint32_t*)(base + L.res_desc + 256 + 20);
+    R.d_tiles_done = (uint32_t*)(base + L.res_tiles_done);
+    static_assert(sizeof(ResidentDesc) <= 256, "resident descriptor size");
+    ResidentDesc D{};
+    uint8_t* hb = R.h_block_dev;
+    D.ring = (const Chunk*)(hb + ring_off);
+    D.ack = (uint64_t*)(hb + ack_off);
+    D.host_ctl = (const uint64_t*)(hb + ctl_off);
+    D.host_exit = (uint32_t*)(hb + exit_off);
+    D.host_results = (DevResult*)(hb + res_off);
+    D.host_done = (uint32_t*)(hb + done_off);
+    D.mirror = ctx->h_fns_dev;
+    D.arena = (DevFn*)(base + L.res_arena);
+    D.partials = ctx->d_partials;
+    D.pos = R.d_pos;
+    D.running = R.d_running;
+    D.tiles_done = R.d_tiles_done;
+    D.ready = (uint32_t*)(base + L.res_ready);
+    D.slot_err = (uint32_t*)(base + L.res_slot_err);
+    D.bad_records = R.d_bad;
+    D.n_partials = ctx->max_partials;
+    D.n_fns = ctx->max_functions;
+    D.n_arena = R.n_arena;
+    D.ring_mask = kRingEntries - 1;
+    D.idle_polls = kIdlePolls;
+    D.ready_polls = kReadyPolls;
+    D.leader_every = kLeaderEvery;
+    // the descriptor goes up through the start-value block (256 bytes, unused
+    // until the first launch); the words after it are zeroed
+    std::memcpy(R.stage, &D, sizeof D);
+    HIP_TRY(hipMemcpyAsync(R.d_desc, R.stage, sizeof D, hipMemcpyHostToDevice, R.stream));
+    HIP_TRY(hipMemsetAsync(base + L.res_desc + 256, 0, L.res_arena - (L.res_desc + 256), R.stream));
+    HIP_TRY(hipStreamSynchronize(R.stream));
+    std::memset(R.stage, 0, 256);
+}
+
+// mc_results on a resident context.  A blocking wait steps the context (which
+// keeps the ring fed and relaunches the kernel when it has gone), spinning,
+// then yielding, then sleeping in short steps, and checks the launch's stream
+// now and then: an error, or an idle stream whose launch never stored its exit
+// word, fails the runs in the ring instead of waiting for them.
+mc_status res_results(mc_ctx* ctx, std::unordered_map<uint64_t, std::unique_ptr<Request>>::iterator it,
+                      mc_result* out, size_t n, int blocking)
+{
+    Request* r = it->second.get();
+    const uint64_t id = r->id;
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        for (uint64_t i = 0; r->fns_done < r->count(); ++i) {
+            if (r->lost) {
+                free_request_resources(ctx, r);
+                ctx->requests.erase(it);
+                return fail(ctx, MC_ERR_HIP, "request %llu cannot complete: the resident launch failed",
+                            (unsigned long long)id);
+            }
+            res_step(ctx);
+            if (r->fns_done == r->count() || r->lost) continue;
+            if (!blocking) return MC_NOT_READY;
+            if (i < 2048) continue;
+            if (i < 16384) {
+                sched_yield();
+                continue;
+            }
+            if ((i & 255) == 0 && res_stream_failed(ctx)) {
+                res_fail(ctx);
+                continue;
+            }
+            struct timespec ts{0, 20000};
+            nanosleep(&ts, nullptr);
+        }
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    std::memcpy(out, r->results.data(), n * sizeof(mc_result));
+    const bool aborted = r->aborted;
+    ctx->requests.erase(it);
+    return aborted ? MC_ERR_ABORTED : MC_OK;
+}
+
 }  // namespace
 
 // ====================================================================== C ABI
@@ -1369,7 +1943,7 @@ mc_status mc_workspace_size(const mc_config* cfg, uint64_t* bytes)
     uint32_t mf, tc, fc;
     uint64_t mp;
     resolve_capacities(*cfg, &mf, &mp, &tc, &fc);
-    *bytes = compute_layout(mf, mp, tc, fc).total;
+    *bytes = compute_layout(mf, mp, tc, fc, (cfg->flags & MC_RESIDENT) != 0).total;
     return MC_OK;
 }
 
@@ -1384,6 +1958,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
     ctx->validate_only = (cfg.flags & MC_VALIDATE_ONLY) != 0;
     ctx->use_graph = (cfg.flags & MC_NO_GRAPH) == 0;
     ctx->promote = (cfg.flags & MC_NO_PROMOTE) == 0;
+    ctx->res.on = (cfg.flags & MC_RESIDENT) != 0;
     ctx->device = cfg.device;
     if (cfg.policy > MC_SCHED_SRPT) return fail(nullptr, MC_ERR_INVALID_ARG, "unknown policy %u", cfg.policy);
     // tiles, finalize records and partial indices are 32-bit; the pinned mirror holds 1 KiB per slot
@@ -1420,7 +1995,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         ctx->blocks_per_cu32 = cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ32);
         ctx->blocks_per_cu64 = (uint32_t)std::max(1, occ64);
 
-        Layout L = compute_layout(ctx->max_functions, ctx->max_partials, ctx->tile_cap, ctx->fin_cap);
+        Layout L = compute_layout(ctx->max_functions, ctx->max_partials, ctx->tile_cap, ctx->fin_cap, ctx->res.on);
         ctx->slot_res_bytes = L.slot_res_bytes;
         ctx->slot_bytes = L.slot_bytes;
         if (cfg.mem_budget_bytes && L.total > cfg.mem_budget_bytes)
@@ -1447,9 +2022,9 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         }
         ctx->mem_bytes = L.total;
         uint8_t* base = (uint8_t*)ctx->mem_base;
-        ctx->d_fns = (DevFn*)(base + L.fns);
+        ctx->d_fns = ctx->res.on ? nullptr : (DevFn*)(base + L.fns);
         ctx->d_partials = (Partial*)(base + L.partials);
-        for (int i = 0; i < kLaunchSlots; ++i) {
+        for (int i = 0; i < (ctx->res.on ? 0 : kLaunchSlots); ++i) {
             LaunchSlot& s = ctx->slots[i];
             s.d_block = base + L.slots + (uint64_t)i * L.slot_bytes;
             s.d_desc = (LaunchDesc*)(s.d_block + L.slot_res_bytes);
@@ -1472,6 +2047,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[0], sizeof(uint32_t), hipMemcpyHostToDevice,
                                ctx->upload_stream));
         HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
+        if (ctx->res.on) create_resident(ctx.get(), L, base);
     } catch (const HipError& e) {
         mc_status st = fail_hip(nullptr, e);
         destroy_device(ctx.get());
@@ -1488,6 +2064,12 @@ mc_status mc_destroy(mc_ctx* ctx)
         quiet(hipSetDevice(ctx->device));
         for (auto& s : ctx->slots)
             if (s.in_flight && s.ev) quiet(hipEventSynchronize(s.ev->done));
+        if (ctx->res.on && ctx->res.stream) {
+            // ask a running launch to leave and wait for it (it leaves within a
+            // chunk per workgroup once it has seen the stop bit)
+            res_request_stop(ctx);
+            quiet(hipStreamSynchronize(ctx->res.stream));
+        }
     }
     if (!ctx->validate_only) destroy_device(ctx);
     delete ctx;
@@ -1568,6 +2150,8 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f, bool
     fs.next_tile = 0;
     fs.f64 = f64;
     fs.needs_upload = false;
+    fs.token = 0;
+    fs.rec = 0;
     fs.tile_cost = sample_cost(d.family, d.dim, f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL) *
                    (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
     r->tiles_total += fs.n_tiles;
@@ -1714,6 +2298,10 @@ mc_status mc_run(mc_ctx* ctx, void* stream)
     bool no_slot = false;
     try {
         HIP_TRY(hipSetDevice(ctx->device));
+        if (ctx->res.on) {
+            res_step(ctx);
+            return MC_OK;
+        }
         hipStream_t s = (hipStream_t)stream;
         reap(ctx, 0);
         if (ctx->abort_requested) finish_abort(ctx);
@@ -1732,7 +2320,8 @@ mc_status mc_poll(mc_ctx* ctx, uint64_t* completed, size_t cap, size_t* n)
     if (ctx->validate_only) return MC_OK;
     try {
         HIP_TRY(hipSetDevice(ctx->device));
-        reap(ctx, 0);
+        if (ctx->res.on) res_step(ctx);
+        else reap(ctx, 0);
     } catch (const HipError& e) {
         return fail_hip(ctx, e);
     }
@@ -1768,6 +2357,7 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
         return fail(ctx, MC_ERR_INVALID_ARG, "request %llu has %zu functions, got n=%zu", (unsigned long long)request_id,
                     r->count(), n);
     if (ctx->validate_only) return fail(ctx, MC_ERR_NO_DEVICE, "validate-only context has no device");
+    if (ctx->res.on) return res_results(ctx, it, out, n, blocking);
     try {
         HIP_TRY(hipSetDevice(ctx->device));
         reap(ctx, 0);
@@ -1810,6 +2400,11 @@ mc_status mc_abort(mc_ctx* ctx)
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (ctx->validate_only) return MC_OK;
+    if (ctx->res.on) {
+        res_request_stop(ctx);
+        ctx->abort_requested = true;
+        return MC_OK;
+    }
     try {
         HIP_TRY(hipSetDevice(ctx->device));
         // The upload stream is non-blocking, so the word changes while kernels run.
@@ -2133,6 +2728,9 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
         return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
     const char* cache = std::getenv("MC_TUNE_CACHE");
     if (cache && *cache && load_tuning(ctx, cache, precision)) return MC_OK;
+    if (ctx->res.on)
+        return fail(ctx, MC_ERR_INVALID_ARG,
+                    "a resident context does not time launches: tune a launch context (with MC_TUNE_CACHE) first");
     const mc_status st = autotune_run(ctx, precision, stream, budget_seconds);
     if (st == MC_OK && cache && *cache) store_tuning(ctx, cache, precision);
     return st;
@@ -2305,6 +2903,7 @@ mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_o
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (!source || !family_out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "a resident context serves the built-in families only");
     if (ctx->n_user >= (uint32_t)kMaxUserFamilies)
         return fail(ctx, MC_ERR_INVALID_ARG, "at most %d run-time families per context", kMaxUserFamilies);
     const uint32_t u = ctx->n_user;

@@ -85,42 +85,8 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
             continue;
         }
         CDevFn* fn = scalar_view(fns + fin.fn);
-        Partial* P = partials + fin.part0;
-        uint32_t n = fin.n_tiles;
-        while (n > 1) {
-            const uint32_t chunks = (n + kWave - 1) / kWave;
-            for (uint32_t c = 0; c < chunks; ++c) {
-                const uint32_t i = c * kWave + lane;
-                double a = 0.0, b = 0.0;
-                if (i < n) {
-                    a = P[i].s1;
-                    b = P[i].s2;
-                }
-                a = wave_sum(a);
-                b = wave_sum(b);
-                if (lane == 0) P[c] = Partial{a, b};
-                __threadfence_block();
-            }
-            n = chunks;
-        }
-        if (lane == 0) {
-            const double g1 = P[0].s1, g2 = P[0].s2;
-            const double S1 = fn->scale1 * g1;
-            const double S2 = fn->scale2 * g2;
-            const uint64_t N = fn->n_samples;
-            const double dn = (double)N;
-            double var = (S2 - S1 * S1 / dn) / (dn - 1.0);
-            if (!(var > 0.0)) var = 0.0;
-            DevResult r;
-            r.mean = fn->volume * (S1 / dn);
-            r.std_error = fn->volume * sqrt(var / dn);
-            r.sum_f = S1;
-            r.sum_f2 = S2;
-            r.n = N;
-            r.status = aborted ? -10 : 0;
-            r.precision = fn->precision;
-            results[fin.res] = r;
-        }
+        const DevResult r = finalize_function(fn, partials + fin.part0, fin.n_tiles, lane, aborted ? -10 : 0);
+        if (lane == 0) results[fin.res] = r;
     }
 }
 

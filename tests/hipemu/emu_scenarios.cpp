@@ -450,10 +450,11 @@ bool fault_workload(uint32_t flags, bool* clean)
     return true;
 }
 
-// Fail the n-th checked HIP call, for every n the workload makes, with and without graphs.
+// Fail the n-th checked HIP call, for every n the workload makes, with and
+// without graphs, and on a resident context.
 bool fault_sweep()
 {
-    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u}) {
+    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u, (uint32_t)MC_RESIDENT}) {
         unsetenv("MC_FAULT_HIP");
         bool clean = false;
         const uint64_t c0 = hipemu::api_calls();
@@ -542,6 +543,178 @@ bool autotune_cache()
     return ok;
 }
 
+// ---------------------------------------------------------------- resident contexts
+
+// Drive requests with mc_run / mc_poll only; returns the ids in completion order.
+bool drive(mc_ctx* ctx, size_t n_requests, std::vector<uint64_t>* order, int max_steps = 2000000)
+{
+    for (int guard = 0; guard < max_steps && order->size() < n_requests; ++guard) {
+        const mc_status st = mc_run(ctx, nullptr);
+        CHECK(st == MC_OK, "run %d: %s", (int)st, mc_last_error(ctx));
+        uint64_t got[16];
+        size_t n = 0;
+        CHECK(mc_poll(ctx, got, 16, &n) == MC_OK, "poll");
+        for (size_t i = 0; i < n; ++i) order->push_back(got[i]);
+    }
+    CHECK(order->size() == n_requests, "%zu of %zu requests completed", order->size(), n_requests);
+    return true;
+}
+
+// Every policy: FP32 requests with rows the FP32 check sends to FP64 (a second
+// run of the function, with a new record), FP64 requests and a grid, submitted
+// together and served by the resident kernel; results exactly as the launch
+// path gives them; nothing left pending; a launch context beside it agrees.
+bool resident_basic()
+{
+    for (uint32_t policy : {MC_SCHED_FAIR, MC_SCHED_FIFO, MC_SCHED_SRPT}) {
+        mc_ctx* ctx = create(MC_RESIDENT, 0, policy);
+        CHECK(ctx, "create: %s", mc_last_error(nullptr));
+        std::vector<std::vector<mc_function>> reqs = {mixed_table(40, 100, 7), mixed_table(3, 101), mixed_table(60, 102),
+                                                      mixed_table(25, 103, 5)};
+        std::vector<uint64_t> ids;
+        for (size_t k = 0; k < reqs.size(); ++k) {
+            uint64_t id = 0;
+            CHECK(mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id) ==
+                      MC_OK, "submit: %s", mc_last_error(ctx));
+            ids.push_back(id);
+        }
+        const mc_function base = make_fn(MC_FAMILY_HARMONIC, 3, 50001, 7ull << 32, 1.5);
+        mc_grid_axis axes[2] = {{MC_PARAM_V0, 5, 1.0, 0.5}, {0, 3, 0.5, 0.25}};
+        uint64_t gid = 0;
+        CHECK(mc_submit_grid(ctx, &base, axes, 2, MC_PREC_FP32_EVAL, &gid) == MC_OK, "grid: %s", mc_last_error(ctx));
+        std::vector<uint64_t> order;
+        if (!drive(ctx, ids.size() + 1, &order)) return false;
+        for (size_t k = 0; k < reqs.size(); ++k) {
+            std::vector<mc_result> r(reqs[k].size());
+            CHECK(mc_results(ctx, ids[k], r.data(), r.size(), 0) == MC_OK, "results: %s", mc_last_error(ctx));
+            if (!check_results(reqs[k], r, k == 1, "resident")) return false;
+        }
+        std::vector<mc_result> gr(15);
+        CHECK(mc_results(ctx, gid, gr.data(), 15, 0) == MC_OK, "grid results");
+        std::vector<mc_function> gt;
+        for (uint64_t i = 0; i < 15; ++i) {
+            mc_function f = base;
+            f.params[MC_PARAM_V0] = 1.0 + (double)(i % 5) * 0.5;
+            f.params[0] = 0.5 + (double)(i / 5) * 0.25;
+            f.seed = base.seed + i;
+            gt.push_back(f);
+        }
+        if (!check_results(gt, gr, false, "resident grid")) return false;
+        mc_stats st;
+        CHECK(mc_get_stats(ctx, &st) == MC_OK && st.bad_records == 0, "stats");
+        CHECK(st.promoted == 6 + 5, "promoted %llu", (unsigned long long)st.promoted);
+        CHECK(st.functions == 40 + 3 + 60 + 25 + 15 + 11, "functions %llu", (unsigned long long)st.functions);
+        uint64_t pr = 1, pt = 1;
+        CHECK(mc_pending(ctx, &pr, &pt) == MC_OK && pr == 0 && pt == 0, "pending");
+        // a blocking request afterwards, and one on a launch context at the same time
+        mc_ctx* other = create(0, 7);
+        CHECK(other, "create launch context");
+        if (!run_request(ctx, mixed_table(9, 104, 3), false, "resident blocking")) return false;
+        if (!run_request(other, mixed_table(9, 104, 3), false, "launch context")) return false;
+        mc_destroy(other);
+        uint32_t fam = 0;
+        CHECK(mc_register_family(ctx, "x", &fam) == MC_ERR_INVALID_ARG, "run-time families refused");
+        CHECK(mc_autotune(ctx, MC_PREC_FP32_EVAL, nullptr, 0.1) == MC_ERR_INVALID_ARG, "autotune refused");
+        mc_destroy(ctx);
+    }
+    return true;
+}
+
+// The kernel leaves by itself after a while without work; the next request
+// starts a new launch.  A context destroyed while its kernel runs stops it.
+bool resident_relaunch()
+{
+    mc_ctx* ctx = create(MC_RESIDENT);
+    CHECK(ctx, "create");
+    if (!run_request(ctx, mixed_table(10, 110), false, "first")) return false;
+    mc_stats st;
+    CHECK(mc_get_stats(ctx, &st) == MC_OK && st.launches == 1, "launches %llu", (unsigned long long)st.launches);
+    usleep(300000);  // longer than the (emulated) idle bound
+    if (!run_request(ctx, mixed_table(10, 111, 4), false, "second")) return false;
+    CHECK(mc_get_stats(ctx, &st) == MC_OK && st.launches == 2, "launches %llu", (unsigned long long)st.launches);
+    uint64_t id = 0;
+    const std::vector<mc_function> t = mixed_table(30, 112);
+    CHECK(mc_submit(ctx, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+    CHECK(mc_run(ctx, nullptr) == MC_OK, "run");
+    mc_destroy(ctx);  // with the kernel running and the request unfinished
+    return true;
+}
+
+// More runs than the record arena holds within one launch: the host ends the
+// launch (the workgroups finish what they read) and starts the next, and every
+// result is as expected.  Small rings of unread entries, every policy.
+bool resident_flush()
+{
+    for (uint32_t policy : {MC_SCHED_FAIR, MC_SCHED_SRPT}) {
+        mc_ctx* ctx = create(MC_RESIDENT, 3, policy, 1200, 1 << 16);
+        CHECK(ctx, "create");
+        std::vector<std::vector<mc_function>> reqs;
+        std::vector<uint64_t> ids;
+        for (int k = 0; k < 10; ++k) {
+            std::vector<mc_function> t;
+            for (int i = 0; i < 1000; ++i) {
+                const uint64_t seed = (200ull + k) << 32 | (uint64_t)i | (i % 97 == 1 ? 1ull << 63 : 0ull);
+                t.push_back(make_fn((uint32_t)(i % 4), 1 + (uint32_t)(i % 5), i % 13 == 0 ? 20001 : 7, seed));
+            }
+            reqs.push_back(t);
+        }
+        std::vector<uint64_t> order;
+        size_t submitted = 0;
+        for (int guard = 0; guard < 4000000 && order.size() < reqs.size(); ++guard) {
+            if (submitted < reqs.size()) {
+                uint64_t id = 0;
+                const mc_status st = mc_submit(ctx, reqs[submitted].data(), reqs[submitted].size(), MC_PREC_FP32_EVAL, &id);
+                CHECK(st == MC_OK, "submit: %s", mc_last_error(ctx));
+                ids.push_back(id);
+                ++submitted;
+            }
+            CHECK(mc_run(ctx, nullptr) == MC_OK, "run: %s", mc_last_error(ctx));
+            uint64_t got[16];
+            size_t n = 0;
+            CHECK(mc_poll(ctx, got, 16, &n) == MC_OK, "poll");
+            for (size_t i = 0; i < n; ++i) order.push_back(got[i]);
+        }
+        CHECK(order.size() == reqs.size(), "requests did not all complete");
+        for (size_t k = 0; k < reqs.size(); ++k) {
+            std::vector<mc_result> r(reqs[k].size());
+            CHECK(mc_results(ctx, ids[k], r.data(), r.size(), 0) == MC_OK, "results");
+            if (!check_results(reqs[k], r, false, "flush")) return false;
+        }
+        mc_stats st;
+        CHECK(mc_get_stats(ctx, &st) == MC_OK && st.bad_records == 0, "stats");
+        CHECK(st.launches >= 2, "launches %llu", (unsigned long long)st.launches);
+        std::printf("resident flush (policy %u): %llu launches, %llu functions, %llu promoted\n", policy,
+                    (unsigned long long)st.launches, (unsigned long long)st.functions,
+                    (unsigned long long)st.promoted);
+        mc_destroy(ctx);
+    }
+    return true;
+}
+
+// Abort while the ring holds work: results that were in complete normally, the
+// rest come back aborted; the context serves the next request.
+bool resident_abort()
+{
+    mc_ctx* ctx = create(MC_RESIDENT, 2);
+    CHECK(ctx, "create");
+    const std::vector<mc_function> t = mixed_table(40, 120);
+    uint64_t id = 0, id2 = 0;
+    CHECK(mc_submit(ctx, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+    CHECK(mc_submit(ctx, t.data(), 5, MC_PREC_FP64, &id2) == MC_OK, "submit");
+    CHECK(mc_run(ctx, nullptr) == MC_OK, "run");
+    CHECK(mc_abort(ctx) == MC_OK, "abort");
+    std::vector<mc_result> r(t.size());
+    const mc_status st = mc_results(ctx, id, r.data(), r.size(), 1);
+    CHECK(st == MC_ERR_ABORTED, "aborted request: %d", (int)st);
+    for (size_t i = 0; i < t.size(); ++i) CHECK(r[i].status == MC_ERR_ABORTED, "status %d", r[i].status);
+    std::vector<mc_result> r2(5);
+    CHECK(mc_results(ctx, id2, r2.data(), 5, 1) == MC_ERR_ABORTED, "second request aborted");
+    if (!run_request(ctx, mixed_table(12, 121, 3), false, "after abort")) return false;
+    if (!run_request(ctx, mixed_table(12, 122), true, "after abort fp64")) return false;
+    mc_destroy(ctx);
+    return true;
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -550,7 +723,9 @@ int main(int argc, char** argv)
         {"basic", basic},     {"many_launches", many_launches}, {"admission", admission},
         {"grid", grid},       {"abort", abort_and_continue},    {"errors", errors},
         {"plain", plain_paths}, {"two_contexts", two_contexts}, {"fault_sweep", fault_sweep},
-        {"autotune_cache", autotune_cache},
+        {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
+        {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
+        {"resident_abort", resident_abort},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {

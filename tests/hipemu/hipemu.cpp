@@ -25,15 +25,26 @@
 //   (expected_batched / expected_plain below).  A tile of the FP32 kernel of a
 //   function whose seed has bit 63 set contributes a constant instead (zero
 //   spread), which the library's FP32 check sends to FP64.
+// * The resident kernel runs in worker threads that start at its launch and
+//   follow the kernel's protocol on the same words: tickets, the host's control
+//   word with the stop bit, acknowledgements, the record copy into the arena
+//   and its ready word, per-slot tile counts, the finalize by whichever worker
+//   counts a run's last tile, done words, the exit word of the last worker to
+//   leave, and the bounded waits (shortened to milliseconds).  A stream whose
+//   resident launch is running finishes it before anything else enqueued on it.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
+#include <time.h>
+
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <set>
+#include <thread>
 #include <vector>
 
 #include "hipemu.hpp"
@@ -248,6 +259,138 @@ void k_plain_reduce(void** a, dim3)
     *res = result_from(*fn, S1, S2, 0, 1u);
 }
 
+// One tile's partial, as the batched emulation computes it.
+Partial tile_partial(const DevFn& fn, uint32_t seg0, uint32_t per_tile, bool fp32_kernel)
+{
+    double s1 = 0.0, s2 = 0.0;
+    for (uint32_t s = seg0; s < seg0 + per_tile && s < fn.n_segments; ++s) {
+        const uint64_t first = (uint64_t)s * kSegSamples;
+        const double n = (double)std::min<uint64_t>(kSegSamples, fn.n_samples - first);
+        if (fp32_kernel && constant_in_fp32(fn)) {
+            s1 += n;
+            s2 += n;
+        } else {
+            const double tag = unit_tag(fn.key0, s);
+            s1 += n + tag;
+            s2 += 3.0 * n + tag * tag;
+        }
+    }
+    return Partial{s1, s2};
+}
+
+void short_sleep()
+{
+    struct timespec ts{0, 2000};
+    nanosleep(&ts, nullptr);
+}
+
+uint64_t fetch_max_u64(uint64_t* p, uint64_t v)
+{
+    uint64_t old = __atomic_load_n(p, __ATOMIC_ACQUIRE);
+    while (old < v && !__atomic_compare_exchange_n(p, &old, v, false, __ATOMIC_ACQ_REL, __ATOMIC_ACQUIRE)) {
+    }
+    return old;
+}
+
+// The resident kernel's loop, for one worker (a workgroup of the real launch).
+void resident_worker(const ResidentDesc* R, uint32_t epoch, bool leader, uint32_t share)
+{
+    uint64_t* pos = R->pos;
+    // the real waits poll every few microseconds; the emulation's polls are
+    // slower, so the bounds are scaled down to keep them in milliseconds
+    const uint32_t idle_polls = std::max<uint32_t>(R->idle_polls / 100, 16);
+    const uint32_t ready_polls = std::max<uint32_t>(R->ready_polls / 1000, 16);
+    for (;;) {
+        const uint64_t t = __atomic_fetch_add(&pos[0], 1ull, __ATOMIC_RELAXED);
+        bool take = false;
+        for (uint32_t polls = 0;; ++polls) {
+            uint64_t c = __atomic_load_n(&pos[1], __ATOMIC_ACQUIRE);
+            if ((leader || (polls & 63u) == 63u) && (c & kCtlStop) == 0u && t >= c) {
+                const uint64_t h = __atomic_load_n(R->host_ctl, __ATOMIC_ACQUIRE);
+                if (h > c) {
+                    const uint64_t old = fetch_max_u64(&pos[1], h);
+                    c = old > h ? old : h;
+                }
+            }
+            if ((c & kCtlStop) != 0u) {
+                take = t < (c & ~kCtlStop);
+                break;
+            }
+            if (t < c) {
+                take = true;
+                break;
+            }
+            if (polls + 1 >= idle_polls) {
+                const uint64_t old = __atomic_fetch_or(&pos[1], kCtlStop, __ATOMIC_ACQ_REL);
+                take = t < (old & ~kCtlStop);
+                break;
+            }
+            short_sleep();
+        }
+        if (!take) break;
+        const Chunk c = R->ring[t & R->ring_mask];
+        __atomic_store_n(&R->ack[t & R->ring_mask], t + 1, __ATOMIC_RELEASE);
+        const uint32_t fi = c.fn, rec = c.rec, token = c.token, count = c.count, first = c.first;
+        const uint32_t seg_log2 = c.seg_flags & 0xFFu;
+        const bool upload = ((c.seg_flags >> 8) & kChunkUpload) != 0u;
+        if (!(fi < R->n_fns) || !(count >= 1u && count <= kChunkTiles)) {
+            __atomic_fetch_add(R->bad_records, 1u, __ATOMIC_RELAXED);
+            continue;
+        }
+        bool ok = rec < R->n_arena && seg_log2 <= (uint32_t)kMaxSegLog2 && first < c.n_tiles &&
+                  count <= c.n_tiles - first && (uint64_t)c.part0 + c.n_tiles <= R->n_partials;
+        if (ok && upload) {
+            std::memcpy(R->arena + rec, R->mirror + fi, sizeof(DevFn));
+            __atomic_store_n(&R->ready[rec], token, __ATOMIC_RELEASE);
+        } else if (ok) {
+            uint32_t n = 0;
+            while (__atomic_load_n(&R->ready[rec], __ATOMIC_ACQUIRE) != token && n < ready_polls) {
+                short_sleep();
+                ++n;
+            }
+            ok = n < ready_polls;
+        }
+        const DevFn& fn = R->arena[ok ? rec : 0u];
+        ok = ok && fn.dim >= 1 && fn.dim <= (uint32_t)kMaxDim && fn.kfam < (uint32_t)kNumFamilies;
+        if (ok) {
+            const uint32_t per_tile = (uint32_t)kBlockWaves << seg_log2;
+            for (uint32_t i = 0; i < count; ++i) {
+                const uint32_t tt = first + i;
+                R->partials[c.part0 + tt] = tile_partial(fn, tt * per_tile, per_tile, fn.precision == 0u);
+            }
+        } else {
+            __atomic_fetch_add(R->bad_records, 1u, __ATOMIC_RELAXED);
+            __atomic_store_n(&R->slot_err[fi], token, __ATOMIC_RELAXED);
+        }
+        const uint32_t before = __atomic_fetch_add(&R->tiles_done[fi], count, __ATOMIC_ACQ_REL);
+        if (before + count != c.n_tiles) continue;
+        DevResult r{};
+        const bool err = !ok || __atomic_load_n(&R->slot_err[fi], __ATOMIC_RELAXED) == token;
+        if (!err) {
+            Partial* P = R->partials + c.part0;
+            double g1 = 0.0, g2 = 0.0;
+            for (uint32_t i = 0; i < c.n_tiles; ++i) {
+                g1 += P[i].s1;
+                g2 += P[i].s2;
+            }
+            P[0] = Partial{g1, g2};
+            for (uint32_t i = 1; i < c.n_tiles; ++i) P[i] = Partial{NAN, NAN};
+            r = result_from(fn, fn.scale1 * g1, fn.scale2 * g2, 0, fn.precision);
+        } else {
+            r.status = -8;
+        }
+        R->host_results[fi] = r;
+        __atomic_store_n(&R->tiles_done[fi], 0u, __ATOMIC_RELAXED);
+        __atomic_store_n(&R->host_done[fi], token, __ATOMIC_RELEASE);
+    }
+    if (__atomic_sub_fetch(R->running, share, __ATOMIC_ACQ_REL) == 0u) {
+        __atomic_store_n(R->host_exit + 1, __atomic_load_n(R->bad_records, __ATOMIC_RELAXED), __ATOMIC_RELAXED);
+        __atomic_store_n(R->host_exit, epoch, __ATOMIC_RELEASE);
+    }
+}
+
+void k_resident(void**, dim3) {}  // (started asynchronously by hipLaunchKernel)
+
 const EmuKernel g_stage{k_stage, {8, 8, 8, 4, 8, 8, 4}};
 const EmuKernel g_batched32{k_batched32, {8}};
 const EmuKernel g_batched64{k_batched64, {8}};
@@ -258,11 +401,12 @@ const EmuKernel g_pack_table{k_pack_table, {8, 4, 4, 8}};
 const EmuKernel g_sample_points{k_sample_points, {8, 8, 8, 8}};
 const EmuKernel g_plain{k_plain, {8, 8}};
 const EmuKernel g_plain_reduce{k_plain_reduce, {8, 8, 4, 8}};
+const EmuKernel g_resident{k_resident, {8, 4}};
 
 const EmuKernel* kernel_of(const void* p)
 {
     for (const EmuKernel* k : {&g_stage, &g_batched32, &g_batched64, &g_finalize, &g_publish, &g_pack_grid,
-                               &g_pack_table, &g_sample_points, &g_plain, &g_plain_reduce})
+                               &g_pack_table, &g_sample_points, &g_plain, &g_plain_reduce, &g_resident})
         if (p == (const void*)k) return k;
     return nullptr;
 }
@@ -288,7 +432,21 @@ uint64_t g_api_calls = 0;  // calls into the emulated runtime
 struct ihipStream_t {
     bool capturing = false;
     std::vector<Launch> captured;
+    std::vector<std::thread> workers;  // a running resident launch
+    std::atomic<int> live{0};
 };
+
+namespace {
+
+// In-order streams: whatever is enqueued after a resident launch waits for it.
+void drain(hipStream_t s)
+{
+    if (!s) return;
+    for (auto& w : s->workers) w.join();
+    s->workers.clear();
+}
+
+}  // namespace
 struct ihipEvent_t {
     int dummy = 0;
 };
@@ -311,6 +469,7 @@ const void* pack_grid_kernel_ptr() { return &g_pack_grid; }
 const void* pack_table_kernel_ptr() { return &g_pack_table; }
 const void* sample_points_kernel_ptr() { return &g_sample_points; }
 const void* plain_reduce_kernel_ptr() { return &g_plain_reduce; }
+const void* resident_kernel_ptr() { return &g_resident; }
 extern const char* const kRtcHeaderDevice;
 extern const char* const kRtcHeaderCode;
 const char* const kRtcHeaderDevice = "";
@@ -441,7 +600,16 @@ hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKin
 {
     ++g_api_calls;
     if (stream && stream->capturing) return hipErrorNotSupported;  // the library captures kernels only
+    drain(stream);
     std::memmove(dst, src, bytes);
+    return hipSuccess;
+}
+hipError_t hipMemsetAsync(void* dst, int value, size_t bytes, hipStream_t stream)
+{
+    ++g_api_calls;
+    if (stream && stream->capturing) return hipErrorNotSupported;
+    drain(stream);
+    std::memset(dst, value, bytes);
     return hipSuccess;
 }
 
@@ -454,11 +622,21 @@ hipError_t hipStreamCreateWithFlags(hipStream_t* stream, unsigned)
 hipError_t hipStreamDestroy(hipStream_t stream)
 {
     ++g_api_calls;
+    drain(stream);
     delete stream;
     return hipSuccess;
 }
-hipError_t hipStreamSynchronize(hipStream_t) {
-    ++g_api_calls; return hipSuccess; }
+hipError_t hipStreamSynchronize(hipStream_t stream)
+{
+    ++g_api_calls;
+    drain(stream);
+    return hipSuccess;
+}
+hipError_t hipStreamQuery(hipStream_t stream)
+{
+    ++g_api_calls;
+    return stream && stream->live.load() > 0 ? hipErrorNotReady : hipSuccess;
+}
 hipError_t hipStreamWaitEvent(hipStream_t, hipEvent_t, unsigned) {
     ++g_api_calls; return hipSuccess; }
 
@@ -515,6 +693,22 @@ hipError_t hipLaunchKernel(const void* kernel, dim3 grid, dim3, void** args, siz
         return hipSuccess;
     }
     ++g_launches;
+    drain(stream);
+    if (k == &g_resident) {
+        if (!stream) return hipErrorInvalidValue;  // (the library gives it a stream of its own)
+        const ResidentDesc* R = *(const ResidentDesc**)args[0];
+        const uint32_t epoch = *(const uint32_t*)args[1];
+        const uint32_t n = std::min<uint32_t>(grid.x, 4);
+        stream->live.store((int)n);
+        for (uint32_t w = 0; w < n; ++w) {
+            const uint32_t share = grid.x / n + (w < grid.x % n ? 1u : 0u);
+            stream->workers.emplace_back([R, epoch, w, share, stream] {
+                resident_worker(R, epoch, w % 2 == 0, share);
+                stream->live.fetch_sub(1);
+            });
+        }
+        return hipSuccess;
+    }
     run(l);
     return hipSuccess;
 }

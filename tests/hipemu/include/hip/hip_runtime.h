@@ -75,10 +75,12 @@ hipError_t hipHostFree(void* ptr);
 hipError_t hipHostGetDevicePointer(void** dev, void* host, unsigned flags);
 hipError_t hipGetSymbolAddress(void** dev, const void* symbol);
 hipError_t hipMemcpyAsync(void* dst, const void* src, size_t bytes, hipMemcpyKind kind, hipStream_t stream);
+hipError_t hipMemsetAsync(void* dst, int value, size_t bytes, hipStream_t stream);
 
 hipError_t hipStreamCreateWithFlags(hipStream_t* stream, unsigned flags);
 hipError_t hipStreamDestroy(hipStream_t stream);
 hipError_t hipStreamSynchronize(hipStream_t stream);
+hipError_t hipStreamQuery(hipStream_t stream);
 hipError_t hipStreamWaitEvent(hipStream_t stream, hipEvent_t event, unsigned flags);
 
 hipError_t hipEventCreate(hipEvent_t* event);

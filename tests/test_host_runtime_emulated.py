@@ -6,8 +6,10 @@ memory, in-order synchronous streams, every kernel replaced by a host routine
 with the kernel's effect on the buffers the host reads back) and driven
 through its C ABI by `tests/hipemu/emu_scenarios.cpp`: admission and queueing,
 launches of a few tiles under every scheduling policy, graphs, promotion,
-parameter grids, abort, error paths, the plain paths, two contexts, the tuning cache, and a
-sweep that fails every checked HIP call of a workload in turn (MC_FAULT_HIP)
+parameter grids, abort, error paths, the plain paths, two contexts, the tuning cache, the
+resident engine (its kernel emulated by worker threads that follow the kernel's
+protocol: relaunch after idling, record-arena recycling, abort, destroy while
+running), and a sweep that fails every checked HIP call of a workload in turn (MC_FAULT_HIP)
 and requires each request to come back either with exactly its results or
 with an error -- never MC_OK with wrong values, never a hang, no leak.
 """
@@ -21,7 +23,8 @@ import pytest
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "hipemu")
 SCENARIOS = ["basic", "many_launches", "admission", "grid", "abort", "errors", "plain", "two_contexts",
-             "fault_sweep", "autotune_cache"]
+             "fault_sweep", "autotune_cache", "resident_basic", "resident_relaunch", "resident_flush",
+             "resident_abort"]
 
 
 @pytest.fixture(scope="module")
