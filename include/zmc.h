@@ -134,7 +134,7 @@ typedef struct mc_config {
     uint32_t max_functions;      /* device function slots, at most 2^24 (0: 1 << 16); each also takes
                                     1 KiB of pinned host memory (the packed-record mirror) */
     uint32_t max_tiles_per_run;  /* tiles one mc_run may launch, at most 2^28; the rest waits (0: 1 << 20).
-                                    MC_RESIDENT: ring entries that may wait unread (0: one per workgroup) */
+                                    MC_RESIDENT: tiles that may wait unread in the ring (0: two per workgroup) */
     uint64_t max_partials;       /* device tile-partial slots, 16 bytes each, at most 2^32 - 1 (0: 1 << 22) */
     uint64_t mem_budget_bytes;   /* upper bound on device memory the context holds (0: no bound) */
     void* workspace;             /* optional caller-owned device memory for every device buffer */

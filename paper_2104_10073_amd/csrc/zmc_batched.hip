@@ -40,8 +40,26 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(con
 }
 
 // ---------------------------------------------------------------- resident engine
+//
+// Memory ordering.  On this GPU an agent-scope acquire invalidates the L2 of the
+// workgroup's XCD and a release writes it back, so the kernel orders only what
+// crosses workgroups: a record copied into the arena (release by the copier,
+// acquire by a chunk that waited for it) and tile partials (the tile count's
+// read-modify-write is acquire-release, so the workgroup that counts a run's
+// last tile sees every partial).  The words it polls -- the ticket counter and
+// the device copy of the control word, the host's control word -- are read with
+// relaxed atomics (coherent at their scope, no cache maintenance), and ring
+// data the host writes (ring entries, the record mirror) is read with
+// system-scope atomic loads, which bypass the GPU's caches, so a line cached
+// before the host rewrote it is never used.
 
 namespace {
+
+// 8-byte words written by the host, read past every cache.
+__device__ __forceinline__ uint64_t host_word(const uint64_t* p)
+{
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+}
 
 // The device's copy of the control word after folding in a value read from the
 // host.  Once the copy carries kCtlStop it is final (fetch_max of a word
@@ -49,7 +67,7 @@ namespace {
 __device__ __forceinline__ uint64_t fold_host_ctl(uint64_t* pos, uint64_t cached, uint64_t host)
 {
     if (host <= cached) return cached;
-    const uint64_t old = __hip_atomic_fetch_max(&pos[1], host, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    const uint64_t old = __hip_atomic_fetch_max(&pos[1], host, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     return old > host ? old : host;
 }
 
@@ -61,16 +79,16 @@ __device__ uint32_t wait_ticket(const ResidentDesc* R, uint64_t t, bool leader)
 {
     uint64_t* pos = R->pos;
     for (uint32_t polls = 0;; ++polls) {
-        uint64_t c = __hip_atomic_load(&pos[1], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+        uint64_t c = __hip_atomic_load(&pos[1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         // leaders read the host's word at every check, the others every 64th
         // (so new entries are seen even while every leader is busy)
         if ((leader || (polls & 63u) == 63u) && (c & kCtlStop) == 0u && t >= c)
-            c = fold_host_ctl(pos, c, __hip_atomic_load(R->host_ctl, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM));
+            c = fold_host_ctl(pos, c, host_word(R->host_ctl));
         if ((c & kCtlStop) != 0u) return t < (c & ~kCtlStop) ? kTake : kLeave;
         if (t < c) return kTake;
         if (polls + 1 >= R->idle_polls) {
             // nothing came for this ticket: stop the launch at the count as it stands
-            const uint64_t old = __hip_atomic_fetch_or(&pos[1], kCtlStop, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+            const uint64_t old = __hip_atomic_fetch_or(&pos[1], kCtlStop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             return t < (old & ~kCtlStop) ? kTake : kLeave;
         }
         __builtin_amdgcn_s_sleep(127);
@@ -78,6 +96,8 @@ __device__ uint32_t wait_ticket(const ResidentDesc* R, uint64_t t, bool leader)
 }
 
 }  // namespace
+
+static_assert(sizeof(DevFn) == kWave * sizeof(uint4), "a record is one 16-byte word per lane of a wave");
 
 // The resident kernel.  Every wait is bounded: a ticket's entry (idle_polls
 // polls, after which the launch stops itself) and a record another workgroup
@@ -97,9 +117,16 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
             const uint64_t t = __hip_atomic_fetch_add(&R->pos[0], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const uint32_t st = wait_ticket(R, t, leader);
             if (st == kTake) {
-                s_chunk = R->ring[t & R->ring_mask];
-                // (release: the entry has been read before the host may reuse its place)
-                __hip_atomic_store(&R->ack[t & R->ring_mask], t + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                // (the host wrote the entry before the count that shows it)
+                const uint64_t* e = reinterpret_cast<const uint64_t*>(R->ring + (t & R->ring_mask));
+                uint64_t w[sizeof(Chunk) / 8];
+                for (uint32_t k = 0; k < (uint32_t)(sizeof(Chunk) / 8); ++k) w[k] = host_word(e + k);
+                __builtin_memcpy(&s_chunk, w, sizeof(Chunk));
+                // the entry has been read (its words are in registers) before the
+                // host may reuse its place
+                __atomic_signal_fence(__ATOMIC_SEQ_CST);
+                __builtin_amdgcn_s_waitcnt(0);
+                __hip_atomic_store(&R->ack[t & R->ring_mask], t + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
             s_state = st;
         }
@@ -125,29 +152,38 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
         bool ok = rec < R->n_arena && seg_log2 <= (uint32_t)kMaxSegLog2 && first < n_tiles &&
                   count <= n_tiles - first && (uint64_t)part0 + n_tiles <= R->n_partials;
         if (ok && upload) {
-            // the run's record goes to its arena position; its other chunks wait for it
-            const uint4* src = reinterpret_cast<const uint4*>(R->mirror + fi);
-            uint4* dst = reinterpret_cast<uint4*>(R->arena + rec);
-            for (uint32_t i = threadIdx.x; i < (uint32_t)(sizeof(DevFn) / sizeof(uint4)); i += blockDim.x)
-                dst[i] = src[i];
-            __threadfence();
-            __syncthreads();
-            if (threadIdx.x == 0) __hip_atomic_store(&R->ready[rec], token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            // the run's record goes to its arena position, copied by wave 0 alone
+            // (one 16-byte word per lane): the release of the ready word waits for
+            // that wave's stores, which a barrier would not do for other waves'
+            if (wave == 0) {
+                const uint64_t* src = reinterpret_cast<const uint64_t*>(R->mirror + fi) + 2 * lane;
+                uint4* dst = reinterpret_cast<uint4*>(R->arena + rec);
+                const uint64_t a = host_word(src), b = host_word(src + 1);
+                dst[lane] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
+                if (lane == 0) __hip_atomic_store(&R->ready[rec], token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            }
+            if (threadIdx.x == 0) s_ok = rec + 1;
         } else if (ok) {
             if (threadIdx.x == 0) {
                 uint32_t n = 0;
-                while (__hip_atomic_load(&R->ready[rec], __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) != token &&
+                while (__hip_atomic_load(&R->ready[rec], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != token &&
                        n < R->ready_polls) {
                     __builtin_amdgcn_s_sleep(8);
                     ++n;
                 }
-                s_ok = n < R->ready_polls ? 1u : 0u;
+                // acquire for the whole CU (its L1 and its XCD's L2) before the record's loads
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                s_ok = n < R->ready_polls ? rec + 1 : 0u;
             }
-            __syncthreads();
-            ok = __builtin_amdgcn_readfirstlane(s_ok) != 0u;
-            __threadfence();  // (every wave: acquire before the record's scalar loads)
+        } else if (threadIdx.x == 0) {
+            s_ok = 0u;
         }
-        CDevFn* fn = scalar_view(R->arena + (ok ? rec : 0u));
+        __syncthreads();
+        // the record's address comes from this LDS word, read after the barrier,
+        // so no load of the record can be moved before the copy or the wait
+        const uint32_t rec1 = __builtin_amdgcn_readfirstlane(s_ok);
+        ok = rec1 != 0u;
+        CDevFn* fn = scalar_view(R->arena + (ok ? rec1 - 1u : 0u));
         if (ok) {
             const uint32_t dim = fn->dim;
             ok = dim >= 1 && dim <= (uint32_t)kMaxDim;
@@ -164,19 +200,22 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
                 __syncthreads();
             }
         }
-        // count the chunk's tiles; the workgroup that counts the run's last one finalizes it
+        // count the chunk's tiles (release: this chunk's partials, written by
+        // this thread); the workgroup that counts the run's last one acquires
+        // everyone else's and finalizes it
         if (threadIdx.x == 0) {
             if (!ok) {
                 atomicAdd(R->bad_records, 1u);
                 __hip_atomic_store(&R->slot_err[fi], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
-            __threadfence();
-            const uint32_t before = atomicAdd(&R->tiles_done[fi], count);
-            s_fin = before + count == n_tiles ? 1u : 0u;
+            const uint32_t before =
+                __hip_atomic_fetch_add(&R->tiles_done[fi], count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+            const bool fin = before + count == n_tiles;
+            if (fin) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            s_fin = fin ? 1u : 0u;
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(s_fin) != 0u && wave == 0) {
-            __threadfence();
             const bool err = !ok || __hip_atomic_load(&R->slot_err[fi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == token;
             DevResult r{};
             if (!err) {
@@ -187,19 +226,18 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
             if (lane == 0) {
                 R->host_results[fi] = r;
                 __hip_atomic_store(&R->tiles_done[fi], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __threadfence_system();
+                // (the result and the counter reset before the done word)
                 __hip_atomic_store(&R->host_done[fi], token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
         __syncthreads();
     }
     if (threadIdx.x == 0) {
-        // (acknowledgements and results above are visible before the exit word)
+        // acknowledgements and results above are visible before the exit word
         const uint32_t left = __hip_atomic_fetch_sub(R->running, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_SYSTEM);
         if (left == 1u) {
             const uint32_t bad = __hip_atomic_load(R->bad_records, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             __hip_atomic_store(R->host_exit + 1, bad, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
-            __threadfence_system();
             __hip_atomic_store(R->host_exit, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
         }
     }

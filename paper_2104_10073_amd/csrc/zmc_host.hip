@@ -438,7 +438,11 @@ struct ResidentState {
     bool on = false;
     hipStream_t stream = nullptr;
     uint32_t grid = 0;             // workgroups per launch
-    uint32_t backlog = 0;          // entries the ring may hold that no workgroup has read yet
+    uint64_t backlog = 0;          // tiles the ring may hold that no workgroup has read yet
+    uint64_t unread_tiles = 0;     // tiles of the entries [acked, pushed)
+    uint64_t tiles_waiting = 0;    // tiles of admitted requests not yet pushed
+    bool active_dirty = false;     // the active list may be out of SRPT order
+    size_t fair_pos = 0;           // FAIR: where the next pass over the active list starts
     // pinned, fine-grained host block
     uint8_t* h_block = nullptr;
     uint8_t* h_block_dev = nullptr;
@@ -716,6 +720,10 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     r->n_promoted++;
     ctx->stats.promoted++;
     if (!was_active) ctx->active.push_back(r);
+    if (ctx->res.on) {
+        ctx->res.tiles_waiting += fs.n_tiles;
+        ctx->res.active_dirty = true;
+    }
 }
 
 // Read a launch's timing events into the statistics.  block = false: only if
@@ -954,6 +962,8 @@ void admit(mc_ctx* ctx)
             r->grid_packed = true;
             ctx->pending.pop_front();
             ctx->active.push_back(r);
+            ctx->res.tiles_waiting += r->tiles_total - r->tiles_launched;
+            ctx->res.active_dirty = true;
             continue;
         }
         Request* r = ctx->pending.front();
@@ -1446,8 +1456,17 @@ void res_publish(ResidentState& R)
 void res_scan_acks(ResidentState& R)
 {
     while (R.acked < R.pushed &&
-           __atomic_load_n(&R.ack[R.acked & (kRingEntries - 1)], __ATOMIC_ACQUIRE) == R.acked + 1)
+           __atomic_load_n(&R.ack[R.acked & (kRingEntries - 1)], __ATOMIC_ACQUIRE) == R.acked + 1) {
+        R.unread_tiles -= R.ring[R.acked & (kRingEntries - 1)].count;
         R.acked++;
+    }
+}
+
+// Entries from `acked` on will never be read (abort, failed launch).
+void res_drop_unread(ResidentState& R)
+{
+    R.acked = R.pushed;
+    R.unread_tiles = 0;
 }
 
 // Whether the last launch has gone.  Every workgroup acknowledges what it read
@@ -1527,7 +1546,7 @@ bool res_alloc_rec(ResidentState& R, uint32_t* out)
 
 bool res_room(const ResidentState& R)
 {
-    return !R.stopping && R.pushed - R.acked < R.backlog && R.pushed < R.acked + kRingEntries;
+    return !R.stopping && R.unread_tiles < R.backlog && R.pushed < R.acked + kRingEntries;
 }
 
 // Push request r's next chunk into the ring (not yet published).  The first
@@ -1553,14 +1572,18 @@ bool res_push_chunk(mc_ctx* ctx, Request* r)
         R.arena_busy[rec] = 1;
         R.runs.push_back(ResRun{r, fi, fs.slot, fs.token, rec});
     }
-    // one tile per chunk until a function has more tiles than the launch has
-    // workgroups: a request's tiles spread over as many workgroups as possible
+    // one tile per chunk while the tiles waiting do not fill the workgroups
+    // (a request's tiles spread over as many of them as possible), up to
+    // kChunkTiles as more wait (fewer entries, less per-chunk overhead)
     const uint32_t left = fs.n_tiles - fs.next_tile;
-    const uint32_t count = std::min(std::min(left, kChunkTiles), std::max(1u, left / R.grid));
+    const uint64_t per_wg = R.tiles_waiting / R.grid;
+    const uint32_t count = std::min(std::min(left, kChunkTiles), (uint32_t)std::max<uint64_t>(1, per_wg));
     R.ring[R.pushed & (kRingEntries - 1)] =
         Chunk{fs.slot, fs.rec, fs.next_tile, count, (uint32_t)fs.part0, fs.n_tiles, fs.token,
               fs.seg_log2 | (first ? kChunkUpload << 8 : 0u)};
     R.pushed++;
+    R.unread_tiles += count;
+    R.tiles_waiting -= std::min<uint64_t>(R.tiles_waiting, count);
     fs.next_tile += count;
     fs.needs_upload = false;
     r->tiles_launched += count;
@@ -1575,34 +1598,47 @@ bool res_push_chunk(mc_ctx* ctx, Request* r)
 }
 
 // Fill the ring up to the backlog by the scheduling policy: FIFO from the
-// oldest request, SRPT from the request with the least work left, FAIR one
-// chunk per request in turn.
+// oldest request, SRPT from the request with the least work left (the list is
+// re-sorted only when admission or a promotion may have changed the order:
+// pushing from the first request only makes it smaller), FAIR one chunk per
+// request in turn, each fill starting where the previous one stopped.
 void res_feed(mc_ctx* ctx)
 {
     ResidentState& R = ctx->res;
     res_scan_acks(R);
     if (!res_room(R) || ctx->active.empty()) return;
     const uint64_t before = R.pushed;
-    if (ctx->policy == MC_SCHED_SRPT)
+    bool exhausted = false;
+    if (ctx->policy == MC_SCHED_SRPT && R.active_dirty) {
         std::stable_sort(ctx->active.begin(), ctx->active.end(),
                          [](const Request* a, const Request* b) { return a->work_left < b->work_left; });
+        R.active_dirty = false;
+    }
     if (ctx->policy == MC_SCHED_FAIR) {
-        for (bool any = true; any && res_room(R);) {
-            any = false;
-            for (Request* r : ctx->active)
-                if (res_push_chunk(ctx, r)) any = true;
+        const size_t n = ctx->active.size();
+        size_t k = R.fair_pos % n, idle = 0;
+        while (idle < n && res_room(R) && !R.flush) {
+            Request* r = ctx->active[k];
+            if (res_push_chunk(ctx, r)) idle = 0;
+            else ++idle;
+            if (!has_work(r)) exhausted = true;
+            k = k + 1 == n ? 0 : k + 1;
         }
+        R.fair_pos = k;
     } else {
         for (Request* r : ctx->active) {
             while (res_push_chunk(ctx, r)) {
             }
+            if (!has_work(r)) exhausted = true;
             if (!res_room(R) || R.flush) break;
         }
     }
-    std::deque<Request*> keep;
-    for (Request* r : ctx->active)
-        if (has_work(r)) keep.push_back(r);
-    ctx->active.swap(keep);
+    if (exhausted) {
+        std::deque<Request*> keep;
+        for (Request* r : ctx->active)
+            if (has_work(r)) keep.push_back(r);
+        ctx->active.swap(keep);
+    }
     if (R.pushed != before) res_publish(R);
     // arena positions of the running launch are exhausted: end it, so that
     // the next one may reuse them
@@ -1687,7 +1723,9 @@ void res_fail(mc_ctx* ctx)
     R.live = false;
     R.stopping = false;
     R.flush = false;
-    R.acked = R.pushed;
+    res_drop_unread(R);
+    R.tiles_waiting = 0;
+    for (Request* r : ctx->active) R.tiles_waiting += r->tiles_total - r->tiles_launched;
     __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
 }
 
@@ -1730,7 +1768,8 @@ void res_finish_abort(mc_ctx* ctx)
         free_request_resources(ctx, r);
         ctx->completed.push_back(r->id);
     }
-    R.acked = R.pushed;
+    res_drop_unread(R);
+    R.tiles_waiting = 0;
     __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
     HIP_TRY(hipMemsetAsync(R.d_tiles_done, 0, (size_t)ctx->max_functions * sizeof(uint32_t), R.stream));
     HIP_TRY(hipStreamSynchronize(R.stream));
@@ -1818,8 +1857,9 @@ void create_resident(mc_ctx* ctx, const Layout& L, uint8_t* base)
     int occ = 0;
     HIP_TRY(hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, resident_kernel_ptr(), kBlockThreads, 0));
     R.grid = (uint32_t)ctx->num_cus * (cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ));
-    R.backlog = cfg.max_tiles_per_run ? std::min<uint32_t>(cfg.max_tiles_per_run, kRingEntries / 2)
-                                      : std::min<uint32_t>(R.grid, kRingEntries / 2);
+    // by default two tiles per workgroup wait unread: enough for the host to
+    // refill before the workgroups run dry, little for a new request to wait behind
+    R.backlog = cfg.max_tiles_per_run ? cfg.max_tiles_per_run : 2ull * R.grid;
     R.n_arena = L.n_arena;
     R.arena_epoch.assign(R.n_arena, 0u);
     R.arena_busy.assign(R.n_arena, 0u);
