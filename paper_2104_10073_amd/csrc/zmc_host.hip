@@ -579,12 +579,16 @@ struct Layout {
     uint32_t n_arena;
 };
 
-// Record arena of a resident context: twice the function slots (a run holds
-// one position until its result is in, and positions read by the running
-// launch wait for the next), at least 8192 and at most 2^17 (128 MiB).
+// Record arena of a resident context: eight positions per function slot, at
+// least 8192 and at most 2^20 (1 GiB).  A run holds one position until its
+// result is in, and a position read by the running launch waits for the next
+// one, so every (arena size - function slots) new runs the kernel is stopped
+// and started again, which stalls the runs in flight for up to a chunk; a
+// large arena makes that rare (a serving mix of 4 x 10^5 functions runs
+// through 2^20 positions without it).
 uint32_t arena_positions(uint32_t max_functions)
 {
-    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(2ull * max_functions, 8192), 1u << 17);
+    return (uint32_t)std::min<uint64_t>(std::max<uint64_t>(8ull * max_functions, 8192), 1u << 20);
 }
 
 Layout compute_layout(uint32_t max_functions, uint64_t max_partials, uint32_t tile_cap, uint32_t fin_cap,

@@ -646,7 +646,7 @@ bool resident_relaunch()
 bool resident_flush()
 {
     for (uint32_t policy : {MC_SCHED_FAIR, MC_SCHED_SRPT}) {
-        mc_ctx* ctx = create(MC_RESIDENT, 3, policy, 1200, 1 << 16);
+        mc_ctx* ctx = create(MC_RESIDENT, 3, policy, 1000, 1 << 16);  // an arena of 8192
         CHECK(ctx, "create");
         std::vector<std::vector<mc_function>> reqs;
         std::vector<uint64_t> ids;

@@ -128,11 +128,11 @@ def test_resident_abort_then_continue():
 
 def test_resident_arena_recycled_across_launches():
     import paper_2104_10073_amd as Z
-    # more runs than the 8192-position record arena within one launch
+    # more runs than the record arena (8192 positions with 1024 function slots) within one launch
     reqs = [W.mixed_batch(1000, dim_range=(1, 4), log10_samples=(2.0, 4.0), gen_seed=530 + k) for k in range(10)]
     ref = _launch_results(Z, [(t, Z.PREC_FP32) for t in reqs])
     print("resident: 10 x 1000 functions through an 8192-record arena", flush=True)
-    with Z.Context(device=0, flags=Z.MC_RESIDENT, max_functions=2048) as c:
+    with Z.Context(device=0, flags=Z.MC_RESIDENT, max_functions=1024) as c:
         ids = [c.submit(t, Z.PREC_FP32) for t in reqs]
         got = _drive(c, ids, {rid: len(t) for rid, t in zip(ids, reqs)})
         st = c.stats()
