@@ -212,7 +212,10 @@ def serving_leg(Z, W, stream, args):
     arriving at t = 0 under the headline scheduling policy; the offered QPS is
     `serve_load` times it.  Latency is arrival to results-on-host; the first
     10 % of requests are warm-up.  The other policies are measured at the same
-    absolute arrival rates.
+    absolute arrival rates, then the same requests and rates go through a
+    resident context (one persistent kernel fed through a ring, no launch per
+    batch), and both engines serve a twentieth of the saturated rate (nearly
+    alone).
     """
     from paper_2104_10073_amd import serving
 
@@ -262,7 +265,7 @@ def serving_leg(Z, W, stream, args):
                 mixed = run["results"][i]
                 same = same and all(np.array_equal(alone[k], mixed[k]) for k in ("mean", "std_error", "sum_f", "sum_f2"))
             head_other = per_load
-    summ.update({"policy": head, "offered_qps": qps, "saturated_qps": sat_qps,
+    summ.update({"engine": "launches", "policy": head, "offered_qps": qps, "saturated_qps": sat_qps,
                  "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
                  "load_fraction": args.serve_load, "alone_equals_mix_bitwise": bool(same),
                  "requests_checked_alone": int(len(picks)),
@@ -270,7 +273,73 @@ def serving_leg(Z, W, stream, args):
                  "other_policies_same_arrivals": compare,
                  "workload": "requests of floor(10^U(0,3)) functions, forms mixed, dims U{1..12}, "
                              "10^U(4,7) samples each, Poisson arrivals"})
+    if args.serve_resident:
+        summ["resident"] = resident_serving(Z, W, serving, reqs, sat_qps, loads, head, others, picks, run, args)
+    # nearly alone: a twentieth of the saturated rate, both engines (the latency a request
+    # sees with the GPU to itself, for comparison with the loaded medians)
+    m = min(n, 400)
+    arr = W.poisson_arrivals(m, 0.05 * sat_qps, seed=5)
+    low = {}
+    for engine in ("launches", "resident") if args.serve_resident else ("launches",):
+        flags_e = Z.MC_RESIDENT if engine == "resident" else flags
+        with Z.Context(device=0, flags=flags_e, policy=SERVE_POLICIES[head](Z),
+                       max_tiles_per_run=0 if engine == "resident" else 1 << 15,
+                       max_functions=1 << 17, max_partials=1 << 24) as ctx:
+            o = serving.serve(ctx, reqs[:m], arr)
+        sm = serving.summarize(o, arr)
+        sm.update({"load_fraction": 0.05, "offered_qps": 0.05 * sat_qps})
+        low[engine] = sm
+        log(f"serving ({engine}, {head}) at 0.05 x saturated: p50 {sm['p50_ms']:.3f} ms, p99 {sm['p99_ms']:.2f} ms")
+    summ["nearly_alone"] = low
     return summ
+
+
+def resident_serving(Z, W, serving, reqs, sat_qps, loads, head, others, picks, launch_run, args):
+    """The same requests through a resident context (MC_RESIDENT: one persistent kernel fed
+    through a ring in pinned memory, no launch per batch), at the same absolute arrival
+    rates as the launch engine.  Every result of the headline load is compared bitwise with
+    the launch engine's result of the same request, and the sampled requests re-run alone."""
+    n = len(reqs)
+
+    def make_ctx(name):
+        return Z.Context(device=0, flags=Z.MC_RESIDENT, policy=SERVE_POLICIES[name](Z),
+                         max_functions=1 << 17, max_partials=1 << 24)
+
+    with make_ctx(head) as ctx:
+        sat = serving.serve(ctx, reqs, np.zeros(n))
+    out = {"engine": "resident", "policy": head, "saturated_qps": n / sat["wall_s"],
+           "saturated_evals_per_s": sat["evals"] / sat["wall_s"], "per_load": {}, "other_policies": {}}
+    log(f"serving (resident, {head}) saturated: {out['saturated_qps']:.0f} requests/s, "
+        f"{out['saturated_evals_per_s']:.3g} evals/s")
+    for name in [head] + others:
+        with make_ctx(name) as ctx:
+            for lf in loads:
+                arr = W.poisson_arrivals(n, lf * sat_qps, seed=5)
+                keep = name == head and lf == args.serve_load
+                o = serving.serve(ctx, reqs, arr, keep_results=keep)
+                sm = serving.summarize(o, arr)
+                sm.update({"load_fraction": lf, "offered_qps": lf * sat_qps})
+                log(f"serving (resident, {name}) at {lf:.2f} x saturated: p50 {sm['p50_ms']:.2f} ms, "
+                    f"p99 {sm['p99_ms']:.2f} ms")
+                if name == head:
+                    out["per_load"][f"{lf:.2f}"] = sm
+                else:
+                    out["other_policies"].setdefault(name, []).append(sm)
+                if keep:
+                    same_launch = all(np.array_equal(o["results"][i][k], launch_run["results"][i][k])
+                                      for i in range(n) for k in ("mean", "std_error", "sum_f", "sum_f2", "n"))
+                    same_alone = True
+                    for i in picks:
+                        alone = ctx.integrate(reqs[i], Z.PREC_FP32)
+                        same_alone = same_alone and all(np.array_equal(alone[k], o["results"][i][k])
+                                                        for k in ("mean", "std_error", "sum_f", "sum_f2"))
+                    out["all_results_equal_launch_engine_bitwise"] = bool(same_launch)
+                    out["alone_equals_mix_bitwise"] = bool(same_alone)
+                    out["stats"] = {k: v for k, v in ctx.stats().items() if k in ("launches", "functions", "promoted",
+                                                                                   "bad_records", "tiles32", "tiles64")}
+                    log(f"serving (resident): every result equals the launch engine's: {same_launch}; "
+                        f"alone equals mix: {same_alone}")
+    return out
 
 
 SERVE_POLICIES = {
@@ -489,6 +558,8 @@ def main():
                     help="policies also measured at the same arrival rates (comma-separated)")
     ap.add_argument("--serve-load", type=float, default=0.5,
                     help="offered load as a fraction of the measured saturated request rate")
+    ap.add_argument("--no-serve-resident", dest="serve_resident", action="store_false",
+                    help="skip the serving measurement through a resident context (MC_RESIDENT)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only copy a device buffer of this many MiB 5 times (scale for HBM counters) and exit")
     args = ap.parse_args()
