@@ -42,16 +42,19 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_batched_fp64(con
 // ---------------------------------------------------------------- resident engine
 //
 // Memory ordering.  On this GPU an agent-scope acquire invalidates the L2 of the
-// workgroup's XCD and a release writes it back, so the kernel orders only what
-// crosses workgroups: a record copied into the arena (release by the copier,
-// acquire by a chunk that waited for it) and tile partials (the tile count's
-// read-modify-write is acquire-release, so the workgroup that counts a run's
-// last tile sees every partial).  The words it polls -- the ticket counter and
-// the device copy of the control word, the host's control word -- are read with
-// relaxed atomics (coherent at their scope, no cache maintenance), and ring
-// data the host writes (ring entries, the record mirror) is read with
-// system-scope atomic loads, which bypass the GPU's caches, so a line cached
-// before the host rewrote it is never used.
+// workgroup's XCD and a release writes it back, and the kernel hands data
+// between workgroups at every chunk, so it uses neither.  Everything one
+// workgroup writes for another -- records in the arena, tile partials, the
+// finalize tree's sums, results in host memory -- is written through to memory
+// with system-scope atomic stores, and waited for (s_waitcnt) before the word
+// that announces it; partials and everything the host writes (ring entries,
+// the record mirror) are read with system-scope atomic loads, which bypass the
+// caches.  No line of shared data is ever dirty or stale in any cache, with one
+// more fact for records: they are read through the scalar cache, and a record
+// is written at a position no CU has read since the launch started (the host
+// hands out fresh arena positions, and every cache is invalidated at a kernel's
+// start), so those loads miss down to memory.  Polled words (tickets, the
+// control words, ready and done tokens, tile counts) are relaxed atomics.
 
 namespace {
 
@@ -157,10 +160,12 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
             // that wave's stores, which a barrier would not do for other waves'
             if (wave == 0) {
                 const uint64_t* src = reinterpret_cast<const uint64_t*>(R->mirror + fi) + 2 * lane;
-                uint4* dst = reinterpret_cast<uint4*>(R->arena + rec);
+                uint64_t* dst = reinterpret_cast<uint64_t*>(R->arena + rec) + 2 * lane;
                 const uint64_t a = host_word(src), b = host_word(src + 1);
-                dst[lane] = make_uint4((uint32_t)a, (uint32_t)(a >> 32), (uint32_t)b, (uint32_t)(b >> 32));
-                if (lane == 0) __hip_atomic_store(&R->ready[rec], token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+                __hip_atomic_store(dst, a, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                __hip_atomic_store(dst + 1, b, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+                CoherentMem::sync();
+                if (lane == 0) __hip_atomic_store(&R->ready[rec], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
             if (threadIdx.x == 0) s_ok = rec + 1;
         } else if (ok) {
@@ -171,8 +176,6 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
                     __builtin_amdgcn_s_sleep(8);
                     ++n;
                 }
-                // acquire for the whole CU (its L1 and its XCD's L2) before the record's loads
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
                 s_ok = n < R->ready_polls ? rec + 1 : 0u;
             }
         } else if (threadIdx.x == 0) {
@@ -196,38 +199,41 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_resident(const R
                 ok = f64 ? BuiltinDispatch<true>::run(fn, fn->kfam, t * per_tile, seg_log2, wave, lane, s_seg)
                          : BuiltinDispatch<false>::run(fn, fn->kfam, t * per_tile, seg_log2, wave, lane, s_seg);
                 __syncthreads();
-                if (ok && wave == 0) tile_tree(s_seg, per_tile, lane, &R->partials[part0 + t]);
+                if (ok && wave == 0) tile_tree<CoherentMem>(s_seg, per_tile, lane, &R->partials[part0 + t]);
                 __syncthreads();
             }
         }
-        // count the chunk's tiles (release: this chunk's partials, written by
-        // this thread); the workgroup that counts the run's last one acquires
-        // everyone else's and finalizes it
+        // count the chunk's tiles once its partials (written by this thread)
+        // are in memory; the workgroup that counts the run's last one finalizes it
         if (threadIdx.x == 0) {
             if (!ok) {
                 atomicAdd(R->bad_records, 1u);
                 __hip_atomic_store(&R->slot_err[fi], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             }
+            CoherentMem::sync();
             const uint32_t before =
-                __hip_atomic_fetch_add(&R->tiles_done[fi], count, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-            const bool fin = before + count == n_tiles;
-            if (fin) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            s_fin = fin ? 1u : 0u;
+                __hip_atomic_fetch_add(&R->tiles_done[fi], count, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_fin = before + count == n_tiles ? 1u : 0u;
         }
         __syncthreads();
         if (__builtin_amdgcn_readfirstlane(s_fin) != 0u && wave == 0) {
             const bool err = !ok || __hip_atomic_load(&R->slot_err[fi], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == token;
             DevResult r{};
             if (!err) {
-                r = finalize_function(fn, R->partials + part0, n_tiles, lane, 0);
+                r = finalize_function<CoherentMem>(fn, R->partials + part0, n_tiles, lane, 0);
             } else {
                 r.status = -8;  // MC_ERR_HIP
             }
             if (lane == 0) {
-                R->host_results[fi] = r;
+                static_assert(sizeof(DevResult) == 6 * sizeof(uint64_t), "result words");
+                uint64_t w[6];
+                __builtin_memcpy(w, &r, sizeof r);
+                uint64_t* dst = reinterpret_cast<uint64_t*>(R->host_results + fi);
+                for (int k = 0; k < 6; ++k) __hip_atomic_store(dst + k, w[k], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
                 __hip_atomic_store(&R->tiles_done[fi], 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                // (the result and the counter reset before the done word)
-                __hip_atomic_store(&R->host_done[fi], token, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+                // (the result and the counter reset are done before the done word)
+                CoherentMem::sync();
+                __hip_atomic_store(&R->host_done[fi], token, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
             }
         }
         __syncthreads();

@@ -520,8 +520,44 @@ __device__ __forceinline__ void tile_segments(CDevFn* fn, uint32_t seg0, uint32_
     }
 }
 
+// How tile partials are read and written.  The launch path's kernels use
+// ordinary loads and stores (a kernel boundary separates the writers from the
+// readers).  The resident kernel, whose workgroups hand partials to each other
+// within one launch, writes them through to memory and reads them past every
+// cache (system-scope atomics), so no line of them is ever dirty or stale in
+// any XCD's L2 and no cache maintenance is needed per tile.
+struct PlainMem {
+    __device__ static __forceinline__ Partial load(const Partial* p) { return *p; }
+    __device__ static __forceinline__ void store(Partial* p, const Partial& v) { *p = v; }
+    __device__ static __forceinline__ void sync() {}
+};
+
+struct CoherentMem {
+    __device__ static __forceinline__ Partial load(const Partial* p)
+    {
+        const uint64_t* q = reinterpret_cast<const uint64_t*>(p);
+        const uint64_t a = __hip_atomic_load(q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        const uint64_t b = __hip_atomic_load(q + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        return Partial{__longlong_as_double((long long)a), __longlong_as_double((long long)b)};
+    }
+    __device__ static __forceinline__ void store(Partial* p, const Partial& v)
+    {
+        uint64_t* q = reinterpret_cast<uint64_t*>(p);
+        __hip_atomic_store(q, (uint64_t)__double_as_longlong(v.s1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        __hip_atomic_store(q + 1, (uint64_t)__double_as_longlong(v.s2), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    }
+    // the wave's stores have completed (every lane's later loads see them)
+    __device__ static __forceinline__ void sync()
+    {
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+        __builtin_amdgcn_s_waitcnt(0);
+        __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    }
+};
+
 // Pairwise tree over the tile's 4 * 2^L segment sums (L <= 6, so at most 4 per lane),
 // then the lane butterfly: the same tree as over the whole function.
+template <class Mem = PlainMem>
 __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, uint32_t lane, Partial* out)
 {
     const uint32_t per = count > kWave ? count / kWave : 1u;
@@ -541,7 +577,7 @@ __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, 
     }
     a = wave_sum(a);
     b = wave_sum(b);
-    if (lane == 0) *out = Partial{a, b};
+    if (lane == 0) Mem::store(out, Partial{a, b});
 }
 
 // ---------------------------------------------------------------- one function's result
@@ -550,6 +586,7 @@ __device__ __forceinline__ void tile_tree(const Partial* s_seg, uint32_t count, 
 // are summed by repeated 64-wide butterflies over aligned chunks (compacted in
 // place), which is the pairwise tree over tile index; then mean and standard
 // error in FP64.  Every lane returns the result.
+template <class Mem = PlainMem>
 __device__ __forceinline__ DevResult finalize_function(CDevFn* fn, Partial* P, uint32_t n, uint32_t lane,
                                                        int32_t status)
 {
@@ -559,17 +596,20 @@ __device__ __forceinline__ DevResult finalize_function(CDevFn* fn, Partial* P, u
             const uint32_t i = c * kWave + lane;
             double a = 0.0, b = 0.0;
             if (i < n) {
-                a = P[i].s1;
-                b = P[i].s2;
+                const Partial q = Mem::load(P + i);
+                a = q.s1;
+                b = q.s2;
             }
             a = wave_sum(a);
             b = wave_sum(b);
-            if (lane == 0) P[c] = Partial{a, b};
+            if (lane == 0) Mem::store(P + c, Partial{a, b});
+            Mem::sync();
             __threadfence_block();
         }
         n = chunks;
     }
-    const double g1 = P[0].s1, g2 = P[0].s2;
+    const Partial top = Mem::load(P);
+    const double g1 = top.s1, g2 = top.s2;
     const double S1 = fn->scale1 * g1;
     const double S2 = fn->scale2 * g2;
     const uint64_t N = fn->n_samples;

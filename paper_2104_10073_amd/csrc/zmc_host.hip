@@ -1576,11 +1576,13 @@ bool res_push_chunk(mc_ctx* ctx, Request* r)
         R.arena_busy[rec] = 1;
         R.runs.push_back(ResRun{r, fi, fs.slot, fs.token, rec});
     }
-    // one tile per chunk while the tiles waiting do not fill the workgroups
-    // (a request's tiles spread over as many of them as possible), up to
-    // kChunkTiles as more wait (fewer entries, less per-chunk overhead)
+    // one tile per chunk while the request's tiles not yet pushed do not fill
+    // the workgroups (its tiles spread over as many of them as possible), up
+    // to kChunkTiles as it has more (fewer entries for the host to write; the
+    // host writes one in tens of nanoseconds, a workgroup runs a tile in tens
+    // of microseconds, so a saturated GPU needs entries of several tiles)
     const uint32_t left = fs.n_tiles - fs.next_tile;
-    const uint64_t per_wg = R.tiles_waiting / R.grid;
+    const uint64_t per_wg = (r->tiles_total - r->tiles_launched) / R.grid;
     const uint32_t count = std::min(std::min(left, kChunkTiles), (uint32_t)std::max<uint64_t>(1, per_wg));
     R.ring[R.pushed & (kRingEntries - 1)] =
         Chunk{fs.slot, fs.rec, fs.next_tile, count, (uint32_t)fs.part0, fs.n_tiles, fs.token,
