@@ -32,6 +32,12 @@
  *     makes from then on report failure without being made (out of memory for
  *     allocations, hipErrorUnknown otherwise), once; every mc_create re-arms
  *     the countdown from the variable or, without it, disarms it.
+ *   - Log level: MC_LOG in the environment when a context is created sets what
+ *     the library writes to stderr, one line per event prefixed "[zmc] ":
+ *     0 or unset nothing; 1 every failure an entry point returns, with its
+ *     message; 2 also context creation, resident-kernel launches and stops,
+ *     tuning choices and promotions to FP64; 3 also every launch and every
+ *     admitted request.  Logging never changes a result.
  */
 #ifndef ZMC_H
 #define ZMC_H

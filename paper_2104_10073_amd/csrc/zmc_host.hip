@@ -152,6 +152,29 @@ inline hipError_t injected_error(const char* what)
                : hipErrorUnknown;
 }
 
+// Log level (MC_LOG at mc_create): 0 nothing, 1 failures, 2 context-level
+// events, 3 every launch and admission.  Lines go to stderr, prefixed "[zmc] ".
+std::atomic<int> g_log_level{0};
+
+void arm_log_level()
+{
+    const char* v = std::getenv("MC_LOG");
+    g_log_level.store(v ? std::atoi(v) : 0, std::memory_order_relaxed);
+}
+
+inline bool log_on(int level) { return g_log_level.load(std::memory_order_relaxed) >= level; }
+
+__attribute__((format(printf, 2, 3))) void log_msg(int level, const char* fmt, ...)
+{
+    if (!log_on(level)) return;
+    char buf[600];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    std::fprintf(stderr, "[zmc] %s\n", buf);
+}
+
 #define HIP_TRY(expr)                                                    \
     do {                                                                 \
         hipError_t e_ = fault_due() ? injected_error(#expr) : (expr);    \
@@ -560,6 +583,7 @@ mc_status fail(mc_ctx* ctx, mc_status st, const char* fmt, ...)
     va_end(ap);
     if (ctx) ctx->err = buf;
     g_thread_error = buf;
+    log_msg(1, "error %d: %s", (int)st, buf);
     return st;
 }
 
@@ -723,6 +747,8 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
     r->redo.push_back(fi);
     r->n_promoted++;
     ctx->stats.promoted++;
+    log_msg(2, "request %llu function %u: FP32 result cannot be trusted, running it in FP64",
+            (unsigned long long)r->id, fi);
     if (!was_active) ctx->active.push_back(r);
     if (ctx->res.on) {
         ctx->res.tiles_waiting += fs.n_tiles;
@@ -966,6 +992,8 @@ void admit(mc_ctx* ctx)
             r->grid_packed = true;
             ctx->pending.pop_front();
             ctx->active.push_back(r);
+            log_msg(3, "request %llu admitted: %llu functions, %llu tiles", (unsigned long long)r->id,
+                    (unsigned long long)nf, (unsigned long long)r->tiles_total);
             ctx->res.tiles_waiting += r->tiles_total - r->tiles_launched;
             ctx->res.active_dirty = true;
             continue;
@@ -1036,6 +1064,8 @@ void admit(mc_ctx* ctx)
         }
         ctx->pending.pop_front();
         ctx->active.push_back(r);
+        log_msg(3, "request %llu admitted: %llu functions, %llu tiles", (unsigned long long)r->id,
+                (unsigned long long)nf, (unsigned long long)r->tiles_total);
     }
 }
 
@@ -1415,6 +1445,8 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     ctx->ev_pending.push_back(evp);
     s.in_flight = true;
     s.seq = ++ctx->launch_seq;
+    log_msg(3, "launch %llu: %u tiles, %u results, %s", (unsigned long long)s.seq, s.n_tiles, s.n_fins,
+            s.graphed ? "graph" : "direct");
     return true;
 }
 
@@ -1482,6 +1514,7 @@ bool res_exited(mc_ctx* ctx)
     ResidentState& R = ctx->res;
     if (!R.live) return true;
     if (__atomic_load_n(R.exit_word, __ATOMIC_ACQUIRE) != R.epoch) return false;
+    log_msg(2, "resident launch %u has left", R.epoch);
     R.live = false;
     R.stopping = false;
     R.flush = false;
@@ -1498,6 +1531,8 @@ void res_request_stop(mc_ctx* ctx)
     if (!R.live || R.stopping) return;
     R.stopping = true;
     res_publish(R);
+    log_msg(2, "resident launch %u: stop requested at ring entry %llu%s", R.epoch, (unsigned long long)R.pushed,
+            R.flush ? " (record arena recycled)" : "");
 }
 
 // Start a launch if entries wait and none runs.
@@ -1526,6 +1561,8 @@ void res_launch(mc_ctx* ctx)
     }
     R.live = true;
     ctx->stats.launches++;
+    log_msg(2, "resident launch %u: %u workgroups, ring entries %llu..%llu", epoch, R.grid,
+            (unsigned long long)R.acked, (unsigned long long)R.pushed);
 }
 
 // A record arena position for a new run.  Records are read through the
@@ -2017,6 +2054,7 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
     resolve_capacities(cfg, &ctx->max_functions, &ctx->max_partials, &ctx->tile_cap, &ctx->fin_cap);
     ctx->fn_alloc.reset(ctx->max_functions);
     ctx->part_alloc.reset(ctx->max_partials);
+    arm_log_level();
     if (ctx->validate_only) {
         *out = ctx.release();
         return MC_OK;
@@ -2099,6 +2137,9 @@ mc_status mc_create(const mc_config* cfg_in, mc_ctx** out)
         destroy_device(ctx.get());
         return st;
     }
+    log_msg(2, "context on device %d (%s, %d CUs): %u function slots, %llu partials, %llu device bytes%s", ctx->device,
+            ctx->device_name.c_str(), ctx->num_cus, ctx->max_functions, (unsigned long long)ctx->max_partials,
+            (unsigned long long)ctx->mem_bytes, ctx->res.on ? ", resident" : "");
     *out = ctx.release();
     return MC_OK;
 }
@@ -2773,12 +2814,19 @@ extern "C" mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, d
     if (precision != MC_PREC_FP32_EVAL && precision != MC_PREC_FP64)
         return fail(ctx, MC_ERR_INVALID_ARG, "unknown precision %d", precision);
     const char* cache = std::getenv("MC_TUNE_CACHE");
-    if (cache && *cache && load_tuning(ctx, cache, precision)) return MC_OK;
+    if (cache && *cache && load_tuning(ctx, cache, precision)) {
+        log_msg(2, "tuning (precision %d) from %s: %u workgroups per CU", (int)precision, cache,
+                precision == MC_PREC_FP64 ? ctx->blocks_per_cu64 : ctx->blocks_per_cu32);
+        return MC_OK;
+    }
     if (ctx->res.on)
         return fail(ctx, MC_ERR_INVALID_ARG,
                     "a resident context does not time launches: tune a launch context (with MC_TUNE_CACHE) first");
     const mc_status st = autotune_run(ctx, precision, stream, budget_seconds);
     if (st == MC_OK && cache && *cache) store_tuning(ctx, cache, precision);
+    if (st == MC_OK)
+        log_msg(2, "tuning (precision %d): %u workgroups per CU", (int)precision,
+                precision == MC_PREC_FP64 ? ctx->blocks_per_cu64 : ctx->blocks_per_cu32);
     return st;
 }
 

@@ -715,6 +715,60 @@ bool resident_abort()
     return true;
 }
 
+// MC_LOG=3: the context, its launches and admissions, the resident kernel's
+// launch and exit, and a failure each leave a "[zmc] " line on stderr; MC_LOG
+// unset leaves none.
+bool log_levels()
+{
+    char path[] = "/tmp/zmc_log_XXXXXX";
+    const int fd = mkstemp(path);
+    CHECK(fd >= 0, "mkstemp");
+    std::fflush(stderr);
+    const int saved = dup(2);
+    dup2(fd, 2);
+    bool ok = true;
+    for (int level : {0, 3}) {
+        if (level) setenv("MC_LOG", "3", 1);
+        else unsetenv("MC_LOG");
+        mc_ctx* a = create(0, 7);
+        mc_ctx* b = create(MC_RESIDENT);
+        ok = ok && a && b;
+        if (ok) {
+            ok = run_request(a, mixed_table(6, 130, 3), false, "log launch") &&
+                 run_request(b, mixed_table(6, 131), false, "log resident");
+            uint64_t id = 0;
+            std::vector<mc_function> bad = mixed_table(3, 132);
+            bad[1].dim = 0;
+            ok = ok && mc_submit(a, bad.data(), bad.size(), MC_PREC_FP32_EVAL, &id) == MC_ERR_BAD_DIM;
+        }
+        if (a) mc_destroy(a);
+        if (b) mc_destroy(b);
+        std::fflush(stderr);
+        if (level == 0) {
+            ok = ok && lseek(fd, 0, SEEK_END) == 0;  // nothing written
+        }
+    }
+    unsetenv("MC_LOG");
+    std::fflush(stderr);
+    dup2(saved, 2);
+    close(saved);
+    std::string text;
+    {
+        FILE* f = std::fopen(path, "r");
+        char buf[4096];
+        size_t n;
+        while (f && (n = std::fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, n);
+        if (f) std::fclose(f);
+    }
+    close(fd);
+    std::remove(path);
+    CHECK(ok, "runs with logging: %s", text.c_str());
+    for (const char* want : {"[zmc] context on device 0", "[zmc] launch 1: ", "admitted: 6 functions",
+                             "[zmc] resident launch 1: ", "[zmc] error -3: function 1:", "resident"})
+        CHECK(text.find(want) != std::string::npos, "no line with \"%s\" in:\n%s", want, text.c_str());
+    return true;
+}
+
 }  // namespace
 
 int main(int argc, char** argv)
@@ -725,7 +779,7 @@ int main(int argc, char** argv)
         {"plain", plain_paths}, {"two_contexts", two_contexts}, {"fault_sweep", fault_sweep},
         {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
-        {"resident_abort", resident_abort},
+        {"resident_abort", resident_abort}, {"log_levels", log_levels},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {
