@@ -273,6 +273,35 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
  * flight, then clears the request so later work runs normally. */
 mc_status mc_abort(mc_ctx* ctx);
 
+/* Checkpoint and resume of one request.  A function's state is its result
+ * once finished, and otherwise the partial sums of the tiles it has run (its
+ * samples are addressed by counter, paper "Solution method": which points a
+ * tile draws never depends on when it runs), so a request snapshotted part way
+ * and restored later -- in another context, process or machine with the same
+ * library version -- completes with results bitwise equal to a run without the
+ * interruption.
+ *
+ * mc_snapshot waits for the launches in flight, then writes request
+ * `request_id`'s state into buf[0 .. *bytes): its functions (a grid as its
+ * expanded table), their tiling and progress, the results already in, and the
+ * partials of the tiles run (16 bytes per tile; native byte order).  With buf
+ * NULL it only stores the size into *bytes.  The request stays in the context
+ * unchanged (continue it, abort it, or take its results).  Errors:
+ * MC_ERR_INVALID_ARG (cap smaller than needed -- *bytes holds the size --, a
+ * request that uses a run-time family, an aborted or failed request, a
+ * resident context), MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP.
+ *
+ * mc_restore checks a snapshot (format, version, every function as mc_submit
+ * does, tiling and progress against the functions) and queues it as a new
+ * request whose id it stores into *out_request_id; its saved partials go to
+ * the device when it is admitted.  Functions whose results were in complete
+ * at once; the restoring context's MC_NO_PROMOTE setting applies to FP32
+ * results not yet in.  Errors: MC_ERR_INVALID_ARG (not a snapshot of this
+ * library version, inconsistent or truncated, a resident context), the
+ * validation codes of mc_submit, MC_ERR_ADMISSION. */
+mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, size_t* bytes);
+mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_request_id);
+
 /* The plain baseline path: for each function one kernel launch with a grid
  * sized to its N (one thread per 4 samples) and a second launch that reduces
  * the block partials, FP64 evaluation, no batching and no graph.  Synchronous:

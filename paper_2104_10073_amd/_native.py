@@ -53,7 +53,7 @@ EXPORTS = [
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
     "mc_segment_samples", "mc_version", "mc_register_family", "mc_submit_grid",
-    "mc_sample_points", "mc_integrate_plain_fp64_noalloc",
+    "mc_sample_points", "mc_integrate_plain_fp64_noalloc", "mc_snapshot", "mc_restore",
 ]
 
 
@@ -121,6 +121,8 @@ def load(path: str = LIB_PATH):
     L.mc_pending.argtypes = [vp, u64p, u64p]
     L.mc_results.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.c_int]
     L.mc_abort.argtypes = [vp]
+    L.mc_snapshot.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
+    L.mc_restore.argtypes = [vp, vp, ctypes.c_size_t, u64p]
     L.mc_integrate_plain_fp64.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.mc_integrate_plain_fp64_noalloc.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.mc_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
@@ -293,6 +295,21 @@ class Context:
     def abort(self):
         """mc_abort: stop the running persistent kernels; queued requests complete as aborted."""
         self._check(self.L.mc_abort(self.h), self.h)
+
+    def snapshot(self, request_id: int) -> bytes:
+        """mc_snapshot: the request's state (results in, tiling, progress, partials of the tiles run)."""
+        need = ctypes.c_size_t()
+        self._check(self.L.mc_snapshot(self.h, request_id, None, 0, ctypes.byref(need)), self.h)
+        buf = ctypes.create_string_buffer(need.value)
+        self._check(self.L.mc_snapshot(self.h, request_id, buf, need.value, ctypes.byref(need)), self.h)
+        return buf.raw[:need.value]
+
+    def restore(self, blob: bytes) -> int:
+        """mc_restore: queue a snapshotted request; returns its new id."""
+        rid = ctypes.c_uint64()
+        data = ctypes.create_string_buffer(bytes(blob), len(blob))
+        self._check(self.L.mc_restore(self.h, data, len(blob), ctypes.byref(rid)), self.h)
+        return int(rid.value)
 
     def register_family(self, source: str) -> int:
         """Compile an integrand family from source (see mc_register_family); returns its family id."""

@@ -369,6 +369,8 @@ struct Request {
     bool lost = false;                // part of its work went to a launch that failed after handing
                                       // finalize records to kernels: it completes with MC_ERR_HIP
     uint32_t n_promoted = 0;
+    bool restored = false;            // built by mc_restore from a snapshot
+    std::vector<Partial> staged;      // restored: its whole partial range, saved tiles filled in (uploaded at admission)
 };
 
 // A function's consecutive tiles in one launch and the cost of one of them.
@@ -687,6 +689,7 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
 
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
+    std::vector<Partial>().swap(r->staged);
     if (r->uploaded) {
         quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
@@ -1021,6 +1024,15 @@ void admit(mc_ctx* ctx)
         bool enqueued = false;
         try {
             if (r->grid) {
+                // a restored grid's rows already promoted to FP64 take host-packed
+                // FP64 records, copied by their first launch after the grid's
+                // device-packed ones, as when they were promoted
+                if (r->restored && r->spec.precision != MC_PREC_FP64)
+                    for (uint64_t i = 0; i < nf; ++i)
+                        if (r->st[i].f64 && r->st[i].next_tile < r->st[i].n_tiles) {
+                            pack_function(r->at(i), MC_PREC_FP64, &ctx->h_fns[slot_off + i]);
+                            r->st[i].needs_upload = true;
+                        }
                 // records built on the device from the grid spec: no table crosses PCIe
                 if (idle) {
                     DevFn* out = ctx->d_fns + slot_off;
@@ -1044,7 +1056,14 @@ void admit(mc_ctx* ctx)
                     for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = true;
                 }
             }
-            if (idle) {
+            // a restored request's saved partials go up on the upload stream;
+            // launches with its tiles wait for the upload event
+            if (!r->staged.empty()) {
+                enqueued = true;
+                HIP_TRY(hipMemcpyAsync(ctx->d_partials + part_off, r->staged.data(), parts * sizeof(Partial),
+                                       hipMemcpyHostToDevice, ctx->upload_stream));
+            }
+            if (idle || !r->staged.empty()) {
                 HIP_TRY(hipEventCreateWithFlags(&r->uploaded, hipEventDisableTiming));
                 HIP_TRY(hipEventRecord(r->uploaded, ctx->upload_stream));
             }
@@ -2158,7 +2177,15 @@ mc_status mc_destroy(mc_ctx* ctx)
             quiet(hipStreamSynchronize(ctx->res.stream));
         }
     }
-    if (!ctx->validate_only) destroy_device(ctx);
+    if (!ctx->validate_only) {
+        // requests still in the context may hold the event of their upload
+        for (auto& kv : ctx->requests)
+            if (kv.second->uploaded) {
+                quiet(hipEventDestroy(kv.second->uploaded));
+                kv.second->uploaded = nullptr;
+            }
+        destroy_device(ctx);
+    }
     delete ctx;
     return MC_OK;
 }
@@ -2254,14 +2281,19 @@ mc_status enqueue_request(mc_ctx* ctx, std::unique_ptr<Request> r, uint64_t* out
         return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
                     (unsigned long long)parts, (unsigned long long)ctx->max_partials);
     const size_t n = r->count();
-    r->order.resize(n);
-    for (size_t i = 0; i < n; ++i) r->order[i] = (uint32_t)i;
+    r->order.clear();
+    for (size_t i = 0; i < n; ++i)
+        if (r->st[i].next_tile < r->st[i].n_tiles) r->order.push_back((uint32_t)i);  // (a restored request: unfinished ones)
     Request* rq = r.get();
     std::stable_sort(rq->order.begin(), rq->order.end(),
                      [rq](uint32_t a, uint32_t b) { return rq->st[a].tile_cost > rq->st[b].tile_cost; });
     r->id = ctx->next_id++;
     *out_request_id = r->id;
     ctx->requests.emplace(rq->id, std::move(r));
+    if (rq->fns_done == rq->count()) {  // a restored request whose results were all in
+        ctx->completed.push_back(rq->id);
+        return MC_OK;
+    }
     if (!ctx->validate_only) {
         ctx->pending.push_back(rq);
         // The request is queued.  Admission is tried at once; if a HIP call of it
@@ -2503,6 +2535,264 @@ mc_status mc_abort(mc_ctx* ctx)
         return fail_hip(ctx, e);
     }
     return MC_OK;
+}
+
+// ---------------------------------------------------------------- checkpoint / resume
+//
+// Snapshot layout (native byte order):
+//   SnapHeader | GridSpec (grids only) | mc_function[n] | SnapFn[n] | mc_result[n] | Partial[n_partials]
+// partials: for each function in index order that has not finished, the
+// partials of its tiles 0 .. next_tile.  A grid stays a grid (its records are
+// packed on the device, which in FP32 need not match the host's packing bit
+// for bit); its functions are listed too, and checked against the spec.
+
+}  // extern "C"
+
+namespace {
+
+constexpr char kSnapMagic[8] = {'Z', 'M', 'C', 'S', 'N', 'A', 'P', '1'};
+
+struct SnapHeader {
+    char magic[8];
+    uint32_t version;         // 1
+    uint32_t header_bytes;    // sizeof(SnapHeader)
+    uint64_t total_bytes;
+    uint64_t n;               // functions
+    uint64_t n_partials;      // partials stored
+    uint32_t seg_samples;     // tiling constants the partials were made with
+    uint32_t block_waves;
+    int32_t precision;
+    uint32_t grid;            // 1: a parameter grid (GridSpec follows the header)
+    uint64_t request_id;      // of the snapshotted request (for the reader's information)
+};
+
+struct SnapFn {
+    uint32_t seg_log2;
+    uint32_t n_tiles;
+    uint32_t next_tile;       // tiles run; n_tiles when the result is in
+    uint32_t f64;             // evaluated in FP64 (requested, or promoted)
+};
+
+static_assert(sizeof(SnapHeader) == 64 && sizeof(SnapFn) == 16, "snapshot layout");
+
+uint64_t snapshot_bytes(uint64_t n, uint64_t n_partials, bool grid)
+{
+    return sizeof(SnapHeader) + (grid ? sizeof(GridSpec) : 0) +
+           n * (sizeof(mc_function) + sizeof(SnapFn) + sizeof(mc_result)) + n_partials * sizeof(Partial);
+}
+
+}  // namespace
+
+extern "C" {
+
+mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, size_t* bytes)
+{
+    if (!ctx || !bytes) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    auto it = ctx->requests.find(request_id);
+    if (it == ctx->requests.end())
+        return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
+    Request* r = it->second.get();
+    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "a resident context keeps no snapshots");
+    const uint64_t n = r->count();
+    if (r->at(0).family >= kUserFamily0)
+        return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
+                    (unsigned long long)request_id);
+    if (!r->grid)
+        for (uint64_t i = 0; i < n; ++i)
+            if (r->fns[i].family >= kUserFamily0)
+                return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
+                            (unsigned long long)request_id);
+    std::vector<Partial> range;
+    try {
+        if (!ctx->validate_only) {
+            HIP_TRY(hipSetDevice(ctx->device));
+            reap(ctx, 2);  // every launch in flight: from here on no kernel touches its partials
+        }
+        if (r->lost || r->aborted)
+            return fail(ctx, MC_ERR_INVALID_ARG, "request %llu was aborted or failed", (unsigned long long)request_id);
+        uint64_t n_partials = 0;
+        for (uint64_t i = 0; i < n; ++i)
+            if (r->st[i].next_tile < r->st[i].n_tiles) n_partials += r->st[i].next_tile;
+        const uint64_t total = snapshot_bytes(n, n_partials, r->grid);
+        *bytes = (size_t)total;
+        if (!buf) return MC_OK;
+        if (cap < total)
+            return fail(ctx, MC_ERR_INVALID_ARG, "snapshot needs %llu bytes, the buffer holds %zu",
+                        (unsigned long long)total, cap);
+        if (n_partials > 0) {
+            // (only an admitted request has run tiles)
+            range.resize(r->part_count);
+            HIP_TRY(hipMemcpyAsync(range.data(), ctx->d_partials + r->part_base, r->part_count * sizeof(Partial),
+                                   hipMemcpyDeviceToHost, ctx->upload_stream));
+            HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
+        }
+        uint8_t* p = (uint8_t*)buf;
+        SnapHeader h{};
+        std::memcpy(h.magic, kSnapMagic, sizeof h.magic);
+        h.version = 1;
+        h.header_bytes = sizeof h;
+        h.total_bytes = total;
+        h.n = n;
+        h.n_partials = n_partials;
+        h.seg_samples = (uint32_t)kSegSamples;
+        h.block_waves = (uint32_t)kBlockWaves;
+        h.precision = r->precision;
+        h.grid = r->grid ? 1u : 0u;
+        h.request_id = r->id;
+        std::memcpy(p, &h, sizeof h);
+        p += sizeof h;
+        if (r->grid) {
+            std::memcpy(p, &r->spec, sizeof r->spec);
+            p += sizeof r->spec;
+        }
+        for (uint64_t i = 0; i < n; ++i, p += sizeof(mc_function)) {
+            const mc_function f = r->at(i);
+            std::memcpy(p, &f, sizeof f);
+        }
+        for (uint64_t i = 0; i < n; ++i, p += sizeof(SnapFn)) {
+            const FnState& fs = r->st[i];
+            const SnapFn sf{fs.seg_log2, fs.n_tiles, fs.next_tile, fs.f64 ? 1u : 0u};
+            std::memcpy(p, &sf, sizeof sf);
+        }
+        for (uint64_t i = 0; i < n; ++i, p += sizeof(mc_result)) {
+            mc_result res{};
+            if (r->st[i].next_tile == r->st[i].n_tiles) res = r->results[i];
+            std::memcpy(p, &res, sizeof res);
+        }
+        uint64_t off = 0;  // function i's first partial within the request's range
+        for (uint64_t i = 0; i < n; ++i) {
+            const FnState& fs = r->st[i];
+            if (fs.next_tile < fs.n_tiles && fs.next_tile > 0) {
+                std::memcpy(p, range.data() + off, (size_t)fs.next_tile * sizeof(Partial));
+                p += (size_t)fs.next_tile * sizeof(Partial);
+            }
+            off += fs.n_tiles;
+        }
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    log_msg(2, "request %llu snapshot: %llu bytes", (unsigned long long)request_id, (unsigned long long)*bytes);
+    return MC_OK;
+}
+
+mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_request_id)
+{
+    if (!ctx || !buf || !out_request_id) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "restore into a launch context, not a resident one");
+    SnapHeader h;
+    if (bytes < sizeof h) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot of %zu bytes is truncated", bytes);
+    std::memcpy(&h, buf, sizeof h);
+    if (std::memcmp(h.magic, kSnapMagic, sizeof h.magic) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+        return fail(ctx, MC_ERR_INVALID_ARG, "not a snapshot of this library version");
+    if (h.seg_samples != (uint32_t)kSegSamples || h.block_waves != (uint32_t)kBlockWaves)
+        return fail(ctx, MC_ERR_INVALID_ARG, "snapshot made with another tiling (%u samples per segment, %u waves)",
+                    h.seg_samples, h.block_waves);
+    if (h.n == 0 || h.n > ctx->max_functions)
+        return fail(ctx, h.n == 0 ? MC_ERR_INVALID_ARG : MC_ERR_ADMISSION,
+                    "snapshot of %llu functions; the context has %u function slots", (unsigned long long)h.n,
+                    ctx->max_functions);
+    if (h.grid > 1u || h.n_partials > ctx->max_partials || h.total_bytes != bytes ||
+        snapshot_bytes(h.n, h.n_partials, h.grid != 0u) != bytes)
+        return fail(ctx, MC_ERR_INVALID_ARG, "snapshot size %zu does not match its contents", bytes);
+    if (h.precision != MC_PREC_FP32_EVAL && h.precision != MC_PREC_FP64)
+        return fail(ctx, MC_ERR_INVALID_ARG, "snapshot precision %d", h.precision);
+    const uint8_t* p = (const uint8_t*)buf + sizeof h;
+    const uint64_t n = h.n;
+    std::unique_ptr<Request> r(new Request());
+    r->precision = h.precision;
+    r->restored = true;
+    r->n = n;
+    if (h.grid) {
+        std::memcpy(&r->spec, p, sizeof r->spec);
+        p += sizeof r->spec;
+        if (r->spec.n != n || r->spec.n_axes < 1 || r->spec.n_axes > (uint32_t)MC_MAX_GRID_AXES ||
+            (r->spec.precision != MC_PREC_FP32_EVAL && r->spec.precision != MC_PREC_FP64))
+            return fail(ctx, MC_ERR_INVALID_ARG, "snapshot's grid does not match its functions");
+        r->grid = true;
+    }
+    r->fns.resize(n);
+    std::memcpy(r->fns.data(), p, n * sizeof(mc_function));
+    p += n * sizeof(mc_function);
+    if (r->grid) {
+        for (uint64_t i = 0; i < n; ++i) {
+            mc_function g;
+            grid_function(r->spec.base, r->spec.axes, r->spec.n_axes, i, &g);
+            if (std::memcmp(&g, &r->fns[i], sizeof g) != 0)
+                return fail(ctx, MC_ERR_INVALID_ARG, "snapshot's grid does not match function %llu",
+                            (unsigned long long)i);
+        }
+    }
+    std::vector<SnapFn> sf(n);
+    std::memcpy(sf.data(), p, n * sizeof(SnapFn));
+    p += n * sizeof(SnapFn);
+    r->results.resize(n);
+    std::memcpy(r->results.data(), p, n * sizeof(mc_result));
+    p += n * sizeof(mc_result);
+    const Partial* saved = (const Partial*)p;
+    r->st.resize(n);
+    uint64_t parts = 0, used = 0;
+    for (uint64_t i = 0; i < n; ++i) {
+        const mc_function& f = r->fns[i];
+        std::string why;
+        if (f.family >= kUserFamily0) return fail(ctx, MC_ERR_INVALID_ARG, "function %llu: run-time family",
+                                                  (unsigned long long)i);
+        const mc_status st = validate_one(f, 0, &why);
+        if (st != MC_OK) return fail(ctx, st, "function %llu: %s", (unsigned long long)i, why.c_str());
+        const uint32_t n_segments = (uint32_t)(((f.n_samples + 3) / 4 + kSegQuads - 1) / kSegQuads);
+        const SnapFn& s = sf[i];
+        if (s.seg_log2 > (uint32_t)kMaxSegLog2 || s.n_tiles != tiles_for(n_segments, s.seg_log2) ||
+            s.next_tile > s.n_tiles || s.f64 > 1u || (h.precision == MC_PREC_FP64 && s.f64 == 0u))
+            return fail(ctx, MC_ERR_INVALID_ARG, "function %llu: tiling or progress does not match the function",
+                        (unsigned long long)i);
+        FnState& fs = r->st[i];
+        fs.seg_log2 = s.seg_log2;
+        fs.n_tiles = s.n_tiles;
+        fs.next_tile = s.next_tile;
+        fs.f64 = s.f64 != 0u;
+        fs.needs_upload = false;
+        fs.token = 0;
+        fs.rec = 0;
+        fs.tile_cost = sample_cost(f.family, f.dim, fs.f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL) *
+                       (double)std::min<uint64_t>(f.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << fs.seg_log2));
+        if (s.next_tile == s.n_tiles) {
+            const mc_result& res = r->results[i];
+            if (res.status != MC_OK || res.n != f.n_samples ||
+                res.precision != (fs.f64 ? (uint32_t)MC_PREC_FP64 : (uint32_t)MC_PREC_FP32_EVAL))
+                return fail(ctx, MC_ERR_INVALID_ARG, "function %llu: its saved result does not match it",
+                            (unsigned long long)i);
+            r->fns_done++;
+        } else {
+            r->results[i] = mc_result{};
+            r->tiles_total += fs.n_tiles;
+            r->tiles_launched += fs.next_tile;
+            r->work_left += fs.tile_cost * (double)(fs.n_tiles - fs.next_tile);
+            used += fs.next_tile;
+        }
+        parts += fs.n_tiles;
+    }
+    if (used != h.n_partials)
+        return fail(ctx, MC_ERR_INVALID_ARG, "snapshot holds %llu partials, its functions' progress needs %llu",
+                    (unsigned long long)h.n_partials, (unsigned long long)used);
+    if (parts > ctx->max_partials)
+        return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
+                    (unsigned long long)parts, (unsigned long long)ctx->max_partials);
+    if (used > 0) {
+        r->staged.assign(parts, Partial{0.0, 0.0});
+        uint64_t off = 0, k = 0;
+        for (uint64_t i = 0; i < n; ++i) {
+            const FnState& fs = r->st[i];
+            if (fs.next_tile < fs.n_tiles && fs.next_tile > 0) {
+                std::memcpy(r->staged.data() + off, saved + k, (size_t)fs.next_tile * sizeof(Partial));
+                k += fs.next_tile;
+            }
+            off += fs.n_tiles;
+        }
+    }
+    if (r->grid) std::vector<mc_function>().swap(r->fns);  // (a grid's functions come from its spec)
+    log_msg(2, "restoring a snapshot of request %llu: %llu functions, %llu finished, %llu partials",
+            (unsigned long long)h.request_id, (unsigned long long)n, (unsigned long long)r->fns_done,
+            (unsigned long long)used);
+    return enqueue_request(ctx, std::move(r), out_request_id);
 }
 
 mc_status mc_integrate_plain_fp64(mc_ctx* ctx, const mc_function* fns, size_t n, mc_result* out, void* stream)

@@ -715,6 +715,124 @@ bool resident_abort()
     return true;
 }
 
+// Checkpoint and resume: requests snapshotted part way through (functions
+// spanning launches, promotions pending, a grid, one still queued, one
+// finished) and restored into another context complete with exactly the
+// expected results; sizes, truncated and altered snapshots, resident contexts.
+bool snapshot_restore()
+{
+    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u}) {
+        mc_ctx* a = create(flags, 5, MC_SCHED_FAIR, 64, 1 << 14);
+        CHECK(a, "create");
+        // a request that has finished (results not yet taken) when it is snapshotted
+        std::vector<mc_function> small = mixed_table(3, 143);
+        uint64_t sid = 0;
+        CHECK(mc_submit(a, small.data(), small.size(), MC_PREC_FP32_EVAL, &sid) == MC_OK, "submit small");
+        bool small_done = false;
+        for (int i = 0; i < 2000 && !small_done; ++i) {
+            size_t n = 0;
+            uint64_t got[8];
+            CHECK(mc_run(a, nullptr) != MC_ERR_HIP && mc_poll(a, got, 8, &n) == MC_OK, "run");
+            for (size_t k = 0; k < n; ++k) small_done = small_done || got[k] == sid;
+        }
+        CHECK(small_done, "small request");
+        std::vector<std::vector<mc_function>> reqs = {mixed_table(20, 140, 4), mixed_table(6, 141), mixed_table(40, 142)};
+        std::vector<uint64_t> ids;
+        for (size_t k = 0; k < reqs.size(); ++k) {
+            uint64_t id = 0;
+            const mc_status st = mc_submit(a, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id);
+            CHECK(st == MC_OK, "submit %zu: %s", k, mc_last_error(a));
+            ids.push_back(id);
+        }
+        const mc_function base = make_fn(MC_FAMILY_HARMONIC, 3, 50001, 7ull << 32, 1.5);
+        mc_grid_axis axes[2] = {{MC_PARAM_V0, 5, 1.0, 0.5}, {0, 3, 0.5, 0.25}};
+        uint64_t gid = 0;
+        CHECK(mc_submit_grid(a, &base, axes, 2, MC_PREC_FP32_EVAL, &gid) == MC_OK, "grid");
+        std::vector<mc_function> gt;
+        for (uint64_t i = 0; i < 15; ++i) {
+            mc_function f = base;
+            f.params[MC_PARAM_V0] = 1.0 + (double)(i % 5) * 0.5;
+            f.params[0] = 0.5 + (double)(i / 5) * 0.25;
+            f.seed = base.seed + i;
+            gt.push_back(f);
+        }
+        ids.push_back(gid);
+        reqs.push_back(gt);
+        // a grid whose rows the FP32 check sends to FP64 (constant in the emulated FP32 kernel)
+        const mc_function pbase = make_fn(MC_FAMILY_GAUSSIAN, 2, 30001, (1ull << 63) | (145ull << 32));
+        mc_grid_axis paxis = {0, 4, 0.5, 0.25};
+        uint64_t pid = 0;
+        CHECK(mc_submit_grid(a, &pbase, &paxis, 1, MC_PREC_FP32_EVAL, &pid) == MC_OK, "promoted grid");
+        std::vector<mc_function> pt;
+        for (uint64_t i = 0; i < 4; ++i) {
+            mc_function f = pbase;
+            f.params[0] = 0.5 + (double)i * 0.25;
+            f.seed = pbase.seed + i;
+            pt.push_back(f);
+        }
+        ids.push_back(pid);
+        reqs.push_back(pt);
+        for (int i = 0; i < 40; ++i) CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
+        ids.push_back(sid);
+        reqs.push_back(small);
+        std::vector<std::vector<uint8_t>> blobs;
+        for (size_t k = 0; k < ids.size(); ++k) {
+            size_t need = 0;
+            CHECK(mc_snapshot(a, ids[k], nullptr, 0, &need) == MC_OK && need > 0, "size %zu: %s", k, mc_last_error(a));
+            std::vector<uint8_t> b(need);
+            size_t got = 0;
+            CHECK(mc_snapshot(a, ids[k], b.data(), need - 1, &got) == MC_ERR_INVALID_ARG && got == need, "small buffer");
+            CHECK(mc_snapshot(a, ids[k], b.data(), b.size(), &got) == MC_OK && got == need, "snapshot %zu: %s", k,
+                  mc_last_error(a));
+            blobs.push_back(b);
+        }
+        uint64_t pending_r = 0, pending_t = 0;
+        CHECK(mc_pending(a, &pending_r, &pending_t) == MC_OK && pending_t > 0, "work left at the snapshot");
+        mc_destroy(a);
+
+        mc_ctx* b = create(flags, 7, MC_SCHED_SRPT, 128, 1 << 15);
+        CHECK(b, "create");
+        uint8_t seg[96];
+        for (int i = 0; i < 96; ++i) seg[i] = 3;  // another tiling for new requests: restored ones keep theirs
+        CHECK(mc_set_tuning(b, 0, seg) == MC_OK, "tuning");
+        std::vector<uint64_t> rids;
+        for (size_t k = 0; k < blobs.size(); ++k) {
+            uint64_t id = 0;
+            CHECK(mc_restore(b, blobs[k].data(), blobs[k].size(), &id) == MC_OK, "restore %zu: %s", k, mc_last_error(b));
+            rids.push_back(id);
+        }
+        for (size_t k = 0; k < rids.size(); ++k) {
+            std::vector<mc_result> r(reqs[k].size());
+            CHECK(mc_results(b, rids[k], r.data(), r.size(), 1) == MC_OK, "results %zu: %s", k, mc_last_error(b));
+            if (!check_results(reqs[k], r, k == 1, "restored")) return false;
+        }
+        // damaged snapshots
+        std::vector<uint8_t> bad = blobs[0];
+        uint64_t id = 0;
+        bad[0] = 'X';
+        CHECK(mc_restore(b, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "magic");
+        CHECK(mc_restore(b, blobs[0].data(), blobs[0].size() - 16, &id) == MC_ERR_INVALID_ARG, "truncated");
+        bad = blobs[0];
+        const size_t fn_off = 64 + reqs[0].size() * sizeof(mc_function);
+        bad[fn_off + 4] ^= 1;  // function 0's tile count
+        CHECK(mc_restore(b, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "tile count: %s", mc_last_error(b));
+        mc_destroy(b);
+    }
+    mc_ctx* r = create(MC_RESIDENT);
+    CHECK(r, "create resident");
+    const std::vector<mc_function> t = mixed_table(4, 144);
+    uint64_t id = 0, nid = 0;
+    size_t need = 0;
+    CHECK(mc_submit(r, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+    CHECK(mc_snapshot(r, id, nullptr, 0, &need) == MC_ERR_INVALID_ARG, "resident snapshot");
+    std::vector<uint8_t> dummy(64, 0);
+    CHECK(mc_restore(r, dummy.data(), dummy.size(), &nid) == MC_ERR_INVALID_ARG, "resident restore");
+    std::vector<mc_result> res(t.size());
+    CHECK(mc_results(r, id, res.data(), res.size(), 1) == MC_OK, "results");
+    mc_destroy(r);
+    return true;
+}
+
 // MC_LOG=3: the context, its launches and admissions, the resident kernel's
 // launch and exit, and a failure each leave a "[zmc] " line on stderr; MC_LOG
 // unset leaves none.
@@ -779,7 +897,7 @@ int main(int argc, char** argv)
         {"plain", plain_paths}, {"two_contexts", two_contexts}, {"fault_sweep", fault_sweep},
         {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
-        {"resident_abort", resident_abort}, {"log_levels", log_levels},
+        {"resident_abort", resident_abort}, {"log_levels", log_levels}, {"snapshot", snapshot_restore},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {
