@@ -370,6 +370,7 @@ struct Request {
                                       // finalize records to kernels: it completes with MC_ERR_HIP
     uint32_t n_promoted = 0;
     bool restored = false;            // built by mc_restore from a snapshot
+    uint32_t fair_credit = 0;         // resident FAIR: tiles the request may still push this pass
     std::vector<Partial> staged;      // restored: its whole partial range, saved tiles filled in (uploaded at admission)
 };
 
@@ -1609,6 +1610,19 @@ bool res_room(const ResidentState& R)
     return !R.stopping && R.unread_tiles < R.backlog && R.pushed < R.acked + kRingEntries;
 }
 
+// Tiles of request r's next chunk (function state fs): one tile while the
+// request's tiles not yet pushed do not fill the workgroups (its tiles spread
+// over as many of them as possible), up to kChunkTiles as it has more (fewer
+// entries for the host to write: the host writes one in tens of nanoseconds, a
+// workgroup runs a tile in tens of microseconds, so a saturated GPU needs
+// entries of several tiles).
+uint32_t res_chunk_tiles(const ResidentState& R, const Request* r, const FnState& fs)
+{
+    const uint32_t left = fs.n_tiles - fs.next_tile;
+    const uint64_t per_wg = (r->tiles_total - r->tiles_launched) / R.grid;
+    return std::min(std::min(left, kChunkTiles), (uint32_t)std::max<uint64_t>(1, per_wg));
+}
+
 // Push request r's next chunk into the ring (not yet published).  The first
 // chunk of a run takes a token and an arena position and carries the upload
 // flag.  Returns false if nothing was pushed.
@@ -1632,14 +1646,7 @@ bool res_push_chunk(mc_ctx* ctx, Request* r)
         R.arena_busy[rec] = 1;
         R.runs.push_back(ResRun{r, fi, fs.slot, fs.token, rec});
     }
-    // one tile per chunk while the request's tiles not yet pushed do not fill
-    // the workgroups (its tiles spread over as many of them as possible), up
-    // to kChunkTiles as it has more (fewer entries for the host to write; the
-    // host writes one in tens of nanoseconds, a workgroup runs a tile in tens
-    // of microseconds, so a saturated GPU needs entries of several tiles)
-    const uint32_t left = fs.n_tiles - fs.next_tile;
-    const uint64_t per_wg = (r->tiles_total - r->tiles_launched) / R.grid;
-    const uint32_t count = std::min(std::min(left, kChunkTiles), (uint32_t)std::max<uint64_t>(1, per_wg));
+    const uint32_t count = res_chunk_tiles(R, r, fs);
     R.ring[R.pushed & (kRingEntries - 1)] =
         Chunk{fs.slot, fs.rec, fs.next_tile, count, (uint32_t)fs.part0, fs.n_tiles, fs.token,
               fs.seg_log2 | (first ? kChunkUpload << 8 : 0u)};
@@ -1677,12 +1684,26 @@ void res_feed(mc_ctx* ctx)
         R.active_dirty = false;
     }
     if (ctx->policy == MC_SCHED_FAIR) {
+        // deficit round robin by tiles: each visit credits a request with
+        // kChunkTiles tiles and it pushes chunks while its credit covers the
+        // next one, so requests cut into large chunks get no larger share
         const size_t n = ctx->active.size();
         size_t k = R.fair_pos % n, idle = 0;
         while (idle < n && res_room(R) && !R.flush) {
             Request* r = ctx->active[k];
-            if (res_push_chunk(ctx, r)) idle = 0;
-            else ++idle;
+            bool pushed = false;
+            if (has_work(r)) {
+                r->fair_credit = std::min(r->fair_credit + kChunkTiles, 2 * kChunkTiles);
+                while (has_work(r) && res_room(R)) {
+                    const bool in_order = r->order_pos < r->order.size();
+                    const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
+                    const uint32_t need = res_chunk_tiles(R, r, r->st[fi]);
+                    if (need > r->fair_credit || !res_push_chunk(ctx, r)) break;
+                    r->fair_credit -= need;
+                    pushed = true;
+                }
+            }
+            idle = pushed ? 0 : idle + 1;
             if (!has_work(r)) exhausted = true;
             k = k + 1 == n ? 0 : k + 1;
         }
