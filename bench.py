@@ -407,6 +407,20 @@ def other_configs(Z, W, stream, keep=None):
         torch.cuda.synchronize()
         return r, time.perf_counter() - t0
 
+    # one GPU's share of the headline batch spread over 8 GPUs: 125 of its 1000
+    # functions, the same number of tiles per GPU as a cost-balanced eighth of its
+    # tile list (the rest of a multi-GPU step, one gather of partials, is not built)
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH, policy=Z.MC_SCHED_FIFO) as sctx:
+        K = 10
+        share = [W.harmonic_batch(125, n_samples=1_000_000, base=2000 + b) for b in range(K + 2)]
+        st0, dt, _, st1 = timed_steps(sctx, share, 125, K, 2, stream)
+        kernel_ms = (st1["fp32_ms"] - st0["fp32_ms"]) / K
+        ev = 125 * 1_000_000
+        out["harmonic_share_1_of_8"] = {
+            "functions": 125, "evals_per_step": ev, "ms_per_step": dt / K * 1e3, "fp32_kernel_ms": kernel_ms,
+            "evals_per_s": ev * K / dt, "kernel_fraction_of_step": kernel_ms / (dt / K * 1e3)}
+        log(f"harmonic_share_1_of_8: {ev * K / dt:.3g} evals/s, {dt / K * 1e3:.3f} ms per step, "
+            f"FP32 kernel {kernel_ms:.3f} ms")
     with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as ctx:
         # the headline batch end to end from a host table: validation, packing, the
         # PCIe upload of 1000 records, the launch and the results back (the
