@@ -410,9 +410,12 @@ def other_configs(Z, W, stream, keep=None):
     # one GPU's share of the headline batch spread over 8 GPUs: 125 of its 1000
     # functions, the same number of tiles per GPU as a cost-balanced eighth of its
     # tile list (the rest of a multi-GPU step, one gather of partials, is not built)
-    with Z.Context(device=0, flags=Z.MC_NO_GRAPH, policy=Z.MC_SCHED_FIFO) as sctx:
-        K = 10
-        share = [W.harmonic_batch(125, n_samples=1_000_000, base=2000 + b) for b in range(K + 2)]
+    K = 10
+    share = [W.harmonic_batch(125, n_samples=1_000_000, base=2000 + b) for b in range(K + 2)]
+    with Z.Context(device=0, flags=Z.MC_VALIDATE_ONLY) as probe:
+        probe.submit(share[0], Z.PREC_FP32)
+        share_tiles = probe.validate_tiles()  # one batch per launch, as in the headline's steps
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH, policy=Z.MC_SCHED_FIFO, max_tiles_per_run=share_tiles) as sctx:
         st0, dt, _, st1 = timed_steps(sctx, share, 125, K, 2, stream)
         kernel_ms = (st1["fp32_ms"] - st0["fp32_ms"]) / K
         ev = 125 * 1_000_000
