@@ -4,7 +4,8 @@ Each run creates a context with MC_FAULT_HIP=n, so the n-th checked HIP call
 the library makes reports failure without being made (the GPU itself never
 faults: the call is simply not issued), and drives three requests -- mixed
 forms in FP32, the edge table (with its promoted rows), a mixed FP64 table --
-through launches of 8 tiles.  Every request must come back either bitwise as
+through launches of 8 tiles, or through a resident context (every third n)
+whose ring holds 8 unread tiles.  Every request must come back either bitwise as
 in a run without failures or with MC_ERR_HIP / MC_ERR_OUT_OF_MEMORY; every
 call returns.  The CPU emulation sweeps every n (test_host_runtime_emulated);
 this runs the same kind of sweep against the real runtime, graphs included.
@@ -68,11 +69,17 @@ def test_failed_hip_calls_never_give_wrong_results():
     os.environ.pop("MC_FAULT_HIP", None)
     ref, errors = _run(Z, Z.MC_NO_GRAPH, tables)
     assert errors == 0 and all(isinstance(v, np.ndarray) for v in ref.values())
+    res_ref, errors = _run(Z, Z.MC_RESIDENT, tables)
+    assert errors == 0
+    for k in ref:
+        for f in FIELDS:
+            assert np.array_equal(res_ref[k][f], ref[k][f]), (k, f)
     seen_errors = 0
     try:
         for n in range(1, 600):
             os.environ["MC_FAULT_HIP"] = str(n)
-            flags = Z.MC_NO_GRAPH if n % 2 else 0
+            # direct launches, graphs, and the resident engine in turn
+            flags = (Z.MC_NO_GRAPH, 0, Z.MC_RESIDENT)[n % 3]
             out, errors = _run(Z, flags, tables)
             if out is None:
                 seen_errors += 1
