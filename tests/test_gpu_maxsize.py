@@ -42,6 +42,15 @@ def test_max_size_functions_match_exact_integrals():
     assert np.all(r32p["precision"] == Z.PREC_FP64) and np.all(r32["precision"] == Z.PREC_FP32)
     for k in ("mean", "std_error", "sum_f", "sum_f2"):
         assert np.array_equal(r32p[k], r64[k]), k
+    # the resident engine: the same tiles and trees, so the same bits (a function
+    # of 2^16 tiles, chunks of up to 8)
+    print("max size through a resident context", flush=True)
+    with Z.Context(device=0, flags=Z.MC_RESIDENT | Z.MC_NO_PROMOTE) as c:
+        q64 = c.integrate(t, Z.PREC_FP64)
+        q32 = c.integrate(t, Z.PREC_FP32)
+    for k in ("mean", "std_error", "sum_f", "sum_f2", "n", "status", "precision"):
+        assert np.array_equal(q64[k], r64[k]), k
+        assert np.array_equal(q32[k], r32[k]), k
     for i in range(len(t)):
         F = float(CF.exact_integral(t, i))
         se = float(CF.exact_se(t, i))
