@@ -24,6 +24,53 @@ namespace zmc {
 
 constexpr double kPackTwoPi = 6.283185307179586476925286766559;
 constexpr double kPackLog2e = 1.4426950408889634073599246810019;
+constexpr double kPackPi = 3.141592653589793238462643383280;
+constexpr double kPackPi2 = 1.570796326794896619231321691640;
+constexpr double kPackPi4 = 0.785398163397448309615660845820;
+
+// Records are packed by the host (tables) and by the device (parameter grids),
+// and a function must get the same record bits either way.  Division, square
+// root, floor and conversions are correctly rounded on both, and no product is
+// fused into a sum (-ffp-contract=off), but libm's hypot and atan2 are not the
+// same functions on the host and the device, so the packing computes them from
+// correctly rounded operations only: the same bits everywhere, within a few
+// units in the last place of the exact values.
+
+// sqrt(a^2 + b^2), scaled by the larger magnitude so no square overflows.
+__host__ __device__ inline double pack_hypot(double a, double b)
+{
+    a = fabs(a);
+    b = fabs(b);
+    const double m = a > b ? a : b, n = a > b ? b : a;
+    if (!(m > 0.0) || !(m <= 1.7976931348623157e308)) return m + n;  // zero, infinity or NaN
+    const double r = n / m;
+    return m * sqrt(1.0 + r * r);
+}
+
+// atan(z) for |z| <= tan(pi/8): one halving, atan z = 2 atan(z / (1 + sqrt(1 + z^2))),
+// brings the argument below 0.2, then the series sum_k (-1)^k h^(2k+1) / (2k + 1)
+// to k = 13 (truncation below 1e-20 relative).
+__host__ __device__ inline double pack_atan_small(double z)
+{
+    const double h = z / (1.0 + sqrt(1.0 + z * z));
+    const double h2 = h * h;
+    double s = 0.0;
+    for (int k = 13; k >= 0; --k) s = s * h2 + ((k & 1) ? -1.0 : 1.0) / (double)(2 * k + 1);
+    return 2.0 * (h * s);
+}
+
+// The angle of (x, y) in (-pi, pi] (0 at the origin).
+__host__ __device__ inline double pack_atan2(double y, double x)
+{
+    const double ax = fabs(x), ay = fabs(y);
+    if (!(ax > 0.0) && !(ay > 0.0)) return 0.0;
+    const bool swap = ay > ax;
+    const double t = swap ? ax / ay : ay / ax;  // in [0, 1]
+    double r = t > 0.41421356237309503 ? kPackPi4 + pack_atan_small((t - 1.0) / (t + 1.0)) : pack_atan_small(t);
+    if (swap) r = kPackPi2 - r;
+    if (x < 0.0) r = kPackPi - r;
+    return y < 0.0 ? -r : r;
+}
 
 __host__ __device__ inline float pack_frac_to_float(double x)
 {
@@ -41,7 +88,7 @@ __host__ __device__ inline double fp32_scale(const mc_function& f)
 {
     if (f.family >= kUserFamily0) return 1.0;
     switch (f.family) {
-    case MC_FAMILY_HARMONIC: return hypot(f.params[0], f.params[1]);
+    case MC_FAMILY_HARMONIC: return pack_hypot(f.params[0], f.params[1]);
     case MC_FAMILY_ABS_LINEAR:
     case MC_FAMILY_GAUSSIAN: return f.params[0];
     default: return 1.0;
@@ -100,7 +147,7 @@ __host__ __device__ inline void pack_function(const mc_function& f, int precisio
     case MC_FAMILY_HARMONIC: {
         const double a = f.params[0], b = f.params[1];
         const double R = fp32_scale(f);
-        const double phi = (R > 0.0) ? atan2(b, a) : 0.0;
+        const double phi = (R > 0.0) ? pack_atan2(b, a) : 0.0;
         double off = -phi / kPackTwoPi;
         for (uint32_t j = 0; j < D; ++j) {
             const double k = f.params[MC_PARAM_V0 + j];

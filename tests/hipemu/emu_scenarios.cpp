@@ -7,6 +7,7 @@
 // emulation defines for that function (hipemu::expected_batched / plain).
 #include <unistd.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
@@ -17,6 +18,9 @@
 
 #include "hipemu.hpp"
 #include "zmc.h"
+#include <hip/hip_runtime.h>  // (the emulation's: host/device keywords for the packing header)
+
+#include "zmc_pack.hpp"
 
 namespace {
 
@@ -833,6 +837,37 @@ bool snapshot_restore()
     return true;
 }
 
+// The packing's own hypot and atan2 (built from correctly rounded operations so
+// that host and device pack the same bits) against libm: within a few units in
+// the last place, over magnitudes 10^-6..10^6, zeros, equal and opposite values.
+bool pack_math()
+{
+    uint64_t s = 0x9E3779B97F4A7C15ull;
+    auto next = [&s]() {
+        s ^= s << 13;
+        s ^= s >> 7;
+        s ^= s << 17;
+        return (double)(s >> 11) * 0x1p-53 * 2.0 - 1.0;
+    };
+    double worst_h = 0.0, worst_a = 0.0;
+    for (int i = 0; i < 400000; ++i) {
+        double a = next() * std::pow(10.0, 6.0 * next()), b = next() * std::pow(10.0, 6.0 * next());
+        if (i % 7 == 0) b = 0.0;
+        if (i % 11 == 0) a = 0.0;
+        if (i % 13 == 0) b = a;
+        if (i % 17 == 0) b = -a;
+        const double h = std::hypot(a, b);
+        worst_h = std::max(worst_h, std::fabs(zmc::pack_hypot(a, b) - h) / (h > 0.0 ? h : 1.0));
+        double e = std::fabs(zmc::pack_atan2(b, a) - ((a == 0.0 && b == 0.0) ? 0.0 : std::atan2(b, a)));
+        if (std::fabs(e - 2.0 * M_PI) < 1e-9) e = std::fabs(e - 2.0 * M_PI);  // the angle of -0 may land on -pi or pi
+        worst_a = std::max(worst_a, e);
+    }
+    CHECK(worst_h <= 4.5e-16, "pack_hypot: relative error %.3g", worst_h);
+    CHECK(worst_a <= 8.9e-16, "pack_atan2: error %.3g rad", worst_a);
+    std::printf("pack_hypot within %.2g relative, pack_atan2 within %.2g rad of libm\n", worst_h, worst_a);
+    return true;
+}
+
 // MC_LOG=3: the context, its launches and admissions, the resident kernel's
 // launch and exit, and a failure each leave a "[zmc] " line on stderr; MC_LOG
 // unset leaves none.
@@ -898,6 +933,7 @@ int main(int argc, char** argv)
         {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
         {"resident_abort", resident_abort}, {"log_levels", log_levels}, {"snapshot", snapshot_restore},
+        {"pack_math", pack_math},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {

@@ -1,6 +1,7 @@
 """Parameter-grid requests (functional mode) on an MI355X: the device builds the
-records from the grid spec; the results equal those of the expanded table
-(FP64: bitwise) and match the oracle on that table."""
+records from the grid spec; the results equal those of the expanded table bit
+for bit (the device packs every coefficient with the host's operations, in both
+precisions) and match the oracle on that table."""
 
 import numpy as np
 import pytest
@@ -22,16 +23,12 @@ def test_grid_equals_table_and_oracle():
             g = c.integrate_grid(base, axes, prec)
             t = c.integrate(table, prec)
             assert np.array_equal(g["n"], t["n"])
+            # the records the device packs from the spec are the host's bits
+            for k in ("mean", "std_error", "sum_f", "sum_f2", "status", "precision"):
+                assert np.array_equal(g[k], t[k]), (prec, k)
             if prec == Z.PREC_FP64:
-                # the FP64 record fields are exact functions of the inputs: same bits
-                for k in ("mean", "std_error", "sum_f", "sum_f2"):
-                    assert np.array_equal(g[k], t[k]), k
                 G.check_fp64(g, orc, "grid fp64")
             else:
-                # FP32 coefficients come from the device's libm instead of the
-                # host's (hypot, atan2 may differ in the last bit before rounding
-                # to float): far inside the FP32 bar
-                assert np.all(np.abs(g["mean"] - t["mean"]) <= 1e-3 * orc["stderr"])
                 G.check_fp32(g, orc, "grid fp32", table=table)
 
 
@@ -56,9 +53,9 @@ def _base(family):
 
 @pytest.mark.parametrize("family", ["abs_linear", "gaussian", "poly", "harmonic_three_axes"])
 def test_grids_of_every_family(family):
-    """Grids with axes on scalar, per-dimension and degree parameters: FP64 results
-    equal the expanded table's bit for bit and match the oracle; FP32 results meet
-    the FP32 bar."""
+    """Grids with axes on scalar, per-dimension and degree parameters: results equal
+    the expanded table's bit for bit in both precisions and match the oracle (FP32
+    at the FP32 bar); through a resident context too."""
     import paper_2104_10073_amd as Z
     base, axes = _base(family)
     table = W.expand_grid(base, axes)
@@ -67,8 +64,13 @@ def test_grids_of_every_family(family):
         g64 = c.integrate_grid(base, axes, Z.PREC_FP64)
         t64 = c.integrate(table, Z.PREC_FP64)
         g32 = c.integrate_grid(base, axes, Z.PREC_FP32)
+        t32 = c.integrate(table, Z.PREC_FP32)
+    with Z.Context(device=0, flags=Z.MC_RESIDENT) as c:
+        q32 = c.integrate_grid(base, axes, Z.PREC_FP32)
     for k in ("mean", "std_error", "sum_f", "sum_f2", "n", "precision"):
         assert np.array_equal(g64[k], t64[k]), k
+        assert np.array_equal(g32[k], t32[k]), k
+        assert np.array_equal(q32[k], g32[k]), k
     G.check_fp64(g64, orc, f"{family} grid fp64")
     f32 = g32["precision"] == 0
     assert f32.any()

@@ -24,7 +24,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "hipemu")
 SCENARIOS = ["basic", "many_launches", "admission", "grid", "abort", "errors", "plain", "two_contexts",
              "fault_sweep", "autotune_cache", "resident_basic", "resident_relaunch", "resident_flush",
-             "resident_abort", "log_levels", "snapshot"]
+             "resident_abort", "log_levels", "snapshot", "pack_math"]
 
 
 @pytest.fixture(scope="module")
