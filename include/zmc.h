@@ -281,24 +281,30 @@ mc_status mc_abort(mc_ctx* ctx);
  * library version -- completes with results bitwise equal to a run without the
  * interruption.
  *
- * mc_snapshot waits for the launches in flight, then writes request
- * `request_id`'s state into buf[0 .. *bytes): its functions (a grid as its
- * expanded table), their tiling and progress, the results already in, and the
- * partials of the tiles run (16 bytes per tile; native byte order).  With buf
- * NULL it only stores the size into *bytes.  The request stays in the context
- * unchanged (continue it, abort it, or take its results).  Errors:
+ * mc_snapshot waits for the launches in flight -- in a resident context it
+ * stops the running launch, which starts again once the snapshot is written
+ * (after a size query it stays stopped until the next call that runs work, so
+ * the size holds for an mc_snapshot that follows at once) --, then
+ * writes request `request_id`'s state into buf[0 .. *bytes): its functions (a
+ * grid as its expanded table), their tiling and progress, the results already
+ * in, and the partials of the tiles run (16 bytes per tile; native byte
+ * order).  With buf NULL it only stores the size into *bytes.  The request
+ * stays in the context unchanged (continue it, abort it, or take its
+ * results).  Snapshots do not depend on the engine: one taken in a launch
+ * context restores into a resident one and the other way round.  Errors:
  * MC_ERR_INVALID_ARG (cap smaller than needed -- *bytes holds the size --, a
- * request that uses a run-time family, an aborted or failed request, a
- * resident context), MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP.
+ * request that uses a run-time family, an aborted or failed request),
+ * MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP.
  *
  * mc_restore checks a snapshot (format, version, every function as mc_submit
  * does, tiling and progress against the functions) and queues it as a new
  * request whose id it stores into *out_request_id; its saved partials go to
- * the device when it is admitted.  Functions whose results were in complete
- * at once; the restoring context's MC_NO_PROMOTE setting applies to FP32
- * results not yet in.  Errors: MC_ERR_INVALID_ARG (not a snapshot of this
- * library version, inconsistent or truncated, a resident context), the
- * validation codes of mc_submit, MC_ERR_ADMISSION. */
+ * the device when it is admitted (a resident context stops its running launch
+ * for that copy).  Functions whose results were in complete at once; the
+ * restoring context's MC_NO_PROMOTE setting applies to FP32 results not yet
+ * in.  Errors: MC_ERR_INVALID_ARG (not a snapshot of this library version,
+ * inconsistent or truncated), the validation codes of mc_submit,
+ * MC_ERR_ADMISSION. */
 mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, size_t* bytes);
 mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_request_id);
 

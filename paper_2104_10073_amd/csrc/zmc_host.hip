@@ -372,6 +372,8 @@ struct Request {
     bool restored = false;            // built by mc_restore from a snapshot
     uint32_t fair_credit = 0;         // resident FAIR: tiles the request may still push this pass
     std::vector<Partial> staged;      // restored: its whole partial range, saved tiles filled in (uploaded at admission)
+    std::vector<uint32_t> staged_counts;  // restored into a resident context: each function's tiles already run
+    bool partials_pending = false;    // resident: admitted, saved partials not yet on the device
 };
 
 // A function's consecutive tiles in one launch and the cost of one of them.
@@ -691,6 +693,7 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
     std::vector<Partial>().swap(r->staged);
+    std::vector<uint32_t>().swap(r->staged_counts);
     if (r->uploaded) {
         quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
@@ -994,6 +997,7 @@ void admit(mc_ctx* ctx)
             }
             r->admitted = true;
             r->grid_packed = true;
+            r->partials_pending = !r->staged.empty();  // (copied by res_upload_restored)
             ctx->pending.pop_front();
             ctx->active.push_back(r);
             log_msg(3, "request %llu admitted: %llu functions, %llu tiles", (unsigned long long)r->id,
@@ -1629,11 +1633,13 @@ uint32_t res_chunk_tiles(const ResidentState& R, const Request* r, const FnState
 bool res_push_chunk(mc_ctx* ctx, Request* r)
 {
     ResidentState& R = ctx->res;
-    if (!has_work(r) || !res_room(R)) return false;
+    if (!has_work(r) || !res_room(R) || r->partials_pending) return false;
     const bool in_order = r->order_pos < r->order.size();
     const uint32_t fi = in_order ? r->order[r->order_pos] : r->redo[r->redo_pos];
     FnState& fs = r->st[fi];
-    const bool first = fs.next_tile == 0;
+    // a run starts at tile 0, or, for a restored function, at the first tile
+    // its snapshot had not run
+    const bool first = fs.next_tile == 0 || fs.token == 0;
     if (first) {
         uint32_t rec = 0;
         if (R.flush || !res_alloc_rec(R, &rec)) {
@@ -1810,6 +1816,10 @@ void res_fail(mc_ctx* ctx)
     R.tiles_waiting = 0;
     for (Request* r : ctx->active) R.tiles_waiting += r->tiles_total - r->tiles_launched;
     __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
+    // the lost runs' tile counters would mislead the next runs in their slots
+    // (after a stream error these calls fail too, and so does every later launch)
+    quiet(hipMemsetAsync(R.d_tiles_done, 0, (size_t)ctx->max_functions * sizeof(uint32_t), R.stream));
+    quiet(hipStreamSynchronize(R.stream));
 }
 
 // After mc_abort on a resident context: the launch has been asked to stop;
@@ -1859,6 +1869,32 @@ void res_finish_abort(mc_ctx* ctx)
     ctx->abort_requested = false;
 }
 
+// Restored requests: their saved partials, and their functions' tile counts
+// (a run's finalizer is the workgroup that counts its last tile), go to the
+// device on the resident stream while no launch runs -- a running one is asked
+// to stop first --, so the next launch, enqueued after the copies, sees them.
+// Until then none of the requests' chunks is pushed.
+void res_upload_restored(mc_ctx* ctx)
+{
+    ResidentState& R = ctx->res;
+    bool any = false;
+    for (const Request* r : ctx->active) any = any || r->partials_pending;
+    if (!any) return;
+    if (!res_exited(ctx)) {
+        res_request_stop(ctx);
+        return;
+    }
+    for (Request* r : ctx->active) {
+        if (!r->partials_pending) continue;
+        HIP_TRY(hipMemcpyAsync(ctx->d_partials + r->part_base, r->staged.data(), r->part_count * sizeof(Partial),
+                               hipMemcpyHostToDevice, R.stream));
+        HIP_TRY(hipMemcpyAsync(R.d_tiles_done + r->slot_base, r->staged_counts.data(), r->count() * sizeof(uint32_t),
+                               hipMemcpyHostToDevice, R.stream));
+        r->partials_pending = false;
+        log_msg(3, "request %llu: saved partials copied to the device", (unsigned long long)r->id);
+    }
+}
+
 // One step of a resident context: collect results, admit, feed the ring and
 // (re)launch the kernel if entries wait and it has gone.
 void res_step(mc_ctx* ctx)
@@ -1868,6 +1904,7 @@ void res_step(mc_ctx* ctx)
     res_reap(ctx);
     if (ctx->abort_requested) res_finish_abort(ctx);
     admit(ctx);
+    res_upload_restored(ctx);
     res_feed(ctx);
     if (!R.live) res_launch(ctx);
 }
@@ -2613,7 +2650,6 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
     if (it == ctx->requests.end())
         return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
     Request* r = it->second.get();
-    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "a resident context keeps no snapshots");
     const uint64_t n = r->count();
     if (r->at(0).family >= kUserFamily0)
         return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
@@ -2624,28 +2660,80 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
                 return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
                             (unsigned long long)request_id);
     std::vector<Partial> range;
+    // each function's tiles run (resident: its open run's first tile still in
+    // the ring); whether a resident run of it is open; whether its result is in
+    std::vector<uint32_t> ran(n), unread(n, UINT32_MAX);
+    std::vector<char> open(n, 0), done(n);
+    // a resident launch stopped for a snapshot written starts again on the way
+    // out if entries wait (if that fails, the next step tries again); after a
+    // size query it stays stopped until the next call that runs work, so the
+    // size holds for the snapshot that follows
+    struct Relaunch {
+        mc_ctx* ctx = nullptr;
+        ~Relaunch()
+        {
+            if (!ctx || ctx->abort_requested) return;
+            try {
+                res_launch(ctx);
+            } catch (const HipError&) {
+            }
+        }
+    } relaunch;
     try {
         if (!ctx->validate_only) {
             HIP_TRY(hipSetDevice(ctx->device));
-            reap(ctx, 2);  // every launch in flight: from here on no kernel touches its partials
+            if (ctx->res.on) {
+                // the resident launch stops and goes (every entry below the count
+                // it last saw is run; from then on no kernel touches a partial),
+                // results that came in are collected, and a run still open has
+                // run its tiles up to its first chunk left unread in the ring
+                // (a launch reads a prefix of the ring; a run's chunks are in it
+                // in tile order)
+                ResidentState& R = ctx->res;
+                res_request_stop(ctx);
+                res_wait_exit(ctx);
+                res_reap(ctx);  // (may send results to FP64: progress is read after it)
+                for (const ResRun& run : R.runs)
+                    if (run.req == r) open[run.index] = 1;
+                for (uint64_t e = R.acked; e < R.pushed && r->admitted; ++e) {
+                    const Chunk& c = R.ring[e & (kRingEntries - 1)];
+                    if (c.fn < r->slot_base || c.fn - r->slot_base >= n) continue;
+                    const uint32_t i = c.fn - r->slot_base;
+                    if (c.token == r->st[i].token) unread[i] = std::min(unread[i], c.first);
+                }
+            } else {
+                reap(ctx, 2);  // every launch in flight: from here on no kernel touches its partials
+            }
         }
+        for (uint64_t i = 0; i < n; ++i) ran[i] = std::min(r->st[i].next_tile, unread[i]);
         if (r->lost || r->aborted)
             return fail(ctx, MC_ERR_INVALID_ARG, "request %llu was aborted or failed", (unsigned long long)request_id);
         uint64_t n_partials = 0;
-        for (uint64_t i = 0; i < n; ++i)
-            if (r->st[i].next_tile < r->st[i].n_tiles) n_partials += r->st[i].next_tile;
+        for (uint64_t i = 0; i < n; ++i) {
+            const FnState& fs = r->st[i];
+            done[i] = fs.next_tile == fs.n_tiles && !open[i];
+            if (done[i]) continue;
+            ran[i] = std::min(ran[i], fs.n_tiles - 1);  // (an open run has a tile left: its result is not in)
+            n_partials += ran[i];
+        }
         const uint64_t total = snapshot_bytes(n, n_partials, r->grid);
         *bytes = (size_t)total;
         if (!buf) return MC_OK;
         if (cap < total)
             return fail(ctx, MC_ERR_INVALID_ARG, "snapshot needs %llu bytes, the buffer holds %zu",
                         (unsigned long long)total, cap);
+        if (ctx->res.on && !ctx->validate_only) relaunch.ctx = ctx;
         if (n_partials > 0) {
-            // (only an admitted request has run tiles)
-            range.resize(r->part_count);
-            HIP_TRY(hipMemcpyAsync(range.data(), ctx->d_partials + r->part_base, r->part_count * sizeof(Partial),
-                                   hipMemcpyDeviceToHost, ctx->upload_stream));
-            HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
+            if (!r->admitted || r->partials_pending) {
+                range = r->staged;  // a restored request whose saved partials are not on the device yet
+            } else {
+                // (on the stream that copied a restored request's saved partials up)
+                hipStream_t st = ctx->res.on ? ctx->res.stream : ctx->upload_stream;
+                range.resize(r->part_count);
+                HIP_TRY(hipMemcpyAsync(range.data(), ctx->d_partials + r->part_base, r->part_count * sizeof(Partial),
+                                       hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+            }
         }
         uint8_t* p = (uint8_t*)buf;
         SnapHeader h{};
@@ -2672,20 +2760,20 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
         }
         for (uint64_t i = 0; i < n; ++i, p += sizeof(SnapFn)) {
             const FnState& fs = r->st[i];
-            const SnapFn sf{fs.seg_log2, fs.n_tiles, fs.next_tile, fs.f64 ? 1u : 0u};
+            const SnapFn sf{fs.seg_log2, fs.n_tiles, done[i] ? fs.n_tiles : ran[i], fs.f64 ? 1u : 0u};
             std::memcpy(p, &sf, sizeof sf);
         }
         for (uint64_t i = 0; i < n; ++i, p += sizeof(mc_result)) {
             mc_result res{};
-            if (r->st[i].next_tile == r->st[i].n_tiles) res = r->results[i];
+            if (done[i]) res = r->results[i];
             std::memcpy(p, &res, sizeof res);
         }
         uint64_t off = 0;  // function i's first partial within the request's range
         for (uint64_t i = 0; i < n; ++i) {
             const FnState& fs = r->st[i];
-            if (fs.next_tile < fs.n_tiles && fs.next_tile > 0) {
-                std::memcpy(p, range.data() + off, (size_t)fs.next_tile * sizeof(Partial));
-                p += (size_t)fs.next_tile * sizeof(Partial);
+            if (!done[i] && ran[i] > 0) {
+                std::memcpy(p, range.data() + off, (size_t)ran[i] * sizeof(Partial));
+                p += (size_t)ran[i] * sizeof(Partial);
             }
             off += fs.n_tiles;
         }
@@ -2699,7 +2787,6 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
 mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_request_id)
 {
     if (!ctx || !buf || !out_request_id) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
-    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "restore into a launch context, not a resident one");
     SnapHeader h;
     if (bytes < sizeof h) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot of %zu bytes is truncated", bytes);
     std::memcpy(&h, buf, sizeof h);
@@ -2798,6 +2885,9 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
         return fail(ctx, MC_ERR_ADMISSION, "request needs %llu tile partials; the context holds %llu",
                     (unsigned long long)parts, (unsigned long long)ctx->max_partials);
     if (used > 0) {
+        r->staged_counts.assign(n, 0u);
+        for (uint64_t i = 0; i < n; ++i)
+            if (r->st[i].next_tile < r->st[i].n_tiles) r->staged_counts[i] = r->st[i].next_tile;
         r->staged.assign(parts, Partial{0.0, 0.0});
         uint64_t off = 0, k = 0;
         for (uint64_t i = 0; i < n; ++i) {

@@ -720,12 +720,46 @@ bool resident_abort()
 }
 
 // Checkpoint and resume: requests snapshotted part way through (functions
-// spanning launches, promotions pending, a grid, one still queued, one
-// finished) and restored into another context complete with exactly the
-// expected results; sizes, truncated and altered snapshots, resident contexts.
+// spanning launches or a resident launch's chunks, promotions pending, a grid,
+// one still queued, one finished), in launch and resident contexts, and
+// restored into a launch and a resident context, complete with exactly the
+// expected results; a request restored a moment ago snapshots to the bytes it
+// came from (queued, admitted with its partials not yet copied, or copied);
+// sizes, truncated and altered snapshots.
+std::vector<uint8_t> take_snapshot(mc_ctx* c, uint64_t id)
+{
+    size_t need = 0, got = 0;
+    if (mc_snapshot(c, id, nullptr, 0, &need) != MC_OK || need == 0) return {};
+    std::vector<uint8_t> b(need);
+    if (mc_snapshot(c, id, b.data(), b.size(), &got) != MC_OK || got != need) return {};
+    return b;
+}
+
+// Two snapshots of one request state: equal but for the request id in the header.
+bool same_snapshot(const std::vector<uint8_t>& x, const std::vector<uint8_t>& y)
+{
+    constexpr size_t kIdAt = 56, kHeader = 64;
+    return x.size() == y.size() && x.size() > kHeader && std::memcmp(x.data(), y.data(), kIdAt) == 0 &&
+           std::memcmp(x.data() + kHeader, y.data() + kHeader, x.size() - kHeader) == 0;
+}
+
+// Functions of a snapshot that had run part of their tiles.
+uint64_t partly_run(const std::vector<uint8_t>& b, size_t n, bool grid)
+{
+    const size_t at = 64 + (grid ? sizeof(zmc::GridSpec) : 0) + n * sizeof(mc_function);
+    uint64_t k = 0;
+    for (size_t i = 0; i < n; ++i) {
+        uint32_t w[4];
+        std::memcpy(w, b.data() + at + 16 * i, sizeof w);
+        k += w[2] > 0 && w[2] < w[1];
+    }
+    return k;
+}
+
 bool snapshot_restore()
 {
-    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u}) {
+    uint64_t partial_fns = 0;
+    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u, (uint32_t)MC_RESIDENT}) {
         mc_ctx* a = create(flags, 5, MC_SCHED_FAIR, 64, 1 << 14);
         CHECK(a, "create");
         // a request that has finished (results not yet taken) when it is snapshotted
@@ -733,7 +767,7 @@ bool snapshot_restore()
         uint64_t sid = 0;
         CHECK(mc_submit(a, small.data(), small.size(), MC_PREC_FP32_EVAL, &sid) == MC_OK, "submit small");
         bool small_done = false;
-        for (int i = 0; i < 2000 && !small_done; ++i) {
+        for (int i = 0; i < 20000 && !small_done; ++i) {
             size_t n = 0;
             uint64_t got[8];
             CHECK(mc_run(a, nullptr) != MC_ERR_HIP && mc_poll(a, got, 8, &n) == MC_OK, "run");
@@ -741,6 +775,7 @@ bool snapshot_restore()
         }
         CHECK(small_done, "small request");
         std::vector<std::vector<mc_function>> reqs = {mixed_table(20, 140, 4), mixed_table(6, 141), mixed_table(40, 142)};
+        std::vector<bool> is_grid = {false, false, false};
         std::vector<uint64_t> ids;
         for (size_t k = 0; k < reqs.size(); ++k) {
             uint64_t id = 0;
@@ -762,6 +797,7 @@ bool snapshot_restore()
         }
         ids.push_back(gid);
         reqs.push_back(gt);
+        is_grid.push_back(true);
         // a grid whose rows the FP32 check sends to FP64 (constant in the emulated FP32 kernel)
         const mc_function pbase = make_fn(MC_FAMILY_GAUSSIAN, 2, 30001, (1ull << 63) | (145ull << 32));
         mc_grid_axis paxis = {0, 4, 0.5, 0.25};
@@ -776,64 +812,111 @@ bool snapshot_restore()
         }
         ids.push_back(pid);
         reqs.push_back(pt);
+        is_grid.push_back(true);
         for (int i = 0; i < 40; ++i) CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
         ids.push_back(sid);
         reqs.push_back(small);
+        is_grid.push_back(false);
         std::vector<std::vector<uint8_t>> blobs;
         for (size_t k = 0; k < ids.size(); ++k) {
             size_t need = 0;
             CHECK(mc_snapshot(a, ids[k], nullptr, 0, &need) == MC_OK && need > 0, "size %zu: %s", k, mc_last_error(a));
             std::vector<uint8_t> b(need);
             size_t got = 0;
-            CHECK(mc_snapshot(a, ids[k], b.data(), need - 1, &got) == MC_ERR_INVALID_ARG && got == need, "small buffer");
+            const mc_status small_st = mc_snapshot(a, ids[k], b.data(), need - 1, &got);
+            CHECK(small_st == MC_ERR_INVALID_ARG && got == need, "small buffer %zu (flags %u): status %d, %zu of %zu: %s", k,
+                  flags, (int)small_st, got, need, mc_last_error(a));
             CHECK(mc_snapshot(a, ids[k], b.data(), b.size(), &got) == MC_OK && got == need, "snapshot %zu: %s", k,
                   mc_last_error(a));
+            partial_fns += partly_run(b, reqs[k].size(), is_grid[k]);
             blobs.push_back(b);
+            // the request goes on where it was (a resident launch between snapshots)
+            for (int i = 0; i < 3; ++i) CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
         }
         uint64_t pending_r = 0, pending_t = 0;
-        CHECK(mc_pending(a, &pending_r, &pending_t) == MC_OK && pending_t > 0, "work left at the snapshot");
+        CHECK(mc_pending(a, &pending_r, &pending_t) == MC_OK, "pending");
+        CHECK(flags == MC_RESIDENT || pending_t > 0, "work left at the snapshot");
+        // the source context finishes its requests as if nothing had happened
+        for (size_t k = 0; k + 1 < ids.size(); ++k) {
+            std::vector<mc_result> r(reqs[k].size());
+            CHECK(mc_results(a, ids[k], r.data(), r.size(), 1) == MC_OK, "source results %zu: %s", k, mc_last_error(a));
+            if (!check_results(reqs[k], r, k == 1, "after the snapshot")) return false;
+        }
         mc_destroy(a);
 
-        mc_ctx* b = create(flags, 7, MC_SCHED_SRPT, 128, 1 << 15);
-        CHECK(b, "create");
-        uint8_t seg[96];
-        for (int i = 0; i < 96; ++i) seg[i] = 3;  // another tiling for new requests: restored ones keep theirs
-        CHECK(mc_set_tuning(b, 0, seg) == MC_OK, "tuning");
-        std::vector<uint64_t> rids;
-        for (size_t k = 0; k < blobs.size(); ++k) {
-            uint64_t id = 0;
-            CHECK(mc_restore(b, blobs[k].data(), blobs[k].size(), &id) == MC_OK, "restore %zu: %s", k, mc_last_error(b));
-            rids.push_back(id);
+        for (uint32_t target : {flags == MC_RESIDENT ? (uint32_t)MC_NO_GRAPH : flags, (uint32_t)MC_RESIDENT}) {
+            mc_ctx* b = create(target, 7, MC_SCHED_SRPT, 128, 1 << 15);
+            CHECK(b, "create");
+            uint8_t seg[96];
+            for (int i = 0; i < 96; ++i) seg[i] = 3;  // another tiling for new requests: restored ones keep theirs
+            CHECK(mc_set_tuning(b, 0, seg) == MC_OK, "tuning");
+            std::vector<uint64_t> rids;
+            for (size_t k = 0; k < blobs.size(); ++k) {
+                uint64_t id = 0;
+                CHECK(mc_restore(b, blobs[k].data(), blobs[k].size(), &id) == MC_OK, "restore %zu: %s", k,
+                      mc_last_error(b));
+                // snapshotted at once: admitted, its saved partials copied or (resident) not yet
+                CHECK(same_snapshot(take_snapshot(b, id), blobs[k]), "restore %zu into flags %u: snapshot differs", k,
+                      target);
+                rids.push_back(id);
+            }
+            for (size_t k = 0; k < rids.size(); ++k) {
+                std::vector<mc_result> r(reqs[k].size());
+                CHECK(mc_results(b, rids[k], r.data(), r.size(), 1) == MC_OK, "results %zu: %s", k, mc_last_error(b));
+                if (!check_results(reqs[k], r, k == 1, "restored")) return false;
+            }
+            mc_destroy(b);
         }
-        for (size_t k = 0; k < rids.size(); ++k) {
-            std::vector<mc_result> r(reqs[k].size());
-            CHECK(mc_results(b, rids[k], r.data(), r.size(), 1) == MC_OK, "results %zu: %s", k, mc_last_error(b));
-            if (!check_results(reqs[k], r, k == 1, "restored")) return false;
-        }
-        // damaged snapshots
-        std::vector<uint8_t> bad = blobs[0];
-        uint64_t id = 0;
-        bad[0] = 'X';
-        CHECK(mc_restore(b, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "magic");
-        CHECK(mc_restore(b, blobs[0].data(), blobs[0].size() - 16, &id) == MC_ERR_INVALID_ARG, "truncated");
-        bad = blobs[0];
-        const size_t fn_off = 64 + reqs[0].size() * sizeof(mc_function);
-        bad[fn_off + 4] ^= 1;  // function 0's tile count
-        CHECK(mc_restore(b, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "tile count: %s", mc_last_error(b));
-        mc_destroy(b);
     }
-    mc_ctx* r = create(MC_RESIDENT);
-    CHECK(r, "create resident");
-    const std::vector<mc_function> t = mixed_table(4, 144);
-    uint64_t id = 0, nid = 0;
-    size_t need = 0;
-    CHECK(mc_submit(r, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
-    CHECK(mc_snapshot(r, id, nullptr, 0, &need) == MC_ERR_INVALID_ARG, "resident snapshot");
-    std::vector<uint8_t> dummy(64, 0);
-    CHECK(mc_restore(r, dummy.data(), dummy.size(), &nid) == MC_ERR_INVALID_ARG, "resident restore");
-    std::vector<mc_result> res(t.size());
-    CHECK(mc_results(r, id, res.data(), res.size(), 1) == MC_OK, "results");
-    mc_destroy(r);
+    std::printf("snapshot: %llu functions were saved part way through\n", (unsigned long long)partial_fns);
+    CHECK(partial_fns > 0, "no function was saved part way through");
+
+    // a restored request still queued (no slots free) snapshots from what it holds
+    {
+        mc_ctx* a = create(MC_NO_GRAPH, 5, MC_SCHED_FIFO, 64, 1 << 14);
+        CHECK(a, "create");
+        const std::vector<mc_function> t = mixed_table(40, 146);
+        uint64_t id = 0;
+        CHECK(mc_submit(a, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+        for (int i = 0; i < 3; ++i) CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
+        const std::vector<uint8_t> blob = take_snapshot(a, id);
+        CHECK(!blob.empty() && partly_run(blob, t.size(), false) > 0, "a snapshot part way through");
+        uint64_t q = 0, q2 = 0;
+        CHECK(mc_submit(a, t.data(), t.size(), MC_PREC_FP32_EVAL, &q2) == MC_OK, "submit");  // takes the free slots
+        CHECK(mc_restore(a, blob.data(), blob.size(), &q) == MC_OK, "restore: %s", mc_last_error(a));
+        uint64_t pr = 0, pt = 0;
+        CHECK(mc_pending(a, &pr, &pt) == MC_OK && pr == 3, "three requests in the context");
+        CHECK(same_snapshot(take_snapshot(a, q), blob), "queued restored request: snapshot differs");
+        for (uint64_t r_id : {id, q2, q}) {
+            std::vector<mc_result> r(t.size());
+            CHECK(mc_results(a, r_id, r.data(), r.size(), 1) == MC_OK, "results: %s", mc_last_error(a));
+            if (!check_results(t, r, false, "queued restore")) return false;
+        }
+        mc_destroy(a);
+    }
+
+    // damaged snapshots
+    {
+        const std::vector<mc_function> t = mixed_table(20, 147);
+        mc_ctx* a = create(MC_NO_GRAPH, 5, MC_SCHED_FIFO, 64, 1 << 14);
+        CHECK(a, "create");
+        uint64_t id = 0;
+        CHECK(mc_submit(a, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
+        for (int i = 0; i < 3; ++i) CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
+        const std::vector<uint8_t> blob = take_snapshot(a, id);
+        CHECK(!blob.empty(), "snapshot");
+        std::vector<mc_result> res(t.size());
+        CHECK(mc_results(a, id, res.data(), res.size(), 1) == MC_OK, "results");
+        std::vector<uint8_t> bad = blob;
+        bad[0] = 'X';
+        CHECK(mc_restore(a, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "magic");
+        CHECK(mc_restore(a, blob.data(), blob.size() - 16, &id) == MC_ERR_INVALID_ARG, "truncated");
+        bad = blob;
+        const size_t fn_off = 64 + t.size() * sizeof(mc_function);
+        bad[fn_off + 4] ^= 1;  // function 0's tile count
+        CHECK(mc_restore(a, bad.data(), bad.size(), &id) == MC_ERR_INVALID_ARG, "tile count: %s", mc_last_error(a));
+        mc_destroy(a);
+    }
     return true;
 }
 

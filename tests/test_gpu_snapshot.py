@@ -1,9 +1,10 @@
 """Checkpoint and resume on an MI355X (mc_snapshot / mc_restore).
 
 Requests are snapshotted part way through -- functions spanning launches of a
-few tiles, FP32 rows whose results were sent to FP64, a grid -- and restored
-into another context (with another tiling for new work) and into another
-process; every result must equal a run without the interruption bit for bit,
+few tiles or a resident launch's chunks, FP32 rows whose results were sent to
+FP64, a grid -- and restored into another context (with another tiling for new
+work, launch or resident) and into another process; every result must equal a
+run without the interruption bit for bit,
 because a tile's samples depend only on the function's seed and the tile's
 index and the partials saved are the ones the tree would have summed.
 """
@@ -99,6 +100,55 @@ def test_snapshot_restore_bitwise(tmp_path):
     assert proc.returncode == 0, proc.stderr[-3000:]
     for k, p in enumerate(paths):
         _same(np.load(p + ".npy"), ref[k], f"request {k} (other process)")
+
+
+def _partly_run(blob):
+    """Functions of a snapshot that had run some but not all of their tiles."""
+    n, n_partials = np.frombuffer(blob, dtype="<u8", count=2, offset=24)
+    grid = int(np.frombuffer(blob, dtype="<u4", count=1, offset=52)[0])
+    fn_bytes = W.FUNC_DTYPE.itemsize
+    per_fn = fn_bytes + 16 + 48
+    spec = len(blob) - 64 - int(n) * per_fn - int(n_partials) * 16 if grid else 0
+    sf = np.frombuffer(blob, dtype="<u4", count=4 * int(n), offset=64 + spec + int(n) * fn_bytes).reshape(-1, 4)
+    return int(np.count_nonzero((sf[:, 2] > 0) & (sf[:, 2] < sf[:, 1])))
+
+
+def test_resident_snapshot_restore_bitwise():
+    """A resident context's requests snapshotted while its launch runs (the
+    launch stops, the snapshot is taken, it starts again) restore into a launch
+    and a resident context; a launch context's snapshot restores into a
+    resident one; the source contexts finish with the uninterrupted results."""
+    import paper_2104_10073_amd as Z
+    jobs = _jobs(Z)
+    with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as c:
+        ref = []
+        for job in jobs:
+            rid, n = _submit(c, job)
+            ref.append(c.results(rid, n))
+    print("snapshot a resident context part way through", flush=True)
+    with Z.Context(device=0, flags=Z.MC_RESIDENT, max_tiles_per_run=64) as a:
+        ids = [_submit(a, job) for job in jobs]
+        for _ in range(3):
+            a.run()
+        res_blobs = [a.snapshot(rid) for rid, _ in ids]
+        for k, (rid, n) in enumerate(ids):
+            _same(a.results(rid, n), ref[k], f"resident source request {k}")
+    print("partly run functions:", [_partly_run(b) for b in res_blobs], flush=True)
+    assert sum(_partly_run(b) for b in res_blobs) > 0, "no function was saved part way through"
+    print("snapshot a launch context part way through", flush=True)
+    with Z.Context(device=0, max_tiles_per_run=64) as a:
+        ids = [_submit(a, job) for job in jobs]
+        for _ in range(6):
+            a.run()
+        launch_blobs = [a.snapshot(rid) for rid, _ in ids]
+    for label, blobs, flags in (("resident -> launch", res_blobs, Z.MC_NO_GRAPH),
+                                ("resident -> resident", res_blobs, Z.MC_RESIDENT),
+                                ("launch -> resident", launch_blobs, Z.MC_RESIDENT)):
+        print("restore", label, flush=True)
+        with Z.Context(device=0, flags=flags) as b:
+            rids = [b.restore(blob) for blob in blobs]
+            for k, (rid, (_, n)) in enumerate(zip(rids, ids)):
+                _same(b.results(rid, n), ref[k], f"{label}: request {k}")
 
 
 def test_snapshot_of_finished_and_queued_requests():
