@@ -348,7 +348,8 @@ mc_status mc_set_tuning(mc_ctx* ctx, uint32_t blocks_per_cu, const uint8_t* seg_
 mc_status mc_autotune(mc_ctx* ctx, int32_t precision, void* stream, double budget_seconds);
 
 /* Kernel timing of the most recent completed direct-launch mc_run (persistent
- * kernels and finalize, in milliseconds, from HIP events on the launch stream). */
+ * kernels, and finalize with publish, in milliseconds, from HIP events on the
+ * launch stream). */
 mc_status mc_last_run_timing(mc_ctx* ctx, double* main_ms, double* finalize_ms);
 
 /* Cumulative counters of a context since it was created (completed launches only). */
@@ -361,7 +362,7 @@ typedef struct mc_stats {
     uint64_t bad_records;        /* records that failed the kernels' bounds checks (always 0 unless corrupt) */
     double fp32_ms;              /* direct launches: sum of FP32 persistent-kernel time (HIP events on the launch stream) */
     double fp64_ms;              /* direct launches: sum of FP64 persistent-kernel time */
-    double finalize_ms;          /* direct launches: sum of finalize time */
+    double finalize_ms;          /* direct launches: sum of finalize and publish time */
     double graph_ms;             /* graph launches: sum of whole-graph time (every kernel of the launch) */
 } mc_stats;
 

@@ -372,7 +372,7 @@ class Context:
         return st.as_dict()
 
     def last_run_timing(self):
-        """mc_last_run_timing: (persistent kernels ms, finalize ms) of the last direct launch."""
+        """mc_last_run_timing: (persistent kernels ms, finalize and publish ms) of the last direct launch."""
         a, b = ctypes.c_double(), ctypes.c_double()
         st = self.L.mc_last_run_timing(self.h, ctypes.byref(a), ctypes.byref(b))
         if st != MC_OK:

@@ -406,7 +406,8 @@ struct RequestUndo {
 // complete, which can be well after the launch has published its results, so
 // they come from a pool of their own rather than from the launch slot.
 struct EvSet {
-    hipEvent_t start = nullptr, mid = nullptr, main = nullptr, end = nullptr, done = nullptr;
+    hipEvent_t start = nullptr, mid = nullptr, main = nullptr, done = nullptr;
+    bool main_is_mid = false;  // no FP64 or run-time family kernel ran: `mid` ends the main kernels
     bool pending = false;   // recorded, not yet read into the statistics
     bool graphed = false;
     bool released = false;  // the launch that recorded it has been reaped
@@ -768,21 +769,22 @@ void promote_to_fp64(mc_ctx* ctx, Request* r, uint32_t fi)
 void collect_timing(mc_ctx* ctx, EvSet& e, bool block)
 {
     if (!e.pending) return;
-    const hipError_t q = block ? hipEventSynchronize(e.end) : hipEventQuery(e.end);
+    const hipError_t q = block ? hipEventSynchronize(e.done) : hipEventQuery(e.done);
     quiet(q);
     if (q == hipErrorNotReady) return;
     e.pending = false;
     if (q != hipSuccess) return;  // timing lost; results are unaffected
     float a = 0.f, a32 = 0.f, b = 0.f, g = 0.f;
     if (e.graphed) {
-        const hipError_t e1 = hipEventElapsedTime(&g, e.start, e.end);
+        const hipError_t e1 = hipEventElapsedTime(&g, e.start, e.done);
         quiet(e1);
         if (e1 == hipSuccess) ctx->stats.graph_ms += g;
         return;
     }
-    const hipError_t e1 = hipEventElapsedTime(&a, e.start, e.main);
+    const hipEvent_t main = e.main_is_mid ? e.mid : e.main;
+    const hipError_t e1 = hipEventElapsedTime(&a, e.start, main);
     const hipError_t e2 = hipEventElapsedTime(&a32, e.start, e.mid);
-    const hipError_t e3 = hipEventElapsedTime(&b, e.main, e.end);
+    const hipError_t e3 = hipEventElapsedTime(&b, main, e.done);
     quiet(e1);
     quiet(e2);
     quiet(e3);
@@ -825,10 +827,9 @@ EvSet* acquire_evset(mc_ctx* ctx)
             HIP_TRY(hipEventCreate(&e->start));
             HIP_TRY(hipEventCreate(&e->mid));
             HIP_TRY(hipEventCreate(&e->main));
-            HIP_TRY(hipEventCreate(&e->end));
-            HIP_TRY(hipEventCreateWithFlags(&e->done, hipEventDisableTiming));
+            HIP_TRY(hipEventCreate(&e->done));
         } catch (const HipError&) {
-            for (hipEvent_t x : {e->start, e->mid, e->main, e->end, e->done})
+            for (hipEvent_t x : {e->start, e->mid, e->main, e->done})
                 if (x) quiet(hipEventDestroy(x));
             throw;
         }
@@ -1131,17 +1132,23 @@ void enqueue_kernels(mc_ctx* ctx, LaunchSlot& s, hipStream_t stream, bool events
         HIP_TRY(hipLaunchKernel(batched_kernel_ptr(true), dim3(ctx->num_cus * ctx->blocks_per_cu64),
                                 dim3(kBlockThreads), args, 0, stream));
     // run-time families: kernels with no tiles in this launch are skipped
+    bool more = events && s.tile_count[kKernelBuiltin64] != 0;
     for (uint32_t u = 0; u < ctx->n_user; ++u)
         for (int p = 0; p < 2; ++p) {
             if (s.tile_count[2 + 2 * u + p] == 0) continue;
             const mc_ctx::UserFamily& uf = ctx->user[u];
+            more = more || events;
             HIP_TRY(hipModuleLaunchKernel(uf.kernel[p], ctx->num_cus * uf.blocks_per_cu[p], 1, 1, kBlockThreads, 1, 1,
                                           0, stream, args, nullptr));
         }
-    if (events) HIP_TRY(hipEventRecord(e->main, stream));
+    // (each event between kernels widens the gap between them by a few
+    // microseconds: one is recorded only where a kernel ran after `mid`, and
+    // the launch's `done` event, recorded after the publish kernel, ends the
+    // finalize-and-publish interval)
+    if (more) HIP_TRY(hipEventRecord(e->main, stream));
+    if (events) e->main_is_mid = !more;
     *progress = 2;
     HIP_TRY(hipLaunchKernel(finalize_kernel_ptr(), dim3(ctx->num_cus * 2), dim3(kBlockThreads), args, 0, stream));
-    if (events) HIP_TRY(hipEventRecord(e->end, stream));
     HIP_TRY(hipLaunchKernel(publish_kernel_ptr(), dim3(1), dim3(1024), args, 0, stream));
 }
 
@@ -1453,12 +1460,11 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
             HIP_TRY(hipEventRecord(ev.start, stream));
             progress = 2;  // a graph launch hands every kernel over at once
             HIP_TRY(hipGraphLaunch(s.graph, stream));
-            HIP_TRY(hipEventRecord(ev.end, stream));
         } else {
             enqueue_kernels(ctx, s, stream, true, &progress);
         }
-        // (orders launches on other streams after this one; completion itself is
-        // read from the done word)
+        // (ends the launch's timing intervals and orders launches on other
+        // streams after this one; completion itself is read from the done word)
         HIP_TRY(hipEventRecord(ev.done, stream));
     } catch (const HipError&) {
         abandon_launch(ctx, s, stream, progress, req_undo, active_before);
@@ -1939,7 +1945,7 @@ void destroy_device(mc_ctx* ctx)
         if (ctx->user[u].module) quiet(hipModuleUnload(ctx->user[u].module));
     ctx->n_user = 0;
     for (auto& e : ctx->ev_pool)
-        for (hipEvent_t x : {e->start, e->mid, e->main, e->end, e->done})
+        for (hipEvent_t x : {e->start, e->mid, e->main, e->done})
             if (x) quiet(hipEventDestroy(x));
     ctx->ev_pool.clear();
     ctx->ev_free.clear();
