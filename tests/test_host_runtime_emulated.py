@@ -6,13 +6,15 @@ memory, in-order synchronous streams, every kernel replaced by a host routine
 with the kernel's effect on the buffers the host reads back) and driven
 through its C ABI by `tests/hipemu/emu_scenarios.cpp`: admission and queueing,
 launches of a few tiles under every scheduling policy, graphs, promotion,
-parameter grids, abort, error paths, the plain paths, two contexts, the tuning cache, the
-resident engine (its kernel emulated by worker threads that follow the kernel's
-protocol: relaunch after idling, record-arena recycling, abort, destroy while
-running), checkpoint and resume between launch and resident contexts (damaged
-snapshots, queued restored requests), logging, the packing's hypot and atan2, and a sweep that fails every checked HIP call of a workload in turn (MC_FAULT_HIP)
-and requires each request to come back either with exactly its results or
-with an error -- never MC_OK with wrong values, never a hang, no leak.
+parameter grids, abort, error paths, the plain paths, two contexts, the tuning
+cache, the resident engine (its kernel emulated by worker threads that follow
+the kernel's protocol: relaunch after idling, record-arena recycling, abort,
+destroy while running), checkpoint and resume between launch and resident
+contexts (damaged snapshots, queued restored requests), logging, the packing's
+hypot and atan2, and a sweep that fails every checked HIP call of a workload
+in turn (MC_FAULT_HIP) and requires each request to come back either with
+exactly its results or with an error -- never MC_OK with wrong values, never a
+hang, no leak.
 """
 
 import os
