@@ -95,9 +95,11 @@ extern "C" __global__ __launch_bounds__(kBlockThreads) void zmc_finalize(const L
 // thread's copies are complete), which the host polls.
 extern "C" __global__ __launch_bounds__(1024) void zmc_publish(const LaunchDesc* __restrict__ Ld)
 {
-    const uint64_t words = (uint64_t)Ld->n_fins * (sizeof(DevResult) / sizeof(uint64_t));
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(Ld->results);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(Ld->host_results);
+    // 16-byte words: both areas are 16-byte aligned (256-aligned blocks, 48-byte results)
+    static_assert(sizeof(DevResult) % sizeof(uint4) == 0, "result size");
+    const uint64_t words = (uint64_t)Ld->n_fins * (sizeof(DevResult) / sizeof(uint4));
+    const uint4* src = reinterpret_cast<const uint4*>(Ld->results);
+    uint4* dst = reinterpret_cast<uint4*>(Ld->host_results);
     for (uint64_t i = threadIdx.x; i < words; i += blockDim.x) dst[i] = src[i];
     if (threadIdx.x < (uint32_t)kNumCounters) Ld->host_counters[threadIdx.x] = Ld->counters[threadIdx.x];
     __threadfence_system();
