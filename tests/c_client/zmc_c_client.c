@@ -2,8 +2,9 @@
  * A plain C client of libzmc (include/zmc.h), for the tests: reads an array of
  * mc_function records from a file, integrates them through the C ABI alone --
  * the batched path in FP32 evaluation and in FP64 (submitted together, launched
- * with mc_run, collected with mc_poll and mc_results) and the plain FP64 path --
- * and writes the three mc_result arrays, one after another, to the output file.
+ * with mc_run, collected with mc_poll and mc_results), the plain FP64 path, and
+ * FP32 evaluation through a resident context (MC_RESIDENT) -- and writes the
+ * four mc_result arrays, one after another, to the output file.
  * It also checks that an invalid function is rejected with MC_ERR_BAD_DIM and a
  * message.  Usage: zmc_c_client <functions.bin> <results.bin>.  Exit status 0 on
  * success; on failure the status and mc_last_error go to stderr.
@@ -44,7 +45,7 @@ int main(int argc, char** argv)
     }
     const size_t n = (size_t)bytes / sizeof(mc_function);
     mc_function* fns = (mc_function*)malloc((size_t)bytes);
-    mc_result* res = (mc_result*)calloc(3 * n, sizeof(mc_result));
+    mc_result* res = (mc_result*)calloc(4 * n, sizeof(mc_result));
     if (!fns || !res || fread(fns, sizeof(mc_function), n, in) != n) {
         fprintf(stderr, "reading %s failed\n", argv[1]);
         fclose(in);
@@ -103,13 +104,38 @@ int main(int argc, char** argv)
     bad = check(ctx, mc_destroy(ctx), "mc_destroy") || bad;
     if (bad) return 1;
 
+    /* the same FP32 request served by a resident kernel: mc_run feeds its ring */
+    mc_ctx* rctx = NULL;
+    cfg.flags = MC_RESIDENT;
+    bad = check(NULL, mc_create(&cfg, &rctx), "mc_create (resident)");
+    uint64_t idr = 0;
+    bad = bad || check(rctx, mc_submit(rctx, fns, n, MC_PREC_FP32_EVAL, &idr), "mc_submit (resident)");
+    int doner = 0;
+    const time_t t1 = time(NULL);
+    while (!bad && !doner) {
+        if (time(NULL) - t1 > 60) {
+            fprintf(stderr, "the resident request did not complete within 60 s\n");
+            bad = 1;
+            break;
+        }
+        bad = check(rctx, mc_run(rctx, NULL), "mc_run (resident)");
+        uint64_t ids[8];
+        size_t got = 0;
+        bad = bad || check(rctx, mc_poll(rctx, ids, 8, &got), "mc_poll (resident)");
+        for (size_t i = 0; i < got; ++i)
+            if (ids[i] == idr) doner = 1;
+    }
+    bad = bad || check(rctx, mc_results(rctx, idr, res + 3 * n, n, 0), "mc_results (resident)");
+    if (rctx) bad = check(rctx, mc_destroy(rctx), "mc_destroy (resident)") || bad;
+    if (bad) return 1;
+
     FILE* out = fopen(argv[2], "wb");
-    if (!out || fwrite(res, sizeof(mc_result), 3 * n, out) != 3 * n) {
+    if (!out || fwrite(res, sizeof(mc_result), 4 * n, out) != 4 * n) {
         perror(argv[2]);
         return 2;
     }
     fclose(out);
-    printf("%zu functions: FP32, FP64 and plain FP64 results written (%llu launches)\n", n,
+    printf("%zu functions: FP32, FP64, plain FP64 and resident FP32 results written (%llu launches)\n", n,
            (unsigned long long)stats.launches);
     free(fns);
     free(res);

@@ -1,7 +1,8 @@
 """The C ABI used from plain C (tests/c_client/zmc_c_client.c, a separate process):
 the same function records give bitwise the results of the Python binding on the
-batched FP32 and FP64 paths and the plain FP64 path, and an invalid function is
-rejected with its status and a message."""
+batched FP32 and FP64 paths and the plain FP64 path, a resident context gives
+the batched FP32 results, and an invalid function is rejected with its status
+and a message."""
 
 import os
 import subprocess
@@ -28,9 +29,10 @@ def test_c_client_matches_python_binding(tmp_path):
     t.tofile(fin)
     p = subprocess.run([EXE, str(fin), str(fout)], capture_output=True, text=True, timeout=180)
     assert p.returncode == 0, p.stdout + p.stderr
-    got = np.fromfile(fout, dtype=Z.RESULT_DTYPE).reshape(3, len(t))
+    got = np.fromfile(fout, dtype=Z.RESULT_DTYPE).reshape(4, len(t))
     with Z.Context(flags=Z.MC_NO_GRAPH) as c:
         want = [c.integrate(t, Z.PREC_FP32), c.integrate(t, Z.PREC_FP64), c.plain_fp64(t)]
-    for k, label in enumerate(("batched FP32", "batched FP64", "plain FP64")):
+    want.append(want[0])
+    for k, label in enumerate(("batched FP32", "batched FP64", "plain FP64", "resident FP32")):
         for f in ("mean", "std_error", "sum_f", "sum_f2", "n", "status", "precision"):
             assert np.array_equal(got[k][f], want[k][f]), f"{label}: field {f} differs"
