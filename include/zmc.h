@@ -273,6 +273,18 @@ mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n,
  * flight, then clears the request so later work runs normally. */
 mc_status mc_abort(mc_ctx* ctx);
 
+/* Cancel one request (a serving loop whose client went away): none of its
+ * work not yet handed to the GPU runs, and work already there is discarded.
+ * It completes -- mc_poll reports it, mc_results returns MC_ERR_ABORTED --
+ * once no kernel refers to its device slots any more: at once if it was still
+ * queued or none of its work is in flight, else when the launches holding its
+ * work have been collected (a resident context stops its running launch for
+ * that, which starts again at once).  Results already in stay; every other
+ * result carries MC_ERR_ABORTED.  Other requests are unaffected, bit for bit.
+ * A request already complete, or lost to a failed launch, is left as it is.
+ * Errors: MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP. */
+mc_status mc_cancel(mc_ctx* ctx, uint64_t request_id);
+
 /* Checkpoint and resume of one request.  A function's state is its result
  * once finished, and otherwise the partial sums of the tiles it has run (its
  * samples are addressed by counter, paper "Solution method": which points a

@@ -53,7 +53,7 @@ EXPORTS = [
     "mc_poll", "mc_pending", "mc_results", "mc_abort", "mc_integrate_plain_fp64", "mc_get_tuning",
     "mc_set_tuning", "mc_autotune", "mc_last_run_timing", "mc_get_stats", "mc_last_error",
     "mc_segment_samples", "mc_version", "mc_register_family", "mc_submit_grid",
-    "mc_sample_points", "mc_integrate_plain_fp64_noalloc", "mc_snapshot", "mc_restore",
+    "mc_sample_points", "mc_integrate_plain_fp64_noalloc", "mc_snapshot", "mc_restore", "mc_cancel",
 ]
 
 
@@ -123,6 +123,7 @@ def load(path: str = LIB_PATH):
     L.mc_abort.argtypes = [vp]
     L.mc_snapshot.argtypes = [vp, ctypes.c_uint64, vp, ctypes.c_size_t, ctypes.POINTER(ctypes.c_size_t)]
     L.mc_restore.argtypes = [vp, vp, ctypes.c_size_t, u64p]
+    L.mc_cancel.argtypes = [vp, ctypes.c_uint64]
     L.mc_integrate_plain_fp64.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.mc_integrate_plain_fp64_noalloc.argtypes = [vp, vp, ctypes.c_size_t, vp, vp]
     L.mc_get_tuning.argtypes = [vp, ctypes.POINTER(ctypes.c_uint32), vp]
@@ -295,6 +296,10 @@ class Context:
     def abort(self):
         """mc_abort: stop the running persistent kernels; queued requests complete as aborted."""
         self._check(self.L.mc_abort(self.h), self.h)
+
+    def cancel(self, request_id: int):
+        """mc_cancel: drop one request's remaining work; it completes as aborted (results already in stay)."""
+        self._check(self.L.mc_cancel(self.h, request_id), self.h)
 
     def snapshot(self, request_id: int) -> bytes:
         """mc_snapshot: the request's state (results in, tiling, progress, partials of the tiles run)."""

@@ -334,6 +334,7 @@ struct FnState {
     bool needs_upload;    // record packed into the host mirror, not yet on the device
     uint32_t token;       // resident engine: the current run's token and record arena position
     uint32_t rec;
+    bool done;            // its final result is in
 };
 
 struct Request {
@@ -374,6 +375,8 @@ struct Request {
     std::vector<Partial> staged;      // restored: its whole partial range, saved tiles filled in (uploaded at admission)
     std::vector<uint32_t> staged_counts;  // restored into a resident context: each function's tiles already run
     bool partials_pending = false;    // resident: admitted, saved partials not yet on the device
+    bool cancelled = false;           // mc_cancel: no more of its work runs; it completes (MC_ERR_ABORTED)
+                                      // once no kernel refers to its slots any more
 };
 
 // A function's consecutive tiles in one launch and the cost of one of them.
@@ -710,6 +713,35 @@ bool has_work(const Request* r)
     return r->order_pos < r->order.size() || r->redo_pos < r->redo.size();
 }
 
+// No more of request r's work is handed to the GPU.
+void drop_work(Request* r)
+{
+    r->order_pos = (uint32_t)r->order.size();
+    r->redo_pos = (uint32_t)r->redo.size();
+    r->tiles_launched = r->tiles_total;
+    r->work_left = 0.0;
+}
+
+// Complete request r as aborted (mc_abort, mc_cancel): results already in
+// stay, every other one carries MC_ERR_ABORTED, its slots are released and its
+// id is reported complete.  Nothing on the GPU may refer to its slots any more.
+void complete_aborted(mc_ctx* ctx, Request* r)
+{
+    for (uint32_t i = 0; i < r->count(); ++i) {
+        if (r->st[i].done) continue;
+        mc_result& out = r->results[i];
+        std::memset(&out, 0, sizeof out);
+        out.n = r->grid ? r->spec.base.n_samples : r->fns[i].n_samples;
+        out.status = MC_ERR_ABORTED;
+        out.precision = (uint32_t)r->precision;
+    }
+    r->aborted = true;
+    r->fns_done = (uint32_t)r->count();
+    drop_work(r);
+    free_request_resources(ctx, r);
+    ctx->completed.push_back(r->id);
+}
+
 // Whether an FP32-evaluated result must be computed again in FP64.  `scale`
 // is the factor the FP32 path takes out of every sample (f = scale * g, the
 // sums scaled in FP64), so only g passes through FP32 arithmetic.
@@ -850,6 +882,19 @@ bool any_in_flight(const mc_ctx* ctx)
     return false;
 }
 
+// Whether a launch in flight still refers to request r (tiles or finalize records).
+bool in_flight_refers(const mc_ctx* ctx, const Request* r)
+{
+    for (const auto& s : ctx->slots) {
+        if (!s.in_flight) continue;
+        for (const Request* t : s.touched)
+            if (t == r) return true;
+        for (const FinRef& f : s.fin_refs)
+            if (f.req == r) return true;
+    }
+    return false;
+}
+
 uint32_t load_done(const mc_ctx* ctx, const LaunchSlot& s)
 {
     const uint32_t* w = ctx->h_done + 16 * (&s - ctx->slots);
@@ -887,6 +932,7 @@ void wait_done(mc_ctx* ctx, LaunchSlot& s)
 // trusted to FP64, and complete the request with its last function.
 void complete_function(mc_ctx* ctx, Request* req, uint32_t index, const DevResult& res, bool bad)
 {
+    if (req->cancelled) return;  // (it completes as aborted once nothing refers to it)
     mc_result& out = req->results[index];
     std::memcpy(&out, &res, sizeof(mc_result));
     if (bad) out.status = MC_ERR_HIP;
@@ -903,6 +949,7 @@ void complete_function(mc_ctx* ctx, Request* req, uint32_t index, const DevResul
         return;
     }
     if (out.status != MC_OK) req->aborted = true;
+    req->st[index].done = true;
     req->fns_done++;
     if (req->fns_done == req->count()) {
         free_request_resources(ctx, req);
@@ -954,8 +1001,13 @@ void reap(mc_ctx* ctx, int wait)
             ctx->stats.bad_records += bad;
         }
         s.in_flight = false;
+        // cancelled requests this launch referred to complete once no other launch does
+        std::vector<Request*> refs(s.touched.begin(), s.touched.end());
+        for (const FinRef& fr : s.fin_refs) refs.push_back(fr.req);
         s.fin_refs.clear();
         s.touched.clear();
+        for (Request* r : refs)
+            if (r->cancelled && r->fns_done < r->count() && !in_flight_refers(ctx, r)) complete_aborted(ctx, r);
     }
 }
 
@@ -1486,23 +1538,8 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
 void finish_abort(mc_ctx* ctx)
 {
     reap(ctx, 2);
-    auto cancel = [&](Request* r) {
-        for (uint32_t i = 0; i < r->count(); ++i) {
-            mc_result& out = r->results[i];
-            std::memset(&out, 0, sizeof out);
-            out.n = r->grid ? r->spec.base.n_samples : r->fns[i].n_samples;
-            out.status = MC_ERR_ABORTED;
-            out.precision = (uint32_t)r->precision;
-        }
-        r->aborted = true;
-        r->fns_done = (uint32_t)r->count();
-        r->order_pos = (uint32_t)r->order.size();
-        r->redo_pos = (uint32_t)r->redo.size();
-        free_request_resources(ctx, r);
-        ctx->completed.push_back(r->id);
-    };
-    for (Request* r : ctx->active) cancel(r);
-    for (Request* r : ctx->pending) cancel(r);
+    for (Request* r : ctx->active) complete_aborted(ctx, r);
+    for (Request* r : ctx->pending) complete_aborted(ctx, r);
     ctx->active.clear();
     ctx->pending.clear();
     HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[0], sizeof(uint32_t), hipMemcpyHostToDevice,
@@ -1849,24 +1886,8 @@ void res_finish_abort(mc_ctx* ctx)
     for (Request* r : ctx->pending) cancel.push_back(r);
     ctx->active.clear();
     ctx->pending.clear();
-    for (Request* r : cancel) {
-        if (r->fns_done == r->count()) continue;  // (listed twice)
-        for (uint32_t i = 0; i < r->count(); ++i) {
-            mc_result& out = r->results[i];
-            std::memset(&out, 0, sizeof out);
-            out.n = r->grid ? r->spec.base.n_samples : r->fns[i].n_samples;
-            out.status = MC_ERR_ABORTED;
-            out.precision = (uint32_t)r->precision;
-        }
-        r->aborted = true;
-        r->fns_done = (uint32_t)r->count();
-        r->order_pos = (uint32_t)r->order.size();
-        r->redo_pos = (uint32_t)r->redo.size();
-        r->tiles_launched = r->tiles_total;
-        r->work_left = 0.0;
-        free_request_resources(ctx, r);
-        ctx->completed.push_back(r->id);
-    }
+    for (Request* r : cancel)
+        if (r->fns_done < r->count()) complete_aborted(ctx, r);  // (a request can be listed twice)
     res_drop_unread(R);
     R.tiles_waiting = 0;
     __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
@@ -1899,6 +1920,54 @@ void res_upload_restored(mc_ctx* ctx)
         r->partials_pending = false;
         log_msg(3, "request %llu: saved partials copied to the device", (unsigned long long)r->id);
     }
+}
+
+// mc_cancel of an admitted request in a resident context (its work already
+// dropped).  With runs of it open, the launch is stopped (it runs every entry
+// below its count, then leaves) and the results that came in are collected
+// (and dropped); the request's entries it did not read (only after an idle
+// stop) are taken out of the ring, the others keeping their order, while no
+// kernel runs; its open runs give back their arena positions and have their
+// slots' tile counters cleared.  Then it completes as aborted.
+void res_cancel(mc_ctx* ctx, Request* r)
+{
+    ResidentState& R = ctx->res;
+    bool open = false;
+    for (const ResRun& run : R.runs) open = open || run.req == r;
+    if (open) {
+        res_request_stop(ctx);
+        res_wait_exit(ctx);
+        res_reap(ctx);
+        uint64_t w = R.acked;
+        for (uint64_t e = R.acked; e < R.pushed; ++e) {
+            const Chunk c = R.ring[e & (kRingEntries - 1)];
+            const bool mine = c.fn >= r->slot_base && c.fn - r->slot_base < r->count() &&
+                              c.token == r->st[c.fn - r->slot_base].token;
+            if (mine) {
+                R.unread_tiles -= c.count;
+                continue;
+            }
+            R.ring[w++ & (kRingEntries - 1)] = c;
+        }
+        R.pushed = w;
+        size_t k = 0;
+        bool runs_left = false;
+        for (const ResRun& run : R.runs) {
+            if (run.req != r) {
+                R.runs[k++] = run;
+                continue;
+            }
+            R.arena_busy[run.rec] = 0;
+            R.arena_epoch[run.rec] = R.epoch;
+            runs_left = true;
+        }
+        R.runs.resize(k);
+        if (runs_left) {
+            HIP_TRY(hipMemsetAsync(R.d_tiles_done + r->slot_base, 0, r->count() * sizeof(uint32_t), R.stream));
+            HIP_TRY(hipStreamSynchronize(R.stream));
+        }
+    }
+    complete_aborted(ctx, r);
 }
 
 // One step of a resident context: collect results, admit, feed the ring and
@@ -2330,6 +2399,7 @@ void init_fn_state(mc_ctx* ctx, Request* r, size_t i, const mc_function& f, bool
     fs.needs_upload = false;
     fs.token = 0;
     fs.rec = 0;
+    fs.done = false;
     fs.tile_cost = sample_cost(d.family, d.dim, f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL) *
                    (double)std::min<uint64_t>(d.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << L));
     r->tiles_total += fs.n_tiles;
@@ -2601,6 +2671,50 @@ mc_status mc_abort(mc_ctx* ctx)
     return MC_OK;
 }
 
+mc_status mc_cancel(mc_ctx* ctx, uint64_t request_id)
+{
+    if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
+    auto it = ctx->requests.find(request_id);
+    if (it == ctx->requests.end())
+        return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
+    Request* r = it->second.get();
+    // a complete request keeps its results; a lost one reports its failure
+    if (r->fns_done == r->count() || r->cancelled || r->lost) return MC_OK;
+    auto drop_from = [r](std::deque<Request*>& q) {
+        for (auto p = q.begin(); p != q.end(); ++p)
+            if (*p == r) {
+                q.erase(p);
+                return;
+            }
+    };
+    log_msg(2, "request %llu cancelled", (unsigned long long)request_id);
+    if (!r->admitted) {
+        drop_from(ctx->pending);
+        complete_aborted(ctx, r);
+        return MC_OK;
+    }
+    try {
+        HIP_TRY(hipSetDevice(ctx->device));
+        if (ctx->res.on) {
+            ResidentState& R = ctx->res;
+            R.tiles_waiting -= std::min<uint64_t>(R.tiles_waiting, r->tiles_total - r->tiles_launched);
+            R.active_dirty = true;
+        }
+        r->cancelled = true;
+        drop_work(r);
+        drop_from(ctx->active);
+        if (ctx->res.on) {
+            res_cancel(ctx, r);
+            if (!ctx->abort_requested) res_launch(ctx);  // (entries of other requests may wait)
+        } else if (!in_flight_refers(ctx, r)) {
+            complete_aborted(ctx, r);
+        }
+    } catch (const HipError& e) {
+        return fail_hip(ctx, e);
+    }
+    return MC_OK;
+}
+
 // ---------------------------------------------------------------- checkpoint / resume
 //
 // Snapshot layout (native byte order):
@@ -2667,9 +2781,8 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
                             (unsigned long long)request_id);
     std::vector<Partial> range;
     // each function's tiles run (resident: its open run's first tile still in
-    // the ring); whether a resident run of it is open; whether its result is in
+    // the ring)
     std::vector<uint32_t> ran(n), unread(n, UINT32_MAX);
-    std::vector<char> open(n, 0), done(n);
     // a resident launch stopped for a snapshot written starts again on the way
     // out if entries wait (if that fails, the next step tries again); after a
     // size query it stays stopped until the next call that runs work, so the
@@ -2699,8 +2812,6 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
                 res_request_stop(ctx);
                 res_wait_exit(ctx);
                 res_reap(ctx);  // (may send results to FP64: progress is read after it)
-                for (const ResRun& run : R.runs)
-                    if (run.req == r) open[run.index] = 1;
                 for (uint64_t e = R.acked; e < R.pushed && r->admitted; ++e) {
                     const Chunk& c = R.ring[e & (kRingEntries - 1)];
                     if (c.fn < r->slot_base || c.fn - r->slot_base >= n) continue;
@@ -2717,9 +2828,8 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
         uint64_t n_partials = 0;
         for (uint64_t i = 0; i < n; ++i) {
             const FnState& fs = r->st[i];
-            done[i] = fs.next_tile == fs.n_tiles && !open[i];
-            if (done[i]) continue;
-            ran[i] = std::min(ran[i], fs.n_tiles - 1);  // (an open run has a tile left: its result is not in)
+            if (fs.done) continue;
+            ran[i] = std::min(ran[i], fs.n_tiles - 1);  // (a run whose result is not in has a tile left)
             n_partials += ran[i];
         }
         const uint64_t total = snapshot_bytes(n, n_partials, r->grid);
@@ -2766,18 +2876,18 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
         }
         for (uint64_t i = 0; i < n; ++i, p += sizeof(SnapFn)) {
             const FnState& fs = r->st[i];
-            const SnapFn sf{fs.seg_log2, fs.n_tiles, done[i] ? fs.n_tiles : ran[i], fs.f64 ? 1u : 0u};
+            const SnapFn sf{fs.seg_log2, fs.n_tiles, fs.done ? fs.n_tiles : ran[i], fs.f64 ? 1u : 0u};
             std::memcpy(p, &sf, sizeof sf);
         }
         for (uint64_t i = 0; i < n; ++i, p += sizeof(mc_result)) {
             mc_result res{};
-            if (done[i]) res = r->results[i];
+            if (r->st[i].done) res = r->results[i];
             std::memcpy(p, &res, sizeof res);
         }
         uint64_t off = 0;  // function i's first partial within the request's range
         for (uint64_t i = 0; i < n; ++i) {
             const FnState& fs = r->st[i];
-            if (!done[i] && ran[i] > 0) {
+            if (!fs.done && ran[i] > 0) {
                 std::memcpy(p, range.data() + off, (size_t)ran[i] * sizeof(Partial));
                 p += (size_t)ran[i] * sizeof(Partial);
             }
@@ -2866,6 +2976,7 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
         fs.needs_upload = false;
         fs.token = 0;
         fs.rec = 0;
+        fs.done = s.next_tile == s.n_tiles;
         fs.tile_cost = sample_cost(f.family, f.dim, fs.f64 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL) *
                        (double)std::min<uint64_t>(f.n_samples, (uint64_t)kSegSamples * ((uint64_t)kBlockWaves << fs.seg_log2));
         if (s.next_tile == s.n_tiles) {

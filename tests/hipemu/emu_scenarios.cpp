@@ -126,6 +126,23 @@ mc_ctx* create(uint32_t flags, uint32_t max_tiles = 0, uint32_t policy = MC_SCHE
     return ctx;
 }
 
+// Results of a request that was aborted or cancelled: those that came in are exact,
+// the others carry MC_ERR_ABORTED.
+bool check_cancelled(const std::vector<mc_function>& t, const std::vector<mc_result>& r, const char* label)
+{
+    for (size_t i = 0; i < t.size(); ++i) {
+        if (r[i].status == MC_OK) {
+            const bool promoted = (t[i].seed >> 63) != 0;
+            CHECK(same_result(r[i], hipemu::expected_batched(t[i], promoted)), "%s: function %zu kept a wrong result",
+                  label, i);
+        } else {
+            CHECK(r[i].status == MC_ERR_ABORTED && r[i].n == t[i].n_samples, "%s: function %zu: status %d", label, i,
+                  r[i].status);
+        }
+    }
+    return true;
+}
+
 bool run_request(mc_ctx* ctx, const std::vector<mc_function>& t, bool fp64, const char* label)
 {
     uint64_t id = 0;
@@ -710,7 +727,7 @@ bool resident_abort()
     std::vector<mc_result> r(t.size());
     const mc_status st = mc_results(ctx, id, r.data(), r.size(), 1);
     CHECK(st == MC_ERR_ABORTED, "aborted request: %d", (int)st);
-    for (size_t i = 0; i < t.size(); ++i) CHECK(r[i].status == MC_ERR_ABORTED, "status %d", r[i].status);
+    if (!check_cancelled(t, r, "aborted")) return false;
     std::vector<mc_result> r2(5);
     CHECK(mc_results(ctx, id2, r2.data(), 5, 1) == MC_ERR_ABORTED, "second request aborted");
     if (!run_request(ctx, mixed_table(12, 121, 3), false, "after abort")) return false;
@@ -920,6 +937,67 @@ bool snapshot_restore()
     return true;
 }
 
+// Cancellation of single requests, in every engine: a queued request completes
+// at once, one whose work is running completes once nothing refers to it
+// (results already in stay, the rest come back aborted), a complete one keeps
+// its results; the other requests, and a request that reuses the cancelled
+// one's slots, come back exactly right.
+bool cancel_requests()
+{
+    for (uint32_t flags : {(uint32_t)MC_NO_GRAPH, 0u, (uint32_t)MC_RESIDENT}) {
+        mc_ctx* ctx = create(flags, 6, MC_SCHED_FIFO, 64, 1 << 14);
+        CHECK(ctx, "create");
+        const std::vector<mc_function> a = mixed_table(20, 150), b = mixed_table(30, 151, 4), c = mixed_table(40, 152);
+        uint64_t ia = 0, ib = 0, ic = 0;
+        // b first: FIFO runs its work first, so it is on the GPU when it is cancelled
+        CHECK(mc_submit(ctx, b.data(), b.size(), MC_PREC_FP32_EVAL, &ib) == MC_OK, "submit b");
+        CHECK(mc_submit(ctx, a.data(), a.size(), MC_PREC_FP32_EVAL, &ia) == MC_OK, "submit a");
+        CHECK(mc_submit(ctx, c.data(), c.size(), MC_PREC_FP32_EVAL, &ic) == MC_OK, "submit c");  // queued: no slots
+        for (int i = 0; i < 3; ++i) CHECK(mc_run(ctx, nullptr) != MC_ERR_HIP, "run");
+        // (the last launch is still in flight: no call has collected it)
+        CHECK(mc_cancel(ctx, ic) == MC_OK, "cancel queued: %s", mc_last_error(ctx));
+        CHECK(mc_cancel(ctx, ib) == MC_OK, "cancel running: %s", mc_last_error(ctx));
+        CHECK(mc_cancel(ctx, ib) == MC_OK, "cancel twice");
+        uint64_t got[16];
+        size_t n = 0;
+        CHECK(mc_poll(ctx, got, 16, &n) == MC_OK, "poll");
+        bool seen_b = false, seen_c = false;
+        for (size_t k = 0; k < n; ++k) {
+            seen_b = seen_b || got[k] == ib;
+            seen_c = seen_c || got[k] == ic;
+        }
+        CHECK(seen_c && seen_b, "cancelled requests complete once their launches are collected (flags %u)", flags);
+        std::vector<mc_result> rc(c.size());
+        CHECK(mc_results(ctx, ic, rc.data(), rc.size(), 0) == MC_ERR_ABORTED, "queued: aborted");
+        for (const mc_result& x : rc) CHECK(x.status == MC_ERR_ABORTED, "queued: status %d", x.status);
+        size_t need = 0;
+        std::vector<mc_result> rb(b.size());
+        CHECK(mc_results(ctx, ib, rb.data(), rb.size(), 0) == MC_ERR_ABORTED, "running: aborted (flags %u)", flags);
+        if (!check_cancelled(b, rb, "running")) return false;
+        CHECK(mc_snapshot(ctx, ib, nullptr, 0, &need) == MC_ERR_UNKNOWN_REQUEST, "taken");
+        // a request in the cancelled one's slots
+        const std::vector<mc_function> d = mixed_table(40, 153, 5);
+        uint64_t id = 0;
+        CHECK(mc_submit(ctx, d.data(), d.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit d");
+        std::vector<mc_result> rd(d.size()), ra(a.size());
+        CHECK(mc_results(ctx, id, rd.data(), rd.size(), 1) == MC_OK, "d: %s", mc_last_error(ctx));
+        if (!check_results(d, rd, false, "after a cancel")) return false;
+        // a complete request keeps its results
+        for (int i = 0; i < 20000; ++i) {
+            CHECK(mc_run(ctx, nullptr) != MC_ERR_HIP && mc_poll(ctx, got, 16, &n) == MC_OK, "run");
+            bool a_done = false;
+            for (size_t k = 0; k < n; ++k) a_done = a_done || got[k] == ia;
+            if (a_done) break;
+        }
+        CHECK(mc_cancel(ctx, ia) == MC_OK, "cancel complete");
+        CHECK(mc_results(ctx, ia, ra.data(), ra.size(), 1) == MC_OK, "a: %s", mc_last_error(ctx));
+        if (!check_results(a, ra, false, "beside the cancels")) return false;
+        CHECK(mc_cancel(ctx, ia) == MC_ERR_UNKNOWN_REQUEST, "unknown id");
+        mc_destroy(ctx);
+    }
+    return true;
+}
+
 // The packing's own hypot and atan2 (built from correctly rounded operations so
 // that host and device pack the same bits) against libm: within a few units in
 // the last place, over magnitudes 10^-6..10^6, zeros, equal and opposite values.
@@ -1016,7 +1094,7 @@ int main(int argc, char** argv)
         {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
         {"resident_abort", resident_abort}, {"log_levels", log_levels}, {"snapshot", snapshot_restore},
-        {"pack_math", pack_math},
+        {"pack_math", pack_math}, {"cancel", cancel_requests},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {

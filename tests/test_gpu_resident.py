@@ -114,7 +114,7 @@ def test_resident_abort_then_continue():
     import paper_2104_10073_amd as Z
     big = W.mixed_batch(600, dim_range=(1, 12), log10_samples=(6.0, 7.0), gen_seed=521)
     small = W.mixed_batch(30, dim_range=(1, 5), log10_samples=(3.0, 5.0), gen_seed=522)
-    ref = _launch_results(Z, [(small, Z.PREC_FP32)])[0]
+    ref, ref_big = _launch_results(Z, [(small, Z.PREC_FP32), (big, Z.PREC_FP32)])
     with Z.Context(device=0, flags=Z.MC_RESIDENT) as c:
         rid = c.submit(big, Z.PREC_FP32)
         c.run()
@@ -122,7 +122,11 @@ def test_resident_abort_then_continue():
         print("resident: abort", flush=True)
         c.abort()
         r = c.results(rid, len(big), blocking=True, allow_aborted=True)
-        assert np.all(r["status"] == -10)
+        # results that came in before the abort stay, bit for bit; the rest are aborted
+        kept = r["status"] == 0
+        assert np.all(r["status"][~kept] == -10) and not np.all(kept)
+        for f in ("mean", "std_error", "sum_f", "sum_f2", "n", "precision"):
+            assert np.array_equal(r[f][kept], ref_big[f][kept]), f
         _same(c.integrate(small, Z.PREC_FP32), ref, "after abort")
 
 
