@@ -1928,7 +1928,9 @@ void res_upload_restored(mc_ctx* ctx)
 // (and dropped); the request's entries it did not read (only after an idle
 // stop) are taken out of the ring, the others keeping their order, while no
 // kernel runs; its open runs give back their arena positions and have their
-// slots' tile counters cleared.  Then it completes as aborted.
+// slots' tile counters cleared.  Then it completes as aborted.  If clearing
+// the counters fails, it completes all the same but keeps its slots (their
+// counters are unknown), and the error is passed on.
 void res_cancel(mc_ctx* ctx, Request* r)
 {
     ResidentState& R = ctx->res;
@@ -1963,8 +1965,14 @@ void res_cancel(mc_ctx* ctx, Request* r)
         }
         R.runs.resize(k);
         if (runs_left) {
-            HIP_TRY(hipMemsetAsync(R.d_tiles_done + r->slot_base, 0, r->count() * sizeof(uint32_t), R.stream));
-            HIP_TRY(hipStreamSynchronize(R.stream));
+            try {
+                HIP_TRY(hipMemsetAsync(R.d_tiles_done + r->slot_base, 0, r->count() * sizeof(uint32_t), R.stream));
+                HIP_TRY(hipStreamSynchronize(R.stream));
+            } catch (const HipError&) {
+                r->admitted = false;  // (its slots are not released)
+                complete_aborted(ctx, r);
+                throw;
+            }
         }
     }
     complete_aborted(ctx, r);

@@ -408,12 +408,15 @@ bool fault_workload(uint32_t flags, bool* clean)
         f.seed = base.seed + i;
         grid_t.push_back(f);
     }
-    std::vector<uint64_t> ids(3, 0);
-    std::vector<int> state(3, 0);  // 0 not submitted, 1 pending, 2 done
-    for (int k = 0; k < 3; ++k) {
-        mc_status st = k < 2 ? mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL,
-                                         &ids[k])
-                             : mc_submit_grid(ctx, &base, &axis, 1, MC_PREC_FP32_EVAL, &ids[k]);
+    // request 3 is cancelled after the first run
+    reqs.push_back(grid_t);
+    reqs.push_back(mixed_table(9, 83));
+    std::vector<uint64_t> ids(4, 0);
+    std::vector<int> state(4, 0);  // 0 not submitted, 1 pending, 2 done
+    for (int k = 0; k < 4; ++k) {
+        mc_status st = k == 2 ? mc_submit_grid(ctx, &base, &axis, 1, MC_PREC_FP32_EVAL, &ids[k])
+                              : mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL,
+                                          &ids[k]);
         if (st == MC_OK) {
             state[k] = 1;
         } else {
@@ -424,29 +427,39 @@ bool fault_workload(uint32_t flags, bool* clean)
     }
     for (int guard = 0; guard < 20000; ++guard) {
         bool all = true;
-        for (int k = 0; k < 3; ++k) all = all && state[k] == 2;
+        for (int k = 0; k < 4; ++k) all = all && state[k] == 2;
         if (all) break;
         const mc_status st = mc_run(ctx, nullptr);
         if (st != MC_OK && st != MC_NOT_READY) {
             *clean = false;
             CHECK(st == MC_ERR_HIP || st == MC_ERR_OUT_OF_MEMORY, "run: status %d", (int)st);
         }
-        for (int k = 0; k < 3; ++k) {
+        if (guard == 0 && state[3] == 1) {
+            const mc_status cs = mc_cancel(ctx, ids[3]);
+            if (cs != MC_OK) {
+                *clean = false;
+                CHECK(cs == MC_ERR_HIP, "cancel: status %d", (int)cs);
+            }
+        }
+        for (int k = 0; k < 4; ++k) {
             if (state[k] != 1) continue;
-            const std::vector<mc_function>& t = k < 2 ? reqs[k] : grid_t;
+            const std::vector<mc_function>& t = reqs[k];
             std::vector<mc_result> r(t.size());
             const mc_status rs = mc_results(ctx, ids[k], r.data(), r.size(), guard > 10000);
             if (rs == MC_NOT_READY) continue;
             state[k] = 2;
             if (rs == MC_OK) {
+                // (the cancelled request too, if the cancel failed before it took effect)
                 if (!check_results(t, r, k == 1, "after injected failures")) return false;
+            } else if (rs == MC_ERR_ABORTED && k == 3) {
+                if (!check_cancelled(t, r, "cancelled")) return false;
             } else {
                 *clean = false;
                 CHECK(rs == MC_ERR_HIP || rs == MC_ERR_OUT_OF_MEMORY, "results %d: status %d", k, (int)rs);
             }
         }
     }
-    for (int k = 0; k < 3; ++k) CHECK(state[k] == 2, "request %d never finished", k);
+    for (int k = 0; k < 4; ++k) CHECK(state[k] == 2, "request %d never finished", k);
     // the context still works: a new request completes (the injected failure
     // fires once, so if it lands here the second attempt must succeed)
     const std::vector<mc_function> after = mixed_table(6, 83);
