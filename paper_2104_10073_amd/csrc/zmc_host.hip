@@ -6,7 +6,10 @@
 // partial arena as space frees up, cut functions into tiles, order tiles by
 // cost, and enqueue launches (persistent FP32 kernel, persistent FP64 kernel,
 // finalize, result copy) on the caller's stream from a small ring of launch
-// slots, each with a captured HIP graph.
+// slots, each with a captured HIP graph -- or, in a resident context, feed one
+// persistent kernel through a ring in pinned memory.  Also: promotion of FP32
+// results to FP64, run-time compiled families, parameter grids, abort and
+// cancellation, checkpoint and resume, tuning, the plain comparator paths.
 #include <hip/hip_runtime.h>
 #include <hip/hiprtc.h>
 
@@ -696,12 +699,16 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
 
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
-    std::vector<Partial>().swap(r->staged);
-    std::vector<uint32_t>().swap(r->staged_counts);
     if (r->uploaded) {
+        // an upload into its slots still on the upload stream (a request aborted
+        // or cancelled before a launch waited for it) lands before the slots
+        // are handed to another request; otherwise it is long complete
+        quiet(hipEventSynchronize(r->uploaded));
         quiet(hipEventDestroy(r->uploaded));
         r->uploaded = nullptr;
     }
+    std::vector<Partial>().swap(r->staged);
+    std::vector<uint32_t>().swap(r->staged_counts);
     if (!r->admitted) return;
     ctx->fn_alloc.release(r->slot_base, r->count());
     ctx->part_alloc.release(r->part_base, r->part_count);
