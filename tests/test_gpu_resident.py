@@ -144,3 +144,24 @@ def test_resident_arena_recycled_across_launches():
         _same(got[rid], ref[k], f"request {k}")
     print(f"{st['launches']} launches, {st['functions']} functions", flush=True)
     assert st["launches"] >= 2 and st["bad_records"] == 0
+
+
+def test_resident_in_a_torch_workspace_on_a_side_stream():
+    """A resident context whose device memory is a caller's torch tensor (every
+    device buffer of the context, the ring's device words and the record arena
+    included), driven while torch works on a stream of its own: bitwise the
+    launch engine's results."""
+    import torch
+    import paper_2104_10073_amd as Z
+    t = W.mixed_batch(120, dim_range=(1, 12), log10_samples=(3.0, 6.0), gen_seed=531)
+    ref = _launch_results(Z, [(t, Z.PREC_FP32)])[0]
+    side = torch.cuda.Stream()
+    with torch.cuda.stream(side):
+        a = torch.randn(2048, 2048, device="cuda")
+        for _ in range(4):
+            a = a @ a.T / 2048.0
+    with Z.Context(device=0, flags=Z.MC_RESIDENT, workspace="torch") as c:
+        got = c.integrate(t, Z.PREC_FP32)
+    torch.cuda.synchronize()
+    assert torch.isfinite(a).all()
+    _same(got, ref, "torch workspace")
