@@ -416,7 +416,10 @@ mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, ui
  * validate-only context the source is compiled but not loaded.  The caller's
  * code runs unchecked inside the library's kernels: an out-of-bounds access in
  * it faults like any kernel.  Launches on a context with registered families
- * are enqueued directly, not as captured graphs. */
+ * are enqueued directly, not as captured graphs.  A resident context
+ * (MC_RESIDENT) compiles its resident kernel again with every family it has
+ * registered (a few tens of seconds), stops its running launch, and launches
+ * the new kernel in its place. */
 mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_out);
 
 /* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */

@@ -506,6 +506,9 @@ struct ResidentState {
     std::vector<uint32_t> arena_epoch;  // per position: the last launch that may have read it
     std::vector<uint8_t> arena_busy;    // per position: used by a run whose result is not in
     std::vector<ResRun> runs;           // runs with chunks pushed whose result is not in
+    // with run-time families registered: the resident kernel compiled with them
+    hipModule_t user_module = nullptr;
+    hipFunction_t user_kernel = nullptr;
 };
 
 constexpr size_t kDescBytes = 512;  // LaunchDesc followed by its counters (zero padded)
@@ -580,6 +583,7 @@ struct mc_ctx {
     };
     UserFamily user[kMaxUserFamilies];
     uint32_t n_user = 0;
+    std::vector<std::string> user_src;  // their sources (a resident kernel is compiled with all of them)
 
     ResidentState res;
 };
@@ -1626,7 +1630,10 @@ void res_launch(mc_ctx* ctx)
         HIP_TRY(hipMemcpyAsync(R.d_running, &R.stage[2], sizeof(uint32_t), hipMemcpyHostToDevice, R.stream));
         ResidentDesc* d = R.d_desc;
         void* args[] = {&d, &epoch};
-        HIP_TRY(hipLaunchKernel(resident_kernel_ptr(), dim3(R.grid), dim3(kBlockThreads), args, 0, R.stream));
+        if (R.user_kernel)
+            HIP_TRY(hipModuleLaunchKernel(R.user_kernel, R.grid, 1, 1, kBlockThreads, 1, 1, 0, R.stream, args, nullptr));
+        else
+            HIP_TRY(hipLaunchKernel(resident_kernel_ptr(), dim3(R.grid), dim3(kBlockThreads), args, 0, R.stream));
     } catch (const HipError&) {
         // the staged start values are rewritten by the next attempt: let what
         // was enqueued finish first
@@ -2016,6 +2023,9 @@ void destroy_device(mc_ctx* ctx)
     ResidentState& R = ctx->res;
     if (R.stream) quiet(hipStreamDestroy(R.stream));
     R.stream = nullptr;
+    if (R.user_module) quiet(hipModuleUnload(R.user_module));
+    R.user_module = nullptr;
+    R.user_kernel = nullptr;
     if (R.h_block) quiet(hipHostFree(R.h_block));
     R.h_block = nullptr;
     for (auto& s : ctx->slots) {
@@ -3489,6 +3499,52 @@ std::string user_family_source(const char* user_source, uint32_t family, uint32_
     return src;
 }
 
+// Source of the resident kernel of a context with run-time families: every
+// family registered so far in its own namespace, and a dispatch that tries the
+// built-in families, then each of them.
+std::string resident_user_source(const std::vector<std::string>& sources)
+{
+    std::string src = "#include \"zmc_device_code.hpp\"\n";
+    char buf[512];
+    for (size_t k = 0; k < sources.size(); ++k) {
+        snprintf(buf, sizeof buf, "namespace zmc_user_%zu {\n#line 1 \"integrand %zu\"\n", k, k);
+        src += buf;
+        src += sources[k];
+        snprintf(buf, sizeof buf,
+                 "\n}  // namespace zmc_user_%zu\n"
+                 "struct ZmcUserFn%zu {\n"
+                 "    template <class T>\n"
+                 "    static __device__ __forceinline__ T f(const T* x, const T* p, uint32_t d)\n"
+                 "    { return zmc_user_%zu::mc_user_integrand<T>(x, p, d); }\n"
+                 "};\n",
+                 k, k, k);
+        src += buf;
+    }
+    src += "template <bool F64>\n"
+           "struct ZmcResidentDispatch {\n"
+           "    __device__ static __forceinline__ bool run(zmc::CDevFn* fn, uint32_t fam, uint32_t seg0, uint32_t seg_log2,\n"
+           "                                               uint32_t wave, uint32_t lane, zmc::Partial* s_seg)\n"
+           "    {\n"
+           "        if (zmc::BuiltinDispatch<F64>::run(fn, fam, seg0, seg_log2, wave, lane, s_seg)) return true;\n";
+    for (size_t k = 0; k < sources.size(); ++k) {
+        snprintf(buf, sizeof buf,
+                 "        if (zmc::UserDispatch<ZmcUserFn%zu, %uu, F64>::run(fn, fam, seg0, seg_log2, wave, lane, s_seg))"
+                 " return true;\n",
+                 k, kUserFamily0 + (uint32_t)k);
+        src += buf;
+    }
+    src += "        return false;\n"
+           "    }\n"
+           "};\n";
+    snprintf(buf, sizeof buf,
+             "extern \"C\" __global__ __launch_bounds__(%d) void zmc_resident_user(const zmc::ResidentDesc* __restrict__ R,"
+             " uint32_t epoch)\n"
+             "{ zmc::resident_body<ZmcResidentDispatch<false>, ZmcResidentDispatch<true>>(R, epoch); }\n",
+             kBlockThreads);
+    src += buf;
+    return src;
+}
+
 // Compile with hipRTC for gfx950; returns the code object or sets *log.
 bool compile_user_family(const std::string& src, std::vector<char>* code, std::string* log)
 {
@@ -3522,6 +3578,53 @@ bool compile_user_family(const std::string& src, std::vector<char>* code, std::s
     return ok;
 }
 
+// mc_register_family on a resident context: the resident kernel is compiled
+// again with every family registered so far and this one; the running launch
+// (of the previous kernel) is stopped and has gone before the new kernel
+// replaces it, and launches again at once if entries wait.
+mc_status register_resident_family(mc_ctx* ctx, const char* source, uint32_t* family_out)
+{
+    ResidentState& R = ctx->res;
+    std::vector<std::string> all = ctx->user_src;
+    all.push_back(source);
+    std::vector<char> code;
+    std::string log;
+    if (!compile_user_family(resident_user_source(all), &code, &log)) {
+        ctx->err = "run-time family did not compile: " + log;
+        g_thread_error = ctx->err;
+        return MC_ERR_COMPILE;
+    }
+    if (!ctx->validate_only) {
+        hipModule_t module = nullptr;
+        try {
+            hipFunction_t kernel = nullptr;
+            int occ = 0;
+            HIP_TRY(hipSetDevice(ctx->device));
+            HIP_TRY(hipModuleLoadData(&module, code.data()));
+            HIP_TRY(hipModuleGetFunction(&kernel, module, "zmc_resident_user"));
+            HIP_TRY(hipModuleOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, kBlockThreads, 0));
+            res_request_stop(ctx);
+            res_wait_exit(ctx);
+            HIP_TRY(hipStreamSynchronize(R.stream));
+            if (R.user_module) quiet(hipModuleUnload(R.user_module));
+            R.user_module = module;
+            R.user_kernel = kernel;
+            module = nullptr;
+            const mc_config& cfg = ctx->cfg;
+            R.grid = (uint32_t)ctx->num_cus * (cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ));
+            log_msg(2, "resident kernel compiled with %zu run-time families: %u workgroups", all.size(), R.grid);
+            if (!ctx->abort_requested) res_launch(ctx);  // (entries may wait)
+        } catch (const HipError& e) {
+            if (module) quiet(hipModuleUnload(module));
+            return fail_hip(ctx, e);
+        }
+    }
+    ctx->user_src.push_back(source);
+    *family_out = kUserFamily0 + ctx->n_user;
+    ctx->n_user++;
+    return MC_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -3530,11 +3633,11 @@ mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_o
 {
     if (!ctx) return fail(nullptr, MC_ERR_INVALID_ARG, "ctx is NULL");
     if (!source || !family_out) return fail(ctx, MC_ERR_INVALID_ARG, "NULL argument");
-    if (ctx->res.on) return fail(ctx, MC_ERR_INVALID_ARG, "a resident context serves the built-in families only");
     if (ctx->n_user >= (uint32_t)kMaxUserFamilies)
         return fail(ctx, MC_ERR_INVALID_ARG, "at most %d run-time families per context", kMaxUserFamilies);
     const uint32_t u = ctx->n_user;
     const uint32_t family = kUserFamily0 + u;
+    if (ctx->res.on) return register_resident_family(ctx, source, family_out);
     const std::string src = user_family_source(source, family, 2 + 2 * u);
     std::vector<char> code;
     std::string log;
@@ -3561,6 +3664,7 @@ mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_o
         }
         ctx->user[u] = uf;
     }
+    ctx->user_src.push_back(source);
     ctx->n_user = u + 1;
     *family_out = family;
     return MC_OK;

@@ -91,6 +91,31 @@ def test_user_family_on_graph_context_matches(setup):
                 assert np.array_equal(got[k], ref[k]), k
 
 
+def test_user_families_on_a_resident_context(setup):
+    """A resident context compiles its kernel again at each registration; the
+    second registration replaces the kernel while the first one's launch is
+    serving a request.  Results are those of the launch context, bit for bit,
+    in FP32 (with its promotions) and FP64."""
+    import paper_2104_10073_amd as Z
+    c, t, _, _ = setup
+    ref32, ref64 = c.integrate(t, Z.PREC_FP32), c.integrate(t, Z.PREC_FP64)
+    fields = ("mean", "std_error", "sum_f", "sum_f2", "n", "status", "precision")
+    with Z.Context(device=0, flags=Z.MC_RESIDENT) as r:
+        assert r.register_family(U.QUAD_SINE_SRC) == Z.MC_FAMILY_USER0
+        first = t[:50]  # built-in rows and the first family's
+        rid = r.submit(first, Z.PREC_FP32)
+        r.run()
+        print("resident: second family registered while a request runs", flush=True)
+        assert r.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0 + 1
+        got_first = r.results(rid, len(first))
+        got32, got64 = r.integrate(t, Z.PREC_FP32), r.integrate(t, Z.PREC_FP64)
+        assert r.stats()["bad_records"] == 0
+    for k in fields:
+        assert np.array_equal(got_first[k], ref32[k][:50]), ("first", k)
+        assert np.array_equal(got32[k], ref32[k]), ("fp32", k)
+        assert np.array_equal(got64[k], ref64[k]), ("fp64", k)
+
+
 def test_plain_path_rejects_user_family(setup):
     import paper_2104_10073_amd as Z
     c, t, _, _ = setup

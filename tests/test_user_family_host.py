@@ -59,3 +59,15 @@ def test_family_limit():
         with pytest.raises(Z.McError) as e:
             c.register_family(U.RATIONAL_SRC)
         assert e.value.status == -1
+
+
+def test_resident_context_compiles_its_kernel_with_the_family():
+    """A resident context compiles its resident kernel again with the caller's
+    family (hipRTC; on a validate-only context nothing is loaded) and then
+    accepts the family's id."""
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY | Z.MC_RESIDENT) as c:
+        t = U.user_table(4, Z.MC_FAMILY_USER0, 1)
+        with pytest.raises(Z.McError):
+            c.submit(t, Z.PREC_FP32)
+        assert c.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0
+        c.submit(np.concatenate([t, W.mixed_batch(4, gen_seed=5)]), Z.PREC_FP32)
