@@ -233,6 +233,8 @@ def serving_leg(Z, W, stream, args):
     with make_ctx(head) as ctx:
         sat = serving.serve(ctx, reqs, np.zeros(n), stream)
     sat_qps = n / sat["wall_s"]
+    # the mix's algorithmic VALU work per evaluation (the roofline count of the headline)
+    mix_slots_per_eval = sum(algorithmic_slots(t) for t in reqs) / float(sat["evals"])
     summ = None
     compare = {}
     for name in [head] + others:
@@ -267,6 +269,8 @@ def serving_leg(Z, W, stream, args):
             head_other = per_load
     summ.update({"engine": "launches", "policy": head, "offered_qps": qps, "saturated_qps": sat_qps,
                  "saturated_evals_per_s": sat["evals"] / sat["wall_s"],
+                 "saturated_valu_frac": sat["evals"] / sat["wall_s"] * mix_slots_per_eval / VALU_SLOT_PEAK,
+                 "mix_slots_per_eval": mix_slots_per_eval,
                  "load_fraction": args.serve_load, "alone_equals_mix_bitwise": bool(same),
                  "requests_checked_alone": int(len(picks)),
                  "other_loads": head_other,
@@ -275,6 +279,8 @@ def serving_leg(Z, W, stream, args):
                              "10^U(4,7) samples each, Poisson arrivals"})
     if args.serve_resident:
         summ["resident"] = resident_serving(Z, W, serving, reqs, sat_qps, loads, head, others, picks, run, args)
+        summ["resident"]["saturated_valu_frac"] = (summ["resident"]["saturated_evals_per_s"] * mix_slots_per_eval /
+                                                   VALU_SLOT_PEAK)
     # nearly alone: a twentieth of the saturated rate, both engines (the latency a request
     # sees with the GPU to itself, for comparison with the loaded medians)
     m = min(n, 400)
