@@ -419,7 +419,9 @@ mc_status mc_sample_points(mc_ctx* ctx, const mc_function* f, uint64_t first, ui
  * are enqueued directly, not as captured graphs.  A resident context
  * (MC_RESIDENT) compiles its resident kernel again with every family it has
  * registered (a few tens of seconds), stops its running launch, and launches
- * the new kernel in its place. */
+ * the new kernel in its place.  Compiled code is kept for the life of the
+ * process, by source: registering the same families again, in this or another
+ * context, compiles nothing. */
 mc_status mc_register_family(mc_ctx* ctx, const char* source, uint32_t* family_out);
 
 /* Message of the last failure on ctx (or of the calling thread when ctx is NULL). */

@@ -3545,8 +3545,33 @@ std::string resident_user_source(const std::vector<std::string>& sources)
     return src;
 }
 
+// Code objects compiled in this process, by source text (the library's headers
+// and compile options are fixed for a build): contexts that register the same
+// families compile them once.  Failed compiles are not kept.
+std::mutex g_rtc_mu;
+std::map<std::string, std::vector<char>> g_rtc_cache;
+
+bool compile_uncached(const std::string& src, std::vector<char>* code, std::string* log);
+
 // Compile with hipRTC for gfx950; returns the code object or sets *log.
 bool compile_user_family(const std::string& src, std::vector<char>* code, std::string* log)
+{
+    {
+        std::lock_guard<std::mutex> lock(g_rtc_mu);
+        auto it = g_rtc_cache.find(src);
+        if (it != g_rtc_cache.end()) {
+            *code = it->second;
+            log_msg(2, "run-time family: code object reused (%zu bytes)", code->size());
+            return true;
+        }
+    }
+    if (!compile_uncached(src, code, log)) return false;
+    std::lock_guard<std::mutex> lock(g_rtc_mu);
+    g_rtc_cache.emplace(src, *code);
+    return true;
+}
+
+bool compile_uncached(const std::string& src, std::vector<char>* code, std::string* log)
 {
     hiprtcProgram prog = nullptr;
     const char* hdr_src[] = {kRtcHeaderDevice, kRtcHeaderCode};
