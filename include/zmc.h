@@ -303,10 +303,10 @@ mc_status mc_cancel(mc_ctx* ctx, uint64_t request_id);
  * order).  With buf NULL it only stores the size into *bytes.  The request
  * stays in the context unchanged (continue it, abort it, or take its
  * results).  Snapshots do not depend on the engine: one taken in a launch
- * context restores into a resident one and the other way round.  Errors:
- * MC_ERR_INVALID_ARG (cap smaller than needed -- *bytes holds the size --, a
- * request that uses a run-time family, an aborted or failed request),
- * MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP.
+ * context restores into a resident one and the other way round.  A request
+ * that uses run-time families carries their source texts.  Errors:
+ * MC_ERR_INVALID_ARG (cap smaller than needed -- *bytes holds the size --, an
+ * aborted or failed request), MC_ERR_UNKNOWN_REQUEST, MC_ERR_HIP.
  *
  * mc_restore checks a snapshot (format, version, every function as mc_submit
  * does, tiling and progress against the functions) and queues it as a new
@@ -314,8 +314,11 @@ mc_status mc_cancel(mc_ctx* ctx, uint64_t request_id);
  * the device when it is admitted (a resident context stops its running launch
  * for that copy).  Functions whose results were in complete at once; the
  * restoring context's MC_NO_PROMOTE setting applies to FP32 results not yet
- * in.  Errors: MC_ERR_INVALID_ARG (not a snapshot of this library version,
- * inconsistent or truncated), the validation codes of mc_submit,
+ * in.  Run-time families are found by source text among those registered on
+ * the restoring context (in any order; the request takes this context's ids).
+ * Errors: MC_ERR_INVALID_ARG (not a snapshot of this library version,
+ * inconsistent or truncated), MC_ERR_UNSUPPORTED_FAMILY (a run-time family
+ * whose source is not registered here), the validation codes of mc_submit,
  * MC_ERR_ADMISSION. */
 mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, size_t* bytes);
 mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_request_id);

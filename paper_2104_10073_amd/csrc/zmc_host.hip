@@ -2744,10 +2744,15 @@ mc_status mc_cancel(mc_ctx* ctx, uint64_t request_id)
 //
 // Snapshot layout (native byte order):
 //   SnapHeader | GridSpec (grids only) | mc_function[n] | SnapFn[n] | mc_result[n] | Partial[n_partials]
+//   | uint32 n_sources, uint32 0 | per run-time family used: {uint32 id, uint32 0, uint64 length,
+//     source text padded with zeros to a multiple of 8 bytes}
 // partials: for each function in index order that has not finished, the
 // partials of its tiles 0 .. next_tile.  A grid stays a grid (its records are
 // packed on the device, which in FP32 need not match the host's packing bit
-// for bit); its functions are listed too, and checked against the spec.
+// for bit); its functions are listed too, and checked against the spec.  The
+// sources of the run-time families the request uses let a restoring context
+// find its own ids for them (it must have registered the same sources).
+// Version 1 (no sources section) is read as well.
 
 }  // extern "C"
 
@@ -2757,7 +2762,7 @@ constexpr char kSnapMagic[8] = {'Z', 'M', 'C', 'S', 'N', 'A', 'P', '1'};
 
 struct SnapHeader {
     char magic[8];
-    uint32_t version;         // 1
+    uint32_t version;         // 2 (1: no sources section)
     uint32_t header_bytes;    // sizeof(SnapHeader)
     uint64_t total_bytes;
     uint64_t n;               // functions
@@ -2784,6 +2789,27 @@ uint64_t snapshot_bytes(uint64_t n, uint64_t n_partials, bool grid)
            n * (sizeof(mc_function) + sizeof(SnapFn) + sizeof(mc_result)) + n_partials * sizeof(Partial);
 }
 
+// The run-time families request r uses, in increasing id order.
+std::vector<uint32_t> user_families_of(const Request* r)
+{
+    std::vector<uint32_t> ids;
+    auto add = [&ids](uint32_t fam) {
+        if (fam >= kUserFamily0 && std::find(ids.begin(), ids.end(), fam) == ids.end()) ids.push_back(fam);
+    };
+    if (r->grid) add(r->spec.base.family);
+    else
+        for (const mc_function& f : r->fns) add(f.family);
+    std::sort(ids.begin(), ids.end());
+    return ids;
+}
+
+uint64_t sources_bytes(const mc_ctx* ctx, const std::vector<uint32_t>& ids)
+{
+    uint64_t b = 8;
+    for (uint32_t id : ids) b += 16 + (ctx->user_src[id - kUserFamily0].size() + 7) / 8 * 8;
+    return b;
+}
+
 }  // namespace
 
 extern "C" {
@@ -2796,14 +2822,7 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
         return fail(ctx, MC_ERR_UNKNOWN_REQUEST, "request %llu unknown or already taken", (unsigned long long)request_id);
     Request* r = it->second.get();
     const uint64_t n = r->count();
-    if (r->at(0).family >= kUserFamily0)
-        return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
-                    (unsigned long long)request_id);
-    if (!r->grid)
-        for (uint64_t i = 0; i < n; ++i)
-            if (r->fns[i].family >= kUserFamily0)
-                return fail(ctx, MC_ERR_INVALID_ARG, "request %llu uses a run-time family (not part of a snapshot)",
-                            (unsigned long long)request_id);
+    const std::vector<uint32_t> fams = user_families_of(r);
     std::vector<Partial> range;
     // each function's tiles run (resident: its open run's first tile still in
     // the ring)
@@ -2857,7 +2876,7 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
             ran[i] = std::min(ran[i], fs.n_tiles - 1);  // (a run whose result is not in has a tile left)
             n_partials += ran[i];
         }
-        const uint64_t total = snapshot_bytes(n, n_partials, r->grid);
+        const uint64_t total = snapshot_bytes(n, n_partials, r->grid) + sources_bytes(ctx, fams);
         *bytes = (size_t)total;
         if (!buf) return MC_OK;
         if (cap < total)
@@ -2879,7 +2898,7 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
         uint8_t* p = (uint8_t*)buf;
         SnapHeader h{};
         std::memcpy(h.magic, kSnapMagic, sizeof h.magic);
-        h.version = 1;
+        h.version = 2;
         h.header_bytes = sizeof h;
         h.total_bytes = total;
         h.n = n;
@@ -2918,6 +2937,21 @@ mc_status mc_snapshot(mc_ctx* ctx, uint64_t request_id, void* buf, size_t cap, s
             }
             off += fs.n_tiles;
         }
+        const uint32_t head[2] = {(uint32_t)fams.size(), 0u};
+        std::memcpy(p, head, sizeof head);
+        p += sizeof head;
+        for (uint32_t id : fams) {
+            const std::string& text = ctx->user_src[id - kUserFamily0];
+            const uint32_t idw[2] = {id, 0u};
+            const uint64_t len = text.size();
+            std::memcpy(p, idw, sizeof idw);
+            std::memcpy(p + 8, &len, sizeof len);
+            p += 16;
+            const uint64_t padded = (len + 7) / 8 * 8;
+            std::memset(p, 0, padded);
+            std::memcpy(p, text.data(), len);
+            p += padded;
+        }
     } catch (const HipError& e) {
         return fail_hip(ctx, e);
     }
@@ -2931,7 +2965,8 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
     SnapHeader h;
     if (bytes < sizeof h) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot of %zu bytes is truncated", bytes);
     std::memcpy(&h, buf, sizeof h);
-    if (std::memcmp(h.magic, kSnapMagic, sizeof h.magic) != 0 || h.version != 1 || h.header_bytes != sizeof h)
+    if (std::memcmp(h.magic, kSnapMagic, sizeof h.magic) != 0 || (h.version != 1 && h.version != 2) ||
+        h.header_bytes != sizeof h)
         return fail(ctx, MC_ERR_INVALID_ARG, "not a snapshot of this library version");
     if (h.seg_samples != (uint32_t)kSegSamples || h.block_waves != (uint32_t)kBlockWaves)
         return fail(ctx, MC_ERR_INVALID_ARG, "snapshot made with another tiling (%u samples per segment, %u waves)",
@@ -2940,9 +2975,57 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
         return fail(ctx, h.n == 0 ? MC_ERR_INVALID_ARG : MC_ERR_ADMISSION,
                     "snapshot of %llu functions; the context has %u function slots", (unsigned long long)h.n,
                     ctx->max_functions);
-    if (h.grid > 1u || h.n_partials > ctx->max_partials || h.total_bytes != bytes ||
-        snapshot_bytes(h.n, h.n_partials, h.grid != 0u) != bytes)
+    const uint64_t body = h.grid > 1u || h.n > (1ull << 32) || h.n_partials > (1ull << 40)
+                              ? UINT64_MAX
+                              : snapshot_bytes(h.n, h.n_partials, h.grid != 0u);
+    if (h.grid > 1u || h.n_partials > ctx->max_partials || h.total_bytes != bytes || body > bytes ||
+        (h.version == 1 && body != bytes))
         return fail(ctx, MC_ERR_INVALID_ARG, "snapshot size %zu does not match its contents", bytes);
+    // run-time families: the snapshot's ids mapped to this context's, by source text
+    std::vector<std::pair<uint32_t, uint32_t>> fam_map;
+    if (h.version == 2) {
+        const uint8_t* q = (const uint8_t*)buf + body;
+        const uint8_t* end = (const uint8_t*)buf + bytes;
+        uint32_t head[2];
+        if (end - q < 8) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot size %zu does not match its contents", bytes);
+        std::memcpy(head, q, sizeof head);
+        q += 8;
+        if (head[0] > (uint32_t)kMaxUserFamilies)
+            return fail(ctx, MC_ERR_INVALID_ARG, "snapshot lists %u run-time families", head[0]);
+        for (uint32_t k = 0; k < head[0]; ++k) {
+            uint32_t idw[2];
+            uint64_t len = 0;
+            if (end - q < 16) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot's family sources are truncated");
+            std::memcpy(idw, q, sizeof idw);
+            std::memcpy(&len, q + 8, sizeof len);
+            q += 16;
+            const uint64_t padded = (len + 7) / 8 * 8;
+            if (len > (uint64_t)(end - q) || padded > (uint64_t)(end - q))
+                return fail(ctx, MC_ERR_INVALID_ARG, "snapshot's family sources are truncated");
+            const std::string text((const char*)q, (size_t)len);
+            q += padded;
+            size_t found = ctx->user_src.size();
+            for (size_t u = 0; u < ctx->user_src.size(); ++u)
+                if (ctx->user_src[u] == text) found = u;
+            if (found == ctx->user_src.size())
+                return fail(ctx, MC_ERR_UNSUPPORTED_FAMILY,
+                            "the snapshot's run-time family %u is not registered on this context (register the "
+                            "same source first)",
+                            idw[0]);
+            fam_map.emplace_back(idw[0], kUserFamily0 + (uint32_t)found);
+        }
+        if (q != end) return fail(ctx, MC_ERR_INVALID_ARG, "snapshot size %zu does not match its contents", bytes);
+    }
+    // (false: a run-time family the snapshot holds no source for)
+    auto remap = [&fam_map](uint32_t* fam) {
+        if (*fam < kUserFamily0) return true;
+        for (const auto& m : fam_map)
+            if (m.first == *fam) {
+                *fam = m.second;
+                return true;
+            }
+        return false;
+    };
     if (h.precision != MC_PREC_FP32_EVAL && h.precision != MC_PREC_FP64)
         return fail(ctx, MC_ERR_INVALID_ARG, "snapshot precision %d", h.precision);
     const uint8_t* p = (const uint8_t*)buf + sizeof h;
@@ -2955,13 +3038,18 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
         std::memcpy(&r->spec, p, sizeof r->spec);
         p += sizeof r->spec;
         if (r->spec.n != n || r->spec.n_axes < 1 || r->spec.n_axes > (uint32_t)MC_MAX_GRID_AXES ||
-            (r->spec.precision != MC_PREC_FP32_EVAL && r->spec.precision != MC_PREC_FP64))
+            (r->spec.precision != MC_PREC_FP32_EVAL && r->spec.precision != MC_PREC_FP64) ||
+            !remap(&r->spec.base.family))
             return fail(ctx, MC_ERR_INVALID_ARG, "snapshot's grid does not match its functions");
         r->grid = true;
     }
     r->fns.resize(n);
     std::memcpy(r->fns.data(), p, n * sizeof(mc_function));
     p += n * sizeof(mc_function);
+    for (uint64_t i = 0; i < n; ++i)
+        if (!remap(&r->fns[i].family))
+            return fail(ctx, MC_ERR_INVALID_ARG, "function %llu: run-time family %u without its source",
+                        (unsigned long long)i, r->fns[i].family);
     if (r->grid) {
         for (uint64_t i = 0; i < n; ++i) {
             mc_function g;
@@ -2983,9 +3071,7 @@ mc_status mc_restore(mc_ctx* ctx, const void* buf, size_t bytes, uint64_t* out_r
     for (uint64_t i = 0; i < n; ++i) {
         const mc_function& f = r->fns[i];
         std::string why;
-        if (f.family >= kUserFamily0) return fail(ctx, MC_ERR_INVALID_ARG, "function %llu: run-time family",
-                                                  (unsigned long long)i);
-        const mc_status st = validate_one(f, 0, &why);
+        const mc_status st = validate_one(f, ctx->n_user, &why);
         if (st != MC_OK) return fail(ctx, st, "function %llu: %s", (unsigned long long)i, why.c_str());
         const uint32_t n_segments = (uint32_t)(((f.n_samples + 3) / 4 + kSegQuads - 1) / kSegQuads);
         const SnapFn& s = sf[i];

@@ -102,14 +102,18 @@ def test_snapshot_restore_bitwise(tmp_path):
         _same(np.load(p + ".npy"), ref[k], f"request {k} (other process)")
 
 
+GRID_SPEC_BYTES = 584  # the parameter grid's description in a snapshot (sizeof(GridSpec))
+
+
 def _partly_run(blob):
     """Functions of a snapshot that had run some but not all of their tiles."""
-    n, n_partials = np.frombuffer(blob, dtype="<u8", count=2, offset=24)
+    n, n_partials = (int(x) for x in np.frombuffer(blob, dtype="<u8", count=2, offset=24))
     grid = int(np.frombuffer(blob, dtype="<u4", count=1, offset=52)[0])
     fn_bytes = W.FUNC_DTYPE.itemsize
-    per_fn = fn_bytes + 16 + 48
-    spec = len(blob) - 64 - int(n) * per_fn - int(n_partials) * 16 if grid else 0
-    sf = np.frombuffer(blob, dtype="<u4", count=4 * int(n), offset=64 + spec + int(n) * fn_bytes).reshape(-1, 4)
+    spec = GRID_SPEC_BYTES if grid else 0
+    # (header, grid, functions, progress, results, partials, then the family sources: 8 bytes without any)
+    assert len(blob) == 64 + spec + n * (fn_bytes + 16 + 48) + n_partials * 16 + 8
+    sf = np.frombuffer(blob, dtype="<u4", count=4 * n, offset=64 + spec + n * fn_bytes).reshape(-1, 4)
     return int(np.count_nonzero((sf[:, 2] > 0) & (sf[:, 2] < sf[:, 1])))
 
 

@@ -116,6 +116,30 @@ def test_user_families_on_a_resident_context(setup):
         assert np.array_equal(got64[k], ref64[k]), ("fp64", k)
 
 
+def test_user_family_snapshot_resumes_under_other_ids(setup):
+    """A request that uses both caller families, snapshotted part way through in
+    a launch context, resumes in a resident context that registered the same
+    sources in the other order (the snapshot carries the sources; the request
+    takes the resident context's ids): results bit for bit as uninterrupted."""
+    import paper_2104_10073_amd as Z
+    c, t, _, _ = setup
+    ref = c.integrate(t, Z.PREC_FP32)
+    with Z.Context(device=0, max_tiles_per_run=16) as a:
+        a.register_family(U.QUAD_SINE_SRC)
+        a.register_family(U.RATIONAL_SRC)
+        rid = a.submit(t, Z.PREC_FP32)
+        for _ in range(3):
+            a.run()
+        blob = a.snapshot(rid)
+        assert a.pending()[1] > 0, "nothing left to resume"
+    with Z.Context(device=0, flags=Z.MC_RESIDENT) as b:
+        assert b.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0
+        assert b.register_family(U.QUAD_SINE_SRC) == Z.MC_FAMILY_USER0 + 1
+        got = b.results(b.restore(blob), len(t))
+    for k in ("mean", "std_error", "sum_f", "sum_f2", "n", "status", "precision"):
+        assert np.array_equal(got[k], ref[k]), k
+
+
 def test_plain_path_rejects_user_family(setup):
     import paper_2104_10073_amd as Z
     c, t, _, _ = setup

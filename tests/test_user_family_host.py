@@ -71,3 +71,25 @@ def test_resident_context_compiles_its_kernel_with_the_family():
             c.submit(t, Z.PREC_FP32)
         assert c.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0
         c.submit(np.concatenate([t, W.mixed_batch(4, gen_seed=5)]), Z.PREC_FP32)
+
+
+def test_snapshot_carries_family_sources():
+    """A snapshot of a request that uses a run-time family holds the family's
+    source; it restores into a context that registered the same source, under
+    that context's id, and nowhere else."""
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY) as a:
+        a.register_family(U.QUAD_SINE_SRC)
+        fb = a.register_family(U.RATIONAL_SRC)
+        assert fb == Z.MC_FAMILY_USER0 + 1
+        t = np.concatenate([U.user_table(3, fb, 2), W.mixed_batch(3, gen_seed=4)])
+        blob = a.snapshot(a.submit(t, Z.PREC_FP32))
+    assert U.RATIONAL_SRC.encode() in blob and U.QUAD_SINE_SRC.encode() not in blob
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY) as c:
+        with pytest.raises(Z.McError) as e:
+            c.restore(blob)
+        assert e.value.status == -2  # MC_ERR_UNSUPPORTED_FAMILY: not registered here
+    with Z.Context(flags=Z.MC_VALIDATE_ONLY) as b:
+        assert b.register_family(U.RATIONAL_SRC) == Z.MC_FAMILY_USER0
+        blob2 = b.snapshot(b.restore(blob))
+    fams = np.frombuffer(blob2, dtype=W.FUNC_DTYPE, count=len(t), offset=64)["family"]
+    assert list(fams) == [Z.MC_FAMILY_USER0] * 3 + list(t["family"][3:])
