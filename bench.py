@@ -477,10 +477,19 @@ def other_configs(Z, W, stream, keep=None):
         for name, table in (("mixed_2000_dims1to7", W.mixed_batch(2000)),
                             ("highdim_500x1e7_dims8to12", W.high_dim_batch(500))):
             ev = W.total_evals(table)
+            # warm-up: the engine clock climbs over the first runs after the GPU has
+            # been idle (the mixed batch's FP32 kernel: 4.6, 4.3, 4.1, 4.0 ms)
+            for _ in range(3):
+                ctx.integrate(table, Z.PREC_FP32, stream=stream)
+            torch.cuda.synchronize()
+            # kernel times and counts of the timed run only
             st0 = ctx.stats()
-            r32, t = timed(lambda: ctx.integrate(table, Z.PREC_FP32, stream=stream))
+            t0 = time.perf_counter()
+            r32 = ctx.integrate(table, Z.PREC_FP32, stream=stream)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
             st1 = ctx.stats()
-            half = {k: (st1[k] - st0[k]) / 2 for k in ("fp32_ms", "fp64_ms", "finalize_ms", "promoted", "launches")}
+            runk = {k: st1[k] - st0[k] for k in ("fp32_ms", "fp64_ms", "finalize_ms", "promoted", "launches")}
             r64 = ctx.integrate(table, Z.PREC_FP64, stream=stream)
             if keep is not None:
                 keep[name] = (table, r32, r64)
@@ -489,10 +498,10 @@ def other_configs(Z, W, stream, keep=None):
             err = np.abs(r32["mean"] - r64["mean"]) / np.maximum(r64["std_error"], 1e-300)
             near_zero = np.abs(r64["mean"]) < 1e-4
             out[name] = {"evals": ev, "wall_ms": t * 1e3, "evals_per_s": ev / t,
-                         "kernel_ms": half["fp32_ms"] + half["fp64_ms"] + half["finalize_ms"],
-                         "fp32_kernel_ms": half["fp32_ms"],
-                         "fp32_kernel_valu_frac": algorithmic_slots(table) / (half["fp32_ms"] * 1e-3) / VALU_SLOT_PEAK,
-                         "promoted_to_fp64_per_run": half["promoted"], "launches_per_run": half["launches"],
+                         "kernel_ms": runk["fp32_ms"] + runk["fp64_ms"] + runk["finalize_ms"],
+                         "fp32_kernel_ms": runk["fp32_ms"],
+                         "fp32_kernel_valu_frac": algorithmic_slots(table) / (runk["fp32_ms"] * 1e-3) / VALU_SLOT_PEAK,
+                         "promoted_to_fp64_per_run": runk["promoted"], "launches_per_run": runk["launches"],
                          "fp32_vs_fp64_max_dF_over_SE": float(err.max()),
                          "fp32_vs_fp64_median_dF_over_SE": float(np.median(err)),
                          "near_zero_functions": int(near_zero.sum()),
