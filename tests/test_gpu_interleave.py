@@ -1,10 +1,11 @@
-"""Checkpoint and resume interleaved with running work, on an MI355X, in both
-engines: a seeded script submits requests (tables and grids, FP32 and FP64),
-runs, polls, snapshots requests while their work is on the GPU, restores the
-snapshots into the same context and into a context of the other engine while
-that one runs other requests, and takes results as they complete.  Whatever
-the timing, every request and every restored copy must come back with the
-results of an uninterrupted run bit for bit."""
+"""Checkpoint, resume and cancellation interleaved with running work, on an
+MI355X, in both engines: a seeded script submits requests (tables and grids,
+FP32 and FP64), runs, polls, snapshots requests while their work is on the GPU,
+restores the snapshots into the same context and into a context of the other
+engine while that one runs other requests, cancels some requests, and takes
+results as they complete.  Whatever the timing, every request and every
+restored copy must come back with the results of an uninterrupted run bit for
+bit, and every cancelled one with exactly the results that were in."""
 
 import numpy as np
 import pytest
@@ -41,6 +42,14 @@ def _same(a, b, label):
         assert np.array_equal(a[f], b[f]), (label, f)
 
 
+def _kept(a, b, label):
+    """A cancelled request: the results that came in equal the reference, the rest are aborted."""
+    kept = a["status"] == 0
+    assert np.all(a["status"][~kept] == -10), label  # MC_ERR_ABORTED
+    for f in FIELDS:
+        assert np.array_equal(a[f][kept], b[f][kept]), (label, f)
+
+
 @pytest.mark.parametrize("first", ["launch", "resident"])
 def test_snapshots_interleaved_with_running_work(first):
     import paper_2104_10073_amd as Z
@@ -53,16 +62,17 @@ def test_snapshots_interleaved_with_running_work(first):
     with Z.Context(device=0, flags=flags[first], max_tiles_per_run=48) as a, \
             Z.Context(device=0, flags=flags[other], max_tiles_per_run=96) as b:
         live = {}      # (context, request id) -> job index
+        cancelled = set()
         checked = 0
         order = list(rng.permutation(len(jobs)))
-        for step in range(120):
-            op = rng.integers(0, 6)
+        for step in range(160):
+            op = rng.integers(0, 7)
             if op == 0 and order:
                 k = int(order.pop())
                 live[(a, _submit(a, jobs[k]))] = k
-            elif op == 1 and live:
+            elif op == 1 and set(live) - cancelled:
                 # snapshot a request while its work runs; resume the copy in one of the contexts
-                keys = list(live)
+                keys = [key for key in live if key not in cancelled]
                 ctx, rid = keys[int(rng.integers(0, len(keys)))]
                 blob = ctx.snapshot(rid)
                 dst = a if rng.random() < 0.5 else b
@@ -74,15 +84,22 @@ def test_snapshots_interleaved_with_running_work(first):
                 for ctx in (a, b):
                     for rid in ctx.poll():
                         k = live.pop((ctx, rid))
-                        _same(ctx.results(rid, jobs[k][3]), ref[k], f"step {step}: job {k}")
+                        got = ctx.results(rid, jobs[k][3], allow_aborted=True)
+                        (_kept if (ctx, rid) in cancelled else _same)(got, ref[k], f"step {step}: job {k}")
                         checked += 1
+            elif op == 5 and len(set(live) - cancelled) > 2 and rng.random() < 0.5:
+                keys = [key for key in live if key not in cancelled]
+                ctx, rid = keys[int(rng.integers(0, len(keys)))]
+                ctx.cancel(rid)
+                cancelled.add((ctx, rid))
             else:
                 a.run()
         for (ctx, rid), k in list(live.items()):
-            _same(ctx.results(rid, jobs[k][3]), ref[k], f"end: job {k}")
+            got = ctx.results(rid, jobs[k][3], allow_aborted=True)
+            (_kept if (ctx, rid) in cancelled else _same)(got, ref[k], f"end: job {k}")
             checked += 1
         for k in order:
             _same(a.results(_submit(a, jobs[k]), jobs[k][3]), ref[k], f"late: job {k}")
             checked += 1
-    print(f"{checked} requests checked", flush=True)
+    print(f"{checked} requests checked, {len(cancelled)} of them cancelled", flush=True)
     assert checked >= len(jobs)
