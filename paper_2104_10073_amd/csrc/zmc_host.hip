@@ -1937,20 +1937,27 @@ void res_upload_restored(mc_ctx* ctx)
 }
 
 // mc_cancel of an admitted request in a resident context (its work already
-// dropped).  With runs of it open, the launch is stopped (it runs every entry
-// below its count, then leaves) and the results that came in are collected
-// (and dropped); the request's entries it did not read (only after an idle
-// stop) are taken out of the ring, the others keeping their order, while no
-// kernel runs; its open runs give back their arena positions and have their
-// slots' tile counters cleared.  Then it completes as aborted.  If clearing
-// the counters fails, it completes all the same but keeps its slots (their
-// counters are unknown), and the error is passed on.
+// dropped).  Its slots go back to the pool, and every slot of the pool must
+// hold a tile count of zero: a slot's counter is non-zero while a run in it is
+// open, and, for a restored request whose saved counts were copied to the
+// device, from that copy until the function's run finalizes.  In either case
+// the launch is stopped (it runs every entry below its count, then leaves) and
+// the results that came in are collected (and dropped); the request's entries
+// it did not read (only after an idle stop) are taken out of the ring, the
+// others keeping their order, while no kernel runs; its open runs give back
+// their arena positions, and its slots' tile counters are cleared.  Then it
+// completes as aborted.  If clearing the counters fails, it completes all the
+// same but keeps its slots (their counters are unknown), and the error is
+// passed on.
 void res_cancel(mc_ctx* ctx, Request* r)
 {
     ResidentState& R = ctx->res;
     bool open = false;
     for (const ResRun& run : R.runs) open = open || run.req == r;
-    if (open) {
+    bool counted = false;  // saved counts on the device of functions without their result
+    if (!r->partials_pending)
+        for (size_t i = 0; i < r->staged_counts.size(); ++i) counted = counted || (r->staged_counts[i] && !r->st[i].done);
+    if (open || counted) {
         res_request_stop(ctx);
         res_wait_exit(ctx);
         res_reap(ctx);
@@ -1978,7 +1985,7 @@ void res_cancel(mc_ctx* ctx, Request* r)
             runs_left = true;
         }
         R.runs.resize(k);
-        if (runs_left) {
+        if (runs_left || counted) {
             try {
                 HIP_TRY(hipMemsetAsync(R.d_tiles_done + r->slot_base, 0, r->count() * sizeof(uint32_t), R.stream));
                 HIP_TRY(hipStreamSynchronize(R.stream));

@@ -128,13 +128,16 @@ mc_ctx* create(uint32_t flags, uint32_t max_tiles = 0, uint32_t policy = MC_SCHE
 
 // Results of a request that was aborted or cancelled: those that came in are exact,
 // the others carry MC_ERR_ABORTED.
-bool check_cancelled(const std::vector<mc_function>& t, const std::vector<mc_result>& r, const char* label)
+bool check_cancelled(const std::vector<mc_function>& t, const std::vector<mc_result>& r, const char* label,
+                     bool fp64 = false)
 {
     for (size_t i = 0; i < t.size(); ++i) {
         if (r[i].status == MC_OK) {
-            const bool promoted = (t[i].seed >> 63) != 0;
-            CHECK(same_result(r[i], hipemu::expected_batched(t[i], promoted)), "%s: function %zu kept a wrong result",
-                  label, i);
+            const bool promoted = !fp64 && (t[i].seed >> 63) != 0;
+            const mc_result want = hipemu::expected_batched(t[i], fp64 || promoted);
+            CHECK(same_result(r[i], want), "%s: function %zu kept a wrong result: got (%.17g, n %llu, prec %u) want "
+                  "(%.17g, n %llu, prec %u)", label, i, r[i].mean, (unsigned long long)r[i].n, r[i].precision,
+                  want.mean, (unsigned long long)want.n, want.precision);
         } else {
             CHECK(r[i].status == MC_ERR_ABORTED && r[i].n == t[i].n_samples, "%s: function %zu: status %d", label, i,
                   r[i].status);
@@ -1012,6 +1015,139 @@ bool cancel_requests()
     return true;
 }
 
+// Snapshots, restores and cancels interleaved with running work in a launch
+// and a resident context (the emulated resident kernel runs in worker threads,
+// so the interleavings vary from run to run), by seeded scripts: every request
+// and every restored copy comes back exact, every cancelled one with exactly
+// the results that were in.  Run under the address sanitizer, a request used
+// after it was released would stop the run.
+bool interleave_one(uint32_t seed, bool resident_first)
+{
+    std::vector<std::vector<mc_function>> jobs;
+    std::vector<bool> fp64;
+    for (uint32_t k = 0; k < 8; ++k) {
+        jobs.push_back(mixed_table(4 + (k * 7 + seed) % 23, 300 + seed * 16 + k, k % 3 == 1 ? 4 : 0));
+        fp64.push_back(k % 4 == 3);
+    }
+    uint64_t state = 0x9E3779B97F4A7C15ull ^ (uint64_t)seed * 0xBF58476D1CE4E5B9ull;
+    auto next = [&state](uint32_t n) {
+        state ^= state << 13;
+        state ^= state >> 7;
+        state ^= state << 17;
+        return (uint32_t)(state % n);
+    };
+    mc_ctx* a = create(resident_first ? MC_RESIDENT : MC_NO_GRAPH, 5, MC_SCHED_FAIR, 128, 1 << 15);
+    mc_ctx* b = create(resident_first ? MC_NO_GRAPH : MC_RESIDENT, 9, MC_SCHED_SRPT, 128, 1 << 15);
+    CHECK(a && b, "create");
+    struct Live {
+        mc_ctx* ctx;
+        uint64_t id;
+        uint32_t job;
+        bool cancelled;
+        std::string how;
+    };
+    std::vector<Live> live;
+    std::vector<uint32_t> order;
+    for (uint32_t k = 0; k < jobs.size(); ++k) order.push_back(k);
+    auto check = [&](const Live& l, int blocking) -> int {
+        std::vector<mc_result> r(jobs[l.job].size());
+        const mc_status st = mc_results(l.ctx, l.id, r.data(), r.size(), blocking);
+        if (st == MC_NOT_READY) return 0;
+        if (l.cancelled) {
+            CHECK(st == MC_OK || st == MC_ERR_ABORTED, "seed %u: cancelled job %u: status %d", seed, l.job, (int)st);
+            if (!check_cancelled(jobs[l.job], r, "interleave (cancelled)", fp64[l.job])) return -1;
+        } else {
+            CHECK(st == MC_OK, "seed %u: job %u: status %d: %s", seed, l.job, (int)st, mc_last_error(l.ctx));
+            if (!check_results(jobs[l.job], r, fp64[l.job], "interleave")) {
+                std::fprintf(stderr, "request %llu in the %s context, job %u: %s\n", (unsigned long long)l.id,
+                             (l.ctx == a) == resident_first ? "resident" : "launch", l.job, l.how.c_str());
+                return -1;
+            }
+        }
+        return 1;
+    };
+    const bool trace = std::getenv("EMU_TRACE") != nullptr;
+    for (int step = 0; step < 120; ++step) {
+        const uint32_t op = next(7);
+        if (trace) {
+            std::fprintf(stderr, "seed %u %s step %d op %u live %zu\n", seed, resident_first ? "res" : "launch", step, op,
+                         live.size());
+            std::fflush(stderr);
+        }
+        if (op == 0 && !order.empty()) {
+            const uint32_t k = order[next((uint32_t)order.size())];
+            order.erase(std::find(order.begin(), order.end(), k));
+            uint64_t id = 0;
+            CHECK(mc_submit(a, jobs[k].data(), jobs[k].size(), fp64[k] ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id) == MC_OK,
+                  "submit: %s", mc_last_error(a));
+            live.push_back(Live{a, id, k, false, "submitted at step " + std::to_string(step)});
+        } else if (op == 1) {
+            std::vector<size_t> cand;
+            for (size_t i = 0; i < live.size(); ++i)
+                if (!live[i].cancelled) cand.push_back(i);
+            if (cand.empty()) continue;
+            const Live src = live[cand[next((uint32_t)cand.size())]];
+            const std::vector<uint8_t> blob = take_snapshot(src.ctx, src.id);
+            CHECK(!blob.empty(), "seed %u: snapshot: %s", seed, mc_last_error(src.ctx));
+            mc_ctx* dst = next(2) ? a : b;
+            uint64_t id = 0;
+            CHECK(mc_restore(dst, blob.data(), blob.size(), &id) == MC_OK, "restore: %s", mc_last_error(dst));
+            live.push_back(Live{dst, id, src.job, false,
+                                "restored at step " + std::to_string(step) + " from request " + std::to_string(src.id) +
+                                    " (" + src.how + ")"});
+        } else if (op == 2) {
+            CHECK(mc_run(a, nullptr) != MC_ERR_HIP && mc_run(b, nullptr) != MC_ERR_HIP, "run");
+        } else if (op == 3) {
+            for (mc_ctx* c : {a, b}) {
+                uint64_t got[64];
+                size_t n = 0;
+                CHECK(mc_poll(c, got, 64, &n) == MC_OK, "poll");
+                for (size_t j = 0; j < n; ++j) {
+                    auto it = std::find_if(live.begin(), live.end(),
+                                           [&](const Live& l) { return l.ctx == c && l.id == got[j]; });
+                    CHECK(it != live.end(), "seed %u: polled id %llu unknown", seed, (unsigned long long)got[j]);
+                    const int rc = check(*it, 0);
+                    CHECK(rc == 1, "seed %u: a polled request is not ready (%d)", seed, rc);
+                    live.erase(it);
+                }
+            }
+        } else if (op == 5) {
+            std::vector<size_t> cand;
+            for (size_t i = 0; i < live.size(); ++i)
+                if (!live[i].cancelled) cand.push_back(i);
+            if (cand.size() <= 2) continue;
+            Live& l = live[cand[next((uint32_t)cand.size())]];
+            CHECK(mc_cancel(l.ctx, l.id) == MC_OK, "seed %u: cancel: %s", seed, mc_last_error(l.ctx));
+            l.cancelled = true;
+        } else {
+            CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
+        }
+    }
+    for (const Live& l : live) {
+        if (trace) {
+            std::fprintf(stderr, "end: waiting for request %llu in the %s context, job %u, %s%s\n",
+                         (unsigned long long)l.id, (l.ctx == a) == resident_first ? "resident" : "launch", l.job,
+                         l.how.c_str(), l.cancelled ? ", cancelled" : "");
+            std::fflush(stderr);
+        }
+        CHECK(check(l, 1) == 1, "seed %u: results at the end", seed);
+    }
+    mc_destroy(a);
+    mc_destroy(b);
+    return true;
+}
+
+bool interleave()
+{
+    for (uint32_t seed = 1; seed <= 24; ++seed)
+        for (bool resident_first : {false, true})
+            if (!interleave_one(seed, resident_first)) {
+                std::fprintf(stderr, "interleave: seed %u, %s first\n", seed, resident_first ? "resident" : "launch");
+                return false;
+            }
+    return true;
+}
+
 // The packing's own hypot and atan2 (built from correctly rounded operations so
 // that host and device pack the same bits) against libm: within a few units in
 // the last place, over magnitudes 10^-6..10^6, zeros, equal and opposite values.
@@ -1108,7 +1244,7 @@ int main(int argc, char** argv)
         {"autotune_cache", autotune_cache}, {"resident_basic", resident_basic},
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
         {"resident_abort", resident_abort}, {"log_levels", log_levels}, {"snapshot", snapshot_restore},
-        {"pack_math", pack_math}, {"cancel", cancel_requests},
+        {"pack_math", pack_math}, {"cancel", cancel_requests}, {"interleave", interleave},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {
