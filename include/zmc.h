@@ -268,9 +268,11 @@ mc_status mc_pending(mc_ctx* ctx, uint64_t* requests, uint64_t* tiles);
 mc_status mc_results(mc_ctx* ctx, uint64_t request_id, mc_result* out, size_t n, int blocking);
 
 /* Ask running persistent kernels to stop fetching tiles.  Every request submitted
- * before the call completes with status MC_ERR_ABORTED on its unfinished functions
- * (mc_results returns MC_ERR_ABORTED); the next mc_run waits for the launches in
- * flight, then clears the request so later work runs normally. */
+ * (or restored) before the call completes with status MC_ERR_ABORTED on its
+ * unfinished functions (mc_results returns MC_ERR_ABORTED); the next mc_run waits
+ * for the launches in flight, then clears the request so later work runs
+ * normally.  Requests submitted after the call, also before that mc_run, are not
+ * affected. */
 mc_status mc_abort(mc_ctx* ctx);
 
 /* Cancel one request (a serving loop whose client went away): none of its

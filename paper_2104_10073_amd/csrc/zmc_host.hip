@@ -554,6 +554,7 @@ struct mc_ctx {
     std::vector<EvSet*> ev_free;
     std::deque<EvSet*> ev_pending;     // recorded sets, oldest first
     bool abort_requested = false;
+    uint64_t abort_below = 0;          // the abort covers the requests with smaller ids
 
     RangeAlloc fn_alloc, part_alloc;
 
@@ -1543,16 +1544,29 @@ bool launch(mc_ctx* ctx, hipStream_t stream, bool* no_slot)
     return true;
 }
 
+// Requests of a queue submitted before the abort call are taken out and
+// collected in `out`; later ones stay (none of their work has been launched:
+// the abort is carried out before anything else in the next step).
+void take_aborted(mc_ctx* ctx, std::deque<Request*>& q, std::vector<Request*>& out)
+{
+    std::deque<Request*> keep;
+    for (Request* r : q) {
+        if (r->id < ctx->abort_below) out.push_back(r);
+        else keep.push_back(r);
+    }
+    q.swap(keep);
+}
+
 // After mc_abort: let the launches in flight drain (their kernels stop at the
-// next tile fetch), complete every request that was queued with status
+// next tile fetch), complete every request queued before the call with status
 // MC_ERR_ABORTED, then clear the abort word so later work runs normally.
 void finish_abort(mc_ctx* ctx)
 {
     reap(ctx, 2);
-    for (Request* r : ctx->active) complete_aborted(ctx, r);
-    for (Request* r : ctx->pending) complete_aborted(ctx, r);
-    ctx->active.clear();
-    ctx->pending.clear();
+    std::vector<Request*> cancel;
+    take_aborted(ctx, ctx->active, cancel);
+    take_aborted(ctx, ctx->pending, cancel);
+    for (Request* r : cancel) complete_aborted(ctx, r);
     HIP_TRY(hipMemcpyAsync(ctx->d_abort_word, &ctx->h_words[0], sizeof(uint32_t), hipMemcpyHostToDevice,
                            ctx->upload_stream));
     HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
@@ -1881,8 +1895,10 @@ void res_fail(mc_ctx* ctx)
 
 // After mc_abort on a resident context: the launch has been asked to stop;
 // once it has gone, results that came in complete normally, every other
-// request completes as aborted, the unread entries are dropped and the slot
-// counters the cancelled runs leave behind are cleared.
+// request submitted before the call completes as aborted, the unread entries
+// are dropped and the slot counters the cancelled runs leave behind are
+// cleared.  Requests submitted later have nothing in the ring yet (the ring is
+// fed only after the abort is carried out) and stay queued.
 void res_finish_abort(mc_ctx* ctx)
 {
     ResidentState& R = ctx->res;
@@ -1896,14 +1912,13 @@ void res_finish_abort(mc_ctx* ctx)
         cancel.push_back(run.req);
     }
     R.runs.clear();
-    for (Request* r : ctx->active) cancel.push_back(r);
-    for (Request* r : ctx->pending) cancel.push_back(r);
-    ctx->active.clear();
-    ctx->pending.clear();
+    take_aborted(ctx, ctx->active, cancel);
+    take_aborted(ctx, ctx->pending, cancel);
     for (Request* r : cancel)
         if (r->fns_done < r->count()) complete_aborted(ctx, r);  // (a request can be listed twice)
     res_drop_unread(R);
     R.tiles_waiting = 0;
+    for (Request* r : ctx->active) R.tiles_waiting += r->tiles_total - r->tiles_launched;
     __atomic_store_n(R.ctl, R.pushed, __ATOMIC_RELEASE);
     HIP_TRY(hipMemsetAsync(R.d_tiles_done, 0, (size_t)ctx->max_functions * sizeof(uint32_t), R.stream));
     HIP_TRY(hipStreamSynchronize(R.stream));
@@ -2688,6 +2703,7 @@ mc_status mc_abort(mc_ctx* ctx)
     if (ctx->res.on) {
         res_request_stop(ctx);
         ctx->abort_requested = true;
+        ctx->abort_below = ctx->next_id;
         return MC_OK;
     }
     try {
@@ -2697,6 +2713,7 @@ mc_status mc_abort(mc_ctx* ctx)
                                ctx->upload_stream));
         HIP_TRY(hipStreamSynchronize(ctx->upload_stream));
         ctx->abort_requested = true;
+        ctx->abort_below = ctx->next_id;
     } catch (const HipError& e) {
         return fail_hip(ctx, e);
     }

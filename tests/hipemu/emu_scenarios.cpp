@@ -274,6 +274,9 @@ bool abort_and_continue()
     CHECK(mc_submit(ctx, t.data(), t.size(), MC_PREC_FP32_EVAL, &id) == MC_OK, "submit");
     CHECK(mc_run(ctx, nullptr) == MC_OK, "run");
     CHECK(mc_abort(ctx) == MC_OK, "abort");
+    uint64_t later = 0;  // submitted after the abort call, before the step that carries it out
+    const std::vector<mc_function> t2 = mixed_table(6, 42);
+    CHECK(mc_submit(ctx, t2.data(), t2.size(), MC_PREC_FP32_EVAL, &later) == MC_OK, "submit after the abort");
     std::vector<mc_result> r(t.size());
     CHECK(mc_results(ctx, id, r.data(), r.size(), 1) == MC_ERR_ABORTED, "aborted request");
     size_t ok = 0;
@@ -286,6 +289,9 @@ bool abort_and_continue()
         }
     }
     CHECK(ok < t.size(), "nothing was aborted");
+    std::vector<mc_result> r2(t2.size());
+    CHECK(mc_results(ctx, later, r2.data(), r2.size(), 1) == MC_OK, "submitted after the abort: %s", mc_last_error(ctx));
+    if (!check_results(t2, r2, false, "submitted after the abort")) return false;
     if (!run_request(ctx, mixed_table(8, 41), false, "after abort")) return false;
     mc_destroy(ctx);
     return true;
@@ -730,7 +736,8 @@ bool resident_flush()
 }
 
 // Abort while the ring holds work: results that were in complete normally, the
-// rest come back aborted; the context serves the next request.
+// rest come back aborted; a request submitted after the call, and the next
+// ones, are served normally.
 bool resident_abort()
 {
     mc_ctx* ctx = create(MC_RESIDENT, 2);
@@ -741,12 +748,18 @@ bool resident_abort()
     CHECK(mc_submit(ctx, t.data(), 5, MC_PREC_FP64, &id2) == MC_OK, "submit");
     CHECK(mc_run(ctx, nullptr) == MC_OK, "run");
     CHECK(mc_abort(ctx) == MC_OK, "abort");
+    uint64_t later = 0;
+    const std::vector<mc_function> t3 = mixed_table(7, 123);
+    CHECK(mc_submit(ctx, t3.data(), t3.size(), MC_PREC_FP32_EVAL, &later) == MC_OK, "submit after the abort");
     std::vector<mc_result> r(t.size());
     const mc_status st = mc_results(ctx, id, r.data(), r.size(), 1);
     CHECK(st == MC_ERR_ABORTED, "aborted request: %d", (int)st);
     if (!check_cancelled(t, r, "aborted")) return false;
     std::vector<mc_result> r2(5);
     CHECK(mc_results(ctx, id2, r2.data(), 5, 1) == MC_ERR_ABORTED, "second request aborted");
+    std::vector<mc_result> r3(t3.size());
+    CHECK(mc_results(ctx, later, r3.data(), r3.size(), 1) == MC_OK, "submitted after the abort: %s", mc_last_error(ctx));
+    if (!check_results(t3, r3, false, "submitted after the abort")) return false;
     if (!run_request(ctx, mixed_table(12, 121, 3), false, "after abort")) return false;
     if (!run_request(ctx, mixed_table(12, 122), true, "after abort fp64")) return false;
     mc_destroy(ctx);

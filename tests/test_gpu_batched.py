@@ -144,7 +144,8 @@ def test_admission_while_launches_are_in_flight(graph):
 
 def test_abort_then_recover():
     """Abort while the persistent kernels run (~0.1 s of work): they stop at their next
-    tile fetch, the request comes back aborted, and later work is unaffected."""
+    tile fetch, the request comes back aborted, and later work, including a request
+    submitted after the call and before the step that carries it out, is unaffected."""
     Z = _Z()
     t = W.harmonic_batch(48, n_samples=1_000_000_000)
     queued = W.eq1_series(n_samples=10_000, n_funcs=4)
@@ -153,10 +154,13 @@ def test_abort_then_recover():
         c.run()
         rid2 = c.submit(queued, Z.PREC_FP32)   # queued before the abort: cancelled too
         c.abort()
+        later = W.eq1_series(n_samples=20_000, n_funcs=6)
+        rid3 = c.submit(later, Z.PREC_FP64)      # after the abort call: served normally
         r = c.results(rid, len(t), allow_aborted=True)
         assert np.all(r["status"] == -10)
         r2 = c.results(rid2, len(queued), allow_aborted=True)
         assert np.all(r2["status"] == -10)
+        G.check_fp64(c.results(rid3, len(later)), G.oracle_results(later), "submitted after the abort")
         # the abort word clears once the queue has drained; new work runs normally
         small = W.eq1_series(n_samples=20_000, n_funcs=8)
         got = c.integrate(small, Z.PREC_FP64)

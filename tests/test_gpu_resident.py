@@ -121,12 +121,14 @@ def test_resident_abort_then_continue():
         time.sleep(0.002)
         print("resident: abort", flush=True)
         c.abort()
+        rid_later = c.submit(small, Z.PREC_FP32)  # after the abort call: served normally
         r = c.results(rid, len(big), blocking=True, allow_aborted=True)
         # results that came in before the abort stay, bit for bit; the rest are aborted
         kept = r["status"] == 0
         assert np.all(r["status"][~kept] == -10) and not np.all(kept)
         for f in ("mean", "std_error", "sum_f", "sum_f2", "n", "precision"):
             assert np.array_equal(r[f][kept], ref_big[f][kept]), f
+        _same(c.results(rid_later, len(small)), ref, "submitted after the abort")
         _same(c.integrate(small, Z.PREC_FP32), ref, "after abort")
 
 
