@@ -1028,8 +1028,8 @@ bool cancel_requests()
     return true;
 }
 
-// Snapshots, restores and cancels interleaved with running work in a launch
-// and a resident context (the emulated resident kernel runs in worker threads,
+// Snapshots, restores, cancels and the odd abort interleaved with running work
+// in a launch and a resident context (the emulated resident kernel runs in worker threads,
 // so the interleavings vary from run to run), by seeded scripts: every request
 // and every restored copy comes back exact, every cancelled one with exactly
 // the results that were in.  Run under the address sanitizer, a request used
@@ -1132,6 +1132,12 @@ bool interleave_one(uint32_t seed, bool resident_first)
             Live& l = live[cand[next((uint32_t)cand.size())]];
             CHECK(mc_cancel(l.ctx, l.id) == MC_OK, "seed %u: cancel: %s", seed, mc_last_error(l.ctx));
             l.cancelled = true;
+        } else if (op == 4 && next(8) == 0) {
+            // abort one context: every request in it so far keeps what came in
+            mc_ctx* c = next(2) ? a : b;
+            CHECK(mc_abort(c) == MC_OK, "seed %u: abort", seed);
+            for (Live& l : live)
+                if (l.ctx == c) l.cancelled = true;
         } else {
             CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
         }

@@ -2,10 +2,11 @@
 MI355X, in both engines: a seeded script submits requests (tables and grids,
 FP32 and FP64), runs, polls, snapshots requests while their work is on the GPU,
 restores the snapshots into the same context and into a context of the other
-engine while that one runs other requests, cancels some requests, and takes
-results as they complete.  Whatever the timing, every request and every
-restored copy must come back with the results of an uninterrupted run bit for
-bit, and every cancelled one with exactly the results that were in."""
+engine while that one runs other requests, cancels some requests, now and then
+aborts a context, and takes results as they complete.  Whatever the timing,
+every request and every restored copy must come back with the results of an
+uninterrupted run bit for bit, and every cancelled or aborted one with exactly
+the results that were in."""
 
 import numpy as np
 import pytest
@@ -53,9 +54,11 @@ def _kept(a, b, label):
 # (seed 105 with a resident first context cancelled a restored request before
 # its runs opened, which left its saved tile counts in the slots the next
 # request took, until cancelling cleared them)
-@pytest.mark.parametrize("first,seed", [("launch", 31), ("resident", 32), ("launch", 105), ("resident", 105),
-                                        ("launch", 113), ("resident", 118)])
-def test_snapshots_interleaved_with_running_work(first, seed):
+@pytest.mark.parametrize("first,seed,aborts", [("launch", 31, False), ("resident", 32, False), ("launch", 105, False),
+                                               ("resident", 105, False), ("launch", 113, False),
+                                               ("resident", 118, False), ("launch", 201, True),
+                                               ("resident", 202, True), ("launch", 203, True), ("resident", 204, True)])
+def test_snapshots_interleaved_with_running_work(first, seed, aborts):
     import paper_2104_10073_amd as Z
     jobs = _pool(Z)
     with Z.Context(device=0, flags=Z.MC_NO_GRAPH) as c:
@@ -91,6 +94,11 @@ def test_snapshots_interleaved_with_running_work(first, seed):
                         got = ctx.results(rid, jobs[k][3], allow_aborted=True)
                         (_kept if (ctx, rid) in cancelled else _same)(got, ref[k], f"step {step}: job {k}")
                         checked += 1
+            elif op == 4 and aborts and rng.random() < 0.125:
+                # abort one context: every request in it so far keeps what came in
+                ctx = a if rng.random() < 0.5 else b
+                ctx.abort()
+                cancelled.update(key for key in live if key[0] is ctx)
             elif op == 5 and len(set(live) - cancelled) > 2 and rng.random() < 0.5:
                 keys = [key for key in live if key not in cancelled]
                 ctx, rid = keys[int(rng.integers(0, len(keys)))]
