@@ -1049,8 +1049,11 @@ bool interleave_one(uint32_t seed, bool resident_first)
         state ^= state << 17;
         return (uint32_t)(state % n);
     };
-    mc_ctx* a = create(resident_first ? MC_RESIDENT : MC_NO_GRAPH, 5, MC_SCHED_FAIR, 128, 1 << 15);
-    mc_ctx* b = create(resident_first ? MC_NO_GRAPH : MC_RESIDENT, 9, MC_SCHED_SRPT, 128, 1 << 15);
+    // (the launch context replays graphs in odd seeds; the policies rotate)
+    const uint32_t launch_flags = seed % 2 ? 0u : (uint32_t)MC_NO_GRAPH;
+    const uint32_t policies[3] = {MC_SCHED_FAIR, MC_SCHED_SRPT, MC_SCHED_FIFO};
+    mc_ctx* a = create(resident_first ? MC_RESIDENT : launch_flags, 5, policies[seed % 3], 128, 1 << 15);
+    mc_ctx* b = create(resident_first ? launch_flags : MC_RESIDENT, 9, policies[(seed + 1) % 3], 128, 1 << 15);
     CHECK(a && b, "create");
     struct Live {
         mc_ctx* ctx;
