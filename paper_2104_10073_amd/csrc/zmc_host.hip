@@ -3747,6 +3747,7 @@ mc_status register_resident_family(mc_ctx* ctx, const char* source, uint32_t* fa
             module = nullptr;
             const mc_config& cfg = ctx->cfg;
             R.grid = (uint32_t)ctx->num_cus * (cfg.blocks_per_cu ? cfg.blocks_per_cu : (uint32_t)std::max(1, occ));
+            if (!cfg.max_tiles_per_run) R.backlog = 2ull * R.grid;  // (as at creation)
             log_msg(2, "resident kernel compiled with %zu run-time families: %u workgroups", all.size(), R.grid);
             if (!ctx->abort_requested) res_launch(ctx);  // (entries may wait)
         } catch (const HipError& e) {
