@@ -714,10 +714,13 @@ def main():
         # batched FP64 and the plain one-launch-per-function FP64 path on the first timed step's batch
         b0 = batches[Wm]
         torch.cuda.synchronize()
+        fp64_ms0 = ctx.stats()["fp64_ms"]
         t1 = time.perf_counter()
         r64 = ctx.integrate(b0, Z.PREC_FP64, stream=stream)
         torch.cuda.synchronize()
         t_b64 = time.perf_counter() - t1
+        # the FP64 kernel's own time, from the launches' HIP events
+        k64_ms = ctx.stats()["fp64_ms"] - fp64_ms0
         t1 = time.perf_counter()
         rp = ctx.plain_fp64(b0, stream=stream)
         torch.cuda.synchronize()
@@ -726,6 +729,8 @@ def main():
         se = r64["std_error"]
         out["comparators"] = {
             "batched_fp64_evals_per_s": evals_per_step / t_b64,
+            "batched_fp64_kernel_ms": k64_ms,
+            "batched_fp64_kernel_evals_per_s": evals_per_step / (k64_ms * 1e-3) if k64_ms > 0 else None,
             "plain_fp64_evals_per_s": evals_per_step / t_plain,
             "fp32_over_plain_fp64": value / (evals_per_step / t_plain),
             "fp32_vs_fp64_max_dF_over_SE": float(np.max(np.abs(r32["mean"] - r64["mean"]) / se)),
