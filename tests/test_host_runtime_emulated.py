@@ -1,4 +1,5 @@
-"""The library's host runtime on the CPU, under AddressSanitizer and UndefinedBehaviorSanitizer.
+"""The library's host runtime on the CPU, under AddressSanitizer and UndefinedBehaviorSanitizer
+(and, for the scenarios whose emulated kernel runs in worker threads, ThreadSanitizer).
 
 `paper_2104_10073_amd/csrc/zmc_host.hip` is compiled as ordinary C++ against a
 CPU emulation of the HIP runtime (`tests/hipemu/`: "device" memory in host
@@ -31,14 +32,17 @@ SCENARIOS = ["basic", "many_launches", "admission", "grid", "abort", "errors", "
              "resident_abort", "log_levels", "snapshot", "pack_math", "cancel", "interleave"]
 
 
-@pytest.fixture(scope="module")
-def emu_binary(tmp_path_factory):
+# scenarios whose emulated kernel runs in worker threads beside the host runtime
+THREADED = ["resident_basic", "resident_relaunch", "resident_flush", "resident_abort", "snapshot", "cancel",
+            "interleave"]
+
+
+def _build(tmp_path_factory, name, sanitize):
     cxx = shutil.which("g++")
     if cxx is None:
         pytest.skip("g++ is not available")
-    exe = str(tmp_path_factory.mktemp("hipemu") / "emu_scenarios")
-    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
-           "-fno-sanitize-recover=undefined", "-Wall",
+    exe = str(tmp_path_factory.mktemp("hipemu") / name)
+    cmd = [cxx, "-std=c++17", "-O1", "-g", "-fno-omit-frame-pointer"] + sanitize + ["-Wall",
            "-I" + os.path.join(EMU, "include"), "-I" + os.path.join(ROOT, "include"),
            "-I" + os.path.join(ROOT, "paper_2104_10073_amd", "csrc"), "-I" + EMU,
            "-x", "c++", os.path.join(ROOT, "paper_2104_10073_amd", "csrc", "zmc_host.hip"),
@@ -47,6 +51,16 @@ def emu_binary(tmp_path_factory):
     proc = subprocess.run(cmd, capture_output=True, text=True)
     assert proc.returncode == 0, proc.stderr[-4000:]
     return exe
+
+
+@pytest.fixture(scope="module")
+def emu_binary(tmp_path_factory):
+    return _build(tmp_path_factory, "emu_scenarios", ["-fsanitize=address,undefined", "-fno-sanitize-recover=undefined"])
+
+
+@pytest.fixture(scope="module")
+def emu_tsan_binary(tmp_path_factory):
+    return _build(tmp_path_factory, "emu_scenarios_tsan", ["-fsanitize=thread"])
 
 
 @pytest.mark.parametrize("scenario", SCENARIOS)
@@ -60,3 +74,17 @@ def test_host_runtime_scenario(emu_binary, scenario):
     assert f"ok {scenario}" in proc.stdout
     if scenario == "fault_sweep":
         print(proc.stdout)
+
+
+@pytest.mark.parametrize("scenario", THREADED)
+def test_host_runtime_threads(emu_tsan_binary, scenario):
+    """The threaded scenarios under ThreadSanitizer: no data race between the
+    host runtime and the emulated resident kernel's workgroups (ring entries,
+    acknowledgements, control and exit words, done words and result slots)."""
+    env = dict(os.environ)
+    env.pop("MC_FAULT_HIP", None)
+    env["TSAN_OPTIONS"] = "halt_on_error=1"
+    proc = subprocess.run([emu_tsan_binary, scenario], capture_output=True, text=True, env=env, timeout=600)
+    assert proc.returncode == 0, (proc.stdout[-2000:], proc.stderr[-6000:])
+    assert f"ok {scenario}" in proc.stdout
+    assert "ThreadSanitizer" not in proc.stderr
