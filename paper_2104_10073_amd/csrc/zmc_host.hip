@@ -702,6 +702,17 @@ uint32_t tiles_for(uint32_t n_segments, uint32_t seg_log2)
     return (n_segments + per_tile - 1) / per_tile;
 }
 
+// Give an admitted request's function slots and partial range back.
+void release_slots(mc_ctx* ctx, Request* r)
+{
+    if (!r->admitted) return;
+    ctx->fn_alloc.release(r->slot_base, r->count());
+    ctx->part_alloc.release(r->part_base, r->part_count);
+    r->admitted = false;
+}
+
+// Everything a finished request holds: its pending upload, a restored
+// request's saved partials and counts, its slots.
 void free_request_resources(mc_ctx* ctx, Request* r)
 {
     if (r->uploaded) {
@@ -714,10 +725,7 @@ void free_request_resources(mc_ctx* ctx, Request* r)
     }
     std::vector<Partial>().swap(r->staged);
     std::vector<uint32_t>().swap(r->staged_counts);
-    if (!r->admitted) return;
-    ctx->fn_alloc.release(r->slot_base, r->count());
-    ctx->part_alloc.release(r->part_base, r->part_count);
-    r->admitted = false;
+    release_slots(ctx, r);
 }
 
 bool has_work(const Request* r)
@@ -1139,8 +1147,9 @@ void admit(mc_ctx* ctx)
             }
         } catch (const HipError&) {
             // the request stays first in the queue, unadmitted, and is admitted
-            // again later; an upload already handed to the stream finishes
-            // before its slots can be handed to anyone else
+            // again later (a restored one keeps its saved partials for that);
+            // an upload already handed to the stream finishes before its slots
+            // can be handed to anyone else
             if (enqueued) quiet(hipStreamSynchronize(ctx->upload_stream));
             if (r->uploaded) {
                 quiet(hipEventDestroy(r->uploaded));
@@ -1148,7 +1157,7 @@ void admit(mc_ctx* ctx)
             }
             for (uint64_t i = 0; i < nf; ++i) r->st[i].needs_upload = false;
             r->grid_packed = false;
-            free_request_resources(ctx, r);
+            release_slots(ctx, r);
             throw;
         }
         ctx->pending.pop_front();
