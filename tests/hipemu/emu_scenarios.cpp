@@ -417,14 +417,16 @@ bool fault_workload(uint32_t flags, bool* clean)
         f.seed = base.seed + i;
         grid_t.push_back(f);
     }
-    // request 3 is cancelled after the first run; request 4 is request 0,
-    // snapshotted then and restored into the same context
+    // request 3 is cancelled after the first run; requests 4 and 5 are
+    // request 0, snapshotted then and restored into the same context, and 5
+    // is cancelled after the second run
     reqs.push_back(grid_t);
     reqs.push_back(mixed_table(9, 83));
     reqs.push_back(reqs[0]);
-    std::vector<uint64_t> ids(5, 0);
-    std::vector<int> state(5, 0);  // 0 not submitted, 1 pending, 2 done
-    state[4] = 2;
+    reqs.push_back(reqs[0]);
+    std::vector<uint64_t> ids(6, 0);
+    std::vector<int> state(6, 0);  // 0 not submitted, 1 pending, 2 done
+    state[4] = state[5] = 2;
     for (int k = 0; k < 4; ++k) {
         mc_status st = k == 2 ? mc_submit_grid(ctx, &base, &axis, 1, MC_PREC_FP32_EVAL, &ids[k])
                               : mc_submit(ctx, reqs[k].data(), reqs[k].size(), k == 1 ? MC_PREC_FP64 : MC_PREC_FP32_EVAL,
@@ -439,7 +441,7 @@ bool fault_workload(uint32_t flags, bool* clean)
     }
     for (int guard = 0; guard < 20000; ++guard) {
         bool all = true;
-        for (int k = 0; k < 5; ++k) all = all && state[k] == 2;
+        for (int k = 0; k < 6; ++k) all = all && state[k] == 2;
         if (all) break;
         const mc_status st = mc_run(ctx, nullptr);
         if (st != MC_OK && st != MC_NOT_READY) {
@@ -462,8 +464,10 @@ bool fault_workload(uint32_t flags, bool* clean)
                 ss = mc_snapshot(ctx, ids[0], blob.data(), blob.size(), &got);
             }
             if (ss == MC_OK) ss = mc_restore(ctx, blob.data(), got, &ids[4]);
+            if (ss == MC_OK) state[4] = 1;
+            if (ss == MC_OK) ss = mc_restore(ctx, blob.data(), got, &ids[5]);
             if (ss == MC_OK) {
-                state[4] = 1;
+                state[5] = 1;
             } else {
                 // (a request lost with a failed launch cannot be snapshotted)
                 *clean = false;
@@ -473,7 +477,14 @@ bool fault_workload(uint32_t flags, bool* clean)
                       "snapshot and restore: status %d: %s", (int)ss, e.c_str());
             }
         }
-        for (int k = 0; k < 5; ++k) {
+        if (guard == 1 && state[5] == 1) {
+            const mc_status cs = mc_cancel(ctx, ids[5]);
+            if (cs != MC_OK) {
+                *clean = false;
+                CHECK(cs == MC_ERR_HIP, "cancel of the restored copy: status %d", (int)cs);
+            }
+        }
+        for (int k = 0; k < 6; ++k) {
             if (state[k] != 1) continue;
             const std::vector<mc_function>& t = reqs[k];
             std::vector<mc_result> r(t.size());
@@ -484,7 +495,7 @@ bool fault_workload(uint32_t flags, bool* clean)
                 // (the cancelled request too, if the cancel failed before it took effect)
                 if (!check_results(t, r, k == 1, k == 4 ? "restored copy, after injected failures" : "after injected failures"))
                     return false;
-            } else if (rs == MC_ERR_ABORTED && k == 3) {
+            } else if (rs == MC_ERR_ABORTED && (k == 3 || k == 5)) {
                 if (!check_cancelled(t, r, "cancelled")) return false;
             } else {
                 *clean = false;
@@ -492,7 +503,7 @@ bool fault_workload(uint32_t flags, bool* clean)
             }
         }
     }
-    for (int k = 0; k < 5; ++k) CHECK(state[k] == 2, "request %d never finished", k);
+    for (int k = 0; k < 6; ++k) CHECK(state[k] == 2, "request %d never finished", k);
     // the context still works: a new request completes (the injected failure
     // fires once, so if it lands here the second attempt must succeed)
     const std::vector<mc_function> after = mixed_table(6, 83);
