@@ -1069,8 +1069,18 @@ bool cancel_requests()
 // and every restored copy comes back exact, every cancelled one with exactly
 // the results that were in.  Run under the address sanitizer, a request used
 // after it was released would stop the run.
-bool interleave_one(uint32_t seed, bool resident_first)
+bool interleave_one(uint32_t seed, bool resident_first, int fault_at = 0, bool* saw_failure = nullptr)
 {
+    // with fault_at > 0, the fault_at-th checked HIP call from the first
+    // context's creation on fails (either context's): a call that reports it
+    // is let through, and every request must still come back exact, aborted
+    // with exactly what was in, or with an error
+    bool failed = false;
+    auto hip_err = [&](mc_status st) {
+        const bool e = fault_at > 0 && (st == MC_ERR_HIP || st == MC_ERR_OUT_OF_MEMORY);
+        failed = failed || e;
+        return e;
+    };
     std::vector<std::vector<mc_function>> jobs;
     std::vector<bool> fp64;
     for (uint32_t k = 0; k < 8; ++k) {
@@ -1087,8 +1097,14 @@ bool interleave_one(uint32_t seed, bool resident_first)
     // (the launch context replays graphs in odd seeds; the policies rotate)
     const uint32_t launch_flags = seed % 2 ? 0u : (uint32_t)MC_NO_GRAPH;
     const uint32_t policies[3] = {MC_SCHED_FAIR, MC_SCHED_SRPT, MC_SCHED_FIFO};
-    mc_ctx* a = create(resident_first ? MC_RESIDENT : launch_flags, 5, policies[seed % 3], 128, 1 << 15);
     mc_ctx* b = create(resident_first ? launch_flags : MC_RESIDENT, 9, policies[(seed + 1) % 3], 128, 1 << 15);
+    if (fault_at > 0) {
+        char buf[32];
+        std::snprintf(buf, sizeof buf, "%d", fault_at);
+        setenv("MC_FAULT_HIP", buf, 1);
+    }
+    mc_ctx* a = create(resident_first ? MC_RESIDENT : launch_flags, 5, policies[seed % 3], 128, 1 << 15);
+    unsetenv("MC_FAULT_HIP");
     CHECK(a && b, "create");
     struct Live {
         mc_ctx* ctx;
@@ -1104,6 +1120,7 @@ bool interleave_one(uint32_t seed, bool resident_first)
         std::vector<mc_result> r(jobs[l.job].size());
         const mc_status st = mc_results(l.ctx, l.id, r.data(), r.size(), blocking);
         if (st == MC_NOT_READY) return 0;
+        if (hip_err(st)) return 1;
         if (l.cancelled) {
             CHECK(st == MC_OK || st == MC_ERR_ABORTED, "seed %u: cancelled job %u: status %d", seed, l.job, (int)st);
             if (!check_cancelled(jobs[l.job], r, "interleave (cancelled)", fp64[l.job])) return -1;
@@ -1129,8 +1146,10 @@ bool interleave_one(uint32_t seed, bool resident_first)
             const uint32_t k = order[next((uint32_t)order.size())];
             order.erase(std::find(order.begin(), order.end(), k));
             uint64_t id = 0;
-            CHECK(mc_submit(a, jobs[k].data(), jobs[k].size(), fp64[k] ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id) == MC_OK,
-                  "submit: %s", mc_last_error(a));
+            const mc_status ss =
+                mc_submit(a, jobs[k].data(), jobs[k].size(), fp64[k] ? MC_PREC_FP64 : MC_PREC_FP32_EVAL, &id);
+            if (hip_err(ss)) continue;
+            CHECK(ss == MC_OK, "submit: %s", mc_last_error(a));
             live.push_back(Live{a, id, k, false, "submitted at step " + std::to_string(step)});
         } else if (op == 1) {
             std::vector<size_t> cand;
@@ -1139,20 +1158,29 @@ bool interleave_one(uint32_t seed, bool resident_first)
             if (cand.empty()) continue;
             const Live src = live[cand[next((uint32_t)cand.size())]];
             const std::vector<uint8_t> blob = take_snapshot(src.ctx, src.id);
-            CHECK(!blob.empty(), "seed %u: snapshot: %s", seed, mc_last_error(src.ctx));
             mc_ctx* dst = next(2) ? a : b;
+            if (blob.empty() && fault_at > 0) {  // (a HIP failure, or a request lost to one)
+                failed = true;
+                continue;
+            }
+            CHECK(!blob.empty(), "seed %u: snapshot: %s", seed, mc_last_error(src.ctx));
             uint64_t id = 0;
-            CHECK(mc_restore(dst, blob.data(), blob.size(), &id) == MC_OK, "restore: %s", mc_last_error(dst));
+            const mc_status rs = mc_restore(dst, blob.data(), blob.size(), &id);
+            if (hip_err(rs)) continue;
+            CHECK(rs == MC_OK, "restore: %s", mc_last_error(dst));
             live.push_back(Live{dst, id, src.job, false,
                                 "restored at step " + std::to_string(step) + " from request " + std::to_string(src.id) +
                                     " (" + src.how + ")"});
         } else if (op == 2) {
-            CHECK(mc_run(a, nullptr) != MC_ERR_HIP && mc_run(b, nullptr) != MC_ERR_HIP, "run");
+            const mc_status ra = mc_run(a, nullptr), rb = mc_run(b, nullptr);
+            CHECK((ra != MC_ERR_HIP || hip_err(ra)) && (rb != MC_ERR_HIP || hip_err(rb)), "run");
         } else if (op == 3) {
             for (mc_ctx* c : {a, b}) {
                 uint64_t got[64];
                 size_t n = 0;
-                CHECK(mc_poll(c, got, 64, &n) == MC_OK, "poll");
+                const mc_status ps = mc_poll(c, got, 64, &n);
+                if (hip_err(ps)) continue;
+                CHECK(ps == MC_OK, "poll");
                 for (size_t j = 0; j < n; ++j) {
                     auto it = std::find_if(live.begin(), live.end(),
                                            [&](const Live& l) { return l.ctx == c && l.id == got[j]; });
@@ -1168,16 +1196,19 @@ bool interleave_one(uint32_t seed, bool resident_first)
                 if (!live[i].cancelled) cand.push_back(i);
             if (cand.size() <= 2) continue;
             Live& l = live[cand[next((uint32_t)cand.size())]];
-            CHECK(mc_cancel(l.ctx, l.id) == MC_OK, "seed %u: cancel: %s", seed, mc_last_error(l.ctx));
+            const mc_status cs = mc_cancel(l.ctx, l.id);
+            CHECK(cs == MC_OK || hip_err(cs), "seed %u: cancel: %s", seed, mc_last_error(l.ctx));
             l.cancelled = true;
         } else if (op == 4 && next(8) == 0) {
             // abort one context: every request in it so far keeps what came in
             mc_ctx* c = next(2) ? a : b;
-            CHECK(mc_abort(c) == MC_OK, "seed %u: abort", seed);
+            const mc_status as = mc_abort(c);
+            CHECK(as == MC_OK || hip_err(as), "seed %u: abort", seed);
             for (Live& l : live)
                 if (l.ctx == c) l.cancelled = true;
         } else {
-            CHECK(mc_run(a, nullptr) != MC_ERR_HIP, "run");
+            const mc_status ra = mc_run(a, nullptr);
+            CHECK(ra != MC_ERR_HIP || hip_err(ra), "run");
         }
     }
     for (const Live& l : live) {
@@ -1191,6 +1222,7 @@ bool interleave_one(uint32_t seed, bool resident_first)
     }
     mc_destroy(a);
     mc_destroy(b);
+    if (saw_failure) *saw_failure = failed;
     return true;
 }
 
@@ -1202,6 +1234,29 @@ bool interleave()
                 std::fprintf(stderr, "interleave: seed %u, %s first\n", seed, resident_first ? "resident" : "launch");
                 return false;
             }
+    return true;
+}
+
+// The same scripts with one checked HIP call failing in each run, at points
+// spread over the scripts' calls.
+bool interleave_faults()
+{
+    int runs = 0, saw = 0;
+    for (int base : {3, 40, 111})
+        for (uint32_t seed = 1; seed <= 24; ++seed)
+            for (bool resident_first : {false, true}) {
+                const int at = base + (int)seed * 53;
+                bool failed = false;
+                if (!interleave_one(seed, resident_first, at, &failed)) {
+                    std::fprintf(stderr, "interleave_faults: seed %u, %s first, failing call %d\n", seed,
+                                 resident_first ? "resident" : "launch", at);
+                    return false;
+                }
+                ++runs;
+                saw += failed ? 1 : 0;
+            }
+    CHECK(saw > runs / 5, "only %d of %d runs saw the failure", saw, runs);
+    std::printf("interleave_faults: %d runs, %d of them saw a failed HIP call\n", runs, saw);
     return true;
 }
 
@@ -1302,6 +1357,7 @@ int main(int argc, char** argv)
         {"resident_relaunch", resident_relaunch}, {"resident_flush", resident_flush},
         {"resident_abort", resident_abort}, {"log_levels", log_levels}, {"snapshot", snapshot_restore},
         {"pack_math", pack_math}, {"cancel", cancel_requests}, {"interleave", interleave},
+        {"interleave_faults", interleave_faults},
     };
     std::vector<std::string> names;
     for (int i = 1; i < argc; ++i) {

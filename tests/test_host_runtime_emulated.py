@@ -13,7 +13,8 @@ the kernel's protocol: relaunch after idling, record-arena recycling, abort,
 destroy while running), checkpoint and resume between launch and resident
 contexts (damaged snapshots, queued restored requests), cancellation of single
 requests, seeded scripts that interleave submissions, snapshots, restores and
-cancels in a launch and a resident context, logging, the packing's hypot and atan2, and a sweep that fails every checked HIP call of a workload
+cancels in a launch and a resident context (also with one HIP call failing
+in each run), logging, the packing's hypot and atan2, and a sweep that fails every checked HIP call of a workload
 in turn (MC_FAULT_HIP) and requires each request to come back either with
 exactly its results or with an error -- never MC_OK with wrong values, never a
 hang, no leak.
@@ -29,7 +30,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU = os.path.join(ROOT, "tests", "hipemu")
 SCENARIOS = ["basic", "many_launches", "admission", "grid", "abort", "errors", "plain", "two_contexts",
              "fault_sweep", "autotune_cache", "resident_basic", "resident_relaunch", "resident_flush",
-             "resident_abort", "log_levels", "snapshot", "pack_math", "cancel", "interleave"]
+             "resident_abort", "log_levels", "snapshot", "pack_math", "cancel", "interleave",
+             "interleave_faults"]
 
 
 # scenarios whose emulated kernel runs in worker threads beside the host runtime
