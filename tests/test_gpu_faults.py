@@ -5,7 +5,8 @@ the library makes reports failure without being made (the GPU itself never
 faults: the call is simply not issued), and drives three requests -- mixed
 forms in FP32, the edge table (with its promoted rows), a mixed FP64 table --
 through launches of 8 tiles, or through a resident context (every third n)
-whose ring holds 8 unread tiles.  Every request must come back either bitwise as
+whose ring holds 8 unread tiles; after the first run the first request is
+snapshotted and restored into the same context as a fourth.  Every request must come back either bitwise as
 in a run without failures or with MC_ERR_HIP / MC_ERR_OUT_OF_MEMORY; every
 call returns.  The CPU emulation sweeps every n (test_host_runtime_emulated);
 this runs the same kind of sweep against the real runtime, graphs included.
@@ -33,29 +34,39 @@ def _run(Z, flags, tables):
         assert e.status in (-6, -8), e
         return None, e.status
     out, ids, run_errors = {}, {}, 0
+    sizes = {k: len(t) for k, (t, _) in enumerate(tables)}
     try:
         for k, (t, prec) in enumerate(tables):
             ids[k] = ctx.submit(t, prec)
         for it in range(20000):
-            if len(out) == len(tables):
+            if len(out) == len(tables) + 1:
                 break
             try:
                 ctx.run()
             except Z.McError as e:
                 assert e.status in (-6, -8), e
                 run_errors += 1
+            if it == 0:
+                # the first request, snapshotted while its work runs, restored into the same context
+                k = len(tables)
+                sizes[k] = sizes[0]
+                try:
+                    ids[k] = ctx.restore(ctx.snapshot(ids[0]))
+                except Z.McError as e:
+                    assert e.status in (-1, -6, -8), e  # (-1: the request was lost to a failed launch)
+                    out[k] = e.status
             for k, rid in ids.items():
                 if k in out:
                     continue
                 try:
-                    r = ctx.results(rid, len(tables[k][0]), blocking=it > 10000)
+                    r = ctx.results(rid, sizes[k], blocking=it > 10000)
                 except Z.McError as e:
                     assert e.status in (-6, -8), e
                     out[k] = e.status
                     continue
                 if r is not None:
                     out[k] = r
-        assert len(out) == len(tables), "requests left unfinished"
+        assert len(out) == len(tables) + 1, "requests left unfinished"
     finally:
         ctx.close()
     return out, run_errors
@@ -69,6 +80,8 @@ def test_failed_hip_calls_never_give_wrong_results():
     os.environ.pop("MC_FAULT_HIP", None)
     ref, errors = _run(Z, Z.MC_NO_GRAPH, tables)
     assert errors == 0 and all(isinstance(v, np.ndarray) for v in ref.values())
+    for f in FIELDS:  # the restored copy completes as the request itself
+        assert np.array_equal(ref[3][f], ref[0][f]), f
     res_ref, errors = _run(Z, Z.MC_RESIDENT, tables)
     assert errors == 0
     for k in ref:
