@@ -36,7 +36,7 @@ SCENARIOS = ["basic", "many_launches", "admission", "grid", "abort", "errors", "
 
 # scenarios whose emulated kernel runs in worker threads beside the host runtime
 THREADED = ["resident_basic", "resident_relaunch", "resident_flush", "resident_abort", "snapshot", "cancel",
-            "interleave"]
+            "interleave", "interleave_faults"]
 
 
 def _build(tmp_path_factory, name, sanitize):
